@@ -1,0 +1,279 @@
+"""CPU oracle for C = A^t A, packed lower triangle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The GPU library never does, and this package imports nothing
+from it.
+
+Functions
+  classical(A)              plain definition, k ascending (Section 3, block
+                            equations; output n(n+1)/2 entries)
+  classical_mt(A, ...)      the same definition, threaded; bitwise equal
+  ata(A, cutoff, ...)       Algorithm 1 with HASA off-diagonal products,
+                            returns (C, counts)
+  hasa(X, Y, cutoff, ...)   the rectangular Strassen/Winograd routine alone
+  ata_mult_count(m, n, c)   multiplication count of Algorithm 1 (no data)
+  bf16_round, bf16_split, e4m3_round, pow2_column_scales
+                            number-format conversions used by the reduced
+                            precision forms, written from the format
+                            definitions (IEEE-754 binary32 -> bfloat16 with
+                            round-to-nearest-even; OCP 8-bit e4m3)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import build, lib_path
+
+__all__ = [
+    "classical", "classical_mt", "ata", "hasa", "ata_mult_count", "unpack", "pack",
+    "tri", "rel_fro", "scaled_err", "freivalds_residual", "bf16_round", "bf16_split",
+    "e4m3_round", "pow2_column_scales", "STRASSEN", "WINOGRAD", "load",
+]
+
+STRASSEN = 0
+WINOGRAD = 1
+_VARIANTS = {"strassen": STRASSEN, "winograd": WINOGRAD, STRASSEN: STRASSEN, WINOGRAD: WINOGRAD}
+
+_lib = None
+
+
+class Counts(ctypes.Structure):
+    _fields_ = [
+        ("mults", ctypes.c_int64),
+        ("adds", ctypes.c_int64),
+        ("ata_leaves", ctypes.c_int64),
+        ("hasa_leaves", ctypes.c_int64),
+        ("hasa_calls", ctypes.c_int64),
+        ("max_hasa_depth", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+def load():
+    """Load the compiled oracle, compiling it first if no build exists."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        build()
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    lib.ora_classical.argtypes = [dp, i64, i64, i64, dp]
+    lib.ora_classical.restype = None
+    lib.ora_classical_mt.argtypes = [dp, i64, i64, i64, i64, i64, dp, ctypes.c_int]
+    lib.ora_classical_mt.restype = ctypes.c_int
+    lib.ora_ata.argtypes = [dp, i64, i64, i64, dp, i64, ctypes.c_int, ctypes.c_int,
+                            ctypes.POINTER(Counts)]
+    lib.ora_ata.restype = None
+    lib.ora_hasa.argtypes = [dp, i64, dp, i64, i64, i64, i64, dp, i64, i64, ctypes.c_int,
+                             ctypes.c_int, ctypes.POINTER(Counts)]
+    lib.ora_hasa.restype = None
+    lib.ora_ata_mult_count.argtypes = [i64, i64, i64, ctypes.c_int]
+    lib.ora_ata_mult_count.restype = i64
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _as_rows(A: np.ndarray):
+    """Return (buffer, m, n, lda) for a row-major float64 matrix view."""
+    A = np.asarray(A)
+    if A.dtype != np.float64:
+        raise TypeError("the oracle works in float64")
+    if A.ndim != 2:
+        raise ValueError("A must be 2-D")
+    m, n = A.shape
+    if A.strides[1] != 8 or (m > 1 and A.strides[0] % 8) or (m > 1 and A.strides[0] < 8 * n):
+        A = np.ascontiguousarray(A)
+    lda = A.strides[0] // 8 if m > 1 else max(n, 1)
+    return A, m, n, lda
+
+
+def tri(n: int) -> int:
+    return n * (n + 1) // 2
+
+
+def classical(A: np.ndarray) -> np.ndarray:
+    """Packed lower triangle of A^t A by the plain definition (k ascending)."""
+    A, m, n, lda = _as_rows(A)
+    C = np.zeros(tri(n), dtype=np.float64)
+    if n:
+        load().ora_classical(_dptr(A), m, n, lda, _dptr(C))
+    return C
+
+
+def classical_mt(A: np.ndarray, rows=None, threads: int | None = None) -> np.ndarray:
+    """Packed rows [i0, i1) of the lower triangle (all rows by default), by the
+    plain definition, tiled and threaded; bitwise equal to classical()."""
+    A, m, n, lda = _as_rows(A)
+    i0, i1 = (0, n) if rows is None else rows
+    if threads is None:
+        threads = os.cpu_count() or 1
+    C = np.zeros(tri(i1) - tri(i0), dtype=np.float64)
+    if i1 > i0:
+        rc = load().ora_classical_mt(_dptr(A), m, n, lda, i0, i1, _dptr(C), int(threads))
+        if rc < 0:
+            raise ValueError("bad row range")
+    return C
+
+
+def ata(A: np.ndarray, cutoff: int = 32, variant="strassen", max_depth: int = -1):
+    """Algorithm 1 (ATA) with HASA off-diagonal products.
+
+    cutoff: base case when m <= cutoff or n <= cutoff; HASA stops at
+    min(M, K, N) <= cutoff.  max_depth >= 0 additionally caps the number of
+    Strassen levels inside each HASA call.  Returns (packed C, counts dict).
+    """
+    if cutoff < 1:
+        raise ValueError("cutoff must be >= 1")
+    A, m, n, lda = _as_rows(A)
+    C = np.zeros(tri(n), dtype=np.float64)
+    cnt = Counts()
+    if n:
+        load().ora_ata(_dptr(A), m, n, lda, _dptr(C), int(cutoff), _VARIANTS[variant],
+                       int(max_depth), ctypes.byref(cnt))
+    return C, cnt.as_dict()
+
+
+def hasa(X: np.ndarray, Y: np.ndarray, cutoff: int = 32, variant="strassen", max_depth: int = -1):
+    """D = X Y by the rectangular Strassen recursion.  Returns (D, counts)."""
+    if cutoff < 1:
+        raise ValueError("cutoff must be >= 1")
+    X, M, K, ldx = _as_rows(X)
+    Y, K2, N, ldy = _as_rows(Y)
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    D = np.zeros((M, N), dtype=np.float64)
+    cnt = Counts()
+    if M and N:
+        load().ora_hasa(_dptr(X), ldx, _dptr(Y), ldy, M, K, N, _dptr(D), max(N, 1), int(cutoff),
+                        _VARIANTS[variant], int(max_depth), ctypes.byref(cnt))
+    return D, cnt.as_dict()
+
+
+def ata_mult_count(m: int, n: int, cutoff: int, max_depth: int = -1) -> int:
+    """Scalar multiplications of Algorithm 1 for an m x n input."""
+    return int(load().ora_ata_mult_count(int(m), int(n), int(cutoff), int(max_depth)))
+
+
+# -------------------------------------------------------------------------
+# Layout helpers and checks
+# -------------------------------------------------------------------------
+
+def unpack(Cp: np.ndarray, n: int) -> np.ndarray:
+    """Full symmetric n x n matrix from the row-major packed lower triangle
+    (entry (i, j), j <= i, at i(i+1)/2 + j)."""
+    full = np.zeros((n, n), dtype=np.asarray(Cp).dtype)
+    il = np.tril_indices(n)
+    full[il] = Cp  # row-major order of tril_indices matches the packing
+    full.T[il] = Cp
+    return full
+
+
+def pack(full: np.ndarray) -> np.ndarray:
+    n = full.shape[0]
+    return np.ascontiguousarray(full[np.tril_indices(n)])
+
+
+def rel_fro(C: np.ndarray, ref: np.ndarray, n: int) -> float:
+    """Relative Frobenius error of packed C against packed ref, measured on
+    the full symmetric matrices (off-diagonal entries counted twice)."""
+    C = np.asarray(C, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    d = C - ref
+    diag = np.array([tri(i + 1) - 1 for i in range(n)], dtype=np.int64)
+    w = np.full(d.shape, 2.0)
+    w[diag] = 1.0
+    num = float(np.sqrt(np.sum(w * d * d)))
+    den = float(np.sqrt(np.sum(w * ref * ref)))
+    return num / den if den > 0 else num
+
+
+def scaled_err(C: np.ndarray, ref: np.ndarray, n: int) -> float:
+    """max |C_ij - ref_ij| / sqrt(ref_ii ref_jj) over the lower triangle."""
+    C = np.asarray(C, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    diag = np.array([ref[tri(i + 1) - 1] for i in range(n)])
+    ii, jj = np.tril_indices(n)
+    den = np.sqrt(np.abs(diag[ii] * diag[jj]))
+    den[den == 0] = 1.0
+    return float(np.max(np.abs(C - ref) / den)) if n else 0.0
+
+
+def freivalds_residual(Cp: np.ndarray, A: np.ndarray, x: np.ndarray) -> float:
+    """|| C x - A^t (A x) || / (||A||_F^2 ||x||): a probabilistic check of C = A^t A
+    in O(mn + n^2) work."""
+    n = A.shape[1]
+    C = unpack(np.asarray(Cp, dtype=np.float64), n)
+    A = np.asarray(A, dtype=np.float64)
+    lhs = C @ x
+    rhs = A.T @ (A @ x)
+    scale = float(np.sum(A * A)) * float(np.linalg.norm(x))
+    return float(np.linalg.norm(lhs - rhs)) / scale if scale > 0 else float(np.linalg.norm(lhs - rhs))
+
+
+# -------------------------------------------------------------------------
+# Number formats for the reduced-precision forms
+# -------------------------------------------------------------------------
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round binary32 values to bfloat16 (round to nearest, ties to even),
+    returned as binary32.  bfloat16 keeps the top 16 bits of binary32; NaN
+    stays NaN."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = x.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = (u + 0x7FFF + lsb) & 0xFFFF0000
+    out = (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32).copy()
+    nan = np.isnan(x)
+    out[nan] = x[nan]
+    return out
+
+
+def bf16_split(x: np.ndarray):
+    """hi = bf16(x), lo = bf16(x - hi) with x - hi formed exactly in binary32."""
+    x = np.asarray(x, dtype=np.float32)
+    hi = bf16_round(x)
+    lo = bf16_round((x - hi).astype(np.float32))
+    return hi, lo
+
+
+E4M3_MAX = 448.0
+
+
+def e4m3_round(x: np.ndarray) -> np.ndarray:
+    """Round binary32 values to OCP e4m3 (1 sign, 4 exponent bits with bias 7,
+    3 mantissa bits, no infinities, max finite 448), ties to even, saturating
+    to +-448; returned as float64 values."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    # normal binade [2^e, 2^(e+1)), e in [-6, 8], step 2^(e-3); subnormals step 2^-9
+    _, ex = np.frexp(np.where(a > 0, a, 1.0))  # a = f 2^ex with f in [0.5, 1)
+    e = np.clip(ex.astype(np.float64) - 1.0, -6, 8)
+    step = np.exp2(e - 3)
+    q = a / step
+    r = np.round(q)  # numpy rounds half to even
+    out = r * step
+    out = np.minimum(out, E4M3_MAX)
+    out[a == 0] = 0.0
+    return np.copysign(out, x)
+
+
+def pow2_column_scales(A: np.ndarray, target: float = E4M3_MAX) -> np.ndarray:
+    """Per-column power-of-two scales s_j = 2^floor(log2(target / max_k |A_kj|));
+    a zero column gets scale 1."""
+    amax = np.max(np.abs(np.asarray(A, dtype=np.float64)), axis=0) if A.shape[0] else np.zeros(A.shape[1])
+    s = np.ones_like(amax)
+    nz = amax > 0
+    s[nz] = np.exp2(np.floor(np.log2(target / amax[nz])))
+    return s

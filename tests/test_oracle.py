@@ -1,0 +1,367 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each pin is chosen so that a plausible mistake in the oracle (a dropped term,
+a wrong sign or index, a transposed operand, a misprinted Strassen product)
+fails at least one of them; test_mutants_are_caught builds such mistakes into
+the oracle and checks exactly that.
+"""
+import ctypes
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import synthetic
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _npl_from_paper_equation(l):
+    # Section 4.1: npl(0) = 1, npl(1) = 6,
+    # npl(l > 1) = 6*4^(l-1) + 2*sum_{k=0}^{l-2} 4^k 7^(l-1-k)
+    if l == 0:
+        return 1
+    if l == 1:
+        return 6
+    return 6 * 4 ** (l - 1) + 2 * sum(4 ** k * 7 ** (l - 1 - k) for k in range(l - 1))
+
+
+def _golden_npl():
+    rows = []
+    with open(os.path.join(HERE, "golden", "npl_counts.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                a, b = line.split()
+                rows.append((int(a), int(b)))
+    return rows
+
+
+# ---------------------------------------------------------------------------
+# Plain definition
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n", [(1, 1), (7, 5), (64, 48), (256, 192), (33, 70)])
+def test_classical_matches_library_product(orc, m, n):
+    """O1 against numpy's A.T @ A (a BLAS routine) to double rounding."""
+    A = synthetic.uniform(m, n, 11 + m + n)
+    C = orc.classical(A)
+    ref = orc.pack(A.T @ A)
+    assert orc.rel_fro(C, ref, n) < 1e-14
+    # exact on small integers
+    Ai = synthetic.integer(m, n, 3 + m)
+    assert np.array_equal(orc.classical(Ai), orc.pack(Ai.T @ Ai))
+
+
+@pytest.mark.parametrize("m,n,rows,threads", [(100, 97, None, 3), (50, 200, (60, 130), 8),
+                                              (1, 5, None, 2), (300, 1, None, 4)])
+def test_classical_mt_bitwise_equal(orc, m, n, rows, threads):
+    A = synthetic.uniform(m, n, 5)
+    full = orc.classical(A)
+    part = orc.classical_mt(A, rows=rows, threads=threads)
+    i0, i1 = rows or (0, n)
+    assert np.array_equal(part, full[orc.tri(i0):orc.tri(i1)])
+
+
+def test_packed_layout_is_row_major_lower(orc):
+    A = np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0]])
+    C = orc.classical(A)
+    # C = A^t A = [[17, 22, 27], [22, 29, 36], [27, 36, 45]]
+    assert C.tolist() == [17.0, 22.0, 29.0, 27.0, 36.0, 45.0]
+
+
+def test_lda_padding_is_ignored(orc):
+    A = synthetic.integer(40, 30, 9)
+    buf = synthetic.with_lda(A, 37)
+    view = buf[:, :30]
+    assert np.array_equal(orc.classical(view), orc.classical(A))
+    C, _ = orc.ata(view, cutoff=4)
+    assert np.array_equal(C, orc.classical(A))
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 (ATA) against the definition, exactly, on integer inputs
+# ---------------------------------------------------------------------------
+
+def test_ata_bruteforce_small_shapes(orc):
+    """Every m, n <= 12, cutoff 1..4, both variants, several depth caps:
+    all intermediates are small integers, so ATA must equal the definition
+    exactly."""
+    rng = np.random.default_rng(123)
+    for m in range(1, 13):
+        for n in range(1, 13):
+            A = rng.integers(-3, 4, size=(m, n)).astype(np.float64)
+            ref = orc.classical(A)
+            for c in (1, 2, 3, 4):
+                for var in ("strassen", "winograd"):
+                    for md in (-1, 1):
+                        C, _ = orc.ata(A, cutoff=c, variant=var, max_depth=md)
+                        assert np.array_equal(C, ref), (m, n, c, var, md)
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (3, 2)])
+def test_ata_exhaustive_pm1(orc, shape):
+    """All matrices with entries in {-1, 0, 1} of the given shape, cutoff 1."""
+    m, n = shape
+    for vals in itertools.product((-1.0, 0.0, 1.0), repeat=m * n):
+        A = np.array(vals).reshape(m, n)
+        for var in ("strassen", "winograd"):
+            C, _ = orc.ata(A, cutoff=1, variant=var)
+            assert np.array_equal(C, orc.classical(A))
+
+
+@pytest.mark.parametrize("m,n,c", [(256, 192, 32), (200, 77, 8), (65, 129, 16), (513, 300, 64),
+                                   (1000, 40, 8)])
+def test_ata_integer_exact_medium(orc, m, n, c):
+    A = synthetic.integer(m, n, 1)
+    ref = orc.classical(A)
+    for var in ("strassen", "winograd"):
+        C, cnt = orc.ata(A, cutoff=c, variant=var)
+        assert np.array_equal(C, ref)
+
+
+def test_ata_fp64_error_small(orc):
+    """Uniform FP64 input of the 256 x 192 correctness workload: Strassen's
+    extra rounding error at two levels stays near double precision."""
+    A = synthetic.uniform(256, 192, synthetic.SEED_UNIFORM_SMALL)
+    ref = orc.classical(A)
+    for var in ("strassen", "winograd"):
+        C, _ = orc.ata(A, cutoff=32, variant=var)
+        assert orc.rel_fro(C, ref, 192) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Structure: multiplication counts
+# ---------------------------------------------------------------------------
+
+def test_mult_count_matches_paper_npl(orc):
+    """Cutoff 1 on 2^l x 2^l: Algorithm 1 performs npl(l) scalar products
+    (golden values printed in Section 4.1; higher l from its equation)."""
+    for l, npl in _golden_npl():
+        assert orc.ata_mult_count(2 ** l, 2 ** l, 1) == npl
+        assert _npl_from_paper_equation(l) == npl
+    for l in range(4, 9):
+        assert orc.ata_mult_count(2 ** l, 2 ** l, 1) == _npl_from_paper_equation(l)
+    # the data-carrying recursion counts the same
+    for l in range(0, 6):
+        A = synthetic.integer(2 ** l, 2 ** l, l)
+        _, cnt = orc.ata(A, cutoff=1)
+        assert cnt["mults"] == _npl_from_paper_equation(l)
+
+
+def test_mult_count_closed_form(orc):
+    """T(n) = 4T(n/2) + 2*7^(log2 n - 1) solves to (2*7^l + 4^l)/3, not the
+    (2/7) n^log2(7) bound the paper states (Section 3.1)."""
+    for l in range(0, 10):
+        cnt = orc.ata_mult_count(2 ** l, 2 ** l, 1)
+        assert 3 * cnt == 2 * 7 ** l + 4 ** l
+        if l >= 2:
+            assert cnt > (2.0 / 7.0) * 7 ** l
+
+
+def test_mult_count_classical_when_cutoff_large(orc):
+    for m, n in [(10, 7), (300, 20), (5, 500)]:
+        assert orc.ata_mult_count(m, n, 10 ** 6) == m * n * (n + 1) // 2
+
+
+def test_c1_tree_shape(orc):
+    """256 x 192 with cutoff 32: depth 3, 64 base-case leaves of 32 x 24 and
+    186 classical HASA leaves of 24 x 32 x 24."""
+    A = synthetic.integer(256, 192, 1)
+    _, cnt = orc.ata(A, cutoff=32)
+    assert cnt["ata_leaves"] == 64
+    assert cnt["hasa_leaves"] == 186
+    assert cnt["mults"] == 64 * 32 * (24 * 25 // 2) + 186 * 24 * 32 * 24
+    assert cnt["mults"] == orc.ata_mult_count(256, 192, 32)
+
+
+# ---------------------------------------------------------------------------
+# HASA / Strassen formulas
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,K,N,c", [(4, 4, 4, 1), (7, 5, 9, 1), (16, 16, 16, 2), (33, 17, 21, 3),
+                                     (64, 8, 64, 4)])
+def test_hasa_equals_product_on_integers(orc, M, K, N, c):
+    rng = np.random.default_rng(M * 100 + K)
+    X = rng.integers(-4, 5, size=(M, K)).astype(np.float64)
+    Y = rng.integers(-4, 5, size=(K, N)).astype(np.float64)
+    for var in ("strassen", "winograd"):
+        D, cnt = orc.hasa(X, Y, cutoff=c, variant=var)
+        assert np.array_equal(D, X @ Y)
+
+
+def test_printed_products_fail():
+    """The HASA-P subsection prints M1 = (A11 + A12)(B11 + B22) and
+    M7 = (A11 - A22)(B21 - B22); with the printed quadrant sums they do not
+    give A B, while Strassen's M1 = (A11 + A22)(B11 + B22) and
+    M7 = (A12 - A22)(B21 + B22) do."""
+    rng = np.random.default_rng(0)
+
+    def combine(a, b, printed):
+        a11, a12, a21, a22 = a[0, 0], a[0, 1], a[1, 0], a[1, 1]
+        b11, b12, b21, b22 = b[0, 0], b[0, 1], b[1, 0], b[1, 1]
+        m1 = (a11 + a12) * (b11 + b22) if printed else (a11 + a22) * (b11 + b22)
+        m2 = (a21 + a22) * b11
+        m3 = a11 * (b12 - b22)
+        m4 = a22 * (b21 - b11)
+        m5 = (a11 + a12) * b22
+        m6 = (a21 - a11) * (b11 + b12)
+        m7 = (a11 - a22) * (b21 - b22) if printed else (a12 - a22) * (b21 + b22)
+        return np.array([[m1 - m5 + m7 + m4, m3 + m5], [m2 + m4, m3 + m6 - m2 + m1]])
+
+    bad = 0
+    for _ in range(20):
+        a = rng.integers(-5, 6, size=(2, 2)).astype(float)
+        b = rng.integers(-5, 6, size=(2, 2)).astype(float)
+        assert np.array_equal(combine(a, b, printed=False), a @ b)
+        bad += not np.array_equal(combine(a, b, printed=True), a @ b)
+    assert bad >= 18
+
+
+# ---------------------------------------------------------------------------
+# Special cases and invariants
+# ---------------------------------------------------------------------------
+
+def test_special_cases(orc):
+    a = synthetic.integer(50, 1, 4)
+    C, _ = orc.ata(a, cutoff=1)
+    assert C.tolist() == [float(np.sum(a * a))]
+    r = synthetic.integer(1, 9, 4)
+    C, _ = orc.ata(r, cutoff=1)
+    assert np.array_equal(C, orc.pack(np.outer(r[0], r[0])))
+    I = np.eye(37)
+    C, _ = orc.ata(I, cutoff=2)
+    assert np.array_equal(C, orc.pack(np.eye(37)))
+
+
+def test_hadamard_columns(orc):
+    """H_256[:, :192] has orthogonal columns of squared norm 256."""
+    H = synthetic.hadamard(256)[:, :192].copy()
+    for var in ("strassen", "winograd"):
+        C, _ = orc.ata(H, cutoff=32, variant=var)
+        assert np.array_equal(C, orc.pack(256.0 * np.eye(192)))
+
+
+def test_invariants(orc):
+    A = synthetic.integer(300, 120, 8)
+    C, _ = orc.ata(A, cutoff=16)
+    n = 120
+    diag = np.array([C[orc.tri(i + 1) - 1] for i in range(n)])
+    assert np.array_equal(diag, np.sum(A * A, axis=0))
+    assert diag.sum() == np.sum(A * A)
+    full = orc.unpack(C, n)
+    ones = np.ones(n)
+    assert ones @ full @ ones == np.sum((A @ ones) ** 2)
+    # Freivalds on random data, and positive definiteness
+    Au = synthetic.uniform(300, 120, 9)
+    Cu, _ = orc.ata(Au, cutoff=16)
+    x = np.random.default_rng(1).standard_normal(n)
+    assert orc.freivalds_residual(Cu, Au, x) < 1e-14
+    np.linalg.cholesky(orc.unpack(Cu, n))
+
+
+def test_power_of_two_column_scaling_is_exact_for_classical(orc):
+    """Classical products commute exactly with power-of-two column scaling:
+    (AD)^t (AD) = D (A^t A) D bitwise."""
+    A = synthetic.uniform(80, 40, 2)
+    d = np.exp2(np.random.default_rng(3).integers(-20, 20, size=40)).astype(np.float64)
+    lhs = orc.classical(A * d[None, :])
+    full = orc.unpack(orc.classical(A), 40)
+    rhs = orc.pack(full * d[:, None] * d[None, :])
+    assert np.array_equal(lhs, rhs)
+
+
+def test_empty_and_degenerate(orc):
+    C, _ = orc.ata(np.zeros((0, 5)), cutoff=4)
+    assert np.array_equal(C, np.zeros(15))
+    C, _ = orc.ata(np.zeros((5, 0)), cutoff=4)
+    assert C.size == 0
+    with pytest.raises(ValueError):
+        orc.ata(np.ones((3, 3)), cutoff=0)
+
+
+# ---------------------------------------------------------------------------
+# Planted mistakes must be caught
+# ---------------------------------------------------------------------------
+
+MUTANTS = {
+    1: "second addend of C11 dropped",
+    2: "sign of M2 in D22 flipped",
+    3: "transposed operand in the C21 product",
+    4: "A21 taken at the wrong row offset",
+    5: "M1 as misprinted",
+    6: "M7 as misprinted",
+    7: "Winograd U3 sign flipped",
+    8: "first term of the base-case sum dropped",
+}
+
+
+def _run_pins(lib_path):
+    """Return True if every integer-exactness pin passes for the library."""
+    import oracle as orc
+    lib = ctypes.CDLL(lib_path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    lib.ora_ata.argtypes = [dp, i64, i64, i64, dp, i64, ctypes.c_int, ctypes.c_int,
+                            ctypes.POINTER(orc.Counts)]
+    ok = True
+    rng = np.random.default_rng(7)
+    for (m, n) in [(9, 8), (12, 12), (17, 10), (40, 33)]:
+        A = rng.integers(-3, 4, size=(m, n)).astype(np.float64)
+        ref = orc.pack(A.T @ A)  # numpy/BLAS on small integers is exact
+        for var in (0, 1):
+            C = np.zeros(orc.tri(n))
+            cnt = orc.Counts()
+            lib.ora_ata(A.ctypes.data_as(dp), m, n, n, C.ctypes.data_as(dp), 2, var, -1,
+                        ctypes.byref(cnt))
+            ok &= bool(np.array_equal(C, ref))
+    return ok
+
+
+def test_mutants_are_caught(tmp_path):
+    from oracle.build import build
+    assert _run_pins(build(mutant=0, out=str(tmp_path / "clean.so")))
+    for k, what in MUTANTS.items():
+        path = build(mutant=k, out=str(tmp_path / ("mut%d.so" % k)))
+        assert not _run_pins(path), "mutant %d (%s) survived the pins" % (k, what)
+
+
+# ---------------------------------------------------------------------------
+# Number formats
+# ---------------------------------------------------------------------------
+
+def test_bf16_round_matches_torch_cast(orc):
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(100000).astype(np.float32) * 10.0 ** rng.uniform(-30, 30, 100000).astype(np.float32),
+                        np.array([0.0, -0.0, 1.0, 1.00390625, 1.01171875, 65504.0, 3.0e38, -1e-40], dtype=np.float32)])
+    x = x[np.isfinite(x)].astype(np.float32)
+    ours = orc.bf16_round(x)
+    theirs = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    fin = np.isfinite(theirs)
+    assert np.array_equal(ours[fin].view(np.uint32), theirs[fin].view(np.uint32))
+    hi, lo = orc.bf16_split(x[:1000])
+    assert np.all(np.abs((hi.astype(np.float64) + lo) - x[:1000]) <= np.abs(x[:1000]) * 2.0 ** -16 + 1e-45)
+
+
+def test_e4m3_round_matches_torch_cast(orc):
+    torch = pytest.importorskip("torch")
+    if not hasattr(torch, "float8_e4m3fn"):
+        pytest.skip("no float8 dtype")
+    rng = np.random.default_rng(1)
+    x = (rng.uniform(-448, 448, 200000) * 10.0 ** rng.uniform(-4, 0, 200000)).astype(np.float32)
+    x = np.concatenate([x, np.array([448.0, -448.0, 0.0, 2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -11, 240.0, 248.0],
+                                    dtype=np.float32)])
+    ours = orc.e4m3_round(x)
+    theirs = torch.from_numpy(x).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(ours, theirs)
+    # saturation (from the format's definition: largest finite value 448)
+    assert orc.e4m3_round(np.array([1000.0, -470.0]))[0] == 448.0
+    assert orc.e4m3_round(np.array([1000.0, -470.0]))[1] == -448.0
+
+
+def test_pow2_scales(orc):
+    A = np.array([[1.0, -3.0, 0.0], [0.5, 2.0, 0.0]])
+    s = orc.pow2_column_scales(A)
+    assert s.tolist() == [256.0, 128.0, 1.0]
+    assert np.all(np.max(np.abs(A), axis=0) * s <= 448.0)
