@@ -1,0 +1,152 @@
+/*
+ * ata.h - C ABI of the MI355X A^t A library (libata.so).
+ *
+ * Computes the lower triangle of the symmetric product C = A^t A of a
+ * rectangular m x n matrix A by the ATA recursion (Section 3, Algorithm 1):
+ * A is split into quadrants with m1 = ceil(m/2), m2 = floor(m/2),
+ * n1 = ceil(n/2), n2 = floor(n/2); the diagonal blocks
+ * C11 = A11^t A11 + A21^t A21 and C22 = A12^t A12 + A22^t A22 come from
+ * recursive ATA calls whose second product is accumulated into the first, and
+ * the off-diagonal block C21 = A12^t A11 + A22^t A21 from rectangular Strassen
+ * products (HASA); C12 is never formed.  The recursion stops when m or n is at
+ * most the cutoff (the paper uses 32) and the block is then multiplied
+ * classically.
+ *
+ * Layout (the paper fixes neither):
+ *   A        row-major, element (i, j) at A[i * lda + j], lda >= n, device
+ *            memory, read only.
+ *   C_lower  row-major packed lower triangle: element (i, j), j <= i, at
+ *            C_lower[i * (i + 1) / 2 + j]; n (n + 1) / 2 elements, device
+ *            memory, overwritten (never read).  This is also LAPACK's
+ *            column-major packed upper storage of the same matrix.
+ *
+ * Every call is asynchronous on the given HIP stream (0 = the null stream);
+ * a status of ATA_OK means the work was enqueued.  Errors raised by kernels
+ * surface at the caller's next synchronisation.  Calls on different streams
+ * may overlap; the plan cache is shared and thread safe.
+ *
+ * Return codes: 0 = ATA_OK; a negative value -k means the k-th argument is
+ * invalid (LAPACK convention); positive values are runtime errors (below).
+ */
+#ifndef ATA_H
+#define ATA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes */
+#define ATA_OK 0
+#define ATA_ENOMEM 1         /* device or host allocation failed */
+#define ATA_EHIP 2           /* a HIP runtime call failed (see ata_last_hip_error) */
+#define ATA_EUNSUPPORTED 3   /* device is not gfx950, or option not supported */
+#define ATA_EWORKSPACE 4     /* caller workspace smaller than ata_workspace_bytes */
+#define ATA_EREJECT 5        /* serving: request can never fit the memory budget */
+#define ATA_EBUSY 6          /* serving: queue full, retry later */
+#define ATA_ENOTFOUND 7      /* serving: unknown ticket */
+#define ATA_EPENDING 8       /* serving: request not finished yet */
+
+/* Arithmetic forms.  The low byte selects input type and leaf arithmetic;
+ * ATA_OUT_F64 selects a double-precision C for the float-input forms. */
+#define ATA_F64 0         /* A double, C double; FP64 MFMA leaves */
+#define ATA_F32 1         /* A float; FP32 MFMA leaves */
+#define ATA_F32_BF16X3 2  /* A float; bfloat16 split leaves: x = hi + lo,
+                             hi^t hi + hi^t lo + lo^t hi, FP32 accumulation */
+#define ATA_F32_FP8 3     /* A float; OCP e4m3 leaves with per-column
+                             power-of-two scales, FP32 accumulation */
+#define ATA_OUT_F64 0x100 /* with 1..3: C is double instead of float */
+
+/* Strassen variants for the HASA products */
+#define ATA_VARIANT_STRASSEN 0 /* Strassen 1969: 7 products, 18 additions */
+#define ATA_VARIANT_WINOGRAD 1 /* Winograd 1971: 7 products, 15 additions */
+
+/* Options for ata_ex / ata_workspace_bytes / ata_plan_info.
+ * Zero-initialise, then set fields; a NULL pointer means all defaults. */
+typedef struct ata_opts {
+    int32_t variant;     /* ATA_VARIANT_*; default Strassen */
+    int32_t max_depth;   /* Strassen levels per HASA call: -1 = unlimited
+                            (the paper's rule: recurse while min(M,K,N) >
+                            cutoff), 0 = classical off-diagonal products,
+                            k > 0 = at most k levels.  Default when the
+                            struct is NULL: ATA_DEFAULT_MAX_DEPTH. */
+    int32_t flags;       /* reserved, must be 0 */
+    int32_t reserved;
+} ata_opts;
+
+#define ATA_DEFAULT_MAX_DEPTH 2
+#define ATA_MAX_DEPTH_LIMIT 4 /* deepest supported Strassen level count */
+
+/*
+ * ata: C_lower = lower(A^t A) for the m x n matrix A (Algorithm 1).
+ *   A        device pointer (double for ATA_F64, else float), lda >= max(n,1)
+ *   m, n     >= 0.  n == 0: nothing is written; m == 0: C_lower is zeroed
+ *            (empty sum).
+ *   C_lower  device pointer, n(n+1)/2 elements of the output type
+ *   dtype    one of ATA_F64, ATA_F32, ATA_F32_BF16X3, ATA_F32_FP8, the last
+ *            three optionally OR-ed with ATA_OUT_F64
+ *   cutoff   > 0: base case when m <= cutoff or n <= cutoff (Algorithm 1);
+ *            HASA stops at min(M, K, N) <= cutoff.  0 = tuned default for
+ *            the shape.  cutoff >= min(m, n) gives one classical product.
+ *   stream   hipStream_t (as void*), 0 for the null stream
+ * Uses ATA_DEFAULT_MAX_DEPTH and allocates its Strassen workspace stream-
+ * ordered on `stream`.
+ */
+int ata(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int dtype,
+        int cutoff, void *stream);
+
+/*
+ * ata_ex: as ata, with options and an optional caller workspace.
+ *   opts       NULL for defaults
+ *   workspace  device memory of ws_bytes, or NULL: the library then
+ *              allocates it stream-ordered.  Must not be used by other work
+ *              until the call's work on `stream` has completed.
+ */
+int ata_ex(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int dtype, int cutoff,
+           void *stream, const ata_opts *opts, void *workspace, size_t ws_bytes);
+
+/* Bytes of device workspace ata_ex needs for this problem (0 if none). */
+int ata_workspace_bytes(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts *opts,
+                        size_t *bytes);
+
+/* Host-only description of the plan (no GPU needed). */
+typedef struct ata_plan_stats {
+    int64_t mults;           /* scalar multiplications of the method */
+    int64_t classical_mults; /* m * n (n + 1) / 2 */
+    int64_t syrk_tasks;      /* diagonal base-case blocks */
+    int64_t gemm_tasks;      /* classical off-diagonal products */
+    int64_t strassen_tasks;  /* in-tile Strassen products (7 leaf products each) */
+    int64_t combine_tasks;   /* workspace combinations */
+    int64_t work_items;      /* workgroup tiles over all launches */
+    int64_t phases;          /* ordered launch groups */
+    int64_t ata_depth;       /* levels of the ATA recursion */
+    int64_t max_hasa_depth;  /* deepest Strassen level count */
+    int64_t workspace_bytes;
+    int64_t cutoff;          /* cutoff used (after resolving 0) */
+} ata_plan_stats;
+
+int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts *opts,
+                  ata_plan_stats *out);
+
+/* Default cutoff chosen for a shape when cutoff == 0. */
+int ata_default_cutoff(int64_t m, int64_t n, int dtype);
+
+/* Text for a status code (static storage). */
+const char *ata_status_string(int status);
+
+/* HIP error code of the last ATA_EHIP on this thread (0 if none). */
+int ata_last_hip_error(void);
+
+/* Library version as "major.minor.patch" (static storage). */
+const char *ata_version(void);
+
+/* Release cached plans and device task tables (all devices). */
+void ata_release_caches(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ATA_H */

@@ -1,0 +1,174 @@
+"""MI355X-native A^t A (Arrigoni & Massini, ATA with Strassen off-diagonal
+products): thin ctypes binding of libata.so.
+
+Every step of the product runs in the library's HIP kernels; PyTorch only
+provides device memory and streams.  The binding fails loudly when the
+library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "F64", "F32", "F32_BF16X3", "F32_FP8", "OUT_F64", "STRASSEN", "WINOGRAD",
+    "load", "gram", "plan_info", "workspace_bytes", "default_cutoff", "status_string",
+    "AtaError", "lib_path", "tri",
+]
+
+F64 = 0
+F32 = 1
+F32_BF16X3 = 2
+F32_FP8 = 3
+OUT_F64 = 0x100
+STRASSEN = 0
+WINOGRAD = 1
+DEFAULT_MAX_DEPTH = 2
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+
+def lib_path() -> str:
+    return os.path.join(_PKG, "libata.so")
+
+
+class AtaError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = status_string(status) if _lib is not None else str(status)
+        extra = ""
+        if status == 2 and _lib is not None:
+            extra = " (hip error %d)" % _lib.ata_last_hip_error()
+        super().__init__("%s: status %d (%s)%s" % (what or "ata", status, msg, extra))
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "mults", "classical_mults", "syrk_tasks", "gemm_tasks", "strassen_tasks", "combine_tasks",
+        "work_items", "phases", "ata_depth", "max_hasa_depth", "workspace_bytes", "cutoff")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+def load():
+    """Load the in-tree libata.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError("libata.so not built: run paper_1902_02104_amd/build.py (or "
+                           "__graft_entry__.build()) first; there is no fallback path")
+    lib = ctypes.CDLL(path)
+    i64, vp, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+    lib.ata.argtypes = [vp, i64, i64, i64, vp, ci, ci, vp]
+    lib.ata.restype = ci
+    lib.ata_ex.argtypes = [vp, i64, i64, i64, vp, ci, ci, vp, ctypes.POINTER(Opts), vp, ctypes.c_size_t]
+    lib.ata_ex.restype = ci
+    lib.ata_workspace_bytes.argtypes = [i64, i64, ci, ci, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_size_t)]
+    lib.ata_workspace_bytes.restype = ci
+    lib.ata_plan_info.argtypes = [i64, i64, ci, ci, ctypes.POINTER(Opts), ctypes.POINTER(PlanStats)]
+    lib.ata_plan_info.restype = ci
+    lib.ata_default_cutoff.argtypes = [i64, i64, ci]
+    lib.ata_default_cutoff.restype = ci
+    lib.ata_status_string.argtypes = [ci]
+    lib.ata_status_string.restype = ctypes.c_char_p
+    lib.ata_last_hip_error.argtypes = []
+    lib.ata_last_hip_error.restype = ci
+    lib.ata_version.argtypes = []
+    lib.ata_version.restype = ctypes.c_char_p
+    lib.ata_release_caches.argtypes = []
+    lib.ata_release_caches.restype = None
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().ata_status_string(int(status)).decode()
+
+
+def tri(n: int) -> int:
+    return n * (n + 1) // 2
+
+
+def _opts(variant, max_depth):
+    o = Opts()
+    o.variant = {"strassen": STRASSEN, "winograd": WINOGRAD}.get(variant, variant)
+    o.max_depth = DEFAULT_MAX_DEPTH if max_depth is None else int(max_depth)
+    o.flags = 0
+    return o
+
+
+def plan_info(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None) -> dict:
+    """Host-only description of the device plan (no GPU needed)."""
+    st = PlanStats()
+    o = _opts(variant, max_depth)
+    rc = load().ata_plan_info(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(st))
+    if rc:
+        raise AtaError(rc, "ata_plan_info")
+    return st.as_dict()
+
+
+def workspace_bytes(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None) -> int:
+    out = ctypes.c_size_t(0)
+    o = _opts(variant, max_depth)
+    rc = load().ata_workspace_bytes(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(out))
+    if rc:
+        raise AtaError(rc, "ata_workspace_bytes")
+    return int(out.value)
+
+
+def default_cutoff(m: int, n: int, dtype: int = F64) -> int:
+    return int(load().ata_default_cutoff(int(m), int(n), int(dtype)))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_depth=None, out=None,
+         workspace=None, stream=None):
+    """Packed lower triangle of A^t A for a 2-D CUDA tensor A (row-major rows,
+    unit column stride, row stride >= n).  Asynchronous on `stream` (default:
+    torch's current stream).  Returns the packed output tensor."""
+    import torch
+    lib = load()
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D")
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    m, n = A.shape
+    if n > 0 and m > 0 and A.stride(1) != 1:
+        raise ValueError("A needs unit column stride")
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    if dtype is None:
+        dtype = F64 if A.dtype == torch.float64 else F32
+    want_in = torch.float64 if (dtype & 0xff) == F64 else torch.float32
+    if A.dtype != want_in:
+        raise TypeError("A must be %s for dtype %#x" % (want_in, dtype))
+    out_t = torch.float64 if ((dtype & 0xff) == F64 or dtype & OUT_F64) else torch.float32
+    if out is None:
+        out = torch.empty(tri(n), dtype=out_t, device=A.device)
+    elif out.dtype != out_t or out.numel() < tri(n) or not out.is_contiguous():
+        raise ValueError("bad output tensor")
+    o = _opts(variant, max_depth)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    with torch.cuda.device(A.device):
+        rc = lib.ata_ex(ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.c_void_p(out.data_ptr()), int(dtype),
+                        int(cutoff), _stream_handle(stream), ctypes.byref(o),
+                        ctypes.c_void_p(ws_ptr) if ws_ptr else None, ws_bytes)
+    if rc:
+        raise AtaError(rc, "ata_ex")
+    return out

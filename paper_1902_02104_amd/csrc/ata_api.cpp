@@ -1,0 +1,361 @@
+// C ABI of the A^t A library: argument checks, plan cache, device task tables,
+// workspace and launch order.  Declarations and argument conventions are in
+// include/ata.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ata.h"
+#include "ata_plan.h"
+
+namespace atalib {
+hipError_t launch_gemm_f64(const double* A, int64_t lda, const DevTask* tasks, const DevTerm* terms,
+                           const int32_t* segs, const WorkItem* items, int nitems, double* C,
+                           hipStream_t s);
+hipError_t launch_str_f64(int variant, const double* A, int64_t lda, const DevTask* tasks,
+                          const DevTerm* terms, const int32_t* segs, const WorkItem* items, int nitems,
+                          double* C, double* W, hipStream_t s);
+hipError_t launch_combine_f64(const DevCombine* cbs, int ncb, int64_t total, const double* W, double* C,
+                              hipStream_t s);
+hipError_t launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
+}  // namespace atalib
+
+using namespace atalib;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? ATA_ENOMEM : ATA_EHIP;
+}
+
+#define HIP_TRY(expr)                          \
+    do {                                       \
+        hipError_t _e = (expr);                \
+        if (_e != hipSuccess) return hip_fail(_e); \
+    } while (0)
+
+// Device copy of one plan's tables.
+struct PhaseDev {
+    int n_str = 0, n_gemm = 0, n_syrk = 0, n_cb = 0;
+    int64_t cb_elems = 0;
+    size_t off_str = 0, off_gemm = 0, off_syrk = 0, off_cb = 0;
+};
+
+struct PlanDev {
+    Plan plan;
+    int device = -1;
+    char* blob = nullptr;  // device memory holding every table
+    size_t off_tasks = 0, off_terms = 0, off_segs = 0;
+    std::vector<PhaseDev> phases;
+    ~PlanDev() {
+        if (blob) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(device);
+            (void)hipFree(blob);
+            (void)hipSetDevice(cur);
+        }
+    }
+};
+
+using PlanKey = std::tuple<int, int64_t, int64_t, int64_t, int, int>;
+
+std::mutex g_mu;
+std::map<PlanKey, std::shared_ptr<PlanDev>> g_plans;
+std::map<int, int> g_device_ok;  // device -> 1 gfx950, 0 not
+
+int check_device(int dev) {
+    auto it = g_device_ok.find(dev);
+    if (it != g_device_ok.end()) return it->second;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
+    const int ok = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+    g_device_ok[dev] = ok;
+    return ok;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Upload a plan's tables into one device allocation.
+int upload(PlanDev& pd, int dev) {
+    const Plan& P = pd.plan;
+    size_t off = 0;
+    pd.off_tasks = off;
+    off = align256(off + P.tasks.size() * sizeof(DevTask));
+    pd.off_terms = off;
+    off = align256(off + P.terms.size() * sizeof(DevTerm));
+    pd.off_segs = off;
+    off = align256(off + P.segs.size() * sizeof(int32_t));
+    pd.phases.resize(P.phases.size());
+    for (size_t i = 0; i < P.phases.size(); ++i) {
+        const Phase& ph = P.phases[i];
+        PhaseDev& d = pd.phases[i];
+        d.n_str = (int)ph.str_items.size();
+        d.n_gemm = (int)ph.gemm_items.size();
+        d.n_syrk = (int)ph.syrk_items.size();
+        d.n_cb = (int)ph.combines.size();
+        d.cb_elems = ph.combine_elems;
+        d.off_str = off;
+        off = align256(off + ph.str_items.size() * sizeof(WorkItem));
+        d.off_gemm = off;
+        off = align256(off + ph.gemm_items.size() * sizeof(WorkItem));
+        d.off_syrk = off;
+        off = align256(off + ph.syrk_items.size() * sizeof(WorkItem));
+        d.off_cb = off;
+        off = align256(off + ph.combines.size() * sizeof(DevCombine));
+    }
+    std::vector<char> host(off ? off : 256, 0);
+    std::memcpy(host.data() + pd.off_tasks, P.tasks.data(), P.tasks.size() * sizeof(DevTask));
+    std::memcpy(host.data() + pd.off_terms, P.terms.data(), P.terms.size() * sizeof(DevTerm));
+    std::memcpy(host.data() + pd.off_segs, P.segs.data(), P.segs.size() * sizeof(int32_t));
+    for (size_t i = 0; i < P.phases.size(); ++i) {
+        const Phase& ph = P.phases[i];
+        const PhaseDev& d = pd.phases[i];
+        std::memcpy(host.data() + d.off_str, ph.str_items.data(), ph.str_items.size() * sizeof(WorkItem));
+        std::memcpy(host.data() + d.off_gemm, ph.gemm_items.data(), ph.gemm_items.size() * sizeof(WorkItem));
+        std::memcpy(host.data() + d.off_syrk, ph.syrk_items.data(), ph.syrk_items.size() * sizeof(WorkItem));
+        std::memcpy(host.data() + d.off_cb, ph.combines.data(), ph.combines.size() * sizeof(DevCombine));
+    }
+    HIP_TRY(hipMalloc(&pd.blob, host.size()));
+    pd.device = dev;
+    HIP_TRY(hipMemcpy(pd.blob, host.data(), host.size(), hipMemcpyHostToDevice));
+    return ATA_OK;
+}
+
+int resolve_opts(const ata_opts* opts, int& variant, int& max_depth) {
+    variant = ATA_VARIANT_STRASSEN;
+    max_depth = ATA_DEFAULT_MAX_DEPTH;
+    if (opts) {
+        variant = opts->variant;
+        max_depth = opts->max_depth;
+        if (opts->flags != 0) return -1;
+    }
+    if (variant != ATA_VARIANT_STRASSEN && variant != ATA_VARIANT_WINOGRAD) return -1;
+    if (max_depth < -1) return -1;
+    return 0;
+}
+
+int elem_bytes_in(int dtype) { return (dtype & 0xff) == ATA_F64 ? 8 : 4; }
+int elem_bytes_out(int dtype) {
+    if ((dtype & 0xff) == ATA_F64) return 8;
+    return (dtype & ATA_OUT_F64) ? 8 : 4;
+}
+bool dtype_valid(int dtype) {
+    const int base = dtype & 0xff, flags = dtype & ~0xff;
+    if (base < ATA_F64 || base > ATA_F32_FP8) return false;
+    if (flags & ~ATA_OUT_F64) return false;
+    if (base == ATA_F64 && flags) return false;
+    return true;
+}
+bool dtype_implemented(int dtype) { return dtype == ATA_F64; }
+
+int64_t default_cutoff(int64_t m, int64_t n, int dtype) {
+    (void)dtype;
+    // Leaves of a few hundred columns keep every workgroup tile busy while the
+    // top levels (where nearly all the work is) still split.
+    const int64_t mn = m < n ? m : n;
+    if (mn <= 1024) return 128;
+    return 256;
+}
+
+// Build (or fetch) the plan for the current device.
+int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, bool need_device,
+             std::shared_ptr<PlanDev>& out) {
+    int dev = -1;
+    if (need_device) {
+        HIP_TRY(hipGetDevice(&dev));
+    }
+    const PlanKey key{dev, m, n, cutoff, variant, max_depth};
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        out = it->second;
+        return ATA_OK;
+    }
+    auto pd = std::make_shared<PlanDev>();
+    PlanOptions po;
+    po.cutoff = cutoff;
+    po.variant = variant;
+    po.max_depth = max_depth;
+    try {
+        pd->plan = build_plan(m, n, po);
+    } catch (const std::length_error&) {
+        return ATA_EUNSUPPORTED;
+    } catch (const std::bad_alloc&) {
+        return ATA_ENOMEM;
+    } catch (const std::exception&) {
+        return ATA_EUNSUPPORTED;
+    }
+    if (need_device) {
+        const int rc = upload(*pd, dev);
+        if (rc != ATA_OK) return rc;
+    }
+    g_plans[key] = pd;
+    out = pd;
+    return ATA_OK;
+}
+
+int common_checks(const void* A, int64_t m, int64_t n, int64_t lda, const void* C, int dtype, int cutoff) {
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (!dtype_valid(dtype)) return -6;
+    if (cutoff < 0) return -7;
+    if (n > 0 && m > 0 && !A) return -1;
+    if (n > 0 && !C) return -5;
+    const uintptr_t ua = (uintptr_t)A, uc = (uintptr_t)C;
+    if (ua % elem_bytes_in(dtype)) return -1;
+    if (uc % elem_bytes_out(dtype)) return -5;
+    if (m > INT32_MAX || n > INT32_MAX) return ATA_EUNSUPPORTED;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ata_version(void) { return "0.1.0"; }
+
+int ata_last_hip_error(void) { return g_last_hip; }
+
+const char* ata_status_string(int status) {
+    if (status < 0) return "invalid argument";
+    switch (status) {
+    case ATA_OK: return "ok";
+    case ATA_ENOMEM: return "out of memory";
+    case ATA_EHIP: return "HIP runtime error";
+    case ATA_EUNSUPPORTED: return "unsupported device, type or option";
+    case ATA_EWORKSPACE: return "workspace too small";
+    case ATA_EREJECT: return "request exceeds the memory budget";
+    case ATA_EBUSY: return "queue full";
+    case ATA_ENOTFOUND: return "unknown ticket";
+    case ATA_EPENDING: return "request pending";
+    default: return "unknown status";
+    }
+}
+
+int ata_default_cutoff(int64_t m, int64_t n, int dtype) { return (int)default_cutoff(m, n, dtype); }
+
+int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* opts, ata_plan_stats* out) {
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (!dtype_valid(dtype)) return -3;
+    if (cutoff < 0) return -4;
+    int variant, max_depth;
+    if (resolve_opts(opts, variant, max_depth)) return -5;
+    if (!out) return -6;
+    const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
+    std::shared_ptr<PlanDev> pd;
+    const int rc = get_plan(m, n, c, variant, max_depth, false, pd);
+    if (rc != ATA_OK) return rc;
+    const Plan& P = pd->plan;
+    std::memset(out, 0, sizeof(*out));
+    out->mults = P.mults;
+    out->classical_mults = m * (n * (n + 1) / 2);
+    out->syrk_tasks = P.syrk_tasks;
+    out->gemm_tasks = P.gemm_tasks;
+    out->strassen_tasks = P.str_tasks;
+    out->combine_tasks = P.combine_tasks;
+    out->work_items = P.work_items;
+    out->phases = (int64_t)P.phases.size();
+    out->ata_depth = P.ata_depth;
+    out->max_hasa_depth = P.max_hasa_depth;
+    out->workspace_bytes = P.ws_elems * (int64_t)sizeof(double);  // combinations run in FP64
+    out->cutoff = c;
+    return ATA_OK;
+}
+
+int ata_workspace_bytes(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* opts, size_t* bytes) {
+    ata_plan_stats st;
+    const int rc = ata_plan_info(m, n, dtype, cutoff, opts, &st);
+    if (rc != ATA_OK) return rc;
+    if (!bytes) return -6;
+    *bytes = (size_t)st.workspace_bytes;
+    return ATA_OK;
+}
+
+int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int dtype, int cutoff,
+           void* stream, const ata_opts* opts, void* workspace, size_t ws_bytes) {
+    int rc = common_checks(A, m, n, lda, C_lower, dtype, cutoff);
+    if (rc) return rc;
+    int variant, max_depth;
+    if (resolve_opts(opts, variant, max_depth)) return -9;
+    if (!dtype_implemented(dtype)) return ATA_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!check_device(dev)) return ATA_EUNSUPPORTED;
+    }
+    if (n == 0) return ATA_OK;
+    const int64_t nout = n * (n + 1) / 2;
+    if (m == 0) {
+        HIP_TRY(launch_fill_zero(C_lower, nout, elem_bytes_out(dtype), s));
+        return ATA_OK;
+    }
+    const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
+    std::shared_ptr<PlanDev> pd;
+    rc = get_plan(m, n, c, variant, max_depth, true, pd);
+    if (rc != ATA_OK) return rc;
+    const Plan& P = pd->plan;
+    const size_t need = (size_t)P.ws_elems * sizeof(double);
+    double* W = nullptr;
+    bool owned = false;
+    if (need) {
+        if (workspace) {
+            if (ws_bytes < need) return ATA_EWORKSPACE;
+            if ((uintptr_t)workspace % 8) return -10;
+            W = (double*)workspace;
+        } else {
+            HIP_TRY(hipMallocAsync((void**)&W, need, s));
+            owned = true;
+        }
+    }
+    const double* Ad = (const double*)A;
+    double* Cd = (double*)C_lower;
+    const DevTask* tasks = (const DevTask*)(pd->blob + pd->off_tasks);
+    const DevTerm* terms = (const DevTerm*)(pd->blob + pd->off_terms);
+    const int32_t* segs = (const int32_t*)(pd->blob + pd->off_segs);
+    hipError_t err = hipSuccess;
+    for (const PhaseDev& ph : pd->phases) {
+        if (err == hipSuccess)
+            err = launch_str_f64(variant, Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_str),
+                                 ph.n_str, Cd, W, s);
+        if (err == hipSuccess)
+            err = launch_gemm_f64(Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_gemm),
+                                  ph.n_gemm, Cd, s);
+        if (err == hipSuccess)
+            err = launch_gemm_f64(Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_syrk),
+                                  ph.n_syrk, Cd, s);
+        if (err == hipSuccess)
+            err = launch_combine_f64((const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W, Cd, s);
+    }
+    if (owned) {
+        hipError_t e2 = hipFreeAsync(W, s);
+        if (err == hipSuccess) err = e2;
+    }
+    if (err != hipSuccess) return hip_fail(err);
+    return ATA_OK;
+}
+
+int ata(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int dtype, int cutoff, void* stream) {
+    return ata_ex(A, m, n, lda, C_lower, dtype, cutoff, stream, nullptr, nullptr, 0);
+}
+
+void ata_release_caches(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plans.clear();
+}
+
+}  // extern "C"

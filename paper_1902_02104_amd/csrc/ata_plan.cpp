@@ -1,0 +1,406 @@
+// Host planner: turns the ATA recursion (Section 3, Algorithm 1) into a
+// device task table.
+//
+// The recursion splits the rows of every sub-problem as well as its columns.
+// A row split only produces a sum (C11 = A11^t A11 + A21^t A21, the "second
+// product accumulated into the first"), so row chunks that share the same
+// column structure become one task whose K loop runs over their row segments
+// in order.  Every scalar product of the paper's recursion tree is formed; only
+// the order in which products of different row chunks are summed changes.
+// Chunks whose sub-trees differ (a row count straddling the cutoff) are kept
+// in separate groups that write the same output in successive phases.
+//
+// HASA (the rectangular Strassen routine for the off-diagonal block) splits
+// M, K and N into ceil/floor halves with implicit zero padding.  The top
+// (d - 1) of its d levels are expanded here into signed operand terms that
+// the kernels sum while staging tiles; the last level is done inside each
+// workgroup tile; products of expanded levels go to a workspace and a
+// combination kernel forms the result quadrants.
+#include "ata_plan.h"
+
+#include <algorithm>
+#include <map>
+#include <stdexcept>
+
+namespace atalib {
+
+// Strassen 1969 (variant 0): M1 = (L11 + L22)(R11 + R22), M2 = (L21 + L22) R11,
+// M3 = L11 (R12 - R22), M4 = L22 (R21 - R11), M5 = (L11 + L12) R22,
+// M6 = (L21 - L11)(R11 + R12), M7 = (L12 - L22)(R21 + R22);
+// D11 = M1 + M4 - M5 + M7, D12 = M3 + M5, D21 = M2 + M4, D22 = M1 - M2 + M3 + M6.
+// Winograd 1971 (variant 1): P1 = L11 R11, P2 = L12 R21, P3 = S4 R22,
+// P4 = L22 T4, P5 = S1 T1, P6 = S2 T2, P7 = S3 T3 with S1 = L21 + L22,
+// S2 = S1 - L11, S3 = L11 - L21, S4 = L12 - S2, T1 = R12 - R11, T2 = R22 - T1,
+// T3 = R22 - R12, T4 = T2 - R21; D11 = P1 + P2, D12 = P1 + P6 + P5 + P3,
+// D21 = P1 + P6 + P7 - P4, D22 = P1 + P6 + P7 + P5.
+// Index order: x_coef [a*2+b] for L_ab, y_coef [b*2+c] for R_bc, d_coef [a*2+c].
+const int x_coef[2][7][4] = {
+    {{1, 0, 0, 1}, {0, 0, 1, 1}, {1, 0, 0, 0}, {0, 0, 0, 1}, {1, 1, 0, 0}, {-1, 0, 1, 0}, {0, 1, 0, -1}},
+    {{1, 0, 0, 0}, {0, 1, 0, 0}, {1, 1, -1, -1}, {0, 0, 0, 1}, {0, 0, 1, 1}, {-1, 0, 1, 1}, {1, 0, -1, 0}},
+};
+const int y_coef[2][7][4] = {
+    {{1, 0, 0, 1}, {1, 0, 0, 0}, {0, 1, 0, -1}, {-1, 0, 1, 0}, {0, 0, 0, 1}, {1, 1, 0, 0}, {0, 0, 1, 1}},
+    {{1, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}, {1, -1, -1, 1}, {-1, 1, 0, 0}, {1, -1, 0, 1}, {0, -1, 0, 1}},
+};
+const int d_coef[2][7][4] = ATA_D_COEF;
+
+namespace {
+
+inline int64_t ceil2(int64_t x) { return (x + 1) / 2; }
+inline int64_t tri(int64_t x) { return x * (x + 1) / 2; }
+
+struct Chunk {
+    int64_t row, h;
+};
+
+// A term of an operand during symbolic expansion: a column range plus one row
+// range per chunk.
+struct XTerm {
+    int32_t sign;
+    int64_t col, cvend;
+    std::vector<int64_t> row, rvend;
+};
+
+struct Product {
+    std::vector<XTerm> x, y;
+};
+
+class Builder {
+public:
+    Builder(Plan& p) : P(p), o(p.opt) {}
+
+    int ata_node(const std::vector<Chunk>& chunks, int64_t c0, int64_t w, int phase, int level);
+
+private:
+    Plan& P;
+    const PlanOptions& o;
+
+    Phase& ph(int idx) {
+        while ((int)P.phases.size() <= idx) P.phases.emplace_back();
+        return P.phases[idx];
+    }
+    int hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M, int64_t yc, int64_t N,
+                   int phase);
+    int hasa_depth(int64_t M, int64_t K, int64_t N) const {
+        int d = 0;
+        while (std::min(M, std::min(K, N)) > o.cutoff && (o.max_depth < 0 || d < o.max_depth)) {
+            M = ceil2(M);
+            K = ceil2(K);
+            N = ceil2(N);
+            ++d;
+        }
+        return d;
+    }
+    void add_segments_merged(DevTask& t, const std::vector<Chunk>& chs);
+    int32_t push_terms(const std::vector<XTerm>& x, const std::vector<XTerm>& y);
+};
+
+static void check32(int64_t v) {
+    if (v < 0 || v > INT32_MAX) throw std::invalid_argument("dimension exceeds 32-bit range");
+}
+
+// Contiguous chunks form one segment: [row, row + klen) for both operands.
+void Builder::add_segments_merged(DevTask& t, const std::vector<Chunk>& chs) {
+    t.seg_off = (int32_t)P.segs.size();
+    t.nseg = 0;
+    size_t i = 0;
+    while (i < chs.size()) {
+        int64_t r = chs[i].row, e = chs[i].row + chs[i].h;
+        size_t j = i + 1;
+        while (j < chs.size() && chs[j].row == e) {
+            e += chs[j].h;
+            ++j;
+        }
+        check32(e);
+        P.segs.push_back((int32_t)(e - r));
+        P.segs.push_back((int32_t)r);
+        P.segs.push_back((int32_t)e);
+        P.segs.push_back((int32_t)r);
+        P.segs.push_back((int32_t)e);
+        ++t.nseg;
+        i = j;
+    }
+}
+
+int32_t Builder::push_terms(const std::vector<XTerm>& x, const std::vector<XTerm>& y) {
+    int32_t off = (int32_t)P.terms.size();
+    for (const auto* list : {&x, &y})
+        for (const XTerm& t : *list) {
+            check32(t.cvend);
+            P.terms.push_back(DevTerm{(int32_t)t.col, (int32_t)t.cvend, t.sign, 0});
+        }
+    return off;
+}
+
+int Builder::ata_node(const std::vector<Chunk>& chunks, int64_t c0, int64_t w, int phase,
+                      int level) {
+    std::vector<Chunk> leaf, rec;
+    for (const Chunk& ch : chunks) {
+        if (ch.h <= o.cutoff || w <= o.cutoff)
+            leaf.push_back(ch);
+        else
+            rec.push_back(ch);
+    }
+    int next = phase;
+    if (!rec.empty()) {
+        if (level + 1 > P.ata_depth) P.ata_depth = level + 1;
+        std::vector<Chunk> sub;
+        sub.reserve(rec.size() * 2);
+        for (const Chunk& ch : rec) {
+            const int64_t h1 = ceil2(ch.h);
+            sub.push_back(Chunk{ch.row, h1});          // rows of A11 / A12
+            sub.push_back(Chunk{ch.row + h1, ch.h / 2});  // rows of A21 / A22
+        }
+        const int64_t n1 = ceil2(w), n2 = w / 2;
+        int p1 = ata_node(sub, c0, n1, phase, level + 1);       // C11 = S1 + S2
+        int p2 = ata_node(sub, c0 + n1, n2, phase, level + 1);  // C22 = S3 + S4
+        int p3 = hasa_block(sub, c0 + n1, n2, c0, n1, phase);   // C21 = S5 + S6
+        next = std::max(p1, std::max(p2, p3));
+    }
+    if (!leaf.empty()) {
+        const int lp = rec.empty() ? phase : next;
+        DevTask t{};
+        t.kind = TK_SYRK;
+        t.M = t.N = (int32_t)w;
+        t.nx = t.ny = 1;
+        t.term_off = push_terms({XTerm{1, c0, c0 + w, {}, {}}}, {XTerm{1, c0, c0 + w, {}, {}}});
+        add_segments_merged(t, leaf);
+        t.dst = 0;
+        t.beta = rec.empty() ? 0 : 1;
+        t.dM = t.dN = (int32_t)w;
+        t.r0 = t.q0 = (int32_t)c0;
+        const int64_t T = (w + kGemmTile - 1) / kGemmTile;
+        t.tiles_m = t.tiles_n = (int32_t)T;
+        int64_t ktot = 0;
+        for (const Chunk& ch : leaf) ktot += ch.h;
+        P.mults += tri(w) * ktot;
+        const int32_t id = (int32_t)P.tasks.size();
+        P.tasks.push_back(t);
+        for (int64_t ti = 0; ti < T; ++ti)
+            for (int64_t tj = 0; tj <= ti; ++tj) ph(lp).syrk_items.push_back(WorkItem{id, (int32_t)ti, (int32_t)tj, 0});
+        ++P.syrk_tasks;
+        next = lp + 1;
+    }
+    return next;
+}
+
+int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M, int64_t yc,
+                        int64_t N, int phase) {
+    // group chunks by the HASA depth their shape gives (heaviest first)
+    std::map<int, std::vector<Chunk>, std::greater<int>> groups;
+    for (const Chunk& ch : chunks) groups[hasa_depth(M, ch.h, N)].push_back(ch);
+    int gi = 0;
+    for (auto& kv : groups) {
+        const int d = kv.first;
+        const std::vector<Chunk>& chs = kv.second;
+        const int gphase = phase + gi;
+        const int beta = gi > 0 ? 1 : 0;
+        ++gi;
+        if (d > P.max_hasa_depth) P.max_hasa_depth = d;
+        int64_t ktot = 0;
+        for (const Chunk& ch : chs) ktot += ch.h;
+        if (d == 0) {
+            DevTask t{};
+            t.kind = TK_GEMM;
+            t.M = (int32_t)M;
+            t.N = (int32_t)N;
+            t.nx = t.ny = 1;
+            t.term_off = push_terms({XTerm{1, xc, xc + M, {}, {}}}, {XTerm{1, yc, yc + N, {}, {}}});
+            add_segments_merged(t, chs);
+            t.dst = 0;
+            t.beta = beta;
+            t.dM = (int32_t)M;
+            t.dN = (int32_t)N;
+            t.r0 = (int32_t)xc;
+            t.q0 = (int32_t)yc;
+            t.tiles_m = (int32_t)((M + kGemmTile - 1) / kGemmTile);
+            t.tiles_n = (int32_t)((N + kGemmTile - 1) / kGemmTile);
+            P.mults += M * N * ktot;
+            const int32_t id = (int32_t)P.tasks.size();
+            P.tasks.push_back(t);
+            for (int32_t a = 0; a < t.tiles_m; ++a)
+                for (int32_t b = 0; b < t.tiles_n; ++b) ph(gphase).gemm_items.push_back(WorkItem{id, a, b, 0});
+            ++P.gemm_tasks;
+            continue;
+        }
+        // symbolic expansion of the top d-1 levels
+        const size_t nch = chs.size();
+        XTerm x0{1, xc, xc + M, {}, {}}, y0{1, yc, yc + N, {}, {}};
+        std::vector<int64_t> K(nch);
+        for (size_t c = 0; c < nch; ++c) {
+            x0.row.push_back(chs[c].row);
+            x0.rvend.push_back(chs[c].row + chs[c].h);
+            K[c] = chs[c].h;
+        }
+        y0.row = x0.row;
+        y0.rvend = x0.rvend;
+        std::vector<Product> prods{Product{{x0}, {y0}}};
+        int64_t Mp = M, Np = N;
+        for (int lev = 1; lev < d; ++lev) {
+            const int64_t MH = ceil2(Mp), NH = ceil2(Np);
+            std::vector<int64_t> KH(nch);
+            for (size_t c = 0; c < nch; ++c) KH[c] = ceil2(K[c]);
+            std::vector<Product> next;
+            next.reserve(prods.size() * 7);
+            for (const Product& pr : prods) {
+                for (int p = 0; p < 7; ++p) {
+                    Product q;
+                    for (int ab = 0; ab < 4; ++ab) {
+                        const int cf = x_coef[o.variant][p][ab];
+                        if (!cf) continue;
+                        const int a = ab >> 1, b = ab & 1;
+                        for (const XTerm& t : pr.x) {
+                            XTerm u;
+                            u.sign = t.sign * cf;
+                            u.col = t.col + a * MH;
+                            u.cvend = a == 0 ? std::min(t.cvend, t.col + MH) : t.cvend;
+                            if (u.cvend <= u.col) continue;  // all-zero quadrant
+                            bool any = false;
+                            for (size_t c = 0; c < nch; ++c) {
+                                const int64_t r = t.row[c] + b * KH[c];
+                                const int64_t e = b == 0 ? std::min(t.rvend[c], t.row[c] + KH[c]) : t.rvend[c];
+                                u.row.push_back(r);
+                                u.rvend.push_back(std::max(r, e));
+                                any |= e > r;
+                            }
+                            if (any) q.x.push_back(u);
+                        }
+                    }
+                    for (int bc = 0; bc < 4; ++bc) {
+                        const int cf = y_coef[o.variant][p][bc];
+                        if (!cf) continue;
+                        const int b = bc >> 1, cc = bc & 1;
+                        for (const XTerm& t : pr.y) {
+                            XTerm u;
+                            u.sign = t.sign * cf;
+                            u.col = t.col + cc * NH;
+                            u.cvend = cc == 0 ? std::min(t.cvend, t.col + NH) : t.cvend;
+                            if (u.cvend <= u.col) continue;
+                            bool any = false;
+                            for (size_t c = 0; c < nch; ++c) {
+                                const int64_t r = t.row[c] + b * KH[c];
+                                const int64_t e = b == 0 ? std::min(t.rvend[c], t.row[c] + KH[c]) : t.rvend[c];
+                                u.row.push_back(r);
+                                u.rvend.push_back(std::max(r, e));
+                                any |= e > r;
+                            }
+                            if (any) q.y.push_back(u);
+                        }
+                    }
+                    next.push_back(std::move(q));
+                }
+            }
+            prods.swap(next);
+            Mp = MH;
+            Np = NH;
+            K = KH;
+        }
+        const bool direct = d == 1;
+        const int64_t ws_base = P.ws_elems;
+        if (!direct) P.ws_elems += (int64_t)prods.size() * Mp * Np;
+        const int64_t MHin = ceil2(Mp), NHin = ceil2(Np);
+        int64_t khalf = 0;
+        for (size_t c = 0; c < nch; ++c) khalf += ceil2(K[c]);
+        for (size_t s = 0; s < prods.size(); ++s) {
+            const Product& pr = prods[s];
+            if ((int)pr.x.size() > kMaxTerms || (int)pr.y.size() > kMaxTerms)
+                throw std::length_error("Strassen depth needs more operand terms than supported");
+            DevTask t{};
+            t.kind = TK_STR;
+            t.variant = o.variant;
+            t.M = (int32_t)Mp;
+            t.N = (int32_t)Np;
+            t.nx = (int32_t)pr.x.size();
+            t.ny = (int32_t)pr.y.size();
+            t.term_off = push_terms(pr.x, pr.y);
+            t.seg_off = (int32_t)P.segs.size();
+            t.nseg = (int32_t)nch;
+            for (size_t c = 0; c < nch; ++c) {
+                check32(K[c]);
+                P.segs.push_back((int32_t)K[c]);
+                for (const auto* list : {&pr.x, &pr.y})
+                    for (const XTerm& u : *list) {
+                        check32(u.rvend[c]);
+                        P.segs.push_back((int32_t)u.row[c]);
+                        P.segs.push_back((int32_t)u.rvend[c]);
+                    }
+            }
+            if (direct) {
+                t.dst = 0;
+                t.beta = beta;
+                t.dM = (int32_t)M;
+                t.dN = (int32_t)N;
+                t.r0 = (int32_t)xc;
+                t.q0 = (int32_t)yc;
+            } else {
+                t.dst = 1;
+                t.beta = 0;
+                t.dM = (int32_t)Mp;
+                t.dN = (int32_t)Np;
+                t.ws_off = ws_base + (int64_t)s * Mp * Np;
+            }
+            t.tiles_m = (int32_t)((MHin + kStrTile - 1) / kStrTile);
+            t.tiles_n = (int32_t)((NHin + kStrTile - 1) / kStrTile);
+            P.mults += 7 * MHin * NHin * khalf;
+            const int32_t id = (int32_t)P.tasks.size();
+            P.tasks.push_back(t);
+            for (int32_t a = 0; a < t.tiles_m; ++a)
+                for (int32_t b = 0; b < t.tiles_n; ++b) ph(gphase).str_items.push_back(WorkItem{id, a, b, 0});
+            ++P.str_tasks;
+        }
+        if (!direct) {
+            DevCombine cb{};
+            cb.M = (int32_t)M;
+            cb.N = (int32_t)N;
+            cb.levels = d - 1;
+            cb.variant = o.variant;
+            cb.r0 = (int32_t)xc;
+            cb.q0 = (int32_t)yc;
+            cb.beta = beta;
+            cb.Mp = (int32_t)Mp;
+            cb.Np = (int32_t)Np;
+            cb.ws_off = ws_base;
+            Phase& pz = ph(gphase);
+            cb.elem_off = pz.combine_elems;
+            pz.combine_elems += M * N;
+            pz.combines.push_back(cb);
+            ++P.combine_tasks;
+        }
+    }
+    return phase + gi;
+}
+
+}  // namespace
+
+Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
+    if (m < 0 || n < 0) throw std::invalid_argument("negative dimension");
+    if (opt.cutoff < 1) throw std::invalid_argument("cutoff must be positive");
+    if (opt.variant != 0 && opt.variant != 1) throw std::invalid_argument("bad variant");
+    check32(m);
+    check32(n);
+    Plan P;
+    P.m = m;
+    P.n = n;
+    P.opt = opt;
+    if (m > 0 && n > 0) {
+        Builder b(P);
+        b.ata_node({Chunk{0, m}}, 0, n, 0, 0);
+    }
+    // longest-processing-time order inside every launch: heavier tiles first
+    for (Phase& ph : P.phases) {
+        auto cost = [&](const WorkItem& w) {
+            const DevTask& t = P.tasks[w.task];
+            int64_t k = 0;
+            for (int s = 0; s < t.nseg; ++s) k += P.segs[t.seg_off + s * (1 + 2 * (t.nx + t.ny))];
+            if (t.kind == TK_STR) return (double)k * (1.0 + 0.1 * (t.nx + t.ny));
+            return (double)k;
+        };
+        for (auto* items : {&ph.str_items, &ph.gemm_items, &ph.syrk_items})
+            std::stable_sort(items->begin(), items->end(),
+                             [&](const WorkItem& a, const WorkItem& b) { return cost(a) > cost(b); });
+        P.work_items += (int64_t)(ph.str_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
+    }
+    return P;
+}
+
+}  // namespace atalib

@@ -1,0 +1,122 @@
+// Host planner of the ATA recursion (Section 3, Algorithm 1) and the device
+// task table it produces.  Shared by the host library code and the kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace atalib {
+
+// Kinds of device tasks.
+enum TaskKind : int32_t {
+    TK_SYRK = 0,  // diagonal base-case block: lower triangle of X^t X
+    TK_GEMM = 1,  // classical off-diagonal product X^t Y
+    TK_STR = 2,   // one Strassen level done inside each workgroup tile
+};
+
+// One signed operand term: columns [col, cvend) of A are valid, the rest of
+// the padded range reads as zero.  Rows are per K segment (see DevTask).
+struct DevTerm {
+    int32_t col;
+    int32_t cvend;
+    int32_t sign;
+    int32_t pad;
+};
+
+// A product D (M x N, padded) = Xop^t Yop, where Xop = sum of signed X terms
+// and Yop = sum of signed Y terms, both K x (M or N) slices of A.  K is a
+// list of segments (row chunks of the recursion); segment s has padded length
+// klen and, per term, a first row and a valid-row end:
+//   seg[seg_off + s*(1 + 2*(nx+ny))] = klen, then (row, rvend) for every X
+//   term, then for every Y term.
+// For TK_STR the product is split once more inside the tile: M, N and each
+// klen into ceil halves, seven products, one workgroup per quadrant tile.
+struct DevTask {
+    int32_t kind;
+    int32_t variant;   // Strassen or Winograd for TK_STR
+    int32_t M, N;      // padded product dims (TK_SYRK: M == N == width)
+    int32_t nx, ny;    // number of X and Y terms
+    int32_t term_off;  // first X term in the term table; Y terms follow
+    int32_t nseg;
+    int32_t seg_off;
+    int32_t dst;       // 0: packed C at (r0, q0); 1: workspace at ws_off, ld N
+    int32_t beta;      // 1: accumulate into packed C, 0: overwrite
+    int32_t dM, dN;    // valid destination extent (crop)
+    int32_t r0, q0;    // packed-C origin: rows of D -> C rows r0.., cols q0..
+    int32_t tiles_m, tiles_n;
+    int32_t pad;
+    int64_t ws_off;    // element offset into the workspace
+};
+
+// Combination of workspace products into an off-diagonal block of C.
+struct DevCombine {
+    int32_t M, N;       // true block extent
+    int32_t levels;     // Strassen levels that were expanded into workspace slots
+    int32_t variant;
+    int32_t r0, q0;
+    int32_t beta;
+    int32_t Mp, Np;     // padded dims of one workspace slot
+    int32_t pad;
+    int64_t ws_off;
+    int64_t elem_off;   // first output element index of this block in the launch
+};
+
+struct WorkItem {
+    int32_t task, ti, tj, pad;
+};
+
+struct PlanOptions {
+    int64_t cutoff = 32;
+    int variant = 0;    // 0 Strassen, 1 Winograd
+    int max_depth = 2;  // < 0: unlimited
+};
+
+// Launch group: everything that may run after the previous group finished.
+struct Phase {
+    std::vector<WorkItem> str_items, gemm_items, syrk_items;
+    std::vector<DevCombine> combines;
+    int64_t combine_elems = 0;
+};
+
+struct Plan {
+    int64_t m = 0, n = 0;
+    PlanOptions opt;
+    std::vector<DevTask> tasks;
+    std::vector<DevTerm> terms;
+    std::vector<int32_t> segs;
+    std::vector<Phase> phases;
+    int64_t ws_elems = 0;
+    // statistics
+    int64_t mults = 0;
+    int64_t syrk_tasks = 0, gemm_tasks = 0, str_tasks = 0, combine_tasks = 0;
+    int64_t work_items = 0;
+    int64_t ata_depth = 0, max_hasa_depth = 0;
+};
+
+// Tile sizes the kernels use (output tile per workgroup).
+constexpr int kGemmTile = 128;  // TK_GEMM / TK_SYRK
+constexpr int kStrTile = 64;    // TK_STR quadrant tile (4 quadrants per workgroup)
+constexpr int kMaxTerms = 8;    // max terms per operand (2^(levels staged))
+
+// Build the plan.  Throws std::invalid_argument for impossible inputs.
+Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt);
+
+// Result-quadrant coefficients of the seven products, [variant][product][a*2+c]
+// (Strassen 1969 and Winograd 1971; see ata_plan.cpp).  Shared by the planner
+// and the combination kernel.
+#define ATA_D_COEF                                                                                    \
+    {                                                                                                 \
+        {{1, 0, 0, 1}, {0, 0, 1, -1}, {0, 1, 0, 1}, {1, 0, 1, 0}, {-1, 1, 0, 0}, {0, 0, 0, 1}, {1, 0, 0, 0}}, \
+        {{1, 1, 1, 1}, {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, -1, 0}, {0, 1, 0, 1}, {0, 1, 1, 1}, {0, 0, 1, 1}}  \
+    }
+
+// Strassen / Winograd quadrant coefficients.  For product p (0..6):
+//   x_coef[v][p][a*2+b] : coefficient of L_ab (M-half a, K-half b) in the left operand
+//   y_coef[v][p][b*2+c] : coefficient of R_bc (K-half b, N-half c) in the right operand
+//   d_coef[v][p][a*2+c] : coefficient of the product in result quadrant D_ac
+extern const int x_coef[2][7][4];
+extern const int y_coef[2][7][4];
+extern const int d_coef[2][7][4];
+
+}  // namespace atalib

@@ -1,0 +1,128 @@
+"""Host-side checks of libata.so that need no GPU: exported symbols, the
+planner's structure against the oracle's recursion, argument validation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1902_02104_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(P.lib_path()):
+        from paper_1902_02104_amd.build import build
+        build()
+    return P.load()
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "ata.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ata\w*)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert "ata" in names and "ata_ex" in names and len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings(lib):
+    assert P.load().ata_version().decode().count(".") == 2
+    assert P.status_string(0) == "ok"
+    assert "invalid" in P.status_string(-3)
+    assert P.status_string(4) == "workspace too small"
+
+
+CASES = [
+    (256, 192, 32, -1), (256, 192, 32, 0), (256, 192, 32, 1), (256, 192, 32, 2),
+    (5000, 5000, 128, 2), (10000, 10000, 256, 2), (10000, 10000, 512, 3), (262144, 2048, 256, 2),
+    (513, 600, 256, 2), (517, 301, 40, 3), (65, 129, 16, -1), (7, 5, 1, -1), (12, 12, 2, -1),
+    (1, 1, 1, -1), (1, 50, 4, -1), (50, 1, 4, -1), (1025, 513, 256, 2), (8192, 8192, 256, 2),
+    (1000, 4096, 256, 2), (65536, 64, 256, 2),
+]
+
+
+@pytest.mark.parametrize("m,n,c,d", CASES)
+def test_plan_multiplications_match_oracle_recursion(lib, orc, m, n, c, d):
+    """The device plan forms exactly the scalar products of Algorithm 1 with
+    HASA (same count as the oracle's literal recursion with the same cutoff
+    and Strassen depth cap)."""
+    st = P.plan_info(m, n, c, max_depth=d)
+    assert st["mults"] == orc.ata_mult_count(m, n, c, d)
+    assert st["classical_mults"] == m * n * (n + 1) // 2
+
+
+def test_plan_depth_zero_is_classical_count(lib, orc):
+    for m, n, c in [(300, 200, 32), (1000, 77, 8)]:
+        st = P.plan_info(m, n, c, max_depth=0)
+        assert st["mults"] == st["classical_mults"]
+        assert st["strassen_tasks"] == 0 and st["combine_tasks"] == 0
+
+
+def test_plan_large_cutoff_is_one_syrk(lib):
+    st = P.plan_info(300, 200, 10 ** 6)
+    assert st["syrk_tasks"] == 1 and st["gemm_tasks"] == 0 and st["strassen_tasks"] == 0
+    assert st["phases"] == 1 and st["ata_depth"] == 0
+
+
+def test_plan_non_uniform_tree_uses_ordered_phases(lib, orc):
+    # 513 rows straddle the cutoff 256 (257 recurses, 256 stops)
+    st = P.plan_info(513, 600, 256, max_depth=2)
+    assert st["phases"] == 2
+    assert st["mults"] == orc.ata_mult_count(513, 600, 256, 2)
+
+
+def test_winograd_depth_limits(lib, orc):
+    st = P.plan_info(2048, 2048, 64, variant="winograd", max_depth=2)
+    assert st["mults"] == orc.ata_mult_count(2048, 2048, 64, 2)
+    with pytest.raises(P.AtaError):
+        P.plan_info(4096, 4096, 64, variant="winograd", max_depth=3)  # 16 operand terms
+
+
+def test_workspace_size(lib):
+    assert P.workspace_bytes(256, 192, 32, max_depth=1) == 0
+    ws = P.workspace_bytes(10000, 10000, 256, max_depth=2)
+    # 7 products per off-diagonal block of levels 0..3, each a quarter block
+    expect = 8 * 7 * (2500 ** 2 + 2 * 1250 ** 2 + 4 * 625 ** 2 + 8 * 313 ** 2)
+    assert ws == expect
+
+
+def test_default_cutoff_is_in_tuned_set(lib):
+    for m, n in [(256, 192), (5000, 5000), (10000, 10000), (262144, 2048)]:
+        assert P.default_cutoff(m, n) in (128, 256, 512)
+
+
+def test_argument_validation_without_gpu(lib):
+    """Bad arguments are rejected before any device call (LAPACK-style codes)."""
+    L = P.load()
+    vp = ctypes.c_void_p
+    buf = (ctypes.c_double * 64)()
+    a = ctypes.cast(buf, vp)
+    assert L.ata(a, -1, 4, 4, a, P.F64, 0, None) == -2
+    assert L.ata(a, 4, -1, 4, a, P.F64, 0, None) == -3
+    assert L.ata(a, 4, 4, 3, a, P.F64, 0, None) == -4
+    assert L.ata(a, 4, 4, 4, None, P.F64, 0, None) == -5
+    assert L.ata(None, 4, 4, 4, a, P.F64, 0, None) == -1
+    assert L.ata(a, 4, 4, 4, a, 7, 0, None) == -6
+    assert L.ata(a, 4, 4, 4, a, P.F64 | P.OUT_F64, 0, None) == -6
+    assert L.ata(a, 4, 4, 4, a, P.F64, -5, None) == -7
+    mis = ctypes.c_void_p(ctypes.addressof(buf) + 4)
+    assert L.ata(mis, 4, 4, 4, a, P.F64, 0, None) == -1
+    o = P.Opts()
+    o.variant, o.max_depth, o.flags = 5, 2, 0
+    assert L.ata_ex(a, 4, 4, 4, a, P.F64, 0, None, ctypes.byref(o), None, 0) == -9
+    o.variant, o.max_depth = 0, -2
+    assert L.ata_ex(a, 4, 4, 4, a, P.F64, 0, None, ctypes.byref(o), None, 0) == -9
+
+
+def test_binding_refuses_host_tensors(lib):
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        P.gram(torch.zeros(4, 4, dtype=torch.float64))
