@@ -125,6 +125,10 @@ typedef struct ata_plan_stats {
     int64_t max_hasa_depth;  /* deepest Strassen level count */
     int64_t workspace_bytes;
     int64_t cutoff;          /* cutoff used (after resolving 0) */
+    int64_t strassen_mults;  /* multiplications done by in-tile Strassen tiles */
+    int64_t gemm_mults;      /* ... by classical off-diagonal tiles */
+    int64_t syrk_mults;      /* ... by diagonal base-case tiles */
+    int64_t combine_elems;   /* output elements formed by workspace combinations */
 } ata_plan_stats;
 
 int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts *opts,
@@ -144,6 +148,23 @@ const char *ata_version(void);
 
 /* Release cached plans and device task tables (all devices). */
 void ata_release_caches(void);
+
+/*
+ * Kernel timing for measurement tools.  While enabled, every kernel launch the
+ * library makes is bracketed by HIP events recorded on the launch's stream.
+ * ata_profile_collect waits for the recorded events, writes the summed
+ * duration in milliseconds and the launch count per kernel kind
+ * (ATA_KERNEL_*), clears the record and returns the number of kinds written.
+ * Enabling adds two event records per launch; it never synchronises.
+ */
+#define ATA_KERNEL_STRASSEN 0 /* in-tile Strassen tiles */
+#define ATA_KERNEL_GEMM 1     /* classical off-diagonal tiles */
+#define ATA_KERNEL_SYRK 2     /* diagonal base-case tiles */
+#define ATA_KERNEL_COMBINE 3  /* workspace combinations */
+#define ATA_KERNEL_OTHER 4    /* fills and conversions */
+#define ATA_KERNEL_KINDS 5
+int ata_profile_enable(int on);
+int ata_profile_collect(double *ms, int64_t *launches, int kinds);
 
 #ifdef __cplusplus
 }

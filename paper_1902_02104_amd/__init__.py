@@ -51,7 +51,8 @@ class Opts(ctypes.Structure):
 class PlanStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "mults", "classical_mults", "syrk_tasks", "gemm_tasks", "strassen_tasks", "combine_tasks",
-        "work_items", "phases", "ata_depth", "max_hasa_depth", "workspace_bytes", "cutoff")]
+        "work_items", "phases", "ata_depth", "max_hasa_depth", "workspace_bytes", "cutoff",
+        "strassen_mults", "gemm_mults", "syrk_mults", "combine_elems")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -86,6 +87,10 @@ def load():
     lib.ata_version.restype = ctypes.c_char_p
     lib.ata_release_caches.argtypes = []
     lib.ata_release_caches.restype = None
+    lib.ata_profile_enable.argtypes = [ci]
+    lib.ata_profile_enable.restype = ci
+    lib.ata_profile_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ci]
+    lib.ata_profile_collect.restype = ci
     _lib = lib
     return lib
 
@@ -123,6 +128,25 @@ def workspace_bytes(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="
     if rc:
         raise AtaError(rc, "ata_workspace_bytes")
     return int(out.value)
+
+
+KERNEL_KINDS = ("strassen", "gemm", "syrk", "combine", "other")
+
+
+def profile_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch with HIP events on its stream."""
+    load().ata_profile_enable(1 if on else 0)
+
+
+def profile_collect() -> dict:
+    """Wait for recorded launches; return {kind: (total_ms, launches)} and clear."""
+    k = len(KERNEL_KINDS)
+    ms = (ctypes.c_double * k)()
+    cnt = (ctypes.c_int64 * k)()
+    rc = load().ata_profile_collect(ms, cnt, k)
+    if rc < 0 or rc > k:
+        raise AtaError(rc, "ata_profile_collect")
+    return {name: (ms[i], int(cnt[i])) for i, name in enumerate(KERNEL_KINDS)}
 
 
 def default_cutoff(m: int, n: int, dtype: int = F64) -> int:

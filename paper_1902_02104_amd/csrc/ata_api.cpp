@@ -19,7 +19,7 @@ namespace atalib {
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const DevTask* tasks, const DevTerm* terms,
                            const int32_t* segs, const WorkItem* items, int nitems, double* C,
                            hipStream_t s);
-hipError_t launch_str_f64(int variant, const double* A, int64_t lda, const DevTask* tasks,
+hipError_t launch_str_f64(int variant, int tmax, const double* A, int64_t lda, const DevTask* tasks,
                           const DevTerm* terms, const int32_t* segs, const WorkItem* items, int nitems,
                           double* C, double* W, hipStream_t s);
 hipError_t launch_combine_f64(const DevCombine* cbs, int ncb, int64_t total, const double* W, double* C,
@@ -46,7 +46,7 @@ int hip_fail(hipError_t e) {
 
 // Device copy of one plan's tables.
 struct PhaseDev {
-    int n_str = 0, n_gemm = 0, n_syrk = 0, n_cb = 0;
+    int n_str = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, str_tmax = 0;
     int64_t cb_elems = 0;
     size_t off_str = 0, off_gemm = 0, off_syrk = 0, off_cb = 0;
 };
@@ -101,6 +101,7 @@ int upload(PlanDev& pd, int dev) {
         const Phase& ph = P.phases[i];
         PhaseDev& d = pd.phases[i];
         d.n_str = (int)ph.str_items.size();
+        d.str_tmax = ph.str_tmax;
         d.n_gemm = (int)ph.gemm_items.size();
         d.n_syrk = (int)ph.syrk_items.size();
         d.n_cb = (int)ph.combines.size();
@@ -205,6 +206,39 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, b
     return ATA_OK;
 }
 
+// ---- kernel timing (measurement tools only) ----
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on = false;
+    ProfScope(int k, hipStream_t st) : kind(k), s(st) {
+        {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            on = g_prof_on;
+        }
+        if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, s);
+        else
+            on = false;
+    }
+    ~ProfScope() {
+        if (!on) return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof.push_back(ProfRec{kind, a, b});
+    }
+};
+
 int common_checks(const void* A, int64_t m, int64_t n, int64_t lda, const void* C, int dtype, int cutoff) {
     if (m < 0) return -2;
     if (n < 0) return -3;
@@ -272,6 +306,10 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     out->max_hasa_depth = P.max_hasa_depth;
     out->workspace_bytes = P.ws_elems * (int64_t)sizeof(double);  // combinations run in FP64
     out->cutoff = c;
+    out->strassen_mults = P.str_mults;
+    out->gemm_mults = P.gemm_mults;
+    out->syrk_mults = P.syrk_mults;
+    out->combine_elems = P.combine_elems;
     return ATA_OK;
 }
 
@@ -301,6 +339,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     if (n == 0) return ATA_OK;
     const int64_t nout = n * (n + 1) / 2;
     if (m == 0) {
+        ProfScope ps(ATA_KERNEL_OTHER, s);
         HIP_TRY(launch_fill_zero(C_lower, nout, elem_bytes_out(dtype), s));
         return ATA_OK;
     }
@@ -329,17 +368,25 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     const int32_t* segs = (const int32_t*)(pd->blob + pd->off_segs);
     hipError_t err = hipSuccess;
     for (const PhaseDev& ph : pd->phases) {
-        if (err == hipSuccess)
-            err = launch_str_f64(variant, Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_str),
+        if (err == hipSuccess && ph.n_str) {
+            ProfScope ps(ATA_KERNEL_STRASSEN, s);
+            err = launch_str_f64(variant, ph.str_tmax, Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_str),
                                  ph.n_str, Cd, W, s);
-        if (err == hipSuccess)
+        }
+        if (err == hipSuccess && ph.n_gemm) {
+            ProfScope ps(ATA_KERNEL_GEMM, s);
             err = launch_gemm_f64(Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_gemm),
                                   ph.n_gemm, Cd, s);
-        if (err == hipSuccess)
+        }
+        if (err == hipSuccess && ph.n_syrk) {
+            ProfScope ps(ATA_KERNEL_SYRK, s);
             err = launch_gemm_f64(Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_syrk),
                                   ph.n_syrk, Cd, s);
-        if (err == hipSuccess)
+        }
+        if (err == hipSuccess && ph.n_cb) {
+            ProfScope ps(ATA_KERNEL_COMBINE, s);
             err = launch_combine_f64((const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W, Cd, s);
+        }
     }
     if (owned) {
         hipError_t e2 = hipFreeAsync(W, s);
@@ -351,6 +398,40 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
 
 int ata(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int dtype, int cutoff, void* stream) {
     return ata_ex(A, m, n, lda, C_lower, dtype, cutoff, stream, nullptr, nullptr, 0);
+}
+
+int ata_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return ATA_OK;
+}
+
+int ata_profile_collect(double* ms, int64_t* launches, int kinds) {
+    if (kinds < 0) return -3;
+    if (kinds > 0 && (!ms || !launches)) return -1;
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        recs.swap(g_prof);
+    }
+    for (int k = 0; k < kinds; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    int rc = ATA_OK;
+    for (ProfRec& r : recs) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess && rc == ATA_OK) rc = hip_fail(e);
+        if (r.kind < kinds) {
+            ms[r.kind] += t;
+            launches[r.kind] += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    return rc == ATA_OK ? (kinds < ATA_KERNEL_KINDS ? kinds : ATA_KERNEL_KINDS) : rc;
 }
 
 void ata_release_caches(void) {

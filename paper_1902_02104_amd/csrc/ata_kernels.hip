@@ -217,7 +217,7 @@ __device__ __forceinline__ void combine_products(const double (&m)[7], double (&
     }
 }
 
-template <int VAR>
+template <int VAR, int TMAX>
 __global__ void __launch_bounds__(256) k_str_f64(const double* __restrict__ A, int64_t lda,
                                                  const DevTask* __restrict__ tasks,
                                                  const DevTerm* __restrict__ terms,
@@ -238,6 +238,40 @@ __global__ void __launch_bounds__(256) k_str_f64(const double* __restrict__ A, i
     // staging map: thread -> k row lk, 2 consecutive columns at lc
     const int lk = tid >> 5, lc = (tid & 31) * 2;
 
+    // Per-term column data, fixed for the whole K loop: first column of each
+    // M (or N) half for this thread, and which of the 2 columns are valid.
+    int xcol[TMAX][2], ycol[TMAX][2];
+    unsigned xmask[TMAX], ymask[TMAX];  // bit a*2+e: column valid
+    double xsgn[TMAX], ysgn[TMAX];
+#pragma unroll
+    for (int u = 0; u < TMAX; ++u) {
+        xmask[u] = ymask[u] = 0u;
+        xsgn[u] = ysgn[u] = 0.0;
+        xcol[u][0] = xcol[u][1] = ycol[u][0] = ycol[u][1] = 0;
+        if (u < t.nx) {
+            const DevTerm tm = terms[t.term_off + u];
+            xsgn[u] = (double)tm.sign;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                xcol[u][a] = tm.col + a * MH + i0 + lc;
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+                    if (i0 + lc + e < MH && xcol[u][a] + e < tm.cvend) xmask[u] |= 1u << (a * 2 + e);
+            }
+        }
+        if (u < t.ny) {
+            const DevTerm tm = terms[t.term_off + t.nx + u];
+            ysgn[u] = (double)tm.sign;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                ycol[u][c] = tm.col + c * NH + j0 + lc;
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+                    if (j0 + lc + e < NH && ycol[u][c] + e < tm.cvend) ymask[u] |= 1u << (c * 2 + e);
+            }
+        }
+    }
+
     double acc[7][8][2];
 #pragma unroll
     for (int p = 0; p < 7; ++p)
@@ -252,59 +286,71 @@ __global__ void __launch_bounds__(256) k_str_f64(const double* __restrict__ A, i
         ntiles += (kh + SK - 1) / SK;
     }
 
-    // staged values: [quad][e] for X (quad = a*2+b) and Y (quad = b*2+c)
-    double xr[4][2], yr[4][2];
+    // raw term values of the next k tile: [term][quad][e]
+    double xraw[TMAX][4][2], yraw[TMAX][4][2];
     int seg = 0, k0 = 0;
     int kh = t.nseg > 0 ? (segs[t.seg_off] + 1) >> 1 : 0;
 
+    // Issue every load of the next k tile; nothing waits on them here.
     auto load = [&]() {
         const int32_t* sg = segs + t.seg_off + seg * stride;
         const int kk = k0 + lk;
         const bool kv = kk < kh;
 #pragma unroll
+        for (int u = 0; u < TMAX; ++u) {
+            if (u < t.nx) {
+                const int row0 = sg[1 + 2 * u], rvend = sg[2 + 2 * u];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int row = row0 + b * kh + kk;
+                    const bool rok = kv && row < rvend;
+                    const double* pr = A + (int64_t)row * lda;
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+                            xraw[u][a * 2 + b][e] =
+                                (rok && ((xmask[u] >> (a * 2 + e)) & 1u)) ? pr[xcol[u][a] + e] : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xraw[u][q][0] = xraw[u][q][1] = 0.0;
+            }
+            if (u < t.ny) {
+                const int row0 = sg[1 + 2 * (t.nx + u)], rvend = sg[2 + 2 * (t.nx + u)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int row = row0 + b * kh + kk;
+                    const bool rok = kv && row < rvend;
+                    const double* pr = A + (int64_t)row * lda;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+                            yraw[u][b * 2 + c][e] =
+                                (rok && ((ymask[u] >> (c * 2 + e)) & 1u)) ? pr[ycol[u][c] + e] : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) yraw[u][q][0] = yraw[u][q][1] = 0.0;
+            }
+        }
+    };
+    // Signed sum of the terms (fixed order) into the LDS buffer.
+    auto store = [&](int buf) {
+#pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int e = 0; e < 2; ++e) xr[q][e] = yr[q][e] = 0.0;
-        for (int u = 0; u < t.nx; ++u) {
-            const DevTerm tm = terms[t.term_off + u];
-            const int row0 = sg[1 + 2 * u], rvend = sg[2 + 2 * u];
-            const double sgn = (double)tm.sign;
+            for (int e = 0; e < 2; ++e) {
+                double x = 0.0, y = 0.0;
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int row = row0 + b * kh + kk;
-                const bool rok = kv && row < rvend;
-                const double* pr = A + (int64_t)row * lda;
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const int ii = i0 + lc + e;
-                        const int col = tm.col + a * MH + ii;
-                        if (rok && ii < MH && col < tm.cvend) xr[a * 2 + b][e] += sgn * pr[col];
-                    }
+                for (int u = 0; u < TMAX; ++u) {
+                    x += xsgn[u] * xraw[u][q][e];
+                    y += ysgn[u] * yraw[u][q][e];
                 }
+                Xs[buf][q][lk][lc + e] = x;
+                Ys[buf][q][lk][lc + e] = y;
             }
-        }
-        for (int u = 0; u < t.ny; ++u) {
-            const DevTerm tm = terms[t.term_off + t.nx + u];
-            const int row0 = sg[1 + 2 * (t.nx + u)], rvend = sg[2 + 2 * (t.nx + u)];
-            const double sgn = (double)tm.sign;
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int row = row0 + b * kh + kk;
-                const bool rok = kv && row < rvend;
-                const double* pr = A + (int64_t)row * lda;
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const int jj = j0 + lc + e;
-                        const int col = tm.col + c * NH + jj;
-                        if (rok && jj < NH && col < tm.cvend) yr[b * 2 + c][e] += sgn * pr[col];
-                    }
-                }
-            }
-        }
     };
     auto advance = [&]() {
         k0 += SK;
@@ -318,13 +364,7 @@ __global__ void __launch_bounds__(256) k_str_f64(const double* __restrict__ A, i
     if (ntiles > 0) load();
     for (int it = 0; it < ntiles; ++it) {
         const int buf = it & 1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                Xs[buf][q][lk][lc + e] = xr[q][e];
-                Ys[buf][q][lk][lc + e] = yr[q][e];
-            }
+        store(buf);
         __syncthreads();
         if (it + 1 < ntiles) {
             advance();
@@ -446,14 +486,30 @@ hipError_t launch_gemm_f64(const double* A, int64_t lda, const DevTask* tasks, c
     return hipGetLastError();
 }
 
-hipError_t launch_str_f64(int variant, const double* A, int64_t lda, const DevTask* tasks,
+template <int VAR>
+static void launch_str_var(int tmax, dim3 g, hipStream_t s, const double* A, int64_t lda, const DevTask* tasks,
+                           const DevTerm* terms, const int32_t* segs, const WorkItem* items, double* C,
+                           double* W) {
+    if (tmax <= 1)
+        hipLaunchKernelGGL((k_str_f64<VAR, 1>), g, dim3(256), 0, s, A, lda, tasks, terms, segs, items, C, W);
+    else if (tmax <= 2)
+        hipLaunchKernelGGL((k_str_f64<VAR, 2>), g, dim3(256), 0, s, A, lda, tasks, terms, segs, items, C, W);
+    else if (tmax <= 4)
+        hipLaunchKernelGGL((k_str_f64<VAR, 4>), g, dim3(256), 0, s, A, lda, tasks, terms, segs, items, C, W);
+    else
+        hipLaunchKernelGGL((k_str_f64<VAR, 8>), g, dim3(256), 0, s, A, lda, tasks, terms, segs, items, C, W);
+}
+
+// tmax: largest number of terms of either operand over the launched tasks.
+hipError_t launch_str_f64(int variant, int tmax, const double* A, int64_t lda, const DevTask* tasks,
                           const DevTerm* terms, const int32_t* segs, const WorkItem* items, int nitems,
                           double* C, double* W, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
+    if (tmax > kMaxTerms) return hipErrorInvalidValue;
     if (variant == 0)
-        hipLaunchKernelGGL(k_str_f64<0>, dim3(nitems), dim3(256), 0, s, A, lda, tasks, terms, segs, items, C, W);
+        launch_str_var<0>(tmax, dim3(nitems), s, A, lda, tasks, terms, segs, items, C, W);
     else
-        hipLaunchKernelGGL(k_str_f64<1>, dim3(nitems), dim3(256), 0, s, A, lda, tasks, terms, segs, items, C, W);
+        launch_str_var<1>(tmax, dim3(nitems), s, A, lda, tasks, terms, segs, items, C, W);
     return hipGetLastError();
 }
 

@@ -174,6 +174,7 @@ int Builder::ata_node(const std::vector<Chunk>& chunks, int64_t c0, int64_t w, i
         int64_t ktot = 0;
         for (const Chunk& ch : leaf) ktot += ch.h;
         P.mults += tri(w) * ktot;
+        P.syrk_mults += tri(w) * ktot;
         const int32_t id = (int32_t)P.tasks.size();
         P.tasks.push_back(t);
         for (int64_t ti = 0; ti < T; ++ti)
@@ -216,6 +217,7 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             t.tiles_m = (int32_t)((M + kGemmTile - 1) / kGemmTile);
             t.tiles_n = (int32_t)((N + kGemmTile - 1) / kGemmTile);
             P.mults += M * N * ktot;
+            P.gemm_mults += M * N * ktot;
             const int32_t id = (int32_t)P.tasks.size();
             P.tasks.push_back(t);
             for (int32_t a = 0; a < t.tiles_m; ++a)
@@ -342,10 +344,12 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             t.tiles_m = (int32_t)((MHin + kStrTile - 1) / kStrTile);
             t.tiles_n = (int32_t)((NHin + kStrTile - 1) / kStrTile);
             P.mults += 7 * MHin * NHin * khalf;
+            P.str_mults += 7 * MHin * NHin * khalf;
             const int32_t id = (int32_t)P.tasks.size();
             P.tasks.push_back(t);
             for (int32_t a = 0; a < t.tiles_m; ++a)
                 for (int32_t b = 0; b < t.tiles_n; ++b) ph(gphase).str_items.push_back(WorkItem{id, a, b, 0});
+            ph(gphase).str_tmax = std::max(ph(gphase).str_tmax, std::max(t.nx, t.ny));
             ++P.str_tasks;
         }
         if (!direct) {
@@ -363,6 +367,7 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             Phase& pz = ph(gphase);
             cb.elem_off = pz.combine_elems;
             pz.combine_elems += M * N;
+            P.combine_elems += M * N;
             pz.combines.push_back(cb);
             ++P.combine_tasks;
         }

@@ -77,6 +77,7 @@ struct Phase {
     std::vector<WorkItem> str_items, gemm_items, syrk_items;
     std::vector<DevCombine> combines;
     int64_t combine_elems = 0;
+    int str_tmax = 0;  // most operand terms of any TK_STR task in this phase
 };
 
 struct Plan {
@@ -89,6 +90,7 @@ struct Plan {
     int64_t ws_elems = 0;
     // statistics
     int64_t mults = 0;
+    int64_t str_mults = 0, gemm_mults = 0, syrk_mults = 0, combine_elems = 0;
     int64_t syrk_tasks = 0, gemm_tasks = 0, str_tasks = 0, combine_tasks = 0;
     int64_t work_items = 0;
     int64_t ata_depth = 0, max_hasa_depth = 0;
