@@ -66,7 +66,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=10000)
     ap.add_argument("--cutoff", type=int, default=0, help="0: tune over {128,256,512}")
-    ap.add_argument("--max-depth", type=int, default=None)
+    ap.add_argument("--max-depth", type=int, default=None, help="default: tune over {1, 2}")
     ap.add_argument("--variant", default="strassen")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -91,9 +91,7 @@ def main():
     A = torch.from_numpy(A_np).to(dev)
     C = torch.empty(P.tri(n), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
-    depth = P.DEFAULT_MAX_DEPTH if args.max_depth is None else args.max_depth
-
-    def run(cutoff, d=depth, variant=args.variant):
+    def run(cutoff, d, variant=args.variant):
         P.gram(A, cutoff=cutoff, max_depth=d, variant=variant, out=C, stream=stream)
 
     def time_steps(fn, steps):
@@ -107,21 +105,23 @@ def main():
         torch.cuda.synchronize(dev)
         return e0.elapsed_time(e1) / steps
 
-    # cutoff tuning over the set the workload names
+    # tuning of the leaf cutoff over the set the workload names, and of the
+    # number of Strassen levels fused per off-diagonal product
     sweep = {}
-    if args.cutoff == 0:
-        for c in (128, 256, 512):
-            run(c)
-            sweep[c] = time_steps(lambda: run(c), 3)
-        cutoff = min(sweep, key=sweep.get)
-    else:
-        cutoff = args.cutoff
+    cutoffs = (128, 256, 512) if args.cutoff == 0 else (args.cutoff,)
+    depths = (1, 2) if args.max_depth is None else (args.max_depth,)
+    for c in cutoffs:
+        for d in depths:
+            run(c, d)
+            sweep["c%d_d%d" % (c, d)] = time_steps(lambda: run(c, d), 3)
+    best = min(sweep, key=sweep.get)
+    cutoff, depth = (int(x[1:]) for x in best.split("_"))
 
     for _ in range(args.warmup):
-        run(cutoff)
+        run(cutoff, depth)
     P.profile_enable(True)
     P.profile_collect()
-    ms = time_steps(lambda: run(cutoff), args.steps)
+    ms = time_steps(lambda: run(cutoff, depth), args.steps)
     prof = P.profile_collect()
     P.profile_enable(False)
 
@@ -182,7 +182,7 @@ def main():
         "config": {
             "workload": "square FP64 A %dx%d, i.i.d. uniform[-1,1] (seed %d), packed lower C = A^tA"
                         % (m, n, synthetic.SEED_SQUARE),
-            "m": m, "n": n, "cutoff": cutoff, "cutoff_sweep_ms": sweep, "variant": args.variant,
+            "m": m, "n": n, "cutoff": cutoff, "tuning_sweep_ms": sweep, "variant": args.variant,
             "max_strassen_depth": depth, "phases": st["phases"], "ata_depth": st["ata_depth"],
             "mults_over_classical": st["mults"] / st["classical_mults"],
         },

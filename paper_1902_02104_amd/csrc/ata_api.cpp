@@ -206,6 +206,39 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, b
     return ATA_OK;
 }
 
+// ---- a second stream per call for the small classical tiles ----
+// The classical off-diagonal and diagonal tiles of a phase write output
+// regions disjoint from the Strassen tiles, so they run on a forked stream and
+// fill the GPU while the Strassen launch drains.  Contexts are pooled per
+// device; an event pair orders the fork and the join on the caller's stream.
+struct ForkCtx {
+    hipStream_t s2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_fork_mu;
+std::map<int, std::vector<ForkCtx>> g_fork_pool;
+
+int fork_get(int dev, ForkCtx& c) {
+    {
+        std::lock_guard<std::mutex> lk(g_fork_mu);
+        auto& v = g_fork_pool[dev];
+        if (!v.empty()) {
+            c = v.back();
+            v.pop_back();
+            return ATA_OK;
+        }
+    }
+    HIP_TRY(hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&c.join, hipEventDisableTiming));
+    return ATA_OK;
+}
+
+void fork_put(int dev, const ForkCtx& c) {
+    std::lock_guard<std::mutex> lk(g_fork_mu);
+    g_fork_pool[dev].push_back(c);
+}
+
 // ---- kernel timing (measurement tools only) ----
 struct ProfRec {
     int kind;
@@ -368,20 +401,34 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     const int32_t* segs = (const int32_t*)(pd->blob + pd->off_segs);
     hipError_t err = hipSuccess;
     for (const PhaseDev& ph : pd->phases) {
+        const bool split = ph.n_str > 0 && (ph.n_gemm + ph.n_syrk) > 0;
+        ForkCtx fc;
+        if (split) {
+            rc = fork_get(dev, fc);
+            if (rc != ATA_OK) return rc;
+            err = hipEventRecord(fc.fork, s);
+            if (err == hipSuccess) err = hipStreamWaitEvent(fc.s2, fc.fork, 0);
+        }
         if (err == hipSuccess && ph.n_str) {
             ProfScope ps(ATA_KERNEL_STRASSEN, s);
-            err = launch_str_f64(variant, ph.str_tmax, Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_str),
-                                 ph.n_str, Cd, W, s);
+            err = launch_str_f64(variant, ph.str_tmax, Ad, lda, tasks, terms, segs,
+                                 (const WorkItem*)(pd->blob + ph.off_str), ph.n_str, Cd, W, s);
         }
+        hipStream_t s_small = split ? fc.s2 : s;
         if (err == hipSuccess && ph.n_gemm) {
-            ProfScope ps(ATA_KERNEL_GEMM, s);
+            ProfScope ps(ATA_KERNEL_GEMM, s_small);
             err = launch_gemm_f64(Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_gemm),
-                                  ph.n_gemm, Cd, s);
+                                  ph.n_gemm, Cd, s_small);
         }
         if (err == hipSuccess && ph.n_syrk) {
-            ProfScope ps(ATA_KERNEL_SYRK, s);
+            ProfScope ps(ATA_KERNEL_SYRK, s_small);
             err = launch_gemm_f64(Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_syrk),
-                                  ph.n_syrk, Cd, s);
+                                  ph.n_syrk, Cd, s_small);
+        }
+        if (split) {
+            if (err == hipSuccess) err = hipEventRecord(fc.join, fc.s2);
+            if (err == hipSuccess) err = hipStreamWaitEvent(s, fc.join, 0);
+            fork_put(dev, fc);
         }
         if (err == hipSuccess && ph.n_cb) {
             ProfScope ps(ATA_KERNEL_COMBINE, s);

@@ -34,9 +34,9 @@ __device__ __forceinline__ int64_t packed_index(int64_t r, int64_t q) { return r
 // ---------------------------------------------------------------------------
 constexpr int GT = kGemmTile;  // 128
 constexpr int GK = 16;
-constexpr int GPAD = 2;
+constexpr int GPAD = 4;
 
-__global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, int64_t lda,
+__global__ void __launch_bounds__(256, 2) k_gemm_f64(const double* __restrict__ A, int64_t lda,
                                                   const DevTask* __restrict__ tasks,
                                                   const DevTerm* __restrict__ terms,
                                                   const int32_t* __restrict__ segs,
@@ -152,8 +152,8 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, 
 // end.  Operand terms of higher levels are summed while staging to LDS.
 // ---------------------------------------------------------------------------
 constexpr int ST = kStrTile;  // 64
-constexpr int SK = 8;
-constexpr int SPAD = 2;
+constexpr int SK_MAX = 16;  // k rows per LDS stage (8 when operands carry several terms)
+constexpr int SPAD = 4;  // row stride = 4 mod 16 doubles: broadcast reads hit disjoint banks
 
 template <int VAR>
 __device__ __forceinline__ void left_operands(double x00, double x01, double x10, double x11, double (&o)[7]) {
@@ -217,31 +217,31 @@ __device__ __forceinline__ void combine_products(const double (&m)[7], double (&
     }
 }
 
-template <int VAR, int TMAX>
-__global__ void __launch_bounds__(256) k_str_f64(const double* __restrict__ A, int64_t lda,
-                                                 const DevTask* __restrict__ tasks,
-                                                 const DevTerm* __restrict__ terms,
-                                                 const int32_t* __restrict__ segs,
-                                                 const WorkItem* __restrict__ items,
-                                                 double* __restrict__ C, double* __restrict__ W) {
+template <int VAR, int TMAX, int SK>
+__global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A, int64_t lda,
+                                                    const DevTask* __restrict__ tasks,
+                                                    const DevTerm* __restrict__ terms,
+                                                    const int32_t* __restrict__ segs,
+                                                    const WorkItem* __restrict__ items,
+                                                    double* __restrict__ C, double* __restrict__ W) {
     __shared__ double Xs[2][4][SK][ST + SPAD];
     __shared__ double Ys[2][4][SK][ST + SPAD];
 
     const WorkItem w = items[blockIdx.x];
     const DevTask t = tasks[w.task];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave >> 1, wn = wave & 1;  // 4 x 2 waves of 16 x 32
     const int MH = (t.M + 1) >> 1, NH = (t.N + 1) >> 1;
     const int i0 = w.ti * ST, j0 = w.tj * ST;
     const int stride = 1 + 2 * (t.nx + t.ny);
 
-    // staging map: thread -> k row lk, 2 consecutive columns at lc
-    const int lk = tid >> 5, lc = (tid & 31) * 2;
+    // staging map: thread -> k rows lk and lk + 8, column lc (two elements per quadrant)
+    const int lk = tid >> 6, lc = tid & 63;
+    constexpr int KR = SK / 8;  // k rows per thread
 
-    // Per-term column data, fixed for the whole K loop: first column of each
-    // M (or N) half for this thread, and which of the 2 columns are valid.
+    // Per-term column data, fixed for the whole K loop.
     int xcol[TMAX][2], ycol[TMAX][2];
-    unsigned xmask[TMAX], ymask[TMAX];  // bit a*2+e: column valid
+    unsigned xmask[TMAX], ymask[TMAX];  // bit a: column of M-half a valid
     double xsgn[TMAX], ysgn[TMAX];
 #pragma unroll
     for (int u = 0; u < TMAX; ++u) {
@@ -254,9 +254,7 @@ __global__ void __launch_bounds__(256) k_str_f64(const double* __restrict__ A, i
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 xcol[u][a] = tm.col + a * MH + i0 + lc;
-#pragma unroll
-                for (int e = 0; e < 2; ++e)
-                    if (i0 + lc + e < MH && xcol[u][a] + e < tm.cvend) xmask[u] |= 1u << (a * 2 + e);
+                if (i0 + lc < MH && xcol[u][a] < tm.cvend) xmask[u] |= 1u << a;
             }
         }
         if (u < t.ny) {
@@ -265,18 +263,16 @@ __global__ void __launch_bounds__(256) k_str_f64(const double* __restrict__ A, i
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 ycol[u][c] = tm.col + c * NH + j0 + lc;
-#pragma unroll
-                for (int e = 0; e < 2; ++e)
-                    if (j0 + lc + e < NH && ycol[u][c] + e < tm.cvend) ymask[u] |= 1u << (c * 2 + e);
+                if (j0 + lc < NH && ycol[u][c] < tm.cvend) ymask[u] |= 1u << c;
             }
         }
     }
 
-    double acc[7][8][2];
+    double acc[7][4][2];
 #pragma unroll
     for (int p = 0; p < 7; ++p)
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[p][a][b] = 0.0;
 
@@ -286,70 +282,67 @@ __global__ void __launch_bounds__(256) k_str_f64(const double* __restrict__ A, i
         ntiles += (kh + SK - 1) / SK;
     }
 
-    // raw term values of the next k tile: [term][quad][e]
-    double xraw[TMAX][4][2], yraw[TMAX][4][2];
+    // raw term values of the next k tile: [term][quad]
+    double xraw[TMAX][KR][4], yraw[TMAX][KR][4];
     int seg = 0, k0 = 0;
     int kh = t.nseg > 0 ? (segs[t.seg_off] + 1) >> 1 : 0;
 
     // Issue every load of the next k tile; nothing waits on them here.
     auto load = [&]() {
         const int32_t* sg = segs + t.seg_off + seg * stride;
-        const int kk = k0 + lk;
-        const bool kv = kk < kh;
 #pragma unroll
-        for (int u = 0; u < TMAX; ++u) {
-            if (u < t.nx) {
-                const int row0 = sg[1 + 2 * u], rvend = sg[2 + 2 * u];
+        for (int r = 0; r < KR; ++r) {
+            const int kk = k0 + lk + 8 * r;
+            const bool kv = kk < kh;
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int row = row0 + b * kh + kk;
-                    const bool rok = kv && row < rvend;
-                    const double* pr = A + (int64_t)row * lda;
+            for (int u = 0; u < TMAX; ++u) {
+                if (u < t.nx) {
+                    const int row0 = sg[1 + 2 * u], rvend = sg[2 + 2 * u];
 #pragma unroll
-                    for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        const int row = row0 + b * kh + kk;
+                        const bool rok = kv && row < rvend;
+                        const double* pr = A + (int64_t)row * lda;
 #pragma unroll
-                        for (int e = 0; e < 2; ++e)
-                            xraw[u][a * 2 + b][e] =
-                                (rok && ((xmask[u] >> (a * 2 + e)) & 1u)) ? pr[xcol[u][a] + e] : 0.0;
+                        for (int a = 0; a < 2; ++a)
+                            xraw[u][r][a * 2 + b] = (rok && ((xmask[u] >> a) & 1u)) ? pr[xcol[u][a]] : 0.0;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) xraw[u][r][q] = 0.0;
                 }
-            } else {
+                if (u < t.ny) {
+                    const int row0 = sg[1 + 2 * (t.nx + u)], rvend = sg[2 + 2 * (t.nx + u)];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) xraw[u][q][0] = xraw[u][q][1] = 0.0;
-            }
-            if (u < t.ny) {
-                const int row0 = sg[1 + 2 * (t.nx + u)], rvend = sg[2 + 2 * (t.nx + u)];
+                    for (int b = 0; b < 2; ++b) {
+                        const int row = row0 + b * kh + kk;
+                        const bool rok = kv && row < rvend;
+                        const double* pr = A + (int64_t)row * lda;
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int row = row0 + b * kh + kk;
-                    const bool rok = kv && row < rvend;
-                    const double* pr = A + (int64_t)row * lda;
+                        for (int c = 0; c < 2; ++c)
+                            yraw[u][r][b * 2 + c] = (rok && ((ymask[u] >> c) & 1u)) ? pr[ycol[u][c]] : 0.0;
+                    }
+                } else {
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
-#pragma unroll
-                        for (int e = 0; e < 2; ++e)
-                            yraw[u][b * 2 + c][e] =
-                                (rok && ((ymask[u] >> (c * 2 + e)) & 1u)) ? pr[ycol[u][c] + e] : 0.0;
+                    for (int q = 0; q < 4; ++q) yraw[u][r][q] = 0.0;
                 }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) yraw[u][q][0] = yraw[u][q][1] = 0.0;
             }
         }
     };
     // Signed sum of the terms (fixed order) into the LDS buffer.
     auto store = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int r = 0; r < KR; ++r)
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
+            for (int q = 0; q < 4; ++q) {
                 double x = 0.0, y = 0.0;
 #pragma unroll
                 for (int u = 0; u < TMAX; ++u) {
-                    x += xsgn[u] * xraw[u][q][e];
-                    y += ysgn[u] * yraw[u][q][e];
+                    x += xsgn[u] * xraw[u][r][q];
+                    y += ysgn[u] * yraw[u][r][q];
                 }
-                Xs[buf][q][lk][lc + e] = x;
-                Ys[buf][q][lk][lc + e] = y;
+                Xs[buf][q][lk + 8 * r][lc] = x;
+                Ys[buf][q][lk + 8 * r][lc] = y;
             }
     };
     auto advance = [&]() {
@@ -381,8 +374,8 @@ __global__ void __launch_bounds__(256) k_str_f64(const double* __restrict__ A, i
                                     Ys[buf][3][kr][cc], ro[cf]);
             }
 #pragma unroll
-            for (int rf = 0; rf < 8; ++rf) {
-                const int rr = wm * 32 + rf * 4 + (lane & 3);
+            for (int rf = 0; rf < 4; ++rf) {
+                const int rr = wm * 16 + rf * 4 + (lane & 3);
                 double lo[7];
                 left_operands<VAR>(Xs[buf][0][kr][rr], Xs[buf][1][kr][rr], Xs[buf][2][kr][rr],
                                    Xs[buf][3][kr][rr], lo);
@@ -396,8 +389,8 @@ __global__ void __launch_bounds__(256) k_str_f64(const double* __restrict__ A, i
 
     // combine the seven products into the four quadrants and store
 #pragma unroll
-    for (int rf = 0; rf < 8; ++rf) {
-        const int li = i0 + wm * 32 + rf * 4 + (lane >> 4);  // row inside a quadrant
+    for (int rf = 0; rf < 4; ++rf) {
+        const int li = i0 + wm * 16 + rf * 4 + (lane >> 4);  // row inside a quadrant
 #pragma unroll
         for (int cf = 0; cf < 2; ++cf) {
             const int lj = j0 + wn * 32 + cf * 16 + (lane & 15);
@@ -491,13 +484,13 @@ static void launch_str_var(int tmax, dim3 g, hipStream_t s, const double* A, int
                            const DevTerm* terms, const int32_t* segs, const WorkItem* items, double* C,
                            double* W) {
     if (tmax <= 1)
-        hipLaunchKernelGGL((k_str_f64<VAR, 1>), g, dim3(256), 0, s, A, lda, tasks, terms, segs, items, C, W);
+        hipLaunchKernelGGL((k_str_f64<VAR, 1, 16>), g, dim3(512), 0, s, A, lda, tasks, terms, segs, items, C, W);
     else if (tmax <= 2)
-        hipLaunchKernelGGL((k_str_f64<VAR, 2>), g, dim3(256), 0, s, A, lda, tasks, terms, segs, items, C, W);
+        hipLaunchKernelGGL((k_str_f64<VAR, 2, 8>), g, dim3(512), 0, s, A, lda, tasks, terms, segs, items, C, W);
     else if (tmax <= 4)
-        hipLaunchKernelGGL((k_str_f64<VAR, 4>), g, dim3(256), 0, s, A, lda, tasks, terms, segs, items, C, W);
+        hipLaunchKernelGGL((k_str_f64<VAR, 4, 8>), g, dim3(512), 0, s, A, lda, tasks, terms, segs, items, C, W);
     else
-        hipLaunchKernelGGL((k_str_f64<VAR, 8>), g, dim3(256), 0, s, A, lda, tasks, terms, segs, items, C, W);
+        hipLaunchKernelGGL((k_str_f64<VAR, 8, 8>), g, dim3(512), 0, s, A, lda, tasks, terms, segs, items, C, W);
 }
 
 // tmax: largest number of terms of either operand over the launched tasks.
