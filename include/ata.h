@@ -111,6 +111,25 @@ int ata_ex(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int 
 int ata_workspace_bytes(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts *opts,
                         size_t *bytes);
 
+/*
+ * Reduced-precision forms (ATA_F32_BF16X3, ATA_F32_FP8): the leaves are
+ * classical products (ata_opts.max_depth must be 0 or the struct NULL); the
+ * ATA recursion itself is unchanged.  FP32 MFMA accumulators are added into
+ * FP64 every 512 rows; Strassen combinations and the workspace are FP64.
+ * ATA_F32 leaves support Strassen levels like ATA_F64.
+ */
+
+/*
+ * ata_precision_convert: the element conversions of the reduced-precision
+ * forms, for verification.  x: `count` floats in device memory.
+ *   ATA_F32_BF16X3: out0[i] = bfloat16 bits of x[i] rounded to nearest even
+ *                   (hi), out1[i] = bits of bf16(x[i] - hi) (lo); uint16 each.
+ *   ATA_F32_FP8:    out0[i] = OCP e4m3 byte of x[i], nearest even, saturated
+ *                   to +-448 (no scaling applied); out1 unused.
+ * Asynchronous on `stream`.
+ */
+int ata_precision_convert(int dtype, const float *x, int64_t count, void *out0, void *out1, void *stream);
+
 /* Host-only description of the plan (no GPU needed). */
 typedef struct ata_plan_stats {
     int64_t mults;           /* scalar multiplications of the method */

@@ -30,7 +30,7 @@ from .build import build, lib_path
 __all__ = [
     "classical", "classical_mt", "ata", "hasa", "ata_mult_count", "unpack", "pack",
     "tri", "rel_fro", "scaled_err", "freivalds_residual", "bf16_round", "bf16_split",
-    "e4m3_round", "pow2_column_scales", "STRASSEN", "WINOGRAD", "load",
+    "e4m3_round", "pow2_column_scales", "gram_bf16x3", "gram_fp8", "STRASSEN", "WINOGRAD", "load",
 ]
 
 STRASSEN = 0
@@ -267,6 +267,27 @@ def e4m3_round(x: np.ndarray) -> np.ndarray:
     out = np.minimum(out, E4M3_MAX)
     out[a == 0] = 0.0
     return np.copysign(out, x)
+
+
+def gram_bf16x3(A32: np.ndarray) -> np.ndarray:
+    """What the bfloat16 split form computes, in exact-as-possible FP64:
+    packed lower of hi^t hi + hi^t lo + lo^t hi with hi, lo = bf16_split(A)
+    (the lo^t lo term is dropped by the method)."""
+    hi, lo = bf16_split(np.asarray(A32, dtype=np.float32))
+    hi = hi.astype(np.float64)
+    lo = lo.astype(np.float64)
+    full = hi.T @ hi + hi.T @ lo + lo.T @ hi
+    return pack(full)
+
+
+def gram_fp8(A32: np.ndarray) -> np.ndarray:
+    """What the e4m3 form computes, in FP64: with power-of-two column scales
+    s, Q = e4m3(A diag(s)) and C = diag(s)^-1 Q^t Q diag(s)^-1 (packed lower)."""
+    A32 = np.asarray(A32, dtype=np.float32)
+    s = pow2_column_scales(A32.astype(np.float64))
+    Q = e4m3_round(A32.astype(np.float64) * s[None, :])
+    full = (Q.T @ Q) / s[:, None] / s[None, :]
+    return pack(full)
 
 
 def pow2_column_scales(A: np.ndarray, target: float = E4M3_MAX) -> np.ndarray:

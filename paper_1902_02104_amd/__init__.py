@@ -87,6 +87,8 @@ def load():
     lib.ata_version.restype = ctypes.c_char_p
     lib.ata_release_caches.argtypes = []
     lib.ata_release_caches.restype = None
+    lib.ata_precision_convert.argtypes = [ci, vp, i64, vp, vp, vp]
+    lib.ata_precision_convert.restype = ci
     lib.ata_profile_enable.argtypes = [ci]
     lib.ata_profile_enable.restype = ci
     lib.ata_profile_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ci]
@@ -103,10 +105,13 @@ def tri(n: int) -> int:
     return n * (n + 1) // 2
 
 
-def _opts(variant, max_depth):
+def _opts(variant, max_depth, dtype=F64):
     o = Opts()
     o.variant = {"strassen": STRASSEN, "winograd": WINOGRAD}.get(variant, variant)
-    o.max_depth = DEFAULT_MAX_DEPTH if max_depth is None else int(max_depth)
+    if max_depth is None:
+        # reduced-precision leaves are classical; other forms fuse two Strassen levels
+        max_depth = 0 if (dtype & 0xff) in (F32_BF16X3, F32_FP8) else DEFAULT_MAX_DEPTH
+    o.max_depth = int(max_depth)
     o.flags = 0
     return o
 
@@ -114,7 +119,7 @@ def _opts(variant, max_depth):
 def plan_info(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None) -> dict:
     """Host-only description of the device plan (no GPU needed)."""
     st = PlanStats()
-    o = _opts(variant, max_depth)
+    o = _opts(variant, max_depth, dtype)
     rc = load().ata_plan_info(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(st))
     if rc:
         raise AtaError(rc, "ata_plan_info")
@@ -123,11 +128,37 @@ def plan_info(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strass
 
 def workspace_bytes(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None) -> int:
     out = ctypes.c_size_t(0)
-    o = _opts(variant, max_depth)
+    o = _opts(variant, max_depth, dtype)
     rc = load().ata_workspace_bytes(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(out))
     if rc:
         raise AtaError(rc, "ata_workspace_bytes")
     return int(out.value)
+
+
+def precision_convert(x, dtype: int, stream=None):
+    """Element conversions of the reduced-precision forms, run on the device:
+    F32_BF16X3 -> (hi, lo) int16 tensors of bfloat16 bits; F32_FP8 -> uint8
+    tensor of OCP e4m3 bytes."""
+    import torch
+    lib = load()
+    x = x.contiguous()
+    if x.dtype != torch.float32 or not x.is_cuda:
+        raise ValueError("x must be a float32 device tensor")
+    if (dtype & 0xff) == F32_BF16X3:
+        o0 = torch.empty(x.numel(), dtype=torch.int16, device=x.device)
+        o1 = torch.empty(x.numel(), dtype=torch.int16, device=x.device)
+        p1 = ctypes.c_void_p(o1.data_ptr())
+    elif (dtype & 0xff) == F32_FP8:
+        o0 = torch.empty(x.numel(), dtype=torch.uint8, device=x.device)
+        o1, p1 = None, None
+    else:
+        raise ValueError("dtype must be F32_BF16X3 or F32_FP8")
+    with torch.cuda.device(x.device):
+        rc = lib.ata_precision_convert(int(dtype), ctypes.c_void_p(x.data_ptr()), x.numel(),
+                                       ctypes.c_void_p(o0.data_ptr()), p1, _stream_handle(stream))
+    if rc:
+        raise AtaError(rc, "ata_precision_convert")
+    return (o0, o1) if o1 is not None else o0
 
 
 KERNEL_KINDS = ("strassen", "gemm", "syrk", "combine", "other")
@@ -185,7 +216,7 @@ def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_d
         out = torch.empty(tri(n), dtype=out_t, device=A.device)
     elif out.dtype != out_t or out.numel() < tri(n) or not out.is_contiguous():
         raise ValueError("bad output tensor")
-    o = _opts(variant, max_depth)
+    o = _opts(variant, max_depth, dtype)
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()

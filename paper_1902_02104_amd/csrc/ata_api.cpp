@@ -15,17 +15,7 @@
 #include "../../include/ata.h"
 #include "ata_plan.h"
 
-namespace atalib {
-hipError_t launch_gemm_f64(const double* A, int64_t lda, const DevTask* tasks, const DevTerm* terms,
-                           const int32_t* segs, const WorkItem* items, int nitems, double* C,
-                           hipStream_t s);
-hipError_t launch_str_f64(int variant, int tmax, const double* A, int64_t lda, const DevTask* tasks,
-                          const DevTerm* terms, const int32_t* segs, const WorkItem* items, int nitems,
-                          double* C, double* W, hipStream_t s);
-hipError_t launch_combine_f64(const DevCombine* cbs, int ncb, int64_t total, const double* W, double* C,
-                              hipStream_t s);
-hipError_t launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
-}  // namespace atalib
+#include "ata_kernels.h"
 
 using namespace atalib;
 
@@ -158,7 +148,43 @@ bool dtype_valid(int dtype) {
     if (base == ATA_F64 && flags) return false;
     return true;
 }
-bool dtype_implemented(int dtype) { return dtype == ATA_F64; }
+bool dtype_lp(int dtype) { return (dtype & 0xff) == ATA_F32_BF16X3 || (dtype & 0xff) == ATA_F32_FP8; }
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Device workspace layout: [FP64 Strassen products][scales][column-max
+// partials][converted copy plane 0][plane 1], each 256-byte aligned.
+struct WsLayout {
+    size_t w = 0, scale = 0, part = 0, t0 = 0, t1 = 0, total = 0;
+    int64_t ldt = 0;
+};
+
+WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems) {
+    WsLayout L;
+    size_t off = (size_t)ws_elems * sizeof(double);
+    off = (off + 255) & ~(size_t)255;
+    if (dtype_lp(dtype) && n > 0) {
+        const bool fp8 = (dtype & 0xff) == ATA_F32_FP8;
+        L.ldt = round_up(m > 0 ? m : 1, 128);
+        L.scale = off;
+        off += (size_t)n * sizeof(float);
+        off = (off + 255) & ~(size_t)255;
+        L.part = off;
+        off += (size_t)((m + 255) / 256) * n * sizeof(float);
+        off = (off + 255) & ~(size_t)255;
+        const size_t plane = (size_t)n * L.ldt * (fp8 ? 1 : 2);
+        L.t0 = off;
+        off += plane;
+        off = (off + 255) & ~(size_t)255;
+        if (!fp8) {
+            L.t1 = off;
+            off += plane;
+            off = (off + 255) & ~(size_t)255;
+        }
+    }
+    L.total = off;
+    return L;
+}
 
 int64_t default_cutoff(int64_t m, int64_t n, int dtype) {
     (void)dtype;
@@ -321,6 +347,10 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     int variant, max_depth;
     if (resolve_opts(opts, variant, max_depth)) return -5;
     if (!out) return -6;
+    if (dtype_lp(dtype)) {
+        if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
+        max_depth = 0;
+    }
     const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
     std::shared_ptr<PlanDev> pd;
     const int rc = get_plan(m, n, c, variant, max_depth, false, pd);
@@ -337,7 +367,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     out->phases = (int64_t)P.phases.size();
     out->ata_depth = P.ata_depth;
     out->max_hasa_depth = P.max_hasa_depth;
-    out->workspace_bytes = P.ws_elems * (int64_t)sizeof(double);  // combinations run in FP64
+    out->workspace_bytes = (int64_t)ws_layout(m, n, dtype, P.ws_elems).total;
     out->cutoff = c;
     out->strassen_mults = P.str_mults;
     out->gemm_mults = P.gemm_mults;
@@ -361,7 +391,14 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     if (rc) return rc;
     int variant, max_depth;
     if (resolve_opts(opts, variant, max_depth)) return -9;
-    if (!dtype_implemented(dtype)) return ATA_EUNSUPPORTED;
+    const bool lp = dtype_lp(dtype);
+    if (lp) {
+        // reduced-precision leaves: classical off-diagonal products only
+        if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
+        max_depth = 0;
+    }
+    const bool f32 = (dtype & 0xff) != ATA_F64;
+    const bool out64 = elem_bytes_out(dtype) == 8;
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -381,26 +418,50 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     rc = get_plan(m, n, c, variant, max_depth, true, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
-    const size_t need = (size_t)P.ws_elems * sizeof(double);
-    double* W = nullptr;
+    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems);
+    if (L.ldt > INT32_MAX) return ATA_EUNSUPPORTED;
+    char* ws = nullptr;
     bool owned = false;
-    if (need) {
+    if (L.total) {
         if (workspace) {
-            if (ws_bytes < need) return ATA_EWORKSPACE;
-            if ((uintptr_t)workspace % 8) return -10;
-            W = (double*)workspace;
+            if (ws_bytes < L.total) return ATA_EWORKSPACE;
+            if ((uintptr_t)workspace % 256) return -10;
+            ws = (char*)workspace;
         } else {
-            HIP_TRY(hipMallocAsync((void**)&W, need, s));
+            HIP_TRY(hipMallocAsync((void**)&ws, L.total, s));
             owned = true;
         }
     }
-    const double* Ad = (const double*)A;
-    double* Cd = (double*)C_lower;
-    const DevTask* tasks = (const DevTask*)(pd->blob + pd->off_tasks);
-    const DevTerm* terms = (const DevTerm*)(pd->blob + pd->off_terms);
-    const int32_t* segs = (const int32_t*)(pd->blob + pd->off_segs);
+    double* W = P.ws_elems ? (double*)(ws + L.w) : nullptr;
+    const DevTables tb{(const DevTask*)(pd->blob + pd->off_tasks), (const DevTerm*)(pd->blob + pd->off_terms),
+                       (const int32_t*)(pd->blob + pd->off_segs)};
     hipError_t err = hipSuccess;
+    const int lp_mode = (dtype & 0xff) == ATA_F32_FP8 ? 1 : 0;
+    if (lp) {
+        ProfScope ps(ATA_KERNEL_OTHER, s);
+        float* scale = (float*)(ws + L.scale);
+        if (lp_mode == 1) err = launch_colscale((const float*)A, lda, (int)m, (int)n, (float*)(ws + L.part), scale, s);
+        if (err == hipSuccess)
+            err = launch_prep_lp(lp_mode, (const float*)A, lda, (int)m, (int)n, (int)L.ldt, scale, ws + L.t0,
+                                 lp_mode == 0 ? (void*)(ws + L.t1) : nullptr, s);
+    }
     for (const PhaseDev& ph : pd->phases) {
+        if (err != hipSuccess) break;
+        if (lp) {
+            const float* scale = (const float*)(ws + L.scale);
+            const void* t1 = lp_mode == 0 ? (const void*)(ws + L.t1) : nullptr;
+            if (ph.n_gemm) {
+                ProfScope ps(ATA_KERNEL_GEMM, s);
+                err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
+                                     (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower, s);
+            }
+            if (err == hipSuccess && ph.n_syrk) {
+                ProfScope ps(ATA_KERNEL_SYRK, s);
+                err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
+                                     (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, s);
+            }
+            continue;
+        }
         const bool split = ph.n_str > 0 && (ph.n_gemm + ph.n_syrk) > 0;
         ForkCtx fc;
         if (split) {
@@ -411,19 +472,19 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
         }
         if (err == hipSuccess && ph.n_str) {
             ProfScope ps(ATA_KERNEL_STRASSEN, s);
-            err = launch_str_f64(variant, ph.str_tmax, Ad, lda, tasks, terms, segs,
-                                 (const WorkItem*)(pd->blob + ph.off_str), ph.n_str, Cd, W, s);
+            err = launch_str(f32, out64, variant, ph.str_tmax, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_str),
+                             ph.n_str, C_lower, W, s);
         }
         hipStream_t s_small = split ? fc.s2 : s;
         if (err == hipSuccess && ph.n_gemm) {
             ProfScope ps(ATA_KERNEL_GEMM, s_small);
-            err = launch_gemm_f64(Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_gemm),
-                                  ph.n_gemm, Cd, s_small);
+            err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower,
+                              s_small);
         }
         if (err == hipSuccess && ph.n_syrk) {
             ProfScope ps(ATA_KERNEL_SYRK, s_small);
-            err = launch_gemm_f64(Ad, lda, tasks, terms, segs, (const WorkItem*)(pd->blob + ph.off_syrk),
-                                  ph.n_syrk, Cd, s_small);
+            err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower,
+                              s_small);
         }
         if (split) {
             if (err == hipSuccess) err = hipEventRecord(fc.join, fc.s2);
@@ -432,15 +493,27 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
         }
         if (err == hipSuccess && ph.n_cb) {
             ProfScope ps(ATA_KERNEL_COMBINE, s);
-            err = launch_combine_f64((const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W, Cd, s);
+            err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W, C_lower, s);
         }
     }
     if (owned) {
-        hipError_t e2 = hipFreeAsync(W, s);
+        hipError_t e2 = hipFreeAsync(ws, s);
         if (err == hipSuccess) err = e2;
     }
     if (err != hipSuccess) return hip_fail(err);
     return ATA_OK;
+}
+
+int ata_precision_convert(int dtype, const float* x, int64_t count, void* out0, void* out1, void* stream) {
+    const int base = dtype & 0xff;
+    if (base != ATA_F32_BF16X3 && base != ATA_F32_FP8) return -1;
+    if (count < 0) return -3;
+    if (count > 0 && !x) return -2;
+    if (count > 0 && !out0) return -4;
+    if (count > 0 && base == ATA_F32_BF16X3 && !out1) return -5;
+    if (count == 0) return ATA_OK;
+    hipError_t e = launch_convert(base == ATA_F32_FP8 ? 1 : 0, x, count, out0, out1, (hipStream_t)stream);
+    return e == hipSuccess ? ATA_OK : hip_fail(e);
 }
 
 int ata(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int dtype, int cutoff, void* stream) {

@@ -1,0 +1,52 @@
+// Launchers of the gfx950 kernels (defined in ata_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ata_plan.h"
+
+namespace atalib {
+
+// Task tables of one plan in device memory.
+struct DevTables {
+    const DevTask* tasks;
+    const DevTerm* terms;
+    const int32_t* segs;
+};
+
+// Classical tiles (TK_SYRK / TK_GEMM) on FP64 or FP32 MFMA.  out_f64 selects
+// a double C for float input.
+hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
+                       const WorkItem* items, int nitems, void* C, hipStream_t s);
+
+// In-tile Strassen tiles (TK_STR).  tmax: most operand terms of any task.
+hipError_t launch_str(bool f32, bool out_f64, int variant, int tmax, const void* A, int64_t lda,
+                      const DevTables& tb, const WorkItem* items, int nitems, void* C, double* W,
+                      hipStream_t s);
+
+// Workspace combinations (FP64 workspace) into packed C.
+hipError_t launch_combine(bool out_f64, const DevCombine* cbs, int ncb, int64_t total, const double* W,
+                          void* C, hipStream_t s);
+
+hipError_t launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
+
+// Reduced-precision forms.  The prepass writes A^t (columns of A as rows,
+// rows of A along the contiguous axis, padded with zeros to ldt) converted
+// to bfloat16 hi/lo planes (mode 0) or to scaled OCP e4m3 (mode 1).
+// For mode 1 the per-column power-of-two scales are computed first from the
+// column maxima (partial maxima per 256-row chunk in `part`).
+hipError_t launch_colscale(const float* A, int64_t lda, int m, int n, float* part, float* scale,
+                           hipStream_t s);
+hipError_t launch_prep_lp(int mode, const float* A, int64_t lda, int m, int n, int ldt, const float* scale,
+                          void* out0, void* out1, hipStream_t s);
+hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1, int ldt,
+                          const float* scale, const DevTables& tb, const WorkItem* items, int nitems,
+                          void* C, hipStream_t s);
+
+// Element conversions exposed for verification: mode 0 -> bfloat16 hi/lo
+// (uint16 pairs), mode 1 -> OCP e4m3 bytes (no scaling).
+hipError_t launch_convert(int mode, const float* x, int64_t count, void* out0, void* out1, hipStream_t s);
+
+}  // namespace atalib

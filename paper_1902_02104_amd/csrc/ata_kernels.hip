@@ -1,31 +1,79 @@
 // CDNA4 (gfx950) kernels of the A^t A library.
 //
-// FP64 products use v_mfma_f64_4x4x4_4b with its A operand broadcast to all
-// four blocks, which turns the instruction into a 4 x 16 x 4 product:
-//   A operand: lane l holds A[row = l & 3][k = l >> 4]
-//   B operand: lane l holds B[k = l >> 4][col = l & 15]
-//   result:    lane l holds D[row = l >> 4][col = l & 15]
-// (measured on MI355X: this form sustains about 64 TFLOP/s, the 16x16x4 FP64
-// instruction about 46 TFLOP/s).
-//
 // Every product here is D = X^t Y where X and Y are K x M and K x N column
-// slices of the row-major A (K runs over rows of A), so both operands are
-// staged in LDS as [k][column] rows copied from contiguous rows of A.
+// slices of the row-major A (K runs over rows of A).  The FP64 and FP32 tile
+// kernels stage both operands in LDS as [k][column] rows copied from
+// contiguous rows of A; the reduced-precision kernels read a transposed,
+// converted copy of A made by a prepass, so that every MFMA lane loads
+// k-contiguous bytes.
+//
+// MFMA forms (lane layouts measured on MI355X):
+//  FP64  v_mfma_f64_4x4x4_4b with the A operand broadcast to all four blocks,
+//        i.e. a 4 x 16 x 4 product: A lane l = A[row l&3][k l>>4],
+//        B lane l = B[k l>>4][col l&15], result lane l = D[row l>>4][col l&15].
+//        This form sustains about 64 TFLOP/s; the 16x16x4 FP64 form about 46.
+//  FP32  v_mfma_f32_16x16x4f32: A lane l = A[row l&15][k l>>4], B as above,
+//        result element e of lane l = D[row 4(l>>4)+e][col l&15].
+//  BF16  v_mfma_f32_16x16x32_bf16: lane l holds 8 consecutive k of row (or
+//        column) l&15 starting at k = 8(l>>4); result as FP32.
+//  FP8   v_mfma_scale_f32_16x16x128_f8f6f4 (OCP e4m3 operands, unit scales):
+//        lane l holds 32 consecutive k starting at k = 32(l>>4); result as FP32.
+// The k assignment of the BF16/FP8 forms only has to agree between the two
+// operands, which it does by construction.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
+#include "ata_kernels.h"
 #include "ata_plan.h"
 
 namespace atalib {
 
-typedef double d1_t;
-
-__device__ __forceinline__ double mfma_f64(double a, double b, double c) {
-    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-}
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef int i8_t __attribute__((ext_vector_type(8)));
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int64_t packed_index(int64_t r, int64_t q) { return r * (r + 1) / 2 + q; }
+
+// ---------------------------------------------------------------------------
+// MFMA engines for the tile kernels staged from A directly
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Eng;
+
+template <>
+struct Eng<double> {
+    static constexpr int RM = 4, RN = 16, NA = 1;  // result rows, cols, elements per lane
+    static constexpr int PAD = 4;  // LDS row stride = 4 mod 16 doubles: broadcast reads hit disjoint banks
+    typedef double accv_t;
+    __device__ static int arow(int lane) { return lane & 3; }
+    __device__ static void mma(double a, double b, accv_t& c) { c = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0); }
+    __device__ static double elem(const accv_t& c, int) { return c; }
+    __device__ static int orow(int lane, int) { return lane >> 4; }
+    __device__ static void zero(accv_t& c) { c = 0.0; }
+};
+
+template <>
+struct Eng<float> {
+    static constexpr int RM = 16, RN = 16, NA = 4;
+    static constexpr int PAD = 16;
+    typedef f4_t accv_t;
+    __device__ static int arow(int lane) { return lane & 15; }
+    __device__ static void mma(float a, float b, accv_t& c) { c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static double elem(const accv_t& c, int e) { return (double)c[e]; }
+    __device__ static int orow(int lane, int e) { return 4 * (lane >> 4) + e; }
+    __device__ static void zero(accv_t& c) { c = f4_t{0.f, 0.f, 0.f, 0.f}; }
+};
+
+// FP32 accumulators are added into FP64 every KFLUSH rows of K.
+constexpr int KFLUSH = 512;
+
+template <typename OUT>
+__device__ __forceinline__ void store_out(OUT* p, int beta, double v) {
+    *p = beta ? (OUT)((double)*p + v) : (OUT)v;
+}
 
 // ---------------------------------------------------------------------------
 // Classical tile kernel: TK_SYRK (lower triangle of a diagonal block) and
@@ -34,16 +82,18 @@ __device__ __forceinline__ int64_t packed_index(int64_t r, int64_t q) { return r
 // ---------------------------------------------------------------------------
 constexpr int GT = kGemmTile;  // 128
 constexpr int GK = 16;
-constexpr int GPAD = 4;
 
-__global__ void __launch_bounds__(256, 2) k_gemm_f64(const double* __restrict__ A, int64_t lda,
-                                                  const DevTask* __restrict__ tasks,
-                                                  const DevTerm* __restrict__ terms,
-                                                  const int32_t* __restrict__ segs,
-                                                  const WorkItem* __restrict__ items,
-                                                  double* __restrict__ C) {
-    __shared__ double Xs[2][GK][GT + GPAD];
-    __shared__ double Ys[2][GK][GT + GPAD];
+template <typename T, typename OUT>
+__global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A, int64_t lda,
+                                                 const DevTask* __restrict__ tasks,
+                                                 const DevTerm* __restrict__ terms,
+                                                 const int32_t* __restrict__ segs,
+                                                 const WorkItem* __restrict__ items, OUT* __restrict__ C) {
+    typedef Eng<T> E;
+    constexpr bool F32 = std::is_same<T, float>::value;
+    constexpr int BR = 64 / E::RM, BC = 64 / E::RN;
+    __shared__ T Xs[2][GK][GT + E::PAD];
+    __shared__ T Ys[2][GK][GT + E::PAD];
 
     const WorkItem w = items[blockIdx.x];
     const DevTask t = tasks[w.task];
@@ -60,11 +110,20 @@ __global__ void __launch_bounds__(256, 2) k_gemm_f64(const double* __restrict__ 
     const int xcv = tx.cvend - xcol;  // columns valid from xcol (may be <= 0)
     const int ycv = ty.cvend - ycol;
 
-    double acc[16][4];
+    typename E::accv_t acc[BR][BC];
+    double acc64[F32 ? BR : 1][F32 ? BC : 1][F32 ? E::NA : 1];
 #pragma unroll
-    for (int a = 0; a < 16; ++a)
+    for (int a = 0; a < BR; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int b = 0; b < BC; ++b) E::zero(acc[a][b]);
+    if (F32) {
+#pragma unroll
+        for (int a = 0; a < (F32 ? BR : 1); ++a)
+#pragma unroll
+            for (int b = 0; b < (F32 ? BC : 1); ++b)
+#pragma unroll
+                for (int e = 0; e < (F32 ? E::NA : 1); ++e) acc64[a][b][e] = 0.0;
+    }
 
     // k-tile cursor over the segments
     const int stride = 1 + 2 * (t.nx + t.ny);
@@ -75,15 +134,15 @@ __global__ void __launch_bounds__(256, 2) k_gemm_f64(const double* __restrict__ 
     int ntiles = 0;
     for (int s = 0; s < t.nseg; ++s) ntiles += (segs[t.seg_off + s * stride] + GK - 1) / GK;
 
-    double xr[8], yr[8];
+    T xr[8], yr[8];
     auto load = [&](int kk0, int kl, int xr0, int yr0) {
         const bool rv = (kk0 + lk) < kl;
-        const double* px = A + (int64_t)(xr0 + kk0 + lk) * lda + xcol;
-        const double* py = A + (int64_t)(yr0 + kk0 + lk) * lda + ycol;
+        const T* px = A + (int64_t)(xr0 + kk0 + lk) * lda + xcol;
+        const T* py = A + (int64_t)(yr0 + kk0 + lk) * lda + ycol;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            xr[e] = (rv && e < xcv) ? px[e] : 0.0;
-            yr[e] = (rv && e < ycv) ? py[e] : 0.0;
+            xr[e] = (rv && e < xcv) ? px[e] : T(0);
+            yr[e] = (rv && e < ycv) ? py[e] : T(0);
         }
     };
     auto advance = [&]() {
@@ -115,31 +174,44 @@ __global__ void __launch_bounds__(256, 2) k_gemm_f64(const double* __restrict__ 
 #pragma unroll
         for (int ks = 0; ks < GK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
-            double bv[4];
+            T bv[BC];
 #pragma unroll
-            for (int cf = 0; cf < 4; ++cf) bv[cf] = Ys[buf][kr][wn * 64 + cf * 16 + (lane & 15)];
+            for (int cf = 0; cf < BC; ++cf) bv[cf] = Ys[buf][kr][wn * 64 + cf * E::RN + (lane & 15)];
 #pragma unroll
-            for (int rf = 0; rf < 16; ++rf) {
-                const double av = Xs[buf][kr][wm * 64 + rf * 4 + (lane & 3)];
+            for (int rb = 0; rb < BR; ++rb) {
+                const T av = Xs[buf][kr][wm * 64 + rb * E::RM + E::arow(lane)];
 #pragma unroll
-                for (int cf = 0; cf < 4; ++cf) acc[rf][cf] = mfma_f64(av, bv[cf], acc[rf][cf]);
+                for (int cf = 0; cf < BC; ++cf) E::mma(av, bv[cf], acc[rb][cf]);
             }
+        }
+        if (F32 && (((it + 1) * GK) % KFLUSH == 0 || it + 1 == ntiles)) {
+#pragma unroll
+            for (int a = 0; a < BR; ++a)
+#pragma unroll
+                for (int b = 0; b < BC; ++b) {
+#pragma unroll
+                    for (int e = 0; e < E::NA; ++e) acc64[F32 ? a : 0][F32 ? b : 0][F32 ? e : 0] += E::elem(acc[a][b], e);
+                    E::zero(acc[a][b]);
+                }
         }
     }
 
     // epilogue: rows of D go to C rows r0 + gi, columns to C columns q0 + gj
     const bool syrk = t.kind == TK_SYRK;
 #pragma unroll
-    for (int rf = 0; rf < 16; ++rf) {
-        const int gi = i0 + wm * 64 + rf * 4 + (lane >> 4);
-        if (gi >= t.dM) continue;
-        const int64_t rowbase = packed_index((int64_t)t.r0 + gi, t.q0);
+    for (int rb = 0; rb < BR; ++rb) {
 #pragma unroll
-        for (int cf = 0; cf < 4; ++cf) {
-            const int gj = j0 + wn * 64 + cf * 16 + (lane & 15);
-            if (gj >= t.dN || (syrk && gj > gi)) continue;
-            double* p = C + rowbase + gj;
-            *p = t.beta ? *p + acc[rf][cf] : acc[rf][cf];
+        for (int e = 0; e < E::NA; ++e) {
+            const int gi = i0 + wm * 64 + rb * E::RM + E::orow(lane, e);
+            if (gi >= t.dM) continue;
+            const int64_t rowbase = packed_index((int64_t)t.r0 + gi, t.q0);
+#pragma unroll
+            for (int cf = 0; cf < BC; ++cf) {
+                const int gj = j0 + wn * 64 + cf * E::RN + (lane & 15);
+                if (gj >= t.dN || (syrk && gj > gi)) continue;
+                const double v = F32 ? acc64[F32 ? rb : 0][F32 ? cf : 0][F32 ? e : 0] : E::elem(acc[rb][cf], e);
+                store_out(C + rowbase + gj, t.beta, v);
+            }
         }
     }
 }
@@ -147,16 +219,16 @@ __global__ void __launch_bounds__(256, 2) k_gemm_f64(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // In-tile Strassen kernel (TK_STR).  The product P = Xop^t Yop (padded M x N,
 // K per segment) is split once more into quadrants; a workgroup owns the
-// 64 x 64 tile at (ti, tj) of all four result quadrants, keeps the seven
-// products in registers (four waves of 32 x 32 each) and combines them at the
-// end.  Operand terms of higher levels are summed while staging to LDS.
+// 64 x 64 tile at (ti, tj) of all four result quadrants and keeps the seven
+// products in registers (eight waves of 16 x 32 each).  Operand terms of
+// higher levels are summed while staging to LDS; the quadrant sums of this
+// level are formed in registers from the four staged quadrant tiles.  The
+// products are combined in FP64.
 // ---------------------------------------------------------------------------
 constexpr int ST = kStrTile;  // 64
-constexpr int SK_MAX = 16;  // k rows per LDS stage (8 when operands carry several terms)
-constexpr int SPAD = 4;  // row stride = 4 mod 16 doubles: broadcast reads hit disjoint banks
 
-template <int VAR>
-__device__ __forceinline__ void left_operands(double x00, double x01, double x10, double x11, double (&o)[7]) {
+template <int VAR, typename T>
+__device__ __forceinline__ void left_operands(T x00, T x01, T x10, T x11, T (&o)[7]) {
     // x_ab = L_ab (M-half a, K-half b)
     if (VAR == 0) {
         o[0] = x00 + x11;
@@ -167,7 +239,7 @@ __device__ __forceinline__ void left_operands(double x00, double x01, double x10
         o[5] = x10 - x00;
         o[6] = x01 - x11;
     } else {
-        const double s1 = x10 + x11, s2 = s1 - x00;
+        const T s1 = x10 + x11, s2 = s1 - x00;
         o[0] = x00;
         o[1] = x01;
         o[2] = x01 - s2;
@@ -178,8 +250,8 @@ __device__ __forceinline__ void left_operands(double x00, double x01, double x10
     }
 }
 
-template <int VAR>
-__device__ __forceinline__ void right_operands(double y00, double y01, double y10, double y11, double (&o)[7]) {
+template <int VAR, typename T>
+__device__ __forceinline__ void right_operands(T y00, T y01, T y10, T y11, T (&o)[7]) {
     // y_bc = R_bc (K-half b, N-half c)
     if (VAR == 0) {
         o[0] = y00 + y11;
@@ -190,7 +262,7 @@ __device__ __forceinline__ void right_operands(double y00, double y01, double y1
         o[5] = y00 + y01;
         o[6] = y10 + y11;
     } else {
-        const double t1 = y01 - y00, t2 = y11 - t1;
+        const T t1 = y01 - y00, t2 = y11 - t1;
         o[0] = y00;
         o[1] = y10;
         o[2] = y11;
@@ -217,15 +289,18 @@ __device__ __forceinline__ void combine_products(const double (&m)[7], double (&
     }
 }
 
-template <int VAR, int TMAX, int SK>
-__global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A, int64_t lda,
-                                                    const DevTask* __restrict__ tasks,
-                                                    const DevTerm* __restrict__ terms,
-                                                    const int32_t* __restrict__ segs,
-                                                    const WorkItem* __restrict__ items,
-                                                    double* __restrict__ C, double* __restrict__ W) {
-    __shared__ double Xs[2][4][SK][ST + SPAD];
-    __shared__ double Ys[2][4][SK][ST + SPAD];
+template <typename T, typename OUT, int VAR, int TMAX, int SK>
+__global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t lda,
+                                                const DevTask* __restrict__ tasks,
+                                                const DevTerm* __restrict__ terms,
+                                                const int32_t* __restrict__ segs,
+                                                const WorkItem* __restrict__ items, OUT* __restrict__ C,
+                                                double* __restrict__ W) {
+    typedef Eng<T> E;
+    constexpr bool F32 = std::is_same<T, float>::value;
+    constexpr int BR = 16 / E::RM, BC = 32 / E::RN;
+    __shared__ T Xs[2][4][SK][ST + E::PAD];
+    __shared__ T Ys[2][4][SK][ST + E::PAD];
 
     const WorkItem w = items[blockIdx.x];
     const DevTask t = tasks[w.task];
@@ -235,22 +310,22 @@ __global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A
     const int i0 = w.ti * ST, j0 = w.tj * ST;
     const int stride = 1 + 2 * (t.nx + t.ny);
 
-    // staging map: thread -> k rows lk and lk + 8, column lc (two elements per quadrant)
+    // staging map: thread -> k rows lk + 8r, column lc (one element per quadrant and row)
     const int lk = tid >> 6, lc = tid & 63;
-    constexpr int KR = SK / 8;  // k rows per thread
+    constexpr int KR = SK / 8;
 
     // Per-term column data, fixed for the whole K loop.
     int xcol[TMAX][2], ycol[TMAX][2];
-    unsigned xmask[TMAX], ymask[TMAX];  // bit a: column of M-half a valid
-    double xsgn[TMAX], ysgn[TMAX];
+    unsigned xmask[TMAX], ymask[TMAX];  // bit a: column of half a valid
+    T xsgn[TMAX], ysgn[TMAX];
 #pragma unroll
     for (int u = 0; u < TMAX; ++u) {
         xmask[u] = ymask[u] = 0u;
-        xsgn[u] = ysgn[u] = 0.0;
+        xsgn[u] = ysgn[u] = T(0);
         xcol[u][0] = xcol[u][1] = ycol[u][0] = ycol[u][1] = 0;
         if (u < t.nx) {
             const DevTerm tm = terms[t.term_off + u];
-            xsgn[u] = (double)tm.sign;
+            xsgn[u] = (T)tm.sign;
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 xcol[u][a] = tm.col + a * MH + i0 + lc;
@@ -259,7 +334,7 @@ __global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A
         }
         if (u < t.ny) {
             const DevTerm tm = terms[t.term_off + t.nx + u];
-            ysgn[u] = (double)tm.sign;
+            ysgn[u] = (T)tm.sign;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 ycol[u][c] = tm.col + c * NH + j0 + lc;
@@ -268,13 +343,19 @@ __global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A
         }
     }
 
-    double acc[7][4][2];
+    typename E::accv_t acc[7][BR][BC];
+    double acc64[F32 ? 7 : 1][F32 ? BR : 1][F32 ? BC : 1][F32 ? E::NA : 1];
 #pragma unroll
     for (int p = 0; p < 7; ++p)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < BR; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[p][a][b] = 0.0;
+            for (int b = 0; b < BC; ++b) {
+                E::zero(acc[p][a][b]);
+                if (F32)
+#pragma unroll
+                    for (int e = 0; e < E::NA; ++e) acc64[F32 ? p : 0][F32 ? a : 0][F32 ? b : 0][F32 ? e : 0] = 0.0;
+            }
 
     int ntiles = 0;
     for (int s = 0; s < t.nseg; ++s) {
@@ -282,8 +363,8 @@ __global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A
         ntiles += (kh + SK - 1) / SK;
     }
 
-    // raw term values of the next k tile: [term][quad]
-    double xraw[TMAX][KR][4], yraw[TMAX][KR][4];
+    // raw term values of the next k tile: [term][row][quad]
+    T xraw[TMAX][KR][4], yraw[TMAX][KR][4];
     int seg = 0, k0 = 0;
     int kh = t.nseg > 0 ? (segs[t.seg_off] + 1) >> 1 : 0;
 
@@ -302,14 +383,14 @@ __global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A
                     for (int b = 0; b < 2; ++b) {
                         const int row = row0 + b * kh + kk;
                         const bool rok = kv && row < rvend;
-                        const double* pr = A + (int64_t)row * lda;
+                        const T* pr = A + (int64_t)row * lda;
 #pragma unroll
                         for (int a = 0; a < 2; ++a)
-                            xraw[u][r][a * 2 + b] = (rok && ((xmask[u] >> a) & 1u)) ? pr[xcol[u][a]] : 0.0;
+                            xraw[u][r][a * 2 + b] = (rok && ((xmask[u] >> a) & 1u)) ? pr[xcol[u][a]] : T(0);
                     }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) xraw[u][r][q] = 0.0;
+                    for (int q = 0; q < 4; ++q) xraw[u][r][q] = T(0);
                 }
                 if (u < t.ny) {
                     const int row0 = sg[1 + 2 * (t.nx + u)], rvend = sg[2 + 2 * (t.nx + u)];
@@ -317,14 +398,14 @@ __global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A
                     for (int b = 0; b < 2; ++b) {
                         const int row = row0 + b * kh + kk;
                         const bool rok = kv && row < rvend;
-                        const double* pr = A + (int64_t)row * lda;
+                        const T* pr = A + (int64_t)row * lda;
 #pragma unroll
                         for (int c = 0; c < 2; ++c)
-                            yraw[u][r][b * 2 + c] = (rok && ((ymask[u] >> c) & 1u)) ? pr[ycol[u][c]] : 0.0;
+                            yraw[u][r][b * 2 + c] = (rok && ((ymask[u] >> c) & 1u)) ? pr[ycol[u][c]] : T(0);
                     }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) yraw[u][r][q] = 0.0;
+                    for (int q = 0; q < 4; ++q) yraw[u][r][q] = T(0);
                 }
             }
         }
@@ -335,7 +416,7 @@ __global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A
         for (int r = 0; r < KR; ++r)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                double x = 0.0, y = 0.0;
+                T x = T(0), y = T(0);
 #pragma unroll
                 for (int u = 0; u < TMAX; ++u) {
                     x += xsgn[u] * xraw[u][r][q];
@@ -366,48 +447,63 @@ __global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A
 #pragma unroll
         for (int ks = 0; ks < SK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
-            double ro[2][7];
+            T ro[BC][7];
 #pragma unroll
-            for (int cf = 0; cf < 2; ++cf) {
-                const int cc = wn * 32 + cf * 16 + (lane & 15);
+            for (int cf = 0; cf < BC; ++cf) {
+                const int cc = wn * 32 + cf * E::RN + (lane & 15);
                 right_operands<VAR>(Ys[buf][0][kr][cc], Ys[buf][1][kr][cc], Ys[buf][2][kr][cc],
                                     Ys[buf][3][kr][cc], ro[cf]);
             }
 #pragma unroll
-            for (int rf = 0; rf < 4; ++rf) {
-                const int rr = wm * 16 + rf * 4 + (lane & 3);
-                double lo[7];
+            for (int rb = 0; rb < BR; ++rb) {
+                const int rr = wm * 16 + rb * E::RM + E::arow(lane);
+                T lo[7];
                 left_operands<VAR>(Xs[buf][0][kr][rr], Xs[buf][1][kr][rr], Xs[buf][2][kr][rr],
                                    Xs[buf][3][kr][rr], lo);
 #pragma unroll
                 for (int p = 0; p < 7; ++p)
 #pragma unroll
-                    for (int cf = 0; cf < 2; ++cf) acc[p][rf][cf] = mfma_f64(lo[p], ro[cf][p], acc[p][rf][cf]);
+                    for (int cf = 0; cf < BC; ++cf) E::mma(lo[p], ro[cf][p], acc[p][rb][cf]);
             }
+        }
+        if (F32 && (((it + 1) * SK) % KFLUSH == 0 || it + 1 == ntiles)) {
+#pragma unroll
+            for (int p = 0; p < 7; ++p)
+#pragma unroll
+                for (int a = 0; a < BR; ++a)
+#pragma unroll
+                    for (int b = 0; b < BC; ++b) {
+#pragma unroll
+                        for (int e = 0; e < E::NA; ++e)
+                            acc64[F32 ? p : 0][F32 ? a : 0][F32 ? b : 0][F32 ? e : 0] += E::elem(acc[p][a][b], e);
+                        E::zero(acc[p][a][b]);
+                    }
         }
     }
 
-    // combine the seven products into the four quadrants and store
+    // combine the seven products (FP64) into the four quadrants and store
 #pragma unroll
-    for (int rf = 0; rf < 4; ++rf) {
-        const int li = i0 + wm * 16 + rf * 4 + (lane >> 4);  // row inside a quadrant
+    for (int rb = 0; rb < BR; ++rb) {
 #pragma unroll
-        for (int cf = 0; cf < 2; ++cf) {
-            const int lj = j0 + wn * 32 + cf * 16 + (lane & 15);
-            double m[7], d[4];
+        for (int e = 0; e < E::NA; ++e) {
+            const int li = i0 + wm * 16 + rb * E::RM + E::orow(lane, e);  // row inside a quadrant
 #pragma unroll
-            for (int p = 0; p < 7; ++p) m[p] = acc[p][rf][cf];
-            combine_products<VAR>(m, d);
-            if (li >= MH || lj >= NH) continue;
+            for (int cf = 0; cf < BC; ++cf) {
+                const int lj = j0 + wn * 32 + cf * E::RN + (lane & 15);
+                double m[7], d[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int gi = (q >> 1) * MH + li, gj = (q & 1) * NH + lj;
-                if (gi >= t.dM || gj >= t.dN) continue;
-                if (t.dst == 0) {
-                    double* p = C + packed_index((int64_t)t.r0 + gi, t.q0) + gj;
-                    *p = t.beta ? *p + d[q] : d[q];
-                } else {
-                    W[t.ws_off + (int64_t)gi * t.N + gj] = d[q];
+                for (int p = 0; p < 7; ++p)
+                    m[p] = F32 ? acc64[F32 ? p : 0][F32 ? rb : 0][F32 ? cf : 0][F32 ? e : 0] : E::elem(acc[p][rb][cf], e);
+                combine_products<VAR>(m, d);
+                if (li >= MH || lj >= NH) continue;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int gi = (q >> 1) * MH + li, gj = (q & 1) * NH + lj;
+                    if (gi >= t.dM || gj >= t.dN) continue;
+                    if (t.dst == 0)
+                        store_out(C + packed_index((int64_t)t.r0 + gi, t.q0) + gj, t.beta, d[q]);
+                    else
+                        W[t.ws_off + (int64_t)gi * t.N + gj] = d[q];
                 }
             }
         }
@@ -416,13 +512,13 @@ __global__ void __launch_bounds__(512, 1) k_str_f64(const double* __restrict__ A
 
 // ---------------------------------------------------------------------------
 // Combination of workspace products into an off-diagonal block of packed C.
-// One thread per output element; fixed summation order.
+// One thread per output element; fixed summation order; FP64.
 // ---------------------------------------------------------------------------
 __constant__ int c_dcoef[2][7][4] = ATA_D_COEF;
 
-__global__ void __launch_bounds__(256) k_combine_f64(const DevCombine* __restrict__ cbs, int ncb,
-                                                     int64_t total, const double* __restrict__ W,
-                                                     double* __restrict__ C) {
+template <typename OUT>
+__global__ void __launch_bounds__(256) k_combine(const DevCombine* __restrict__ cbs, int ncb, int64_t total,
+                                                 const double* __restrict__ W, OUT* __restrict__ C) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     int lo = 0, hi = ncb - 1;
@@ -458,8 +554,7 @@ __global__ void __launch_bounds__(256) k_combine_f64(const DevCombine* __restric
         }
         if (coef) s += coef > 0 ? base[path * slot_elems] : -base[path * slot_elems];
     }
-    double* p = C + packed_index((int64_t)cb.r0 + i, cb.q0) + j;
-    *p = cb.beta ? *p + s : s;
+    store_out(C + packed_index((int64_t)cb.r0 + i, cb.q0) + j, cb.beta, s);
 }
 
 template <typename T>
@@ -469,48 +564,397 @@ __global__ void k_fill_zero(T* __restrict__ p, int64_t count) {
 }
 
 // ---------------------------------------------------------------------------
-// Host-side launchers (called from the C ABI layer)
+// Reduced-precision forms: conversions
 // ---------------------------------------------------------------------------
-hipError_t launch_gemm_f64(const double* A, int64_t lda, const DevTask* tasks, const DevTerm* terms,
-                           const int32_t* segs, const WorkItem* items, int nitems, double* C,
-                           hipStream_t s) {
+// binary32 -> bfloat16, round to nearest even (bfloat16 keeps the top 16
+// bits of binary32); NaN stays NaN.
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// binary32 -> OCP FP8 e4m3 (bias 7, 3 mantissa bits, no infinities, largest
+// finite 448), round to nearest even, saturating to +-448.
+__device__ __forceinline__ uint8_t e4m3_rne(float x) {
+    const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+    const float a = fabsf(x);
+    if (!(a == a)) return (uint8_t)(sign | 0x7fu);
+    if (a >= 448.0f) return (uint8_t)(sign | 0x7eu);
+    if (a < 0.015625f) {  // below 2^-6: subnormal steps of 2^-9
+        const float q = __builtin_rintf(a * 512.0f);  // exact scaling, then RNE
+        return (uint8_t)(sign | (uint32_t)q);          // q == 8 encodes 2^-6 (exponent field 1)
+    }
+    int e = (int)((__float_as_uint(a) >> 23) & 0xffu) - 127;  // a = 1.f * 2^e, e in [-6, 8]
+    const float mant = a * __builtin_ldexpf(1.0f, -e);         // [1, 2), exact
+    float q = __builtin_rintf((mant - 1.0f) * 8.0f);           // exact scaling, then RNE
+    if (q >= 8.0f) {
+        q = 0.0f;
+        ++e;
+    }
+    if (e > 8 || (e == 8 && q >= 7.0f)) return (uint8_t)(sign | 0x7eu);
+    return (uint8_t)(sign | ((uint32_t)(e + 7) << 3) | (uint32_t)q);
+}
+
+__global__ void k_convert(int mode, const float* __restrict__ x, int64_t count, void* __restrict__ o0,
+                          void* __restrict__ o1) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float v = x[i];
+    if (mode == 0) {
+        const uint16_t h = bf16_rne(v);
+        const float hf = __uint_as_float((uint32_t)h << 16);
+        ((uint16_t*)o0)[i] = h;
+        ((uint16_t*)o1)[i] = bf16_rne(v - hf);
+    } else {
+        ((uint8_t*)o0)[i] = e4m3_rne(v);
+    }
+}
+
+// Column maxima of |A| in 256-row chunks, then power-of-two scales
+// s_j = 2^floor(log2(448 / max_j)) (1 for a zero column).
+__global__ void __launch_bounds__(256) k_colmax_part(const float* __restrict__ A, int64_t lda, int m, int n,
+                                                     float* __restrict__ part) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int chunk = blockIdx.y;
+    if (j >= n) return;
+    const int r0 = chunk * 256, r1 = min(m, r0 + 256);
+    float mx = 0.0f;
+    for (int r = r0; r < r1; ++r) mx = fmaxf(mx, fabsf(A[(int64_t)r * lda + j]));
+    part[(int64_t)chunk * n + j] = mx;
+}
+
+__global__ void __launch_bounds__(256) k_colscale(const float* __restrict__ part, int nchunks, int n,
+                                                  float* __restrict__ scale) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    float mx = 0.0f;
+    for (int c = 0; c < nchunks; ++c) mx = fmaxf(mx, part[(int64_t)c * n + j]);
+    float s = 1.0f;
+    if (mx > 0.0f) {
+        // largest power of two s with s * mx <= 448: 448 / mx = f 2^e, f in [0.5, 1)
+        int e;
+        (void)frexpf(448.0f / mx, &e);
+        s = __builtin_ldexpf(1.0f, e - 1);
+        if (s * mx > 448.0f) s *= 0.5f;  // guard against the rounding of 448 / mx
+    }
+    scale[j] = s;
+}
+
+// Transposed, converted copy of A: out[i * ldt + k] for column i of A and
+// row k (k >= m zero).  64 x 64 tiles through LDS.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_prep_lp(const float* __restrict__ A, int64_t lda, int m, int n, int ldt,
+                                                 const float* __restrict__ scale, void* __restrict__ o0,
+                                                 void* __restrict__ o1) {
+    __shared__ float tile[64][65];
+    const int k0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+    for (int r = ty; r < 64; r += 4) {
+        const int k = k0 + r, c = c0 + tx;
+        float v = 0.0f;
+        if (k < m && c < n) {
+            v = A[(int64_t)k * lda + c];
+            if (MODE == 1) v *= scale[c];  // exact: power-of-two scale
+        }
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int c = c0 + r, k = k0 + tx;
+        if (c >= n || k >= ldt) continue;
+        const float v = tile[tx][r];
+        const int64_t o = (int64_t)c * ldt + k;
+        if (MODE == 0) {
+            const uint16_t h = bf16_rne(v);
+            const float hf = __uint_as_float((uint32_t)h << 16);
+            ((uint16_t*)o0)[o] = h;
+            ((uint16_t*)o1)[o] = bf16_rne(v - hf);
+        } else {
+            ((uint8_t*)o0)[o] = e4m3_rne(v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduced-precision classical tiles (TK_SYRK / TK_GEMM) on the transposed
+// copy: 128 x 128 output tile, four waves of 64 x 64 (4 x 4 blocks of
+// 16 x 16), FP32 MFMA accumulation added into FP64 every KFLUSH rows.
+//   MODE 0: bfloat16 split, hi^t hi + hi^t lo + lo^t hi per block; 64 k per stage
+//   MODE 1: e4m3, 128 k per stage; result de-scaled by 1 / (s_i s_j)
+// Rows of the copy are columns of A; the k range of a segment is its row range.
+// ---------------------------------------------------------------------------
+template <int MODE>
+struct LpCfg;
+template <>
+struct LpCfg<0> {
+    static constexpr int KT = 64;              // k per LDS stage (elements)
+    static constexpr int EB = 2;               // bytes per element
+    static constexpr int PLANES = 2;           // hi, lo
+    static constexpr int ROWB = KT * EB + 16;  // LDS row stride in bytes (padded)
+};
+template <>
+struct LpCfg<1> {
+    static constexpr int KT = 128;
+    static constexpr int EB = 1;
+    static constexpr int PLANES = 1;
+    static constexpr int ROWB = KT * EB + 16;
+};
+
+template <int MODE, typename OUT>
+__global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0, const uint8_t* __restrict__ T1,
+                                                    int ldt, const float* __restrict__ scale,
+                                                    const DevTask* __restrict__ tasks,
+                                                    const DevTerm* __restrict__ terms,
+                                                    const int32_t* __restrict__ segs,
+                                                    const WorkItem* __restrict__ items, OUT* __restrict__ C) {
+    typedef LpCfg<MODE> L;
+    constexpr int KT = L::KT, EB = L::EB, PL = L::PLANES, ROWB = L::ROWB;
+    constexpr int ROWBYTES = KT * EB;           // bytes of one tile row per stage
+    constexpr int CHUNKS = GT * ROWBYTES / 16;  // 16-byte chunks per plane and operand
+    constexpr int CPT = CHUNKS / 256;           // chunks per thread per plane and operand
+    __shared__ __attribute__((aligned(16))) uint8_t Xs[PL][GT * ROWB];
+    __shared__ __attribute__((aligned(16))) uint8_t Ys[PL][GT * ROWB];
+
+    const WorkItem w = items[blockIdx.x];
+    const DevTask t = tasks[w.task];
+    const DevTerm tx = terms[t.term_off];
+    const DevTerm ty = terms[t.term_off + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int i0 = w.ti * GT, j0 = w.tj * GT;
+    const int stride = 1 + 2 * (t.nx + t.ny);
+
+    f4_t acc[4][4];
+    double acc64[4][4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc64[a][b][e] = 0.0;
+        }
+
+    int ntiles = 0;
+    for (int s = 0; s < t.nseg; ++s) ntiles += (segs[t.seg_off + s * stride] + KT - 1) / KT;
+
+    // staged chunks: [plane][operand][chunk]
+    u4_t rg[PL][2][CPT];
+    int seg = 0, k0 = 0;
+    int klen = t.nseg > 0 ? segs[t.seg_off] : 0;
+    int krow = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
+
+    auto load = [&]() {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int ch = tid + 256 * c;
+            const int r = ch / (ROWBYTES / 16);               // tile row
+            const int kb = (ch % (ROWBYTES / 16)) * 16 / EB;  // first k of the chunk
+            const int kk = k0 + kb;                            // k offset inside the segment
+#pragma unroll
+            for (int op = 0; op < 2; ++op) {
+                const int tcol = op == 0 ? tx.col : ty.col;
+                const int tend = op == 0 ? tx.cvend : ty.cvend;
+                const int row = tcol + (op == 0 ? i0 : j0) + r;  // column of A = row of the copy
+                const bool rv = row < tend;
+                const int64_t base = (int64_t)row * ldt + krow + kk;
+                const int nval = klen - kk;  // valid elements from kk
+#pragma unroll
+                for (int p = 0; p < PL; ++p) {
+                    u4_t v = u4_t{0u, 0u, 0u, 0u};
+                    if (rv && nval > 0) {
+                        const uint8_t* src = (p == 0 ? T0 : T1) + base * EB;
+                        if (nval >= 16 / EB && (((uintptr_t)src) & 15u) == 0) {
+                            v = *(const u4_t*)src;
+                        } else {
+                            unsigned wd[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                            for (int q = 0; q < 16; ++q)
+                                if (q / EB < nval) wd[q >> 2] |= (unsigned)src[q] << (8 * (q & 3));
+                            v = u4_t{wd[0], wd[1], wd[2], wd[3]};
+                        }
+                    }
+                    rg[p][op][c] = v;
+                }
+            }
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int ch = tid + 256 * c;
+            const int r = ch / (ROWBYTES / 16);
+            const int off = r * ROWB + (ch % (ROWBYTES / 16)) * 16;
+#pragma unroll
+            for (int p = 0; p < PL; ++p) {
+                *(u4_t*)(&Xs[p][off]) = rg[p][0][c];
+                *(u4_t*)(&Ys[p][off]) = rg[p][1][c];
+            }
+        }
+    };
+    auto advance = [&]() {
+        k0 += KT;
+        if (k0 >= klen) {
+            k0 = 0;
+            ++seg;
+            if (seg < t.nseg) {
+                klen = segs[t.seg_off + seg * stride];
+                krow = segs[t.seg_off + seg * stride + 1];
+            }
+        }
+    };
+
+    if (ntiles > 0) load();
+    for (int it = 0; it < ntiles; ++it) {
+        __syncthreads();  // previous stage fully read
+        store();
+        __syncthreads();
+        if (it + 1 < ntiles) {
+            advance();
+            load();
+        }
+        const int rsel = lane & 15, kq = lane >> 4;
+        if (MODE == 0) {
+#pragma unroll
+            for (int ks = 0; ks < KT / 32; ++ks) {
+                const int kb = (ks * 32 + kq * 8) * EB;
+                bf8_t bh[4], bl[4];
+#pragma unroll
+                for (int cf = 0; cf < 4; ++cf) {
+                    const int rr = wn * 64 + cf * 16 + rsel;
+                    bh[cf] = *(const bf8_t*)(&Ys[0][rr * ROWB + kb]);
+                    bl[cf] = *(const bf8_t*)(&Ys[PL - 1][rr * ROWB + kb]);
+                }
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const int rr = wm * 64 + rb * 16 + rsel;
+                    const bf8_t ah = *(const bf8_t*)(&Xs[0][rr * ROWB + kb]);
+                    const bf8_t al = *(const bf8_t*)(&Xs[PL - 1][rr * ROWB + kb]);
+#pragma unroll
+                    for (int cf = 0; cf < 4; ++cf) {
+                        acc[rb][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cf], acc[rb][cf], 0, 0, 0);
+                        acc[rb][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cf], acc[rb][cf], 0, 0, 0);
+                        acc[rb][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cf], acc[rb][cf], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            const int kb = kq * 32;
+            i8_t bq[4];
+#pragma unroll
+            for (int cf = 0; cf < 4; ++cf) {
+                const int rr = wn * 64 + cf * 16 + rsel;
+                bq[cf] = *(const i8_t*)(&Ys[0][rr * ROWB + kb]);
+            }
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int rr = wm * 64 + rb * 16 + rsel;
+                const i8_t aq = *(const i8_t*)(&Xs[0][rr * ROWB + kb]);
+#pragma unroll
+                for (int cf = 0; cf < 4; ++cf)
+                    acc[rb][cf] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aq, bq[cf], acc[rb][cf], 0, 0, 0,
+                                                                                  0, 0, 0);
+            }
+        }
+        if (((it + 1) * KT) % KFLUSH == 0 || it + 1 == ntiles) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc64[a][b][e] += (double)acc[a][b][e];
+                    acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+    }
+
+    const bool syrk = t.kind == TK_SYRK;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int gi = i0 + wm * 64 + rb * 16 + 4 * (lane >> 4) + e;
+            if (gi >= t.dM) continue;
+            const int64_t rowbase = packed_index((int64_t)t.r0 + gi, t.q0);
+            const double si = MODE == 1 ? 1.0 / (double)scale[tx.col + gi] : 1.0;
+#pragma unroll
+            for (int cf = 0; cf < 4; ++cf) {
+                const int gj = j0 + wn * 64 + cf * 16 + (lane & 15);
+                if (gj >= t.dN || (syrk && gj > gi)) continue;
+                double v = acc64[rb][cf][e];
+                if (MODE == 1) v = v * si / (double)scale[ty.col + gj];  // exact power-of-two de-scale
+                store_out(C + rowbase + gj, t.beta, v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
+                       const WorkItem* items, int nitems, void* C, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gemm_f64, dim3(nitems), dim3(256), 0, s, A, lda, tasks, terms, segs, items, C);
+    const dim3 g(nitems), b(256);
+    if (!f32)
+        hipLaunchKernelGGL((k_gemm<double, double>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.terms, tb.segs,
+                           items, (double*)C);
+    else if (out_f64)
+        hipLaunchKernelGGL((k_gemm<float, double>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms, tb.segs,
+                           items, (double*)C);
+    else
+        hipLaunchKernelGGL((k_gemm<float, float>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms, tb.segs,
+                           items, (float*)C);
     return hipGetLastError();
 }
 
-template <int VAR>
-static void launch_str_var(int tmax, dim3 g, hipStream_t s, const double* A, int64_t lda, const DevTask* tasks,
-                           const DevTerm* terms, const int32_t* segs, const WorkItem* items, double* C,
-                           double* W) {
+template <typename T, typename OUT, int VAR>
+static void launch_str_t(int tmax, dim3 g, hipStream_t s, const T* A, int64_t lda, const DevTables& tb,
+                         const WorkItem* items, OUT* C, double* W) {
+    const dim3 b(512);
     if (tmax <= 1)
-        hipLaunchKernelGGL((k_str_f64<VAR, 1, 16>), g, dim3(512), 0, s, A, lda, tasks, terms, segs, items, C, W);
+        hipLaunchKernelGGL((k_str<T, OUT, VAR, 1, 16>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W);
     else if (tmax <= 2)
-        hipLaunchKernelGGL((k_str_f64<VAR, 2, 8>), g, dim3(512), 0, s, A, lda, tasks, terms, segs, items, C, W);
+        hipLaunchKernelGGL((k_str<T, OUT, VAR, 2, 8>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W);
     else if (tmax <= 4)
-        hipLaunchKernelGGL((k_str_f64<VAR, 4, 8>), g, dim3(512), 0, s, A, lda, tasks, terms, segs, items, C, W);
+        hipLaunchKernelGGL((k_str<T, OUT, VAR, 4, 8>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W);
     else
-        hipLaunchKernelGGL((k_str_f64<VAR, 8, 8>), g, dim3(512), 0, s, A, lda, tasks, terms, segs, items, C, W);
+        hipLaunchKernelGGL((k_str<T, OUT, VAR, 8, 8>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W);
 }
 
-// tmax: largest number of terms of either operand over the launched tasks.
-hipError_t launch_str_f64(int variant, int tmax, const double* A, int64_t lda, const DevTask* tasks,
-                          const DevTerm* terms, const int32_t* segs, const WorkItem* items, int nitems,
-                          double* C, double* W, hipStream_t s) {
+template <typename T, typename OUT>
+static void launch_str_v(int variant, int tmax, dim3 g, hipStream_t s, const T* A, int64_t lda, const DevTables& tb,
+                         const WorkItem* items, OUT* C, double* W) {
+    if (variant == 0)
+        launch_str_t<T, OUT, 0>(tmax, g, s, A, lda, tb, items, C, W);
+    else
+        launch_str_t<T, OUT, 1>(tmax, g, s, A, lda, tb, items, C, W);
+}
+
+hipError_t launch_str(bool f32, bool out_f64, int variant, int tmax, const void* A, int64_t lda,
+                      const DevTables& tb, const WorkItem* items, int nitems, void* C, double* W, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     if (tmax > kMaxTerms) return hipErrorInvalidValue;
-    if (variant == 0)
-        launch_str_var<0>(tmax, dim3(nitems), s, A, lda, tasks, terms, segs, items, C, W);
+    const dim3 g(nitems);
+    if (!f32)
+        launch_str_v<double, double>(variant, tmax, g, s, (const double*)A, lda, tb, items, (double*)C, W);
+    else if (out_f64)
+        launch_str_v<float, double>(variant, tmax, g, s, (const float*)A, lda, tb, items, (double*)C, W);
     else
-        launch_str_var<1>(tmax, dim3(nitems), s, A, lda, tasks, terms, segs, items, C, W);
+        launch_str_v<float, float>(variant, tmax, g, s, (const float*)A, lda, tb, items, (float*)C, W);
     return hipGetLastError();
 }
 
-hipError_t launch_combine_f64(const DevCombine* cbs, int ncb, int64_t total, const double* W, double* C,
-                              hipStream_t s) {
+hipError_t launch_combine(bool out_f64, const DevCombine* cbs, int ncb, int64_t total, const double* W, void* C,
+                          hipStream_t s) {
     if (ncb <= 0 || total <= 0) return hipSuccess;
     const int64_t blocks = (total + 255) / 256;
-    hipLaunchKernelGGL(k_combine_f64, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, C);
+    if (out_f64)
+        hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, (double*)C);
+    else
+        hipLaunchKernelGGL(k_combine<float>, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, (float*)C);
     return hipGetLastError();
 }
 
@@ -519,8 +963,60 @@ hipError_t launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t 
     const int64_t blocks = (count + 255) / 256;
     if (elem_bytes == 8)
         hipLaunchKernelGGL(k_fill_zero<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double*)p, count);
-    else
+    else if (elem_bytes == 4)
         hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float*)p, count);
+    else
+        hipLaunchKernelGGL(k_fill_zero<uint8_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint8_t*)p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_colscale(const float* A, int64_t lda, int m, int n, float* part, float* scale, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nch = m > 0 ? (m + 255) / 256 : 0;
+    if (nch > 0) hipLaunchKernelGGL(k_colmax_part, dim3((n + 255) / 256, nch), dim3(256), 0, s, A, lda, m, n, part);
+    hipLaunchKernelGGL(k_colscale, dim3((n + 255) / 256), dim3(256), 0, s, part, nch, n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_lp(int mode, const float* A, int64_t lda, int m, int n, int ldt, const float* scale,
+                          void* out0, void* out1, hipStream_t s) {
+    if (n <= 0 || ldt <= 0) return hipSuccess;
+    const dim3 g((ldt + 63) / 64, (n + 63) / 64);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_prep_lp<0>, g, dim3(256), 0, s, A, lda, m, n, ldt, scale, out0, out1);
+    else
+        hipLaunchKernelGGL(k_prep_lp<1>, g, dim3(256), 0, s, A, lda, m, n, ldt, scale, out0, out1);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1, int ldt, const float* scale,
+                          const DevTables& tb, const WorkItem* items, int nitems, void* C, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const dim3 g(nitems), b(256);
+    const uint8_t* t0 = (const uint8_t*)T0;
+    const uint8_t* t1 = (const uint8_t*)(T1 ? T1 : T0);
+    if (mode == 0) {
+        if (out_f64)
+            hipLaunchKernelGGL((k_gemm_lp<0, double>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
+                               items, (double*)C);
+        else
+            hipLaunchKernelGGL((k_gemm_lp<0, float>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
+                               items, (float*)C);
+    } else {
+        if (out_f64)
+            hipLaunchKernelGGL((k_gemm_lp<1, double>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
+                               items, (double*)C);
+        else
+            hipLaunchKernelGGL((k_gemm_lp<1, float>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
+                               items, (float*)C);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int mode, const float* x, int64_t count, void* out0, void* out1, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(k_convert, dim3((unsigned)blocks), dim3(256), 0, s, mode, x, count, out0, out1);
     return hipGetLastError();
 }
 

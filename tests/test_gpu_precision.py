@@ -1,0 +1,175 @@
+"""GPU parity of the reduced-precision forms.
+
+Each form is checked three ways: bit-exact on inputs whose products and sums
+the form represents exactly; tightly against the oracle's reference of what
+the form computes (same conversions, exact FP64 products: only the FP32
+accumulation rounding differs); and against the FP64 Gram matrix within the
+form's stated error bound.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+# stated relative Frobenius bounds against the FP64 Gram of the FP32 input
+BOUND_F32 = 2e-5
+BOUND_BF16X3 = 5e-5
+BOUND_FP8 = 5e-2
+# against the oracle's reference of the same conversions (FP32 accumulation only)
+TIGHT = 2e-6
+# the e4m3 MFMA sums 128 products inside one instruction with its own internal
+# accumulation (measured 5e-6 relative against exact products); a conversion
+# error would show at the format's resolution, about 1e-2
+TIGHT_FP8 = 2e-5
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1902_02104_amd as P
+    P.load()
+    return torch, P
+
+
+def _gram(env, A32, dtype, **kw):
+    torch, P = env
+    A = torch.from_numpy(np.ascontiguousarray(A32, dtype=np.float32)).cuda()
+    C = P.gram(A, dtype=dtype, **kw)
+    torch.cuda.synchronize()
+    return C.double().cpu().numpy()
+
+
+def test_conversions_match_torch_casts(env, orc):
+    torch, P = env
+    print("case: conversions", flush=True)
+    rng = np.random.default_rng(0)
+    x = (rng.standard_normal(300000) * 10.0 ** rng.uniform(-20, 20, 300000)).astype(np.float32)
+    x = np.concatenate([x, np.array([0.0, -0.0, 1.0, 1.00390625, 65504.0, 3e38, 1e-40], np.float32)])
+    hi, lo = P.precision_convert(torch.from_numpy(x).cuda(), P.F32_BF16X3)
+    torch.cuda.synchronize()
+    ref_hi = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy()
+    assert np.array_equal(hi.cpu().numpy(), ref_hi)
+    hf = torch.from_numpy(ref_hi).view(torch.bfloat16).float().numpy()
+    ref_lo = torch.from_numpy(x - hf).to(torch.bfloat16).view(torch.int16).numpy()
+    assert np.array_equal(lo.cpu().numpy(), ref_lo)
+    # e4m3 (values inside the format's range; torch does not saturate)
+    y = (rng.uniform(-448, 448, 300000) * 10.0 ** rng.uniform(-5, 0, 300000)).astype(np.float32)
+    y = np.concatenate([y, np.array([448.0, -448.0, 0.0, 2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -11, 464.0 - 1e-3],
+                                    np.float32)])
+    q = P.precision_convert(torch.from_numpy(y).cuda(), P.F32_FP8)
+    torch.cuda.synchronize()
+    ref_q = torch.from_numpy(y).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    assert np.array_equal(q.cpu().numpy(), ref_q)
+    # saturation to the largest finite value (format definition)
+    s = P.precision_convert(torch.tensor([1000.0, -500.0], dtype=torch.float32).cuda(), P.F32_FP8)
+    assert s.cpu().tolist() == [0x7E, 0xFE]
+
+
+@pytest.mark.parametrize("depth", [0, 1, 2])
+def test_f32_integer_bit_exact(env, orc, depth):
+    torch, P = env
+    print("case: f32 integer depth", depth, flush=True)
+    A = synthetic.integer(256, 192, synthetic.SEED_INTEGER_SMALL)
+    exact = orc.classical(A)
+    for out in (0, P.OUT_F64):
+        C = _gram(env, A, P.F32 | out, cutoff=32, max_depth=depth)
+        assert np.array_equal(C, exact)
+
+
+@pytest.mark.parametrize("depth,bound", [(0, 2e-6), (1, BOUND_F32), (2, BOUND_F32)])
+def test_f32_uniform(env, orc, depth, bound):
+    torch, P = env
+    print("case: f32 uniform depth", depth, flush=True)
+    A = synthetic.uniform(700, 600, 8, dtype=np.float32)
+    ref = orc.classical(A.astype(np.float64))
+    for out in (0, P.OUT_F64):
+        C = _gram(env, A, P.F32 | out, cutoff=64, max_depth=depth)
+        assert orc.rel_fro(C, ref, 600) <= bound
+
+
+def test_bf16x3(env, orc):
+    torch, P = env
+    print("case: bf16x3", flush=True)
+    Ai = synthetic.integer(300, 200, 7).astype(np.float32)
+    exact = orc.classical(Ai.astype(np.float64))
+    for c in (32, 10 ** 6):
+        assert np.array_equal(_gram(env, Ai, P.F32_BF16X3 | P.OUT_F64, cutoff=c), exact)
+    A = synthetic.uniform(900, 500, 9, dtype=np.float32)
+    ref = orc.gram_bf16x3(A)
+    ex = orc.classical(A.astype(np.float64))
+    for out in (0, P.OUT_F64):
+        for c in (64, 10 ** 6):
+            C = _gram(env, A, P.F32_BF16X3 | out, cutoff=c)
+            assert orc.rel_fro(C, ref, 500) <= TIGHT
+            assert orc.rel_fro(C, ex, 500) <= BOUND_BF16X3
+
+
+def test_fp8(env, orc):
+    torch, P = env
+    print("case: fp8", flush=True)
+    Ai = synthetic.integer(64, 150, 11).astype(np.float32)
+    exact = orc.classical(Ai.astype(np.float64))
+    for c in (16, 10 ** 6):
+        assert np.array_equal(_gram(env, Ai, P.F32_FP8 | P.OUT_F64, cutoff=c), exact)
+    A = synthetic.uniform(1000, 420, 12, dtype=np.float32)
+    ref = orc.gram_fp8(A)
+    ex = orc.classical(A.astype(np.float64))
+    for out in (0, P.OUT_F64):
+        for c in (64, 10 ** 6):
+            C = _gram(env, A, P.F32_FP8 | out, cutoff=c)
+            assert orc.rel_fro(C, ref, 420) <= TIGHT_FP8
+            assert orc.rel_fro(C, ex, 420) <= BOUND_FP8
+
+
+def test_reduced_precision_ragged_and_strided(env, orc):
+    """Odd shapes, a row stride above n and a non-uniform recursion tree."""
+    torch, P = env
+    print("case: lp ragged", flush=True)
+    for (m, n, c) in [(513, 600, 256), (77, 33, 8), (1, 5, 1), (130, 1, 4)]:
+        A = synthetic.uniform(m, n, m + n, dtype=np.float32)
+        buf = synthetic.with_lda(A, n + 3, fill=np.float32(1e30))
+        At = torch.from_numpy(buf).cuda()[:, :n]
+        for dt, ref in ((P.F32_BF16X3, orc.gram_bf16x3(A)), (P.F32_FP8, orc.gram_fp8(A))):
+            C = P.gram(At, dtype=dt | P.OUT_F64, cutoff=c)
+            torch.cuda.synchronize()
+            tol = TIGHT_FP8 if dt == P.F32_FP8 else TIGHT
+            assert orc.rel_fro(C.cpu().numpy(), ref, n) <= tol, (m, n, c, dt)
+    with pytest.raises(P.AtaError):
+        P.gram(torch.zeros(8, 8, device="cuda"), dtype=P.F32_FP8, max_depth=1)
+
+
+def test_precision_forms_full_size_sampled(env, orc):
+    """The 8192 x 8192 precision workload: sampled entries of each form
+    against the oracle's reference of that form."""
+    torch, P = env
+    print("case: 8192 precision forms", flush=True)
+    n = 8192
+    A = synthetic.uniform(n, n, synthetic.SEED_PRECISION, dtype=np.float32)
+    At = torch.from_numpy(A).cuda()
+    rng = np.random.default_rng(3)
+    pairs = [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(24)] + [(n - 1, 0), (n - 1, n - 1)]
+    A64 = A.astype(np.float64)
+    s = orc.pow2_column_scales(A64)
+    for dt in (P.F32, P.F32_BF16X3, P.F32_FP8):
+        C = P.gram(At, dtype=dt | P.OUT_F64, cutoff=256).cpu().numpy()
+        worst = 0.0
+        for i, j in pairs:
+            i, j = max(i, j), min(i, j)
+            ai, aj = A[:, i], A[:, j]
+            if dt == P.F32_BF16X3:
+                hi, lo = orc.bf16_split(np.stack([ai, aj], 1))
+                hi, lo = hi.astype(np.float64), lo.astype(np.float64)
+                ref = hi[:, 0] @ hi[:, 1] + hi[:, 0] @ lo[:, 1] + lo[:, 0] @ hi[:, 1]
+            elif dt == P.F32_FP8:
+                qi = orc.e4m3_round(A64[:, i] * s[i])
+                qj = orc.e4m3_round(A64[:, j] * s[j])
+                ref = (qi @ qj) / s[i] / s[j]
+            else:
+                ref = A64[:, i] @ A64[:, j]
+            scale = np.sqrt((A64[:, i] @ A64[:, i]) * (A64[:, j] @ A64[:, j]))
+            worst = max(worst, abs(C[i * (i + 1) // 2 + j] - ref) / scale)
+        assert worst <= (1e-5 if dt == P.F32_BF16X3 else 2e-5), (dt, worst)

@@ -91,7 +91,18 @@ def test_workspace_size(lib):
     ws = P.workspace_bytes(10000, 10000, 256, max_depth=2)
     # 7 products per off-diagonal block of levels 0..3, each a quarter block
     expect = 8 * 7 * (2500 ** 2 + 2 * 1250 ** 2 + 4 * 625 ** 2 + 8 * 313 ** 2)
-    assert ws == expect
+    assert expect <= ws < expect + 256  # rounded up to 256-byte alignment
+
+
+def test_workspace_size_reduced_precision(lib):
+    m, n = 1000, 300
+    ldt = (m + 127) // 128 * 128
+    bf = P.workspace_bytes(m, n, 0, dtype=P.F32_BF16X3, max_depth=0)
+    f8 = P.workspace_bytes(m, n, 0, dtype=P.F32_FP8, max_depth=0)
+    assert bf >= 2 * n * ldt * 2 + n * 4
+    assert f8 >= n * ldt + n * 4 and f8 < bf
+    with pytest.raises(P.AtaError):
+        P.plan_info(m, n, 0, dtype=P.F32_FP8, max_depth=1)  # classical leaves only
 
 
 def test_default_cutoff_is_in_tuned_set(lib):

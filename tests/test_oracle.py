@@ -365,3 +365,19 @@ def test_pow2_scales(orc):
     s = orc.pow2_column_scales(A)
     assert s.tolist() == [256.0, 128.0, 1.0]
     assert np.all(np.max(np.abs(A), axis=0) * s <= 448.0)
+
+
+def test_precision_references_reduce_to_exact(orc):
+    """On inputs the formats represent exactly the reduced-precision
+    references equal the exact Gram matrix; on uniform data their errors sit
+    at the formats' resolution."""
+    Ai = synthetic.integer(40, 30, 3).astype(np.float32)  # small integers: bf16 and e4m3 exact
+    exact = orc.classical(Ai.astype(np.float64))
+    assert np.array_equal(orc.gram_bf16x3(Ai), exact)
+    assert np.array_equal(orc.gram_fp8(Ai), exact)
+    Au = synthetic.uniform(300, 64, 4).astype(np.float32)
+    ex = orc.classical(Au.astype(np.float64))
+    e_bf = orc.rel_fro(orc.gram_bf16x3(Au), ex, 64)
+    e_f8 = orc.rel_fro(orc.gram_fp8(Au), ex, 64)
+    assert 0 < e_bf < 2.0 ** -15
+    assert 2.0 ** -8 < e_f8 < 2.0 ** -3
