@@ -59,6 +59,51 @@ def _cpu_baseline(A_np, target_s: float):
     }
 
 
+def _precision_forms(P, torch, dev, stream, n: int, steps: int):
+    """The 8192 x 8192 precision workload: FP32, bfloat16-split and e4m3
+    leaves on the FP32-rounded uniform input, each timed and checked against
+    the FP64 oracle (plain definition) of the same FP32 input."""
+    import oracle
+    import synthetic
+    A32 = synthetic.uniform(n, n, synthetic.SEED_PRECISION, dtype=np.float32)
+    At = torch.from_numpy(A32).to(dev)
+    t0 = time.perf_counter()
+    ref = oracle.classical_mt(A32.astype(np.float64))
+    ref_s = time.perf_counter() - t0
+    C = torch.empty(P.tri(n), dtype=torch.float64, device=dev)
+    flops = float(n) ** 3
+    out = {"workload": "square FP32 A %dx%d, uniform[-1,1] generated in FP64 (seed %d), C in FP64"
+                       % (n, n, synthetic.SEED_PRECISION),
+           "oracle": "FP64 plain definition on the FP32 input, %.1f s on the host" % ref_s}
+    # (name, dtype, depths, MFMA products per classical product, MFMA peak TFLOP/s)
+    for name, dt, depths, mult, peak in (("fp32", P.F32, (0, 1, 2), 1, 157.3),
+                                         ("bf16x3", P.F32_BF16X3, (0,), 3, 2500.0),
+                                         ("fp8_e4m3", P.F32_FP8, (0,), 1, 5000.0)):
+        best = None
+        for d in depths:
+            fn = lambda: P.gram(At, dtype=dt | P.OUT_F64, cutoff=256, max_depth=d, out=C, stream=stream)
+            fn()
+            torch.cuda.synchronize(dev)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize(dev)
+            ms = e0.elapsed_time(e1) / steps
+            err = oracle.rel_fro(C.cpu().numpy(), ref, n)
+            rec = {"ms": ms, "tflops_mn2": flops / (ms * 1e-3) / 1e12, "rel_fro_vs_fp64": err, "depth": d,
+                   "cutoff": 256}
+            rec["mfma_frac"] = mult * rec["tflops_mn2"] * P.plan_info(n, n, 256, dtype=dt, max_depth=d)["mults"] / \
+                (n * P.tri(n)) / peak
+            out["%s_d%d" % (name, d)] = rec
+            if best is None or ms < best["ms"]:
+                best = rec
+        out[name] = best
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +116,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classical", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--precision-n", type=int, default=8192)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -162,6 +209,10 @@ def main():
         classical = {"ms": cms, "tflops_mn2": flops_mn2 / (cms * 1e-3) / 1e12,
                      "what": "classical SYRK on the same GPU (same MFMA tile kernel, cutoff >= n)"}
 
+    forms = None
+    if not args.no_precision:
+        forms = _precision_forms(P, torch, dev, stream, args.precision_n, 5)
+
     cpu = None
     if not args.no_cpu:
         cpu = _cpu_baseline(A_np, args.cpu_seconds)
@@ -191,6 +242,7 @@ def main():
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
         "classical_same_gpu": classical,
         "cpu_baseline": cpu,
+        "precision_forms": forms,
         "check": {"diag_max_rel_err": diag_err},
     }
     print(json.dumps(out), flush=True)

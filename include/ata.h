@@ -185,6 +185,94 @@ void ata_release_caches(void);
 int ata_profile_enable(int on);
 int ata_profile_collect(double *ms, int64_t *launches, int kinds);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: a persistent loop for streams of Gram-matrix requests            */
+/* ------------------------------------------------------------------------ */
+/*
+ * A server owns a device memory pool of `budget_bytes` and a scheduler
+ * thread.  Requests are admitted in arrival order when their footprint
+ * (A + packed C + workspace of their plan) fits in the free pool and fewer
+ * than `max_active` requests are in flight; up to 8 queued requests behind a
+ * blocked one may be admitted first if they fit.  Admitted requests run
+ * concurrently on `streams` HIP streams; requests whose plan is a single
+ * classical diagonal block (n or m at most the cutoff) are batched into one
+ * grouped launch per scheduler pass.  A result is bit-identical whether the
+ * request ran alone or in a mix: its tiles, their K order and the kernels are
+ * a function of the request only.  Results stay in the pool until taken.
+ * Calls are thread safe.
+ */
+typedef struct ata_server ata_server;
+
+#define ATA_SRC_HOST 0   /* copy A from host memory `a` (m x n, row stride n) */
+#define ATA_SRC_DEVICE 1 /* copy A from device memory `a` (row stride n) */
+#define ATA_SRC_NORMAL 2 /* i.i.d. N(0,1) entries drawn on the device from `seed`
+                            (Philox4x32-10 counter = element pair, Box-Muller) */
+
+typedef struct ata_request {
+    int64_t m, n;
+    int32_t dtype;     /* ATA_F64 or ATA_F32 */
+    int32_t cutoff;    /* 0 = default */
+    int32_t max_depth; /* Strassen levels, -2 = library default */
+    int32_t src;       /* ATA_SRC_* */
+    const void *a;     /* source of A for ATA_SRC_HOST / ATA_SRC_DEVICE; must
+                          stay valid until the request has been admitted */
+    uint64_t seed;     /* ATA_SRC_NORMAL */
+    int32_t keep_a;    /* 1: keep A in the pool until taken (ata_server_take
+                          can copy it out); 0: free it when the product ends */
+    int32_t reserved;  /* must be 0 */
+} ata_request;
+
+#define ATA_REQ_QUEUED 0
+#define ATA_REQ_ADMITTED 1
+#define ATA_REQ_RUNNING 2
+#define ATA_REQ_DONE 3
+
+typedef struct ata_request_info {
+    int32_t state;      /* ATA_REQ_* */
+    int32_t status;     /* ATA_OK or the error the request ended with */
+    int64_t m, n;
+    double t_submit;    /* seconds on the server's steady clock */
+    double t_admit, t_launch, t_done;
+    int32_t batched;    /* 1 if it ran in a grouped launch */
+    int32_t stream;     /* stream index it ran on */
+    int64_t footprint;  /* bytes held in the pool while in flight */
+    double flops;       /* m * n * n, the classical count of the metric */
+} ata_request_info;
+
+typedef struct ata_server_stats {
+    int64_t submitted, admitted, completed, rejected;
+    int64_t batches;          /* grouped launches */
+    int64_t batched_requests; /* requests that ran in grouped launches */
+    int64_t pool_bytes, pool_in_use, pool_peak;
+    int64_t queued, active;
+} ata_server_stats;
+
+#define ATA_SERVER_SIMULATE 1 /* host-only: no device memory or kernels; a
+                                 request completes flops / (simulate_tflops 1e12)
+                                 seconds after admission.  For scheduler tests. */
+
+/* budget_bytes > 0; max_active >= 1; streams in [1, 16]; flags ATA_SERVER_*. */
+int ata_server_create(size_t budget_bytes, int max_active, int streams, int flags, double simulate_tflops,
+                      ata_server **out);
+/* Queue a request.  ATA_EREJECT if its footprint exceeds the budget, negative
+ * codes for invalid fields.  The ticket identifies it in the calls below. */
+int ata_server_submit(ata_server *srv, const ata_request *req, uint64_t *ticket);
+/* ATA_OK when done (info filled), ATA_EPENDING while queued or running. */
+int ata_server_query(ata_server *srv, uint64_t ticket, ata_request_info *info);
+/* Block until done or timeout_s elapses (ATA_EPENDING). */
+int ata_server_wait(ata_server *srv, uint64_t ticket, double timeout_s, ata_request_info *info);
+/* Copy the packed result (n(n+1)/2 elements of the request's type) to `c`
+ * (device memory if c_on_device, else host) and, if `a_host` is not NULL, A
+ * (m x n) to host memory; then release the request's pool memory. */
+int ata_server_take(ata_server *srv, uint64_t ticket, void *c, int c_on_device, void *a_host);
+/* Release a finished request without copying anything. */
+int ata_server_release(ata_server *srv, uint64_t ticket);
+int ata_server_get_stats(ata_server *srv, ata_server_stats *out);
+/* Seconds on the server's steady clock (the clock of the info timestamps). */
+double ata_server_now(ata_server *srv);
+/* Stop the loop after in-flight work completes and free everything. */
+int ata_server_destroy(ata_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

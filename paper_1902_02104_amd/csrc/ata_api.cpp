@@ -15,11 +15,13 @@
 #include "../../include/ata.h"
 #include "ata_plan.h"
 
+#include "ata_internal.h"
 #include "ata_kernels.h"
 
 using namespace atalib;
 
-namespace {
+namespace atalib {
+namespace detail {
 
 thread_local int g_last_hip = 0;
 
@@ -33,30 +35,6 @@ int hip_fail(hipError_t e) {
         hipError_t _e = (expr);                \
         if (_e != hipSuccess) return hip_fail(_e); \
     } while (0)
-
-// Device copy of one plan's tables.
-struct PhaseDev {
-    int n_str = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, str_tmax = 0;
-    int64_t cb_elems = 0;
-    size_t off_str = 0, off_gemm = 0, off_syrk = 0, off_cb = 0;
-};
-
-struct PlanDev {
-    Plan plan;
-    int device = -1;
-    char* blob = nullptr;  // device memory holding every table
-    size_t off_tasks = 0, off_terms = 0, off_segs = 0;
-    std::vector<PhaseDev> phases;
-    ~PlanDev() {
-        if (blob) {
-            int cur = 0;
-            (void)hipGetDevice(&cur);
-            (void)hipSetDevice(device);
-            (void)hipFree(blob);
-            (void)hipSetDevice(cur);
-        }
-    }
-};
 
 using PlanKey = std::tuple<int, int64_t, int64_t, int64_t, int, int>;
 
@@ -151,13 +129,6 @@ bool dtype_valid(int dtype) {
 bool dtype_lp(int dtype) { return (dtype & 0xff) == ATA_F32_BF16X3 || (dtype & 0xff) == ATA_F32_FP8; }
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
-
-// Device workspace layout: [FP64 Strassen products][scales][column-max
-// partials][converted copy plane 0][plane 1], each 256-byte aligned.
-struct WsLayout {
-    size_t w = 0, scale = 0, part = 0, t0 = 0, t1 = 0, total = 0;
-    int64_t ldt = 0;
-};
 
 WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems) {
     WsLayout L;
@@ -313,7 +284,87 @@ int common_checks(const void* A, int64_t m, int64_t n, int64_t lda, const void* 
     return 0;
 }
 
-}  // namespace
+// Enqueue every launch of one product on stream s (see ata_ex).  ws holds
+// L.total bytes (may be null when L.total is 0).
+hipError_t enqueue_product(const PlanDev& pdr, const WsLayout& L, const void* A, int64_t m, int64_t n, int64_t lda,
+                           void* C_lower, int dtype, int variant, char* ws, hipStream_t s, int dev) {
+    const PlanDev* pd = &pdr;
+    const Plan& P = pd->plan;
+    const bool lp = dtype_lp(dtype);
+    const bool f32 = (dtype & 0xff) != ATA_F64;
+    const bool out64 = elem_bytes_out(dtype) == 8;
+    int rc = ATA_OK;
+    double* W = P.ws_elems ? (double*)(ws + L.w) : nullptr;
+    const DevTables tb{(const DevTask*)(pd->blob + pd->off_tasks), (const DevTerm*)(pd->blob + pd->off_terms),
+                       (const int32_t*)(pd->blob + pd->off_segs)};
+    hipError_t err = hipSuccess;
+    const int lp_mode = (dtype & 0xff) == ATA_F32_FP8 ? 1 : 0;
+    if (lp) {
+        ProfScope ps(ATA_KERNEL_OTHER, s);
+        float* scale = (float*)(ws + L.scale);
+        if (lp_mode == 1) err = launch_colscale((const float*)A, lda, (int)m, (int)n, (float*)(ws + L.part), scale, s);
+        if (err == hipSuccess)
+            err = launch_prep_lp(lp_mode, (const float*)A, lda, (int)m, (int)n, (int)L.ldt, scale, ws + L.t0,
+                                 lp_mode == 0 ? (void*)(ws + L.t1) : nullptr, s);
+    }
+    for (const PhaseDev& ph : pd->phases) {
+        if (err != hipSuccess) break;
+        if (lp) {
+            const float* scale = (const float*)(ws + L.scale);
+            const void* t1 = lp_mode == 0 ? (const void*)(ws + L.t1) : nullptr;
+            if (ph.n_gemm) {
+                ProfScope ps(ATA_KERNEL_GEMM, s);
+                err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
+                                     (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower, s);
+            }
+            if (err == hipSuccess && ph.n_syrk) {
+                ProfScope ps(ATA_KERNEL_SYRK, s);
+                err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
+                                     (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, s);
+            }
+            continue;
+        }
+        const bool split = ph.n_str > 0 && (ph.n_gemm + ph.n_syrk) > 0;
+        ForkCtx fc;
+        if (split) {
+            rc = fork_get(dev, fc);
+            if (rc != ATA_OK) return hipErrorOutOfMemory;
+            err = hipEventRecord(fc.fork, s);
+            if (err == hipSuccess) err = hipStreamWaitEvent(fc.s2, fc.fork, 0);
+        }
+        if (err == hipSuccess && ph.n_str) {
+            ProfScope ps(ATA_KERNEL_STRASSEN, s);
+            err = launch_str(f32, out64, variant, ph.str_tmax, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_str),
+                             ph.n_str, C_lower, W, s);
+        }
+        hipStream_t s_small = split ? fc.s2 : s;
+        if (err == hipSuccess && ph.n_gemm) {
+            ProfScope ps(ATA_KERNEL_GEMM, s_small);
+            err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower,
+                              s_small);
+        }
+        if (err == hipSuccess && ph.n_syrk) {
+            ProfScope ps(ATA_KERNEL_SYRK, s_small);
+            err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower,
+                              s_small);
+        }
+        if (split) {
+            if (err == hipSuccess) err = hipEventRecord(fc.join, fc.s2);
+            if (err == hipSuccess) err = hipStreamWaitEvent(s, fc.join, 0);
+            fork_put(dev, fc);
+        }
+        if (err == hipSuccess && ph.n_cb) {
+            ProfScope ps(ATA_KERNEL_COMBINE, s);
+            err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W, C_lower, s);
+        }
+    }
+    return err;
+}
+
+}  // namespace detail
+}  // namespace atalib
+
+using namespace atalib::detail;
 
 extern "C" {
 
@@ -397,8 +448,6 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
         if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
         max_depth = 0;
     }
-    const bool f32 = (dtype & 0xff) != ATA_F64;
-    const bool out64 = elem_bytes_out(dtype) == 8;
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -432,70 +481,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
             owned = true;
         }
     }
-    double* W = P.ws_elems ? (double*)(ws + L.w) : nullptr;
-    const DevTables tb{(const DevTask*)(pd->blob + pd->off_tasks), (const DevTerm*)(pd->blob + pd->off_terms),
-                       (const int32_t*)(pd->blob + pd->off_segs)};
-    hipError_t err = hipSuccess;
-    const int lp_mode = (dtype & 0xff) == ATA_F32_FP8 ? 1 : 0;
-    if (lp) {
-        ProfScope ps(ATA_KERNEL_OTHER, s);
-        float* scale = (float*)(ws + L.scale);
-        if (lp_mode == 1) err = launch_colscale((const float*)A, lda, (int)m, (int)n, (float*)(ws + L.part), scale, s);
-        if (err == hipSuccess)
-            err = launch_prep_lp(lp_mode, (const float*)A, lda, (int)m, (int)n, (int)L.ldt, scale, ws + L.t0,
-                                 lp_mode == 0 ? (void*)(ws + L.t1) : nullptr, s);
-    }
-    for (const PhaseDev& ph : pd->phases) {
-        if (err != hipSuccess) break;
-        if (lp) {
-            const float* scale = (const float*)(ws + L.scale);
-            const void* t1 = lp_mode == 0 ? (const void*)(ws + L.t1) : nullptr;
-            if (ph.n_gemm) {
-                ProfScope ps(ATA_KERNEL_GEMM, s);
-                err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
-                                     (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower, s);
-            }
-            if (err == hipSuccess && ph.n_syrk) {
-                ProfScope ps(ATA_KERNEL_SYRK, s);
-                err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
-                                     (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, s);
-            }
-            continue;
-        }
-        const bool split = ph.n_str > 0 && (ph.n_gemm + ph.n_syrk) > 0;
-        ForkCtx fc;
-        if (split) {
-            rc = fork_get(dev, fc);
-            if (rc != ATA_OK) return rc;
-            err = hipEventRecord(fc.fork, s);
-            if (err == hipSuccess) err = hipStreamWaitEvent(fc.s2, fc.fork, 0);
-        }
-        if (err == hipSuccess && ph.n_str) {
-            ProfScope ps(ATA_KERNEL_STRASSEN, s);
-            err = launch_str(f32, out64, variant, ph.str_tmax, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_str),
-                             ph.n_str, C_lower, W, s);
-        }
-        hipStream_t s_small = split ? fc.s2 : s;
-        if (err == hipSuccess && ph.n_gemm) {
-            ProfScope ps(ATA_KERNEL_GEMM, s_small);
-            err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower,
-                              s_small);
-        }
-        if (err == hipSuccess && ph.n_syrk) {
-            ProfScope ps(ATA_KERNEL_SYRK, s_small);
-            err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower,
-                              s_small);
-        }
-        if (split) {
-            if (err == hipSuccess) err = hipEventRecord(fc.join, fc.s2);
-            if (err == hipSuccess) err = hipStreamWaitEvent(s, fc.join, 0);
-            fork_put(dev, fc);
-        }
-        if (err == hipSuccess && ph.n_cb) {
-            ProfScope ps(ATA_KERNEL_COMBINE, s);
-            err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W, C_lower, s);
-        }
-    }
+    hipError_t err = enqueue_product(*pd, L, A, m, n, lda, C_lower, dtype, variant, ws, s, dev);
     if (owned) {
         hipError_t e2 = hipFreeAsync(ws, s);
         if (err == hipSuccess) err = e2;

@@ -1,0 +1,59 @@
+// Internals of libata shared between the C ABI layer and the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <vector>
+
+#include "ata_plan.h"
+
+namespace atalib {
+namespace detail {
+
+// Device copy of one plan's tables.
+struct PhaseDev {
+    int n_str = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, str_tmax = 0;
+    int64_t cb_elems = 0;
+    size_t off_str = 0, off_gemm = 0, off_syrk = 0, off_cb = 0;
+};
+
+struct PlanDev {
+    Plan plan;
+    int device = -1;
+    char* blob = nullptr;  // device memory holding every table
+    size_t off_tasks = 0, off_terms = 0, off_segs = 0;
+    std::vector<PhaseDev> phases;
+    ~PlanDev() {
+        if (blob) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(device);
+            (void)hipFree(blob);
+            (void)hipSetDevice(cur);
+        }
+    }
+};
+
+// Device workspace layout: [FP64 Strassen products][scales][column-max
+// partials][converted copy plane 0][plane 1], each 256-byte aligned.
+struct WsLayout {
+    size_t w = 0, scale = 0, part = 0, t0 = 0, t1 = 0, total = 0;
+    int64_t ldt = 0;
+};
+
+int hip_fail(hipError_t e);
+int check_device(int dev);
+bool dtype_lp(int dtype);
+int elem_bytes_in(int dtype);
+int elem_bytes_out(int dtype);
+int64_t default_cutoff(int64_t m, int64_t n, int dtype);
+WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems);
+int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, bool need_device,
+             std::shared_ptr<PlanDev>& out);
+hipError_t enqueue_product(const PlanDev& pd, const WsLayout& L, const void* A, int64_t m, int64_t n, int64_t lda,
+                           void* C_lower, int dtype, int variant, char* ws, hipStream_t s, int dev);
+
+}  // namespace detail
+}  // namespace atalib

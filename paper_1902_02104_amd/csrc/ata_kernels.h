@@ -21,6 +21,15 @@ struct DevTables {
 hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
                        const WorkItem* items, int nitems, void* C, hipStream_t s);
 
+// Classical tiles of several requests in one launch: work item w uses
+// batch[w.slot] for its matrices and tables.
+hipError_t launch_gemm_batch(bool f32, bool out_f64, const BatchEntry* batch, const WorkItem* items, int nitems,
+                             hipStream_t s);
+
+// Fill count elements with i.i.d. standard normal values drawn from
+// (seed, element index) by Philox4x32-10 and the Box-Muller transform.
+hipError_t launch_fill_normal(void* p, int64_t count, uint64_t seed, bool f64, hipStream_t s);
+
 // In-tile Strassen tiles (TK_STR).  tmax: most operand terms of any task.
 hipError_t launch_str(bool f32, bool out_f64, int variant, int tmax, const void* A, int64_t lda,
                       const DevTables& tb, const WorkItem* items, int nitems, void* C, double* W,

@@ -83,12 +83,13 @@ __device__ __forceinline__ void store_out(OUT* p, int beta, double v) {
 constexpr int GT = kGemmTile;  // 128
 constexpr int GK = 16;
 
-template <typename T, typename OUT>
-__global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A, int64_t lda,
-                                                 const DevTask* __restrict__ tasks,
-                                                 const DevTerm* __restrict__ terms,
-                                                 const int32_t* __restrict__ segs,
-                                                 const WorkItem* __restrict__ items, OUT* __restrict__ C) {
+template <typename T, typename OUT, bool BATCH>
+__global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64_t lda_,
+                                                 const DevTask* __restrict__ tasks_,
+                                                 const DevTerm* __restrict__ terms_,
+                                                 const int32_t* __restrict__ segs_,
+                                                 const WorkItem* __restrict__ items, OUT* __restrict__ C_,
+                                                 const BatchEntry* __restrict__ batch) {
     typedef Eng<T> E;
     constexpr bool F32 = std::is_same<T, float>::value;
     constexpr int BR = 64 / E::RM, BC = 64 / E::RN;
@@ -96,6 +97,21 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A, int64_
     __shared__ T Ys[2][GK][GT + E::PAD];
 
     const WorkItem w = items[blockIdx.x];
+    const T* __restrict__ A = A_;
+    OUT* __restrict__ C = C_;
+    const DevTask* __restrict__ tasks = tasks_;
+    const DevTerm* __restrict__ terms = terms_;
+    const int32_t* __restrict__ segs = segs_;
+    int64_t lda = lda_;
+    if (BATCH) {
+        const BatchEntry be = batch[w.slot];
+        A = (const T*)be.A;
+        C = (OUT*)be.C;
+        tasks = be.tasks;
+        terms = be.terms;
+        segs = be.segs;
+        lda = be.lda;
+    }
     const DevTask t = tasks[w.task];
     const DevTerm tx = terms[t.term_off];
     const DevTerm ty = terms[t.term_off + 1];
@@ -898,15 +914,76 @@ hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const
                        const WorkItem* items, int nitems, void* C, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const dim3 g(nitems), b(256);
+    const BatchEntry* nb = nullptr;
     if (!f32)
-        hipLaunchKernelGGL((k_gemm<double, double>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.terms, tb.segs,
-                           items, (double*)C);
+        hipLaunchKernelGGL((k_gemm<double, double, false>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.terms,
+                           tb.segs, items, (double*)C, nb);
     else if (out_f64)
-        hipLaunchKernelGGL((k_gemm<float, double>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms, tb.segs,
-                           items, (double*)C);
+        hipLaunchKernelGGL((k_gemm<float, double, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
+                           tb.segs, items, (double*)C, nb);
     else
-        hipLaunchKernelGGL((k_gemm<float, float>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms, tb.segs,
-                           items, (float*)C);
+        hipLaunchKernelGGL((k_gemm<float, float, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
+                           tb.segs, items, (float*)C, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_batch(bool f32, bool out_f64, const BatchEntry* batch, const WorkItem* items, int nitems,
+                             hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const dim3 g(nitems), b(256);
+    if (!f32)
+        hipLaunchKernelGGL((k_gemm<double, double, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
+                           nullptr, batch);
+    else if (out_f64)
+        hipLaunchKernelGGL((k_gemm<float, double, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
+                           nullptr, batch);
+    else
+        hipLaunchKernelGGL((k_gemm<float, float, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
+                           nullptr, batch);
+    return hipGetLastError();
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): counter = element
+// group index, key = seed; two uniform 32-bit words per normal value via the
+// Box-Muller transform.
+__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = (uint32_t)p1;
+        c[2] = n2;
+        c[3] = (uint32_t)p0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+template <typename T>
+__global__ void k_fill_normal(T* __restrict__ p, int64_t count, uint64_t seed) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // group of 2 values
+    if (2 * g >= count) return;
+    uint32_t c[4] = {(uint32_t)g, (uint32_t)((uint64_t)g >> 32), 0u, 0u};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    // uniforms in (0, 1]
+    const double u1 = ((double)c[0] + 1.0) * (1.0 / 4294967296.0);
+    const double u2 = ((double)c[1]) * (1.0 / 4294967296.0);
+    const double r = sqrt(-2.0 * log(u1));
+    const double a = 6.283185307179586 * u2;
+    p[2 * g] = (T)(r * cos(a));
+    if (2 * g + 1 < count) p[2 * g + 1] = (T)(r * sin(a));
+}
+
+hipError_t launch_fill_normal(void* p, int64_t count, uint64_t seed, bool f64, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t groups = (count + 1) / 2;
+    const int64_t blocks = (groups + 255) / 256;
+    if (f64)
+        hipLaunchKernelGGL(k_fill_normal<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double*)p, count, seed);
+    else
+        hipLaunchKernelGGL(k_fill_normal<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float*)p, count, seed);
     return hipGetLastError();
 }
 

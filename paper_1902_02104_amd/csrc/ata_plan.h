@@ -62,8 +62,21 @@ struct DevCombine {
     int64_t elem_off;   // first output element index of this block in the launch
 };
 
+// Work item of a launch: tile (ti, tj) of task `task`.  In a batched launch
+// `slot` selects the request (see BatchEntry); otherwise it is 0.
 struct WorkItem {
-    int32_t task, ti, tj, pad;
+    int32_t task, ti, tj, slot;
+};
+
+// One request of a batched launch of classical tiles: its matrices and the
+// device task tables of its plan.
+struct BatchEntry {
+    const void* A;
+    void* C;
+    const DevTask* tasks;
+    const DevTerm* terms;
+    const int32_t* segs;
+    int64_t lda;
 };
 
 struct PlanOptions {
