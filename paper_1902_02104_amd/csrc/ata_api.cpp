@@ -54,8 +54,8 @@ int check_device(int dev) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Upload a plan's tables into one device allocation.
-int upload(PlanDev& pd, int dev) {
+// Lay out a plan's tables in one host image (offsets recorded in pd).
+void serialize(PlanDev& pd) {
     const Plan& P = pd.plan;
     size_t off = 0;
     pd.off_tasks = off;
@@ -83,7 +83,8 @@ int upload(PlanDev& pd, int dev) {
         d.off_cb = off;
         off = align256(off + ph.combines.size() * sizeof(DevCombine));
     }
-    std::vector<char> host(off ? off : 256, 0);
+    std::vector<char>& host = pd.host_blob;
+    host.assign(off ? off : 256, 0);
     std::memcpy(host.data() + pd.off_tasks, P.tasks.data(), P.tasks.size() * sizeof(DevTask));
     std::memcpy(host.data() + pd.off_terms, P.terms.data(), P.terms.size() * sizeof(DevTerm));
     std::memcpy(host.data() + pd.off_segs, P.segs.data(), P.segs.size() * sizeof(int32_t));
@@ -95,9 +96,13 @@ int upload(PlanDev& pd, int dev) {
         std::memcpy(host.data() + d.off_syrk, ph.syrk_items.data(), ph.syrk_items.size() * sizeof(WorkItem));
         std::memcpy(host.data() + d.off_cb, ph.combines.data(), ph.combines.size() * sizeof(DevCombine));
     }
-    HIP_TRY(hipMalloc(&pd.blob, host.size()));
+}
+
+// Copy a serialized plan into one device allocation.
+int upload(PlanDev& pd, int dev) {
+    HIP_TRY(hipMalloc(&pd.blob, pd.host_blob.size()));
     pd.device = dev;
-    HIP_TRY(hipMemcpy(pd.blob, host.data(), host.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(pd.blob, pd.host_blob.data(), pd.host_blob.size(), hipMemcpyHostToDevice));
     return ATA_OK;
 }
 
@@ -194,6 +199,7 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, b
     } catch (const std::exception&) {
         return ATA_EUNSUPPORTED;
     }
+    serialize(*pd);
     if (need_device) {
         const int rc = upload(*pd, dev);
         if (rc != ATA_OK) return rc;
@@ -286,10 +292,16 @@ int common_checks(const void* A, int64_t m, int64_t n, int64_t lda, const void* 
 
 // Enqueue every launch of one product on stream s (see ata_ex).  ws holds
 // L.total bytes (may be null when L.total is 0).
-hipError_t enqueue_product(const PlanDev& pdr, const WsLayout& L, const void* A, int64_t m, int64_t n, int64_t lda,
-                           void* C_lower, int dtype, int variant, char* ws, hipStream_t s, int dev) {
-    const PlanDev* pd = &pdr;
-    const Plan& P = pd->plan;
+hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout& L, const void* A, int64_t m,
+                           int64_t n, int64_t lda, void* C_lower, int dtype, int variant, char* ws, hipStream_t s,
+                           int dev) {
+    struct {
+        const char* blob;
+        size_t off_tasks, off_terms, off_segs;
+        const std::vector<PhaseDev>& phases;
+    } v{dblob, pdr.off_tasks, pdr.off_terms, pdr.off_segs, pdr.phases};
+    const auto* pd = &v;
+    const Plan& P = pdr.plan;
     const bool lp = dtype_lp(dtype);
     const bool f32 = (dtype & 0xff) != ATA_F64;
     const bool out64 = elem_bytes_out(dtype) == 8;
@@ -315,12 +327,17 @@ hipError_t enqueue_product(const PlanDev& pdr, const WsLayout& L, const void* A,
             if (ph.n_gemm) {
                 ProfScope ps(ATA_KERNEL_GEMM, s);
                 err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
-                                     (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower, s);
+                                     (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower, W, s);
             }
             if (err == hipSuccess && ph.n_syrk) {
                 ProfScope ps(ATA_KERNEL_SYRK, s);
                 err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
-                                     (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, s);
+                                     (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, W, s);
+            }
+            if (err == hipSuccess && ph.n_cb) {  // sums of split K parts
+                ProfScope ps(ATA_KERNEL_COMBINE, s);
+                err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W,
+                                     C_lower, s);
             }
             continue;
         }
@@ -341,12 +358,12 @@ hipError_t enqueue_product(const PlanDev& pdr, const WsLayout& L, const void* A,
         if (err == hipSuccess && ph.n_gemm) {
             ProfScope ps(ATA_KERNEL_GEMM, s_small);
             err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower,
-                              s_small);
+                              W, s_small);
         }
         if (err == hipSuccess && ph.n_syrk) {
             ProfScope ps(ATA_KERNEL_SYRK, s_small);
             err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower,
-                              s_small);
+                              W, s_small);
         }
         if (split) {
             if (err == hipSuccess) err = hipEventRecord(fc.join, fc.s2);
@@ -481,7 +498,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
             owned = true;
         }
     }
-    hipError_t err = enqueue_product(*pd, L, A, m, n, lda, C_lower, dtype, variant, ws, s, dev);
+    hipError_t err = enqueue_product(*pd, pd->blob, L, A, m, n, lda, C_lower, dtype, variant, ws, s, dev);
     if (owned) {
         hipError_t e2 = hipFreeAsync(ws, s);
         if (err == hipSuccess) err = e2;

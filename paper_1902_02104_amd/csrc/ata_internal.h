@@ -22,7 +22,8 @@ struct PhaseDev {
 struct PlanDev {
     Plan plan;
     int device = -1;
-    char* blob = nullptr;  // device memory holding every table
+    char* blob = nullptr;          // device memory holding every table
+    std::vector<char> host_blob;  // the same tables on the host
     size_t off_tasks = 0, off_terms = 0, off_segs = 0;
     std::vector<PhaseDev> phases;
     ~PlanDev() {
@@ -52,8 +53,10 @@ int64_t default_cutoff(int64_t m, int64_t n, int dtype);
 WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems);
 int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, bool need_device,
              std::shared_ptr<PlanDev>& out);
-hipError_t enqueue_product(const PlanDev& pd, const WsLayout& L, const void* A, int64_t m, int64_t n, int64_t lda,
-                           void* C_lower, int dtype, int variant, char* ws, hipStream_t s, int dev);
+// dblob: device copy of pd.host_blob (pd.blob, or a copy the caller made)
+hipError_t enqueue_product(const PlanDev& pd, const char* dblob, const WsLayout& L, const void* A, int64_t m,
+                           int64_t n, int64_t lda, void* C_lower, int dtype, int variant, char* ws, hipStream_t s,
+                           int dev);
 
 }  // namespace detail
 }  // namespace atalib

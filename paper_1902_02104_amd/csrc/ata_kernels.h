@@ -19,7 +19,7 @@ struct DevTables {
 // Classical tiles (TK_SYRK / TK_GEMM) on FP64 or FP32 MFMA.  out_f64 selects
 // a double C for float input.
 hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
-                       const WorkItem* items, int nitems, void* C, hipStream_t s);
+                       const WorkItem* items, int nitems, void* C, double* W, hipStream_t s);
 
 // Classical tiles of several requests in one launch: work item w uses
 // batch[w.slot] for its matrices and tables.
@@ -52,7 +52,7 @@ hipError_t launch_prep_lp(int mode, const float* A, int64_t lda, int m, int n, i
                           void* out0, void* out1, hipStream_t s);
 hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1, int ldt,
                           const float* scale, const DevTables& tb, const WorkItem* items, int nitems,
-                          void* C, hipStream_t s);
+                          void* C, double* W, hipStream_t s);
 
 // Element conversions exposed for verification: mode 0 -> bfloat16 hi/lo
 // (uint16 pairs), mode 1 -> OCP e4m3 bytes (no scaling).

@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
                                                  const DevTerm* __restrict__ terms_,
                                                  const int32_t* __restrict__ segs_,
                                                  const WorkItem* __restrict__ items, OUT* __restrict__ C_,
-                                                 const BatchEntry* __restrict__ batch) {
+                                                 double* __restrict__ W, const BatchEntry* __restrict__ batch) {
     typedef Eng<T> E;
     constexpr bool F32 = std::is_same<T, float>::value;
     constexpr int BR = 64 / E::RM, BC = 64 / E::RN;
@@ -141,14 +141,16 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
                 for (int e = 0; e < (F32 ? E::NA : 1); ++e) acc64[a][b][e] = 0.0;
     }
 
-    // k-tile cursor over the segments
-    const int stride = 1 + 2 * (t.nx + t.ny);
-    int seg = 0, k0 = 0;
-    int klen = t.nseg > 0 ? segs[t.seg_off] : 0;
-    int xrow = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
-    int yrow = t.nseg > 0 ? segs[t.seg_off + 3] : 0;
+    // k-tile cursor over the segments: rows row + k for k in [kbeg, kend)
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
+    int seg = 0;
+    int k0 = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
+    int klen = t.nseg > 0 ? segs[t.seg_off + 2] : 0;  // window end
+    int xrow = t.nseg > 0 ? segs[t.seg_off + kSegHdr] : 0;
+    int yrow = t.nseg > 0 ? segs[t.seg_off + kSegHdr + 2] : 0;
     int ntiles = 0;
-    for (int s = 0; s < t.nseg; ++s) ntiles += (segs[t.seg_off + s * stride] + GK - 1) / GK;
+    for (int s = 0; s < t.nseg; ++s)
+        ntiles += (segs[t.seg_off + s * stride + 2] - segs[t.seg_off + s * stride + 1] + GK - 1) / GK;
 
     T xr[8], yr[8];
     auto load = [&](int kk0, int kl, int xr0, int yr0) {
@@ -164,12 +166,12 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
     auto advance = [&]() {
         k0 += GK;
         if (k0 >= klen) {
-            k0 = 0;
             ++seg;
             if (seg < t.nseg) {
-                klen = segs[t.seg_off + seg * stride];
-                xrow = segs[t.seg_off + seg * stride + 1];
-                yrow = segs[t.seg_off + seg * stride + 3];
+                k0 = segs[t.seg_off + seg * stride + 1];
+                klen = segs[t.seg_off + seg * stride + 2];
+                xrow = segs[t.seg_off + seg * stride + kSegHdr];
+                yrow = segs[t.seg_off + seg * stride + kSegHdr + 2];
             }
         }
     };
@@ -226,7 +228,10 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
                 const int gj = j0 + wn * 64 + cf * E::RN + (lane & 15);
                 if (gj >= t.dN || (syrk && gj > gi)) continue;
                 const double v = F32 ? acc64[F32 ? rb : 0][F32 ? cf : 0][F32 ? e : 0] : E::elem(acc[rb][cf], e);
-                store_out(C + rowbase + gj, t.beta, v);
+                if (t.dst == 0)
+                    store_out(C + rowbase + gj, t.beta, v);
+                else
+                    W[t.ws_off + (int64_t)gi * t.N + gj] = v;
             }
         }
     }
@@ -324,7 +329,7 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
     const int wm = wave >> 1, wn = wave & 1;  // 4 x 2 waves of 16 x 32
     const int MH = (t.M + 1) >> 1, NH = (t.N + 1) >> 1;
     const int i0 = w.ti * ST, j0 = w.tj * ST;
-    const int stride = 1 + 2 * (t.nx + t.ny);
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
 
     // staging map: thread -> k rows lk + 8r, column lc (one element per quadrant and row)
     const int lk = tid >> 6, lc = tid & 63;
@@ -373,16 +378,17 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
                     for (int e = 0; e < E::NA; ++e) acc64[F32 ? p : 0][F32 ? a : 0][F32 ? b : 0][F32 ? e : 0] = 0.0;
             }
 
+    // per segment: K half length kh = ceil(klen / 2), window [kbeg, kend) of it
     int ntiles = 0;
-    for (int s = 0; s < t.nseg; ++s) {
-        const int kh = (segs[t.seg_off + s * stride] + 1) >> 1;
-        ntiles += (kh + SK - 1) / SK;
-    }
+    for (int s = 0; s < t.nseg; ++s)
+        ntiles += (segs[t.seg_off + s * stride + 2] - segs[t.seg_off + s * stride + 1] + SK - 1) / SK;
 
     // raw term values of the next k tile: [term][row][quad]
     T xraw[TMAX][KR][4], yraw[TMAX][KR][4];
-    int seg = 0, k0 = 0;
+    int seg = 0;
     int kh = t.nseg > 0 ? (segs[t.seg_off] + 1) >> 1 : 0;
+    int k0 = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
+    int kend = t.nseg > 0 ? segs[t.seg_off + 2] : 0;
 
     // Issue every load of the next k tile; nothing waits on them here.
     auto load = [&]() {
@@ -390,11 +396,11 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
 #pragma unroll
         for (int r = 0; r < KR; ++r) {
             const int kk = k0 + lk + 8 * r;
-            const bool kv = kk < kh;
+            const bool kv = kk < kend;
 #pragma unroll
             for (int u = 0; u < TMAX; ++u) {
                 if (u < t.nx) {
-                    const int row0 = sg[1 + 2 * u], rvend = sg[2 + 2 * u];
+                    const int row0 = sg[kSegHdr + 2 * u], rvend = sg[kSegHdr + 1 + 2 * u];
 #pragma unroll
                     for (int b = 0; b < 2; ++b) {
                         const int row = row0 + b * kh + kk;
@@ -409,7 +415,7 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
                     for (int q = 0; q < 4; ++q) xraw[u][r][q] = T(0);
                 }
                 if (u < t.ny) {
-                    const int row0 = sg[1 + 2 * (t.nx + u)], rvend = sg[2 + 2 * (t.nx + u)];
+                    const int row0 = sg[kSegHdr + 2 * (t.nx + u)], rvend = sg[kSegHdr + 1 + 2 * (t.nx + u)];
 #pragma unroll
                     for (int b = 0; b < 2; ++b) {
                         const int row = row0 + b * kh + kk;
@@ -444,10 +450,13 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
     };
     auto advance = [&]() {
         k0 += SK;
-        if (k0 >= kh) {
-            k0 = 0;
+        if (k0 >= kend) {
             ++seg;
-            if (seg < t.nseg) kh = (segs[t.seg_off + seg * stride] + 1) >> 1;
+            if (seg < t.nseg) {
+                kh = (segs[t.seg_off + seg * stride] + 1) >> 1;
+                k0 = segs[t.seg_off + seg * stride + 1];
+                kend = segs[t.seg_off + seg * stride + 2];
+            }
         }
     };
 
@@ -546,6 +555,7 @@ __global__ void __launch_bounds__(256) k_combine(const DevCombine* __restrict__ 
     const DevCombine cb = cbs[lo];
     const int64_t loc = e - cb.elem_off;
     const int i = (int)(loc / cb.N), j = (int)(loc % cb.N);
+    if (cb.lower && j > i) return;
     int ii = i, jj = j, Mc = cb.M, Nc = cb.N;
     int quad[4];
     for (int l = 0; l < cb.levels; ++l) {
@@ -562,13 +572,16 @@ __global__ void __launch_bounds__(256) k_combine(const DevCombine* __restrict__ 
     double s = 0.0;
     int npaths = 1;
     for (int l = 0; l < cb.levels; ++l) npaths *= 7;
-    for (int path = 0; path < npaths; ++path) {
-        int rem = path, coef = 1;
-        for (int l = cb.levels - 1; l >= 0; --l) {
-            coef *= c_dcoef[cb.variant][rem % 7][quad[l]];
-            rem /= 7;
+    for (int part = 0; part < cb.nparts; ++part) {
+        const double* pb = base + (int64_t)part * cb.part_stride;
+        for (int path = 0; path < npaths; ++path) {
+            int rem = path, coef = 1;
+            for (int l = cb.levels - 1; l >= 0; --l) {
+                coef *= c_dcoef[cb.variant][rem % 7][quad[l]];
+                rem /= 7;
+            }
+            if (coef) s += coef > 0 ? pb[path * slot_elems] : -pb[path * slot_elems];
         }
-        if (coef) s += coef > 0 ? base[path * slot_elems] : -base[path * slot_elems];
     }
     store_out(C + packed_index((int64_t)cb.r0 + i, cb.q0) + j, cb.beta, s);
 }
@@ -724,7 +737,8 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
                                                     const DevTask* __restrict__ tasks,
                                                     const DevTerm* __restrict__ terms,
                                                     const int32_t* __restrict__ segs,
-                                                    const WorkItem* __restrict__ items, OUT* __restrict__ C) {
+                                                    const WorkItem* __restrict__ items, OUT* __restrict__ C,
+                                                    double* __restrict__ W) {
     typedef LpCfg<MODE> L;
     constexpr int KT = L::KT, EB = L::EB, PL = L::PLANES, ROWB = L::ROWB;
     constexpr int ROWBYTES = KT * EB;           // bytes of one tile row per stage
@@ -740,7 +754,7 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int i0 = w.ti * GT, j0 = w.tj * GT;
-    const int stride = 1 + 2 * (t.nx + t.ny);
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
 
     f4_t acc[4][4];
     double acc64[4][4][4];
@@ -754,13 +768,15 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
         }
 
     int ntiles = 0;
-    for (int s = 0; s < t.nseg; ++s) ntiles += (segs[t.seg_off + s * stride] + KT - 1) / KT;
+    for (int s = 0; s < t.nseg; ++s)
+        ntiles += (segs[t.seg_off + s * stride + 2] - segs[t.seg_off + s * stride + 1] + KT - 1) / KT;
 
     // staged chunks: [plane][operand][chunk]
     u4_t rg[PL][2][CPT];
-    int seg = 0, k0 = 0;
-    int klen = t.nseg > 0 ? segs[t.seg_off] : 0;
-    int krow = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
+    int seg = 0;
+    int k0 = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
+    int klen = t.nseg > 0 ? segs[t.seg_off + 2] : 0;  // window end
+    int krow = t.nseg > 0 ? segs[t.seg_off + kSegHdr] : 0;
 
     auto load = [&]() {
 #pragma unroll
@@ -813,11 +829,11 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
     auto advance = [&]() {
         k0 += KT;
         if (k0 >= klen) {
-            k0 = 0;
             ++seg;
             if (seg < t.nseg) {
-                klen = segs[t.seg_off + seg * stride];
-                krow = segs[t.seg_off + seg * stride + 1];
+                k0 = segs[t.seg_off + seg * stride + 1];
+                klen = segs[t.seg_off + seg * stride + 2];
+                krow = segs[t.seg_off + seg * stride + kSegHdr];
             }
         }
     };
@@ -901,7 +917,10 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
                 if (gj >= t.dN || (syrk && gj > gi)) continue;
                 double v = acc64[rb][cf][e];
                 if (MODE == 1) v = v * si / (double)scale[ty.col + gj];  // exact power-of-two de-scale
-                store_out(C + rowbase + gj, t.beta, v);
+                if (t.dst == 0)
+                    store_out(C + rowbase + gj, t.beta, v);
+                else
+                    W[t.ws_off + (int64_t)gi * t.N + gj] = v;
             }
         }
     }
@@ -911,19 +930,19 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
 // Host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
-                       const WorkItem* items, int nitems, void* C, hipStream_t s) {
+                       const WorkItem* items, int nitems, void* C, double* W, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const dim3 g(nitems), b(256);
     const BatchEntry* nb = nullptr;
     if (!f32)
         hipLaunchKernelGGL((k_gemm<double, double, false>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (double*)C, nb);
+                           tb.segs, items, (double*)C, W, nb);
     else if (out_f64)
         hipLaunchKernelGGL((k_gemm<float, double, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (double*)C, nb);
+                           tb.segs, items, (double*)C, W, nb);
     else
         hipLaunchKernelGGL((k_gemm<float, float, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (float*)C, nb);
+                           tb.segs, items, (float*)C, W, nb);
     return hipGetLastError();
 }
 
@@ -933,13 +952,13 @@ hipError_t launch_gemm_batch(bool f32, bool out_f64, const BatchEntry* batch, co
     const dim3 g(nitems), b(256);
     if (!f32)
         hipLaunchKernelGGL((k_gemm<double, double, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
-                           nullptr, batch);
+                           nullptr, nullptr, batch);
     else if (out_f64)
         hipLaunchKernelGGL((k_gemm<float, double, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
-                           nullptr, batch);
+                           nullptr, nullptr, batch);
     else
         hipLaunchKernelGGL((k_gemm<float, float, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
-                           nullptr, batch);
+                           nullptr, nullptr, batch);
     return hipGetLastError();
 }
 
@@ -1067,7 +1086,8 @@ hipError_t launch_prep_lp(int mode, const float* A, int64_t lda, int m, int n, i
 }
 
 hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1, int ldt, const float* scale,
-                          const DevTables& tb, const WorkItem* items, int nitems, void* C, hipStream_t s) {
+                          const DevTables& tb, const WorkItem* items, int nitems, void* C, double* W,
+                          hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const dim3 g(nitems), b(256);
     const uint8_t* t0 = (const uint8_t*)T0;
@@ -1075,17 +1095,17 @@ hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1
     if (mode == 0) {
         if (out_f64)
             hipLaunchKernelGGL((k_gemm_lp<0, double>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
-                               items, (double*)C);
+                               items, (double*)C, W);
         else
             hipLaunchKernelGGL((k_gemm_lp<0, float>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
-                               items, (float*)C);
+                               items, (float*)C, W);
     } else {
         if (out_f64)
             hipLaunchKernelGGL((k_gemm_lp<1, double>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
-                               items, (double*)C);
+                               items, (double*)C, W);
         else
             hipLaunchKernelGGL((k_gemm_lp<1, float>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
-                               items, (float*)C);
+                               items, (float*)C, W);
     }
     return hipGetLastError();
 }

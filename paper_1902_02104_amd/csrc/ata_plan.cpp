@@ -112,6 +112,8 @@ void Builder::add_segments_merged(DevTask& t, const std::vector<Chunk>& chs) {
             ++j;
         }
         check32(e);
+        P.segs.push_back((int32_t)(e - r));  // klen
+        P.segs.push_back(0);                 // window [0, klen)
         P.segs.push_back((int32_t)(e - r));
         P.segs.push_back((int32_t)r);
         P.segs.push_back((int32_t)e);
@@ -319,7 +321,9 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             t.nseg = (int32_t)nch;
             for (size_t c = 0; c < nch; ++c) {
                 check32(K[c]);
-                P.segs.push_back((int32_t)K[c]);
+                P.segs.push_back((int32_t)K[c]);            // klen
+                P.segs.push_back(0);                        // window over the K half
+                P.segs.push_back((int32_t)ceil2(K[c]));
                 for (const auto* list : {&pr.x, &pr.y})
                     for (const XTerm& u : *list) {
                         check32(u.rvend[c]);
@@ -363,6 +367,9 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             cb.beta = beta;
             cb.Mp = (int32_t)Mp;
             cb.Np = (int32_t)Np;
+            cb.nparts = 1;
+            cb.lower = 0;
+            cb.part_stride = 0;
             cb.ws_off = ws_base;
             Phase& pz = ph(gphase);
             cb.elem_off = pz.combine_elems;
@@ -373,6 +380,159 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
         }
     }
     return phase + gi;
+}
+
+// Window lengths of a task's segments (rows of K each covers).
+int64_t task_k(const Plan& P, const DevTask& t) {
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
+    int64_t k = 0;
+    for (int s = 0; s < t.nseg; ++s) k += P.segs[t.seg_off + s * stride + 2] - P.segs[t.seg_off + s * stride + 1];
+    return k;
+}
+
+// Copy of task t restricted to the k range [a, b) of its concatenated windows.
+void restrict_window(Plan& P, DevTask& t, int64_t a, int64_t b) {
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
+    std::vector<int32_t> out;
+    int nseg = 0;
+    int64_t pos = 0;
+    for (int s = 0; s < t.nseg; ++s) {
+        const int32_t* sg = &P.segs[t.seg_off + s * stride];
+        const int64_t w0 = sg[1], w1 = sg[2], len = w1 - w0;
+        const int64_t lo = std::max(a, pos), hi = std::min(b, pos + len);
+        if (hi > lo) {
+            std::vector<int32_t> seg(sg, sg + stride);
+            seg[1] = (int32_t)(w0 + (lo - pos));
+            seg[2] = (int32_t)(w0 + (hi - pos));
+            out.insert(out.end(), seg.begin(), seg.end());
+            ++nseg;
+        }
+        pos += len;
+    }
+    t.seg_off = (int32_t)P.segs.size();
+    t.nseg = nseg;
+    P.segs.insert(P.segs.end(), out.begin(), out.end());
+}
+
+// Split long K ranges of launches that have too few tiles to fill the GPU.
+// A task writing C becomes nparts tasks writing dense partial blocks to the
+// workspace plus a combination that sums them (in part order) into C; the
+// products of a block already written to the workspace get nparts slot sets
+// and their combination sums over parts as well.  The scalar products are
+// unchanged; only the order of summation over K differs.
+void split_k(Plan& P) {
+    const PlanOptions& o = P.opt;
+    if (o.split_target <= 0) return;
+    for (size_t pi = 0; pi < P.phases.size(); ++pi) {
+        Phase& ph = P.phases[pi];
+        const int64_t items = (int64_t)(ph.str_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
+        if (items == 0 || items >= o.split_target) continue;
+        const int64_t want = std::min<int64_t>(64, o.split_target / items);
+        if (want < 2) continue;
+        // decide a part count per task (workspace blocks: per combine block)
+        std::map<int32_t, int> parts;  // task id -> parts
+        auto decide = [&](int32_t id) {
+            if (parts.count(id)) return;
+            const int64_t k = task_k(P, P.tasks[id]);
+            parts[id] = (int)std::max<int64_t>(1, std::min<int64_t>(want, k / o.split_min_k));
+        };
+        for (auto* items_v : {&ph.str_items, &ph.gemm_items, &ph.syrk_items})
+            for (const WorkItem& w : *items_v) decide(w.task);
+        // products of one workspace block must share the part count
+        for (DevCombine& cb : ph.combines) {
+            int np = 64;
+            const int64_t span = (int64_t)cb.Mp * cb.Np * [&] { int p = 1; for (int l = 0; l < cb.levels; ++l) p *= 7; return p; }();
+            for (auto& kv : parts) {
+                const DevTask& t = P.tasks[kv.first];
+                if (t.dst == 1 && t.ws_off >= cb.ws_off && t.ws_off < cb.ws_off + span) np = std::min(np, kv.second);
+            }
+            for (auto& kv : parts) {
+                const DevTask& t = P.tasks[kv.first];
+                if (t.dst == 1 && t.ws_off >= cb.ws_off && t.ws_off < cb.ws_off + span) kv.second = np;
+            }
+            if (np > 1) {
+                // fresh workspace for np slot sets; the first keeps the old offset range
+                const int64_t base = P.ws_elems;
+                P.ws_elems += span * np;
+                for (auto& kv : parts) {
+                    DevTask& t = P.tasks[kv.first];
+                    if (t.dst == 1 && t.ws_off >= cb.ws_off && t.ws_off < cb.ws_off + span)
+                        t.ws_off = base + (t.ws_off - cb.ws_off);
+                }
+                cb.ws_off = base;
+                cb.nparts = np;
+                cb.part_stride = span;
+            }
+        }
+        // rewrite the tasks and their work items
+        std::map<int32_t, std::vector<int32_t>> newids;  // task -> part task ids
+        std::map<int32_t, int64_t> stride_of;             // part stride of workspace tasks
+        for (auto& kv : parts) {
+            const int32_t id = kv.first;
+            const int np = kv.second;
+            if (np < 2) continue;
+            const DevTask t0 = P.tasks[id];
+            const int64_t k = task_k(P, t0);
+            int64_t pstride = 0;
+            int64_t wbase = 0;
+            if (t0.dst == 0) {
+                // partial blocks written densely, then summed into C
+                pstride = (int64_t)t0.dM * t0.N;
+                wbase = P.ws_elems;
+                P.ws_elems += pstride * np;
+                DevCombine cb{};
+                cb.M = t0.dM;
+                cb.N = t0.dN;
+                cb.levels = 0;
+                cb.variant = 0;
+                cb.r0 = t0.r0;
+                cb.q0 = t0.q0;
+                cb.beta = t0.beta;
+                cb.Mp = t0.dM;
+                cb.Np = t0.N;
+                cb.nparts = np;
+                cb.lower = t0.kind == TK_SYRK ? 1 : 0;
+                cb.part_stride = pstride;
+                cb.ws_off = wbase;
+                cb.elem_off = ph.combine_elems;
+                ph.combine_elems += (int64_t)t0.dM * t0.dN;
+                ph.combines.push_back(cb);
+                ++P.combine_tasks;
+            } else {
+                for (const DevCombine& cb : ph.combines)
+                    if (cb.nparts == np && t0.ws_off >= cb.ws_off && t0.ws_off < cb.ws_off + cb.part_stride)
+                        pstride = cb.part_stride;
+            }
+            for (int p = 0; p < np; ++p) {
+                DevTask t = t0;
+                restrict_window(P, t, k * p / np, k * (p + 1) / np);
+                if (t0.dst == 0) {
+                    t.dst = 1;
+                    t.beta = 0;
+                    t.ws_off = wbase + p * pstride;
+                } else {
+                    t.ws_off = t0.ws_off + p * pstride;
+                }
+                newids[id].push_back((int32_t)P.tasks.size());
+                P.tasks.push_back(t);
+            }
+        }
+        for (auto* items_v : {&ph.str_items, &ph.gemm_items, &ph.syrk_items}) {
+            std::vector<WorkItem> out;
+            for (const WorkItem& w : *items_v) {
+                auto it = newids.find(w.task);
+                if (it == newids.end()) {
+                    out.push_back(w);
+                    continue;
+                }
+                for (int32_t nid : it->second) out.push_back(WorkItem{nid, w.ti, w.tj, w.slot});
+            }
+            items_v->swap(out);
+        }
+        // combination blocks ordered by element offset
+        std::sort(ph.combines.begin(), ph.combines.end(),
+                  [](const DevCombine& a, const DevCombine& b) { return a.elem_off < b.elem_off; });
+    }
 }
 
 }  // namespace
@@ -391,14 +551,14 @@ Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
         Builder b(P);
         b.ata_node({Chunk{0, m}}, 0, n, 0, 0);
     }
+    split_k(P);
     // longest-processing-time order inside every launch: heavier tiles first
     for (Phase& ph : P.phases) {
         auto cost = [&](const WorkItem& w) {
             const DevTask& t = P.tasks[w.task];
-            int64_t k = 0;
-            for (int s = 0; s < t.nseg; ++s) k += P.segs[t.seg_off + s * (1 + 2 * (t.nx + t.ny))];
-            if (t.kind == TK_STR) return (double)k * (1.0 + 0.1 * (t.nx + t.ny));
-            return (double)k;
+            const double k = (double)task_k(P, t);
+            if (t.kind == TK_STR) return 2.0 * k * (1.0 + 0.1 * (t.nx + t.ny));
+            return k;
         };
         for (auto* items : {&ph.str_items, &ph.gemm_items, &ph.syrk_items})
             std::stable_sort(items->begin(), items->end(),

@@ -17,6 +17,8 @@ enum TaskKind : int32_t {
 
 // One signed operand term: columns [col, cvend) of A are valid, the rest of
 // the padded range reads as zero.  Rows are per K segment (see DevTask).
+constexpr int kSegHdr = 3;
+
 struct DevTerm {
     int32_t col;
     int32_t cvend;
@@ -27,9 +29,12 @@ struct DevTerm {
 // A product D (M x N, padded) = Xop^t Yop, where Xop = sum of signed X terms
 // and Yop = sum of signed Y terms, both K x (M or N) slices of A.  K is a
 // list of segments (row chunks of the recursion); segment s has padded length
-// klen and, per term, a first row and a valid-row end:
-//   seg[seg_off + s*(1 + 2*(nx+ny))] = klen, then (row, rvend) for every X
-//   term, then for every Y term.
+// klen, a window [kbeg, kend) of the k it covers (of [0, klen), or of the half
+// range [0, ceil(klen/2)) for TK_STR), and per term a first row and a
+// valid-row end:
+//   seg[seg_off + s*(kSegHdr + 2*(nx+ny))] = klen, kbeg, kend, then
+//   (row, rvend) for every X term, then for every Y term.
+// Windows let one product's K range be split over several workgroups.
 // For TK_STR the product is split once more inside the tile: M, N and each
 // klen into ceil halves, seven products, one workgroup per quadrant tile.
 struct DevTask {
@@ -50,6 +55,8 @@ struct DevTask {
 };
 
 // Combination of workspace products into an off-diagonal block of C.
+// Each output element sums, over nparts K parts (slot sets part_stride
+// elements apart) and over the 7^levels products, the signed workspace values.
 struct DevCombine {
     int32_t M, N;       // true block extent
     int32_t levels;     // Strassen levels that were expanded into workspace slots
@@ -57,7 +64,10 @@ struct DevCombine {
     int32_t r0, q0;
     int32_t beta;
     int32_t Mp, Np;     // padded dims of one workspace slot
+    int32_t nparts;     // K parts summed (1 when the K range was not split)
+    int32_t lower;      // 1: write only j <= i (a diagonal block)
     int32_t pad;
+    int64_t part_stride;
     int64_t ws_off;
     int64_t elem_off;   // first output element index of this block in the launch
 };
@@ -83,6 +93,11 @@ struct PlanOptions {
     int64_t cutoff = 32;
     int variant = 0;    // 0 Strassen, 1 Winograd
     int max_depth = 2;  // < 0: unlimited
+    // K splitting: a launch with fewer workgroup tiles than split_target
+    // splits long K ranges (at least split_min_k each part) over several
+    // workgroups whose partial results a combination sums in part order.
+    int split_target = 768;
+    int split_min_k = 2048;
 };
 
 // Launch group: everything that may run after the previous group finished.

@@ -95,8 +95,8 @@ struct Req {
     int batched = 0, stream = -1;
     int64_t footprint = 0;
     double flops = 0;
-    Block a, c, w;
-    std::shared_ptr<PlanDev> plan;  // device plan (host plan in simulate mode)
+    Block a, c, w, tb;
+    std::shared_ptr<PlanDev> plan;  // host plan; its tables are copied into block tb
     WsLayout L;
     int64_t cutoff = 0;
     int variant = 0, depth = 0;
@@ -161,6 +161,7 @@ void ata_server::finish(Req* q, int status, double t) {
     q->t_done = t;
     if (!q->r.keep_a) release_block(q->a);
     release_block(q->w);
+    release_block(q->tb);
     if (q->ev) {
         (void)hipEventDestroy(q->ev);
         q->ev = nullptr;
@@ -194,31 +195,35 @@ bool ata_server::admit(Req* q, int pass_stream) {
         w.bytes = q->L.total;
         w.held = true;
     }
+    Block tb;
+    const size_t tbytes = q->plan->host_blob.size();
+    if (!pool.alloc(tbytes, tb.off)) {
+        release_block(a);
+        release_block(c);
+        release_block(w);
+        return false;
+    }
+    tb.bytes = tbytes;
+    tb.held = true;
     q->a = a;
     q->c = c;
     q->w = w;
+    q->tb = tb;
     q->state = ATA_REQ_ADMITTED;
     q->t_admit = now();
     ++active;
     ++st.admitted;
     if (sim()) return true;
-    // device plan (tables uploaded once per shape)
-    std::shared_ptr<PlanDev> pd;
-    int rc = get_plan(m, n, q->cutoff, q->variant, q->depth, true, pd);
-    if (rc != ATA_OK) {
-        finish(q, rc, now());
-        release_block(q->a);
-        return true;
-    }
-    q->plan = pd;
-    const Plan& P = pd->plan;
+    const Plan& P = q->plan->plan;
     q->small = P.phases.size() == 1 && P.phases[0].str_items.empty() && P.phases[0].gemm_items.empty() &&
                P.phases[0].combines.empty();
     q->stream = q->small ? pass_stream : (int)((pass + q->id) % streams.size());
     hipStream_t s = streams[q->stream];
     void* A = base + q->a.off;
-    hipError_t e = hipSuccess;
-    if (q->r.src == ATA_SRC_HOST)
+    // the plan's tables travel with the request (no synchronous upload)
+    hipError_t e = hipMemcpyAsync(base + q->tb.off, q->plan->host_blob.data(), tbytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+    } else if (q->r.src == ATA_SRC_HOST)
         e = hipMemcpyAsync(A, q->r.a, abytes, hipMemcpyHostToDevice, s);
     else if (q->r.src == ATA_SRC_DEVICE)
         e = hipMemcpyAsync(A, q->r.a, abytes, hipMemcpyDeviceToDevice, s);
@@ -319,7 +324,7 @@ void ata_server::loop() {
                         continue;
                     }
                     hipStream_t s = streams[q->stream];
-                    hipError_t e = enqueue_product(*q->plan, q->L, base + q->a.off, q->r.m, q->r.n, q->r.n,
+                    hipError_t e = enqueue_product(*q->plan, base + q->tb.off, q->L, base + q->a.off, q->r.m, q->r.n, q->r.n,
                                                    base + q->c.off, q->r.dtype, q->variant,
                                                    q->w.held ? base + q->w.off : nullptr, s, dev);
                     if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
@@ -339,10 +344,11 @@ void ata_server::loop() {
                     for (size_t slot = 0; slot < group.size(); ++slot) {
                         Req* q = group[slot];
                         const PlanDev& pd = *q->plan;
+                        const char* tb = base + q->tb.off;
                         b.entries.push_back(BatchEntry{base + q->a.off, base + q->c.off,
-                                                       (const DevTask*)(pd.blob + pd.off_tasks),
-                                                       (const DevTerm*)(pd.blob + pd.off_terms),
-                                                       (const int32_t*)(pd.blob + pd.off_segs), q->r.n});
+                                                       (const DevTask*)(tb + pd.off_tasks),
+                                                       (const DevTerm*)(tb + pd.off_terms),
+                                                       (const int32_t*)(tb + pd.off_segs), q->r.n});
                         for (WorkItem wi : pd.plan.phases[0].syrk_items) {
                             wi.slot = (int32_t)slot;
                             b.items.push_back(wi);
@@ -484,10 +490,12 @@ int ata_server_submit(ata_server* srv, const ata_request* req, uint64_t* ticket)
         rc = get_plan(req->m, req->n, q->cutoff, q->variant, q->depth, false, hp);
         if (rc != ATA_OK) return rc;
         q->L = ws_layout(req->m, req->n, req->dtype, hp->plan.ws_elems);
+        q->plan = hp;
     }
     const size_t eb = elem_bytes(req->dtype);
     q->footprint = (int64_t)(align_up((size_t)req->m * req->n * eb) +
-                             align_up((size_t)(req->n * (req->n + 1) / 2) * eb) + align_up(q->L.total));
+                             align_up((size_t)(req->n * (req->n + 1) / 2) * eb) + align_up(q->L.total) +
+                             (hp ? align_up(hp->host_blob.size()) : 0));
     std::lock_guard<std::mutex> lk(srv->mu);
     ++srv->st.submitted;
     if ((size_t)q->footprint > srv->pool.size) {
@@ -584,6 +592,7 @@ int ata_server_take(ata_server* srv, uint64_t ticket, void* c, int c_on_device, 
     srv->release_block(q->a);
     srv->release_block(q->c);
     srv->release_block(q->w);
+    srv->release_block(q->tb);
     delete q;
     srv->kick = true;
     srv->cv_work.notify_one();

@@ -234,3 +234,35 @@ def test_square_full_size_sampled(env, orc, n, cutoff):
     rhs = A.T @ (A @ x)
     res = (lhs - rhs).norm().item() / (A.norm().item() ** 2 * x.norm().item())
     assert res < 1e-14, res
+
+
+@pytest.mark.parametrize("dtype_name,depth", [("f64", 0), ("f64", 1), ("f64", 2), ("f32", 1)])
+def test_split_k_tall_skinny_integer(env, orc, dtype_name, depth):
+    """Tall inputs with few output tiles split their K range over several
+    workgroups; the parts are summed in a fixed order: still exact."""
+    torch, P = env
+    m, n = 24000, 300
+    st = P.plan_info(m, n, 64, max_depth=depth)
+    assert st["combine_tasks"] >= 1  # split parts are combined
+    _say("case: split-K", dtype_name, depth, st["work_items"])
+    A = synthetic.integer(m, n, 77, dtype=np.float64 if dtype_name == "f64" else np.float32)
+    At = torch.from_numpy(A).cuda()
+    C = P.gram(At, cutoff=64, max_depth=depth, dtype=P.F64 if dtype_name == "f64" else P.F32 | P.OUT_F64)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy(), orc.classical(A.astype(np.float64)))
+    C2 = P.gram(At, cutoff=64, max_depth=depth, dtype=P.F64 if dtype_name == "f64" else P.F32 | P.OUT_F64)
+    torch.cuda.synchronize()
+    assert torch.equal(C, C2)  # deterministic
+
+
+def test_split_k_tall_scaled_fp64(env, orc):
+    """The least-squares shape at reduced size: relative error and the scaled
+    error max |dC_ij| / sqrt(C_ii C_jj) of the classical-leaf plan stay at
+    double precision."""
+    torch, P = env
+    _say("case: tall scaled")
+    A = synthetic.tall_scaled(32768, 256)
+    C = P.gram(torch.from_numpy(A).cuda(), cutoff=64, max_depth=0).cpu().numpy()
+    ref = orc.classical(A)
+    assert orc.rel_fro(C, ref, 256) <= FP64_TOL
+    assert orc.scaled_err(C, ref, 256) <= FP64_TOL

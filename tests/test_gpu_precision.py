@@ -173,3 +173,13 @@ def test_precision_forms_full_size_sampled(env, orc):
             scale = np.sqrt((A64[:, i] @ A64[:, i]) * (A64[:, j] @ A64[:, j]))
             worst = max(worst, abs(C[i * (i + 1) // 2 + j] - ref) / scale)
         assert worst <= (1e-5 if dt == P.F32_BF16X3 else 2e-5), (dt, worst)
+
+
+def test_reduced_precision_split_k(env, orc):
+    torch, P = env
+    print("case: lp split-K", flush=True)
+    A = synthetic.uniform(20000, 200, 13, dtype=np.float32)
+    for dt, ref, tol in ((P.F32_BF16X3, orc.gram_bf16x3(A), TIGHT), (P.F32_FP8, orc.gram_fp8(A), TIGHT_FP8)):
+        assert P.plan_info(20000, 200, 64, dtype=dt)["combine_tasks"] >= 1
+        C = _gram(env, A, dt | P.OUT_F64, cutoff=64)
+        assert orc.rel_fro(C, ref, 200) <= tol
