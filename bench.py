@@ -26,28 +26,64 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
 
 
+def _profiled_traffic(kernel: str, n: int, cutoff: int, depth: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (two rocprofv3 --pmc passes scaled by a plain copy), or None when the
+    summary was taken on other kernel sources or another configuration."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "k_str_f64_10000_traffic.md")
+    try:
+        kv = dict(line.strip().split(": ", 1) for line in open(path) if line.startswith("    ") and ": " in line
+                  and not line.strip().startswith("cd "))
+        src = open(os.path.join(root, "paper_1902_02104_amd", "csrc", "ata_kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    if kv.get("kernels_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    if not kernel.startswith("k_str") or (kv.get("n"), kv.get("cutoff"), kv.get("max_depth")) != \
+            (str(n), str(cutoff), str(depth)):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def _log(msg):
+    """Progress of the legs on stderr; stdout carries only the result line."""
+    print("[bench %.0fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
 def _cpu_baseline(A_np, target_s: float):
     """The oracle's threaded classical product on a bounded sample of the
     same workload: the last rows of packed C (all columns j <= i)."""
     import oracle
     m, n = A_np.shape
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    threads = max(1, min(threads, 64))
-    # calibrate on a small slab, then size the timed sample
-    r0 = min(n, 40)
-    t = time.perf_counter()
-    oracle.classical_mt(A_np, rows=(n - r0, n), threads=threads)
-    dt = max(time.perf_counter() - t, 1e-3)
-    ent0 = oracle.tri(n) - oracle.tri(n - r0)
-    rate = ent0 / dt  # entries per second
-    want = int(rate * target_s)
-    i0 = n
-    while i0 > 0 and oracle.tri(n) - oracle.tri(i0) < want:
-        i0 -= 1
-    t = time.perf_counter()
-    oracle.classical_mt(A_np, rows=(i0, n), threads=threads)
-    dt = time.perf_counter() - t
-    ent = oracle.tri(n) - oracle.tri(i0)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():  # the process's CPU share
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    threads = max(1, min(threads, 16))
+
+    def first_row(entries):
+        i0 = n
+        while i0 > 0 and oracle.tri(n) - oracle.tri(i0) < entries:
+            i0 -= 1
+        return i0
+
+    # Time slabs of the last rows, resizing from the last rate until one takes
+    # most of the target; the oracle hands whole row tiles to its threads, so
+    # small slabs run slower than large ones.
+    ent, dt = 4 * threads * n, 0.0
+    for _ in range(6):
+        i0 = first_row(ent)
+        t = time.perf_counter()
+        oracle.classical_mt(A_np, rows=(i0, n), threads=threads)
+        dt = time.perf_counter() - t
+        ent = oracle.tri(n) - oracle.tri(i0)
+        if dt >= 0.6 * target_s or i0 == 0:
+            break
+        ent = int(ent * min(16.0, target_s / max(dt, 1e-3)))
     flops = 2.0 * m * ent  # the same per-entry count as m*n^2 for the whole product
     return {
         "value": flops / dt / 1e12,
@@ -98,6 +134,7 @@ def _precision_forms(P, torch, dev, stream, n: int, steps: int):
             rec["mfma_frac"] = mult * rec["tflops_mn2"] * P.plan_info(n, n, 256, dtype=dt, max_depth=d)["mults"] / \
                 (n * P.tri(n)) / peak
             out["%s_d%d" % (name, d)] = rec
+            _log("precision %s depth %d: %.2f ms" % (name, d, ms))
             if best is None or ms < best["ms"]:
                 best = rec
         out[name] = best
@@ -174,6 +211,7 @@ def _serving(P, torch, n_req: int, budget: int, max_active: int, streams: int):
 
     closed = run(None, checks=8)
     x = closed["throughput_req_s"]
+    _log("serving closed loop: %.1f req/s" % x)
     out = {"workload": "%d requests, m log-uniform [1024, 65536], n log-uniform [64, 4096], FP32 N(0,1) "
                        "drawn on the device, HBM budget %.0f GB, %d in flight, %d streams"
                        % (n_req, budget / 1e9, max_active, streams),
@@ -182,6 +220,7 @@ def _serving(P, torch, n_req: int, budget: int, max_active: int, streams: int):
         r = run(frac * x)
         r["rate_req_s"] = frac * x
         out["open_%.1fX" % frac] = r
+        _log("serving open loop %.1fX: p50 %.2f ms p99 %.2f ms" % (frac, r["p50_ms"], r["p99_ms"]))
     return out
 
 
@@ -225,6 +264,7 @@ def _tall_skinny(P, torch, dev, stream, m: int, n: int, steps: int):
             rec = {"ms": ms_, "tflops_mn2": float(m) * n * n / (ms_ * 1e-3) / 1e12, "depth": d,
                    "scaled_err_sampled": worst}
             out["%s_d%d" % (name, d)] = rec
+            _log("tall %s depth %d: %.2f ms" % (name, d, ms_))
             if best is None or ms_ < best["ms"]:
                 best = rec
         out[name] = best
@@ -241,15 +281,18 @@ def main():
     ap.add_argument("--cutoff", type=int, default=0, help="0: tune over {128,256,512}")
     ap.add_argument("--max-depth", type=int, default=None, help="default: tune over {1, 2}")
     ap.add_argument("--variant", default="strassen")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classical", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--precision-n", type=int, default=8192)
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=10000)
+    ap.add_argument("--serving-requests", type=int, default=5000)
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--no-tall", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="after the timed steps, copy this many bytes device to device three times "
+                         "(a plain copy of known size for scaling hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -293,6 +336,7 @@ def main():
         for d in depths:
             run(c, d)
             sweep["c%d_d%d" % (c, d)] = time_steps(lambda: run(c, d), 3)
+            _log("sweep cutoff %d depth %d: %.2f ms" % (c, d, sweep["c%d_d%d" % (c, d)]))
     best = min(sweep, key=sweep.get)
     cutoff, depth = (int(x[1:]) for x in best.split("_"))
 
@@ -303,6 +347,7 @@ def main():
     ms = time_steps(lambda: run(cutoff, depth), args.steps)
     prof = P.profile_collect()
     P.profile_enable(False)
+    _log("timed %d steps: %.3f ms/step" % (args.steps, ms))
 
     # correctness spot check of the timed output (diagonal = squared column norms)
     diag_idx = torch.arange(1, n + 1, device=dev, dtype=torch.int64)
@@ -324,14 +369,22 @@ def main():
     if mult_key:
         alg_flops = 2.0 * st[mult_key] / launches_per_step
         roof = {"bound": "mfma", "achieved": alg_flops / (avg_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
+                "unit": "TFLOP/s", "algorithmic_flops_per_launch": alg_flops}
     else:
         roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] else None
-    roof["traffic"] = None
     roof["kernel"] = {"strassen": "k_str_f64", "gemm": "k_gemm_f64", "syrk": "k_gemm_f64",
                       "combine": "k_combine_f64"}.get(dom, dom)
+    roof["traffic"] = _profiled_traffic(roof["kernel"], n, cutoff, depth)
     roof["avg_launch_ms"] = avg_ms
+
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        del src, dst
 
     classical = None
     if not args.no_classical:
@@ -355,6 +408,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        _log("oracle CPU baseline")
         cpu = _cpu_baseline(A_np, args.cpu_seconds)
 
     out = {

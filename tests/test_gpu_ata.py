@@ -205,16 +205,17 @@ def _sampled_check(orc, A_np, C, pairs, tol):
     return worst
 
 
-@pytest.mark.parametrize("n,cutoff", [(5000, 256), (10000, 256)])
-def test_square_full_size_sampled(env, orc, n, cutoff):
-    """Full-size square workload in the benchmark's configuration: sampled
-    entries against the oracle, the diagonal against squared column norms,
-    and a Freivalds product check."""
+@pytest.mark.parametrize("n,cutoff,depth", [(5000, 256, 2), (5000, 512, 1)] +
+                         [(10000, c, d) for c in (128, 256, 512) for d in (1, 2)])
+def test_square_full_size_sampled(env, orc, n, cutoff, depth):
+    """Full-size square workload in every configuration the benchmark's
+    tuning may choose: sampled entries against the oracle, the diagonal
+    against squared column norms, and a Freivalds product check."""
     torch, P = env
-    _say("case: square", n, cutoff)
+    _say("case: square", n, cutoff, depth)
     A_np = synthetic.uniform(n, n, synthetic.SEED_SQUARE)
     A = torch.from_numpy(A_np).cuda()
-    C = P.gram(A, cutoff=cutoff)
+    C = P.gram(A, cutoff=cutoff, max_depth=depth)
     torch.cuda.synchronize()
     Cn = C.cpu().numpy()
     rng = np.random.default_rng(5)
@@ -266,3 +267,58 @@ def test_split_k_tall_scaled_fp64(env, orc):
     ref = orc.classical(A)
     assert orc.rel_fro(C, ref, 256) <= FP64_TOL
     assert orc.scaled_err(C, ref, 256) <= FP64_TOL
+
+
+@pytest.fixture(scope="module")
+def tall_full(env):
+    torch, P = env
+    A64 = synthetic.tall_scaled(262144, 2048)
+    return A64, torch.from_numpy(A64).cuda()
+
+
+# Scaled-error bounds max |dC_ij| / sqrt(C_ii C_jj) for the least-squares
+# shape, whose column scales span 1e-3..1e3.  Classical leaves keep every
+# entry at its own scale; a Strassen level adds and subtracts columns of
+# very different size before the product, so small entries inherit the
+# rounding of large ones (error growth of fast products, measured here).
+TALL_BOUNDS = {("f64", 0): 1e-13, ("f64", 1): 1e-9, ("f64", 2): 1e-9,
+               ("f32", 0): 1e-6, ("f32", 1): 2e-2, ("f32", 2): 2e-2}
+
+
+@pytest.mark.parametrize("dtype_name,depth", sorted(TALL_BOUNDS))
+def test_tall_full_size_sampled(env, orc, tall_full, dtype_name, depth):
+    """The 262144 x 2048 least-squares shape at full size in the benchmark's
+    configurations (cutoff 256, 0-2 Strassen levels): sampled scaled errors
+    against the oracle and a normwise Freivalds check."""
+    torch, P = env
+    A64, A64d = tall_full
+    _say("case: tall full", dtype_name, depth)
+    if dtype_name == "f64":
+        Ad, Ah, dt = A64d, A64, P.F64
+    else:
+        Ad = A64d.float()
+        Ah, dt = Ad.cpu().numpy().astype(np.float64), P.F32 | P.OUT_F64
+    C = P.gram(Ad, dtype=dt, cutoff=256, max_depth=depth)
+    torch.cuda.synchronize()
+    Cn = C.cpu().numpy()
+    n = Ah.shape[1]
+    rng = np.random.default_rng(11)
+    pairs = [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(40)]
+    pairs += [(n - 1, 0), (n - 1, n - 1), (n // 2, n // 2 - 1)]
+    worst = 0.0
+    for i, j in pairs:
+        i, j = max(i, j), min(i, j)
+        cols = np.ascontiguousarray(Ah[:, [j, i]])
+        ref = orc.classical(cols)
+        cij = ref[1] if i != j else ref[0]
+        worst = max(worst, abs(Cn[i * (i + 1) // 2 + j] - cij) / np.sqrt(ref[0] * ref[2]))
+    assert worst <= TALL_BOUNDS[(dtype_name, depth)], worst
+    # normwise: || C x - A^t (A x) || / (||A||_F^2 ||x||), FP64 on the GPU
+    x = torch.from_numpy(rng.standard_normal(n)).cuda()
+    full = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    il = torch.tril_indices(n, n, device="cuda")
+    full[il[0], il[1]] = C
+    full = full + full.tril(-1).T
+    Ad64 = torch.from_numpy(Ah).cuda() if dtype_name == "f32" else A64d
+    res = ((full @ x) - Ad64.T @ (Ad64 @ x)).norm().item() / (Ad64.norm().item() ** 2 * x.norm().item())
+    assert res <= (1e-14 if dtype_name == "f64" else 1e-6), res
