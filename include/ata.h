@@ -72,16 +72,26 @@ typedef struct ata_opts {
                             cutoff), 0 = classical off-diagonal products,
                             k > 0 = at most k levels.  Default when the
                             struct is NULL: ATA_DEFAULT_MAX_DEPTH. */
-    int32_t flags;       /* reserved, must be 0 */
+    int32_t flags;       /* ATA_OPT_* bits, default 0 */
     int32_t reserved;
 } ata_opts;
+
+/* ata_opts.flags: run the last Strassen level of each off-diagonal product
+ * inside the workgroup tile (seven products in registers, combined in the
+ * epilogue).  Without it every level up to two is expanded into signed
+ * operand terms: each of the 7^d products is a classical tile whose staging
+ * sums the terms, written to the workspace and combined by a separate pass
+ * (deeper products use the in-tile form either way). */
+#define ATA_OPT_INTILE 0x1
 
 #define ATA_DEFAULT_MAX_DEPTH 2
 #define ATA_MAX_DEPTH_LIMIT 4 /* deepest supported Strassen level count */
 
 /*
  * ata: C_lower = lower(A^t A) for the m x n matrix A (Algorithm 1).
- *   A        device pointer (double for ATA_F64, else float), lda >= max(n,1)
+ *   A        device pointer (double for ATA_F64, else float), lda >= max(n,1);
+ *            rows longer than 64 MiB (lda x element bytes) give
+ *            ATA_EUNSUPPORTED
  *   m, n     >= 0.  n == 0: nothing is written; m == 0: C_lower is zeroed
  *            (empty sum).
  *   C_lower  device pointer, n(n+1)/2 elements of the output type

@@ -24,6 +24,7 @@ OUT_F64 = 0x100
 STRASSEN = 0
 WINOGRAD = 1
 DEFAULT_MAX_DEPTH = 2
+OPT_INTILE = 0x1
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _lib = None
@@ -105,30 +106,32 @@ def tri(n: int) -> int:
     return n * (n + 1) // 2
 
 
-def _opts(variant, max_depth, dtype=F64):
+def _opts(variant, max_depth, dtype=F64, intile=False):
     o = Opts()
     o.variant = {"strassen": STRASSEN, "winograd": WINOGRAD}.get(variant, variant)
     if max_depth is None:
         # reduced-precision leaves are classical; other forms fuse two Strassen levels
         max_depth = 0 if (dtype & 0xff) in (F32_BF16X3, F32_FP8) else DEFAULT_MAX_DEPTH
     o.max_depth = int(max_depth)
-    o.flags = 0
+    o.flags = OPT_INTILE if intile else 0
     return o
 
 
-def plan_info(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None) -> dict:
+def plan_info(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None,
+              intile=False) -> dict:
     """Host-only description of the device plan (no GPU needed)."""
     st = PlanStats()
-    o = _opts(variant, max_depth, dtype)
+    o = _opts(variant, max_depth, dtype, intile)
     rc = load().ata_plan_info(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(st))
     if rc:
         raise AtaError(rc, "ata_plan_info")
     return st.as_dict()
 
 
-def workspace_bytes(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None) -> int:
+def workspace_bytes(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None,
+                    intile=False) -> int:
     out = ctypes.c_size_t(0)
-    o = _opts(variant, max_depth, dtype)
+    o = _opts(variant, max_depth, dtype, intile)
     rc = load().ata_workspace_bytes(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(out))
     if rc:
         raise AtaError(rc, "ata_workspace_bytes")
@@ -192,10 +195,11 @@ def _stream_handle(stream):
 
 
 def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_depth=None, out=None,
-         workspace=None, stream=None):
+         workspace=None, stream=None, intile=False):
     """Packed lower triangle of A^t A for a 2-D CUDA tensor A (row-major rows,
     unit column stride, row stride >= n).  Asynchronous on `stream` (default:
-    torch's current stream).  Returns the packed output tensor."""
+    torch's current stream).  Returns the packed output tensor.  intile: run
+    the last Strassen level inside each workgroup tile (OPT_INTILE)."""
     import torch
     lib = load()
     if A.dim() != 2:
@@ -216,7 +220,7 @@ def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_d
         out = torch.empty(tri(n), dtype=out_t, device=A.device)
     elif out.dtype != out_t or out.numel() < tri(n) or not out.is_contiguous():
         raise ValueError("bad output tensor")
-    o = _opts(variant, max_depth, dtype)
+    o = _opts(variant, max_depth, dtype, intile)
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()

@@ -36,7 +36,7 @@ int hip_fail(hipError_t e) {
         if (_e != hipSuccess) return hip_fail(_e); \
     } while (0)
 
-using PlanKey = std::tuple<int, int64_t, int64_t, int64_t, int, int>;
+using PlanKey = std::tuple<int, int64_t, int64_t, int64_t, int, int, int>;
 
 std::mutex g_mu;
 std::map<PlanKey, std::shared_ptr<PlanDev>> g_plans;
@@ -70,12 +70,16 @@ void serialize(PlanDev& pd) {
         PhaseDev& d = pd.phases[i];
         d.n_str = (int)ph.str_items.size();
         d.str_tmax = ph.str_tmax;
+        d.n_tg = (int)ph.tg_items.size();
+        d.tg_tmax = ph.tg_tmax;
         d.n_gemm = (int)ph.gemm_items.size();
         d.n_syrk = (int)ph.syrk_items.size();
         d.n_cb = (int)ph.combines.size();
         d.cb_elems = ph.combine_elems;
         d.off_str = off;
         off = align256(off + ph.str_items.size() * sizeof(WorkItem));
+        d.off_tg = off;
+        off = align256(off + ph.tg_items.size() * sizeof(WorkItem));
         d.off_gemm = off;
         off = align256(off + ph.gemm_items.size() * sizeof(WorkItem));
         d.off_syrk = off;
@@ -92,6 +96,7 @@ void serialize(PlanDev& pd) {
         const Phase& ph = P.phases[i];
         const PhaseDev& d = pd.phases[i];
         std::memcpy(host.data() + d.off_str, ph.str_items.data(), ph.str_items.size() * sizeof(WorkItem));
+        std::memcpy(host.data() + d.off_tg, ph.tg_items.data(), ph.tg_items.size() * sizeof(WorkItem));
         std::memcpy(host.data() + d.off_gemm, ph.gemm_items.data(), ph.gemm_items.size() * sizeof(WorkItem));
         std::memcpy(host.data() + d.off_syrk, ph.syrk_items.data(), ph.syrk_items.size() * sizeof(WorkItem));
         std::memcpy(host.data() + d.off_cb, ph.combines.data(), ph.combines.size() * sizeof(DevCombine));
@@ -106,13 +111,15 @@ int upload(PlanDev& pd, int dev) {
     return ATA_OK;
 }
 
-int resolve_opts(const ata_opts* opts, int& variant, int& max_depth) {
+int resolve_opts(const ata_opts* opts, int& variant, int& max_depth, int& flags) {
     variant = ATA_VARIANT_STRASSEN;
     max_depth = ATA_DEFAULT_MAX_DEPTH;
+    flags = 0;
     if (opts) {
         variant = opts->variant;
         max_depth = opts->max_depth;
-        if (opts->flags != 0) return -1;
+        flags = opts->flags;
+        if (flags & ~ATA_OPT_INTILE) return -1;
     }
     if (variant != ATA_VARIANT_STRASSEN && variant != ATA_VARIANT_WINOGRAD) return -1;
     if (max_depth < -1) return -1;
@@ -172,13 +179,13 @@ int64_t default_cutoff(int64_t m, int64_t n, int dtype) {
 }
 
 // Build (or fetch) the plan for the current device.
-int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, bool need_device,
+int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, int flags, bool need_device,
              std::shared_ptr<PlanDev>& out) {
     int dev = -1;
     if (need_device) {
         HIP_TRY(hipGetDevice(&dev));
     }
-    const PlanKey key{dev, m, n, cutoff, variant, max_depth};
+    const PlanKey key{dev, m, n, cutoff, variant, max_depth, flags};
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
@@ -190,6 +197,7 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, b
     po.cutoff = cutoff;
     po.variant = variant;
     po.max_depth = max_depth;
+    po.intile = (flags & ATA_OPT_INTILE) != 0;
     try {
         pd->plan = build_plan(m, n, po);
     } catch (const std::length_error&) {
@@ -287,6 +295,7 @@ int common_checks(const void* A, int64_t m, int64_t n, int64_t lda, const void* 
     if (ua % elem_bytes_in(dtype)) return -1;
     if (uc % elem_bytes_out(dtype)) return -5;
     if (m > INT32_MAX || n > INT32_MAX) return ATA_EUNSUPPORTED;
+    if (lda > kMaxRowBytes / elem_bytes_in(dtype)) return ATA_EUNSUPPORTED;
     return 0;
 }
 
@@ -341,7 +350,7 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             }
             continue;
         }
-        const bool split = ph.n_str > 0 && (ph.n_gemm + ph.n_syrk) > 0;
+        const bool split = (ph.n_str + ph.n_tg) > 0 && (ph.n_gemm + ph.n_syrk) > 0;
         ForkCtx fc;
         if (split) {
             rc = fork_get(dev, fc);
@@ -353,6 +362,11 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             ProfScope ps(ATA_KERNEL_STRASSEN, s);
             err = launch_str(f32, out64, variant, ph.str_tmax, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_str),
                              ph.n_str, C_lower, W, s);
+        }
+        if (err == hipSuccess && ph.n_tg) {
+            ProfScope ps(ATA_KERNEL_STRASSEN, s);
+            err = launch_gemm_terms(f32, out64, ph.tg_tmax, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_tg),
+                                    ph.n_tg, C_lower, W, s);
         }
         hipStream_t s_small = split ? fc.s2 : s;
         if (err == hipSuccess && ph.n_gemm) {
@@ -412,8 +426,8 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     if (n < 0) return -2;
     if (!dtype_valid(dtype)) return -3;
     if (cutoff < 0) return -4;
-    int variant, max_depth;
-    if (resolve_opts(opts, variant, max_depth)) return -5;
+    int variant, max_depth, flags;
+    if (resolve_opts(opts, variant, max_depth, flags)) return -5;
     if (!out) return -6;
     if (dtype_lp(dtype)) {
         if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
@@ -421,7 +435,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     }
     const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
     std::shared_ptr<PlanDev> pd;
-    const int rc = get_plan(m, n, c, variant, max_depth, false, pd);
+    const int rc = get_plan(m, n, c, variant, max_depth, flags, false, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
     std::memset(out, 0, sizeof(*out));
@@ -457,8 +471,8 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
            void* stream, const ata_opts* opts, void* workspace, size_t ws_bytes) {
     int rc = common_checks(A, m, n, lda, C_lower, dtype, cutoff);
     if (rc) return rc;
-    int variant, max_depth;
-    if (resolve_opts(opts, variant, max_depth)) return -9;
+    int variant, max_depth, flags;
+    if (resolve_opts(opts, variant, max_depth, flags)) return -9;
     const bool lp = dtype_lp(dtype);
     if (lp) {
         // reduced-precision leaves: classical off-diagonal products only
@@ -481,7 +495,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     }
     const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
     std::shared_ptr<PlanDev> pd;
-    rc = get_plan(m, n, c, variant, max_depth, true, pd);
+    rc = get_plan(m, n, c, variant, max_depth, flags, true, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
     const WsLayout L = ws_layout(m, n, dtype, P.ws_elems);

@@ -14,9 +14,9 @@ namespace detail {
 
 // Device copy of one plan's tables.
 struct PhaseDev {
-    int n_str = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, str_tmax = 0;
+    int n_str = 0, n_tg = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, str_tmax = 0, tg_tmax = 0;
     int64_t cb_elems = 0;
-    size_t off_str = 0, off_gemm = 0, off_syrk = 0, off_cb = 0;
+    size_t off_str = 0, off_tg = 0, off_gemm = 0, off_syrk = 0, off_cb = 0;
 };
 
 struct PlanDev {
@@ -51,7 +51,7 @@ int elem_bytes_in(int dtype);
 int elem_bytes_out(int dtype);
 int64_t default_cutoff(int64_t m, int64_t n, int dtype);
 WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems);
-int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, bool need_device,
+int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, int flags, bool need_device,
              std::shared_ptr<PlanDev>& out);
 // dblob: device copy of pd.host_blob (pd.blob, or a copy the caller made)
 hipError_t enqueue_product(const PlanDev& pd, const char* dblob, const WsLayout& L, const void* A, int64_t m,

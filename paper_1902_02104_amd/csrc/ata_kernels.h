@@ -21,6 +21,11 @@ struct DevTables {
 hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
                        const WorkItem* items, int nitems, void* C, double* W, hipStream_t s);
 
+// Strassen product tiles: classical tiles whose operands are signed sums of
+// up to tmax terms (column padding reads as zero), written to the workspace.
+hipError_t launch_gemm_terms(bool f32, bool out_f64, int tmax, const void* A, int64_t lda, const DevTables& tb,
+                             const WorkItem* items, int nitems, void* C, double* W, hipStream_t s);
+
 // Classical tiles of several requests in one launch: work item w uses
 // batch[w.slot] for its matrices and tables.
 hipError_t launch_gemm_batch(bool f32, bool out_f64, const BatchEntry* batch, const WorkItem* items, int nitems,

@@ -38,6 +38,44 @@ typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int64_t packed_index(int64_t r, int64_t q) { return r * (r + 1) / 2 + q; }
 
 // ---------------------------------------------------------------------------
+// Operand staging through raw buffer loads.  A buffer resource covers the
+// valid rows of one operand slab (num_records = rows x row bytes); a load
+// whose offset lies at or past num_records returns zero without touching
+// memory.  This gives the zero padding of ragged quadrants and K tails
+// without branches.  Offsets are 32-bit: a slab spans at most kStageRows
+// rows of at most kMaxRowBytes (checked at the API).
+// ---------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t kOOB = 0x80000000u;  // an offset past every record count used here
+constexpr int kStageRows = 16;
+static_assert(kStageRows * kMaxRowBytes <= (int64_t)kOOB / 2, "slab offsets must stay below kOOB");
+
+__device__ __forceinline__ rsrc_t slab_rsrc(const void* base, int nrows, int64_t row_bytes) {
+    const int bytes = nrows > 0 ? (int)(nrows * row_bytes) : 0;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T bload(rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
+// x with its sign bit flipped when flip is set (an exact negation).
+__device__ __forceinline__ double flip_sign(double x, bool flip) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x) ^ (flip ? 0x8000000000000000ull : 0ull);
+    return __builtin_bit_cast(double, b);
+}
+__device__ __forceinline__ float flip_sign(float x, bool flip) {
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x) ^ (flip ? 0x80000000u : 0u));
+}
+
+// ---------------------------------------------------------------------------
 // MFMA engines for the tile kernels staged from A directly
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -78,12 +116,19 @@ __device__ __forceinline__ void store_out(OUT* p, int beta, double v) {
 // ---------------------------------------------------------------------------
 // Classical tile kernel: TK_SYRK (lower triangle of a diagonal block) and
 // TK_GEMM (dense off-diagonal block).  128 x 128 output tile per workgroup,
-// four waves of 64 x 64, K staged 16 rows at a time, double-buffered LDS.
+// four waves of 64 x 64, double-buffered LDS, two workgroups per CU.
+//   TMAX == 1: base-case tiles; K staged 16 rows at a time.  Columns past an
+//              operand's end only feed outputs that are never stored, so they
+//              load unmasked.
+//   TMAX > 1:  Strassen product tiles: each operand is a signed sum of up to
+//              TMAX terms (quadrant blocks of A), summed in term order while
+//              staging; a term's columns past its end (padding) stage as
+//              zero.  Four-term operands stage 8 rows at a time to bound the
+//              registers that hold the terms in flight.
 // ---------------------------------------------------------------------------
 constexpr int GT = kGemmTile;  // 128
-constexpr int GK = 16;
 
-template <typename T, typename OUT, bool BATCH>
+template <typename T, typename OUT, bool BATCH, int TMAX>
 __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64_t lda_,
                                                  const DevTask* __restrict__ tasks_,
                                                  const DevTerm* __restrict__ terms_,
@@ -93,6 +138,9 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
     typedef Eng<T> E;
     constexpr bool F32 = std::is_same<T, float>::value;
     constexpr int BR = 64 / E::RM, BC = 64 / E::RN;
+    constexpr int GK = (TMAX == 1 || (TMAX == 2 && !F32)) ? 16 : 8;  // k rows per stage
+    constexpr int EPT = GK * GT / 256;           // elements per thread, term and side
+    constexpr int TPR = GT / EPT;                // threads per staged row
     __shared__ T Xs[2][GK][GT + E::PAD];
     __shared__ T Ys[2][GK][GT + E::PAD];
 
@@ -113,18 +161,43 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
         lda = be.lda;
     }
     const DevTask t = tasks[w.task];
-    const DevTerm tx = terms[t.term_off];
-    const DevTerm ty = terms[t.term_off + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int i0 = w.ti * GT, j0 = w.tj * GT;
 
-    // staging map: thread -> row lk of the k tile, 8 consecutive columns at lc
-    const int lk = tid >> 4, lc = (tid & 15) * 8;
-    const int xcol = tx.col + i0 + lc;
-    const int ycol = ty.col + j0 + lc;
-    const int xcv = tx.cvend - xcol;  // columns valid from xcol (may be <= 0)
-    const int ycv = ty.cvend - ycol;
+    // staging map: thread -> row lk of the k tile, EPT consecutive columns at lc
+    const int lk = tid / TPR, lc = (tid % TPR) * EPT;
+    const int64_t row_bytes = lda * (int64_t)sizeof(T);
+    constexpr uint32_t ES = (uint32_t)sizeof(T);
+    // per term: byte offset of the thread's first column inside a slab and
+    // the number of its columns inside the term (later ones are padding)
+    uint32_t xo[TMAX], yo[TMAX];
+    int xcv[TMAX], ycv[TMAX];
+    T xsgn[TMAX], ysgn[TMAX];
+#pragma unroll
+    for (int u = 0; u < TMAX; ++u) {
+        xsgn[u] = ysgn[u] = T(0);
+        xo[u] = yo[u] = 0;
+        xcv[u] = ycv[u] = 0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int nt = side == 0 ? t.nx : t.ny;
+            if (u >= nt) continue;
+            const DevTerm tm = terms[t.term_off + (side == 0 ? u : t.nx + u)];
+            const int col = tm.col + (side == 0 ? i0 : j0) + lc;
+            const uint32_t base = (uint32_t)(lk * row_bytes) + (uint32_t)col * ES;
+            const int cv = TMAX == 1 ? EPT : tm.cvend - col;
+            if (side == 0) {
+                xo[u] = base;
+                xcv[u] = cv;
+                xsgn[u] = (T)tm.sign;
+            } else {
+                yo[u] = base;
+                ycv[u] = cv;
+                ysgn[u] = (T)tm.sign;
+            }
+        }
+    }
 
     typename E::accv_t acc[BR][BC];
     double acc64[F32 ? BR : 1][F32 ? BC : 1][F32 ? E::NA : 1];
@@ -141,53 +214,79 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
                 for (int e = 0; e < (F32 ? E::NA : 1); ++e) acc64[a][b][e] = 0.0;
     }
 
-    // k-tile cursor over the segments: rows row + k for k in [kbeg, kend)
+    // k-tile cursor over the segments: rows row_u + k for k in [kbeg, kend)
     const int stride = kSegHdr + 2 * (t.nx + t.ny);
     int seg = 0;
     int k0 = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
-    int klen = t.nseg > 0 ? segs[t.seg_off + 2] : 0;  // window end
-    int xrow = t.nseg > 0 ? segs[t.seg_off + kSegHdr] : 0;
-    int yrow = t.nseg > 0 ? segs[t.seg_off + kSegHdr + 2] : 0;
+    int kend = t.nseg > 0 ? segs[t.seg_off + 2] : 0;
     int ntiles = 0;
     for (int s = 0; s < t.nseg; ++s)
         ntiles += (segs[t.seg_off + s * stride + 2] - segs[t.seg_off + s * stride + 1] + GK - 1) / GK;
 
-    T xr[8], yr[8];
-    auto load = [&](int kk0, int kl, int xr0, int yr0) {
-        const bool rv = (kk0 + lk) < kl;
-        const T* px = A + (int64_t)(xr0 + kk0 + lk) * lda + xcol;
-        const T* py = A + (int64_t)(yr0 + kk0 + lk) * lda + ycol;
+    T xr[TMAX][EPT], yr[TMAX][EPT];
+    // Issue the loads of the k tile at k0: the slab of term u holds its rows
+    // below both the window end and the term's row end.
+    auto load = [&]() {
+        const int32_t* sg = segs + t.seg_off + seg * stride;
+        const int krem = kend - k0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            xr[e] = (rv && e < xcv) ? px[e] : T(0);
-            yr[e] = (rv && e < ycv) ? py[e] : T(0);
+        for (int u = 0; u < TMAX; ++u) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int nt = side == 0 ? t.nx : t.ny;
+                const int h = side == 0 ? 2 * u : 2 * (t.nx + u);
+                const int row0 = u < nt ? sg[kSegHdr + h] : 0;
+                const int rvend = u < nt ? sg[kSegHdr + 1 + h] : 0;
+                const int base = row0 + k0;
+                int nv = rvend - base < krem ? rvend - base : krem;
+                nv = nv < GK ? nv : GK;
+                const rsrc_t rs = slab_rsrc(A + (int64_t)base * lda, u < nt ? nv : 0, row_bytes);
+                // unmasked: reads stay inside the slab or return zero; term
+                // padding is zeroed when the terms are summed
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    if (side == 0) xr[u][e] = bload<T>(rs, xo[u] + e * ES);
+                    else yr[u][e] = bload<T>(rs, yo[u] + e * ES);
+                }
+            }
         }
     };
     auto advance = [&]() {
         k0 += GK;
-        if (k0 >= klen) {
+        if (k0 >= kend) {
             ++seg;
             if (seg < t.nseg) {
                 k0 = segs[t.seg_off + seg * stride + 1];
-                klen = segs[t.seg_off + seg * stride + 2];
-                xrow = segs[t.seg_off + seg * stride + kSegHdr];
-                yrow = segs[t.seg_off + seg * stride + kSegHdr + 2];
+                kend = segs[t.seg_off + seg * stride + 2];
             }
         }
     };
 
-    if (ntiles > 0) load(k0, klen, xrow, yrow);
+    if (ntiles > 0) load();
     for (int it = 0; it < ntiles; ++it) {
         const int buf = it & 1;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            Xs[buf][lk][lc + e] = xr[e];
-            Ys[buf][lk][lc + e] = yr[e];
+        for (int e = 0; e < EPT; ++e) {
+            T x, y;
+            if (TMAX == 1) {
+                x = xr[0][e];
+                y = yr[0][e];
+            } else {
+                x = xsgn[0] * (e < xcv[0] ? xr[0][e] : T(0));
+                y = ysgn[0] * (e < ycv[0] ? yr[0][e] : T(0));
+#pragma unroll
+                for (int u = 1; u < TMAX; ++u) {
+                    x += xsgn[u] * (e < xcv[u] ? xr[u][e] : T(0));
+                    y += ysgn[u] * (e < ycv[u] ? yr[u][e] : T(0));
+                }
+            }
+            Xs[buf][lk][lc + e] = x;
+            Ys[buf][lk][lc + e] = y;
         }
         __syncthreads();
         if (it + 1 < ntiles) {
             advance();
-            load(k0, klen, xrow, yrow);
+            load();
         }
 #pragma unroll
         for (int ks = 0; ks < GK / 4; ++ks) {
@@ -241,10 +340,11 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
 // In-tile Strassen kernel (TK_STR).  The product P = Xop^t Yop (padded M x N,
 // K per segment) is split once more into quadrants; a workgroup owns the
 // 64 x 64 tile at (ti, tj) of all four result quadrants and keeps the seven
-// products in registers (eight waves of 16 x 32 each).  Operand terms of
-// higher levels are summed while staging to LDS; the quadrant sums of this
-// level are formed in registers from the four staged quadrant tiles.  The
-// products are combined in FP64.
+// products in registers (eight waves of 16 x 32 each).  While a k tile is
+// staged, each thread sums the operand terms of higher levels, forms the
+// seven left and seven right operands of this level from the four quadrant
+// values it holds, and writes them to fourteen LDS planes; the MFMA loop
+// then reads operands directly.  The products are combined in FP64.
 // ---------------------------------------------------------------------------
 constexpr int ST = kStrTile;  // 64
 
@@ -320,8 +420,8 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
     typedef Eng<T> E;
     constexpr bool F32 = std::is_same<T, float>::value;
     constexpr int BR = 16 / E::RM, BC = 32 / E::RN;
-    __shared__ T Xs[2][4][SK][ST + E::PAD];
-    __shared__ T Ys[2][4][SK][ST + E::PAD];
+    __shared__ T Xs[2][7][SK][ST + E::PAD];
+    __shared__ T Ys[2][7][SK][ST + E::PAD];
 
     const WorkItem w = items[blockIdx.x];
     const DevTask t = tasks[w.task];
@@ -335,31 +435,36 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
     const int lk = tid >> 6, lc = tid & 63;
     constexpr int KR = SK / 8;
 
-    // Per-term column data, fixed for the whole K loop.
-    int xcol[TMAX][2], ycol[TMAX][2];
-    unsigned xmask[TMAX], ymask[TMAX];  // bit a: column of half a valid
+    // Per-term column byte offsets, fixed for the whole K loop; a column
+    // outside the term (quadrant padding) gets an out-of-range offset and
+    // stages as zero.  Absent terms (u >= nx) have zero-row slabs.
+    const int64_t row_bytes = lda * (int64_t)sizeof(T);
+    uint32_t xoff[TMAX][2], yoff[TMAX][2];
+    bool xneg[TMAX], yneg[TMAX];
     T xsgn[TMAX], ysgn[TMAX];
 #pragma unroll
     for (int u = 0; u < TMAX; ++u) {
-        xmask[u] = ymask[u] = 0u;
+        xoff[u][0] = xoff[u][1] = yoff[u][0] = yoff[u][1] = kOOB;
+        xneg[u] = yneg[u] = false;
         xsgn[u] = ysgn[u] = T(0);
-        xcol[u][0] = xcol[u][1] = ycol[u][0] = ycol[u][1] = 0;
         if (u < t.nx) {
             const DevTerm tm = terms[t.term_off + u];
             xsgn[u] = (T)tm.sign;
+            xneg[u] = tm.sign < 0;
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-                xcol[u][a] = tm.col + a * MH + i0 + lc;
-                if (i0 + lc < MH && xcol[u][a] < tm.cvend) xmask[u] |= 1u << a;
+                const int col = tm.col + a * MH + i0 + lc;
+                if (i0 + lc < MH && col < tm.cvend) xoff[u][a] = (uint32_t)col * (uint32_t)sizeof(T);
             }
         }
         if (u < t.ny) {
             const DevTerm tm = terms[t.term_off + t.nx + u];
             ysgn[u] = (T)tm.sign;
+            yneg[u] = tm.sign < 0;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                ycol[u][c] = tm.col + c * NH + j0 + lc;
-                if (j0 + lc < NH && ycol[u][c] < tm.cvend) ymask[u] |= 1u << c;
+                const int col = tm.col + c * NH + j0 + lc;
+                if (j0 + lc < NH && col < tm.cvend) yoff[u][c] = (uint32_t)col * (uint32_t)sizeof(T);
             }
         }
     }
@@ -391,62 +496,69 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
     int kend = t.nseg > 0 ? segs[t.seg_off + 2] : 0;
 
     // Issue every load of the next k tile; nothing waits on them here.
+    // Rows of half b of term u for this tile start at row0 + b kh + k0; the
+    // slab holds those below both the window end and the term's row end.
+    const uint32_t roff = (uint32_t)(lk * row_bytes);
     auto load = [&]() {
         const int32_t* sg = segs + t.seg_off + seg * stride;
+        const int krem = kend - k0;
 #pragma unroll
-        for (int r = 0; r < KR; ++r) {
-            const int kk = k0 + lk + 8 * r;
-            const bool kv = kk < kend;
+        for (int u = 0; u < TMAX; ++u) {
 #pragma unroll
-            for (int u = 0; u < TMAX; ++u) {
-                if (u < t.nx) {
-                    const int row0 = sg[kSegHdr + 2 * u], rvend = sg[kSegHdr + 1 + 2 * u];
+            for (int side = 0; side < 2; ++side) {
+                const int nt = side == 0 ? t.nx : t.ny;
+                const int h = side == 0 ? 2 * u : 2 * (t.nx + u);
+                const int row0 = u < nt ? sg[kSegHdr + h] : 0, rvend = u < nt ? sg[kSegHdr + 1 + h] : 0;
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const int row = row0 + b * kh + kk;
-                        const bool rok = kv && row < rvend;
-                        const T* pr = A + (int64_t)row * lda;
+                for (int b = 0; b < 2; ++b) {
+                    const int base = row0 + b * kh + k0;
+                    int nv = rvend - base < krem ? rvend - base : krem;
+                    nv = nv < SK ? nv : SK;
+                    const rsrc_t rs = slab_rsrc(A + (int64_t)base * lda, u < nt ? nv : 0, row_bytes);
 #pragma unroll
-                        for (int a = 0; a < 2; ++a)
-                            xraw[u][r][a * 2 + b] = (rok && ((xmask[u] >> a) & 1u)) ? pr[xcol[u][a]] : T(0);
-                    }
-                } else {
+                    for (int r = 0; r < KR; ++r)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) xraw[u][r][q] = T(0);
-                }
-                if (u < t.ny) {
-                    const int row0 = sg[kSegHdr + 2 * (t.nx + u)], rvend = sg[kSegHdr + 1 + 2 * (t.nx + u)];
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const int row = row0 + b * kh + kk;
-                        const bool rok = kv && row < rvend;
-                        const T* pr = A + (int64_t)row * lda;
-#pragma unroll
-                        for (int c = 0; c < 2; ++c)
-                            yraw[u][r][b * 2 + c] = (rok && ((ymask[u] >> c) & 1u)) ? pr[ycol[u][c]] : T(0);
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) yraw[u][r][q] = T(0);
+                        for (int a = 0; a < 2; ++a) {
+                            const uint32_t off = roff + (uint32_t)(8 * r * row_bytes);
+                            if (side == 0)
+                                xraw[u][r][a * 2 + b] = bload<T>(rs, off + xoff[u][a]);
+                            else
+                                yraw[u][r][b * 2 + a] = bload<T>(rs, off + yoff[u][a]);
+                        }
                 }
             }
         }
     };
-    // Signed sum of the terms (fixed order) into the LDS buffer.
+    // Signed sum of the terms (fixed order), then this level's seven left
+    // and right operands, into the LDS buffer.
     auto store = [&](int buf) {
 #pragma unroll
-        for (int r = 0; r < KR; ++r)
+        for (int r = 0; r < KR; ++r) {
+            T x[4], y[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                T x = T(0), y = T(0);
+                if (TMAX == 1) {
+                    x[q] = flip_sign(xraw[0][r][q], xneg[0]);
+                    y[q] = flip_sign(yraw[0][r][q], yneg[0]);
+                } else {
+                    x[q] = xsgn[0] * xraw[0][r][q];
+                    y[q] = ysgn[0] * yraw[0][r][q];
 #pragma unroll
-                for (int u = 0; u < TMAX; ++u) {
-                    x += xsgn[u] * xraw[u][r][q];
-                    y += ysgn[u] * yraw[u][r][q];
+                    for (int u = 1; u < TMAX; ++u) {
+                        x[q] += xsgn[u] * xraw[u][r][q];
+                        y[q] += ysgn[u] * yraw[u][r][q];
+                    }
                 }
-                Xs[buf][q][lk + 8 * r][lc] = x;
-                Ys[buf][q][lk + 8 * r][lc] = y;
             }
+            T lo[7], ro[7];
+            left_operands<VAR>(x[0], x[1], x[2], x[3], lo);
+            right_operands<VAR>(y[0], y[1], y[2], y[3], ro);
+#pragma unroll
+            for (int p = 0; p < 7; ++p) {
+                Xs[buf][p][lk + 8 * r][lc] = lo[p];
+                Ys[buf][p][lk + 8 * r][lc] = ro[p];
+            }
+        }
     };
     auto advance = [&]() {
         k0 += SK;
@@ -476,15 +588,15 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
 #pragma unroll
             for (int cf = 0; cf < BC; ++cf) {
                 const int cc = wn * 32 + cf * E::RN + (lane & 15);
-                right_operands<VAR>(Ys[buf][0][kr][cc], Ys[buf][1][kr][cc], Ys[buf][2][kr][cc],
-                                    Ys[buf][3][kr][cc], ro[cf]);
+#pragma unroll
+                for (int p = 0; p < 7; ++p) ro[cf][p] = Ys[buf][p][kr][cc];
             }
 #pragma unroll
             for (int rb = 0; rb < BR; ++rb) {
                 const int rr = wm * 16 + rb * E::RM + E::arow(lane);
                 T lo[7];
-                left_operands<VAR>(Xs[buf][0][kr][rr], Xs[buf][1][kr][rr], Xs[buf][2][kr][rr],
-                                   Xs[buf][3][kr][rr], lo);
+#pragma unroll
+                for (int p = 0; p < 7; ++p) lo[p] = Xs[buf][p][kr][rr];
 #pragma unroll
                 for (int p = 0; p < 7; ++p)
 #pragma unroll
@@ -935,14 +1047,43 @@ hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const
     const dim3 g(nitems), b(256);
     const BatchEntry* nb = nullptr;
     if (!f32)
-        hipLaunchKernelGGL((k_gemm<double, double, false>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.terms,
+        hipLaunchKernelGGL((k_gemm<double, double, false, 1>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.terms,
                            tb.segs, items, (double*)C, W, nb);
     else if (out_f64)
-        hipLaunchKernelGGL((k_gemm<float, double, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
+        hipLaunchKernelGGL((k_gemm<float, double, false, 1>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
                            tb.segs, items, (double*)C, W, nb);
     else
-        hipLaunchKernelGGL((k_gemm<float, float, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
+        hipLaunchKernelGGL((k_gemm<float, float, false, 1>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
                            tb.segs, items, (float*)C, W, nb);
+    return hipGetLastError();
+}
+
+template <int TM>
+static void launch_gemm_terms_t(bool f32, bool out_f64, dim3 g, const void* A, int64_t lda, const DevTables& tb,
+                                const WorkItem* items, void* C, double* W, hipStream_t s) {
+    const dim3 b(256);
+    const BatchEntry* nb = nullptr;
+    if (!f32)
+        hipLaunchKernelGGL((k_gemm<double, double, false, TM>), g, b, 0, s, (const double*)A, lda, tb.tasks,
+                           tb.terms, tb.segs, items, (double*)C, W, nb);
+    else if (out_f64)
+        hipLaunchKernelGGL((k_gemm<float, double, false, TM>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
+                           tb.segs, items, (double*)C, W, nb);
+    else
+        hipLaunchKernelGGL((k_gemm<float, float, false, TM>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
+                           tb.segs, items, (float*)C, W, nb);
+}
+
+hipError_t launch_gemm_terms(bool f32, bool out_f64, int tmax, const void* A, int64_t lda, const DevTables& tb,
+                             const WorkItem* items, int nitems, void* C, double* W, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const dim3 g(nitems);
+    if (tmax <= 2)
+        launch_gemm_terms_t<2>(f32, out_f64, g, A, lda, tb, items, C, W, s);
+    else if (tmax <= 4)
+        launch_gemm_terms_t<4>(f32, out_f64, g, A, lda, tb, items, C, W, s);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -951,13 +1092,13 @@ hipError_t launch_gemm_batch(bool f32, bool out_f64, const BatchEntry* batch, co
     if (nitems <= 0) return hipSuccess;
     const dim3 g(nitems), b(256);
     if (!f32)
-        hipLaunchKernelGGL((k_gemm<double, double, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
+        hipLaunchKernelGGL((k_gemm<double, double, true, 1>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
                            nullptr, nullptr, batch);
     else if (out_f64)
-        hipLaunchKernelGGL((k_gemm<float, double, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
+        hipLaunchKernelGGL((k_gemm<float, double, true, 1>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
                            nullptr, nullptr, batch);
     else
-        hipLaunchKernelGGL((k_gemm<float, float, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
+        hipLaunchKernelGGL((k_gemm<float, float, true, 1>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
                            nullptr, nullptr, batch);
     return hipGetLastError();
 }
@@ -1010,8 +1151,10 @@ template <typename T, typename OUT, int VAR>
 static void launch_str_t(int tmax, dim3 g, hipStream_t s, const T* A, int64_t lda, const DevTables& tb,
                          const WorkItem* items, OUT* C, double* W) {
     const dim3 b(512);
+    // k rows per stage: fourteen operand planes fill most of the LDS
+    constexpr int SK1 = std::is_same<T, float>::value ? 16 : 8;
     if (tmax <= 1)
-        hipLaunchKernelGGL((k_str<T, OUT, VAR, 1, 16>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W);
+        hipLaunchKernelGGL((k_str<T, OUT, VAR, 1, SK1>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W);
     else if (tmax <= 2)
         hipLaunchKernelGGL((k_str<T, OUT, VAR, 2, 8>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W);
     else if (tmax <= 4)

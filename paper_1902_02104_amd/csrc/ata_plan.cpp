@@ -227,7 +227,10 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             ++P.gemm_tasks;
             continue;
         }
-        // symbolic expansion of the top d-1 levels
+        // symbolic expansion of the top d-1 levels (all d for product tiles)
+        // (Winograd operands reach four terms per level: one level only)
+        const bool tiled = !o.intile && d <= (o.variant == 0 ? kMaxExpandDepth : 1);
+        const int expand = tiled ? d : d - 1;
         const size_t nch = chs.size();
         XTerm x0{1, xc, xc + M, {}, {}}, y0{1, yc, yc + N, {}, {}};
         std::vector<int64_t> K(nch);
@@ -240,7 +243,7 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
         y0.rvend = x0.rvend;
         std::vector<Product> prods{Product{{x0}, {y0}}};
         int64_t Mp = M, Np = N;
-        for (int lev = 1; lev < d; ++lev) {
+        for (int lev = 1; lev <= expand; ++lev) {
             const int64_t MH = ceil2(Mp), NH = ceil2(Np);
             std::vector<int64_t> KH(nch);
             for (size_t c = 0; c < nch; ++c) KH[c] = ceil2(K[c]);
@@ -299,13 +302,59 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             Np = NH;
             K = KH;
         }
-        const bool direct = d == 1;
+        const bool direct = !tiled && d == 1;
         const int64_t ws_base = P.ws_elems;
         if (!direct) P.ws_elems += (int64_t)prods.size() * Mp * Np;
         const int64_t MHin = ceil2(Mp), NHin = ceil2(Np);
-        int64_t khalf = 0;
-        for (size_t c = 0; c < nch; ++c) khalf += ceil2(K[c]);
-        for (size_t s = 0; s < prods.size(); ++s) {
+        int64_t khalf = 0, kfull = 0;
+        for (size_t c = 0; c < nch; ++c) {
+            khalf += ceil2(K[c]);
+            kfull += K[c];
+        }
+        for (size_t s = 0; tiled && s < prods.size(); ++s) {
+            // product s of the fully expanded recursion as a classical tile task
+            const Product& pr = prods[s];
+            if ((int)pr.x.size() > kMaxTerms || (int)pr.y.size() > kMaxTerms)
+                throw std::length_error("Strassen depth needs more operand terms than supported");
+            DevTask t{};
+            t.kind = TK_GEMM;
+            t.variant = o.variant;
+            t.M = (int32_t)Mp;
+            t.N = (int32_t)Np;
+            t.nx = (int32_t)pr.x.size();
+            t.ny = (int32_t)pr.y.size();
+            t.term_off = push_terms(pr.x, pr.y);
+            t.seg_off = (int32_t)P.segs.size();
+            t.nseg = (int32_t)nch;
+            for (size_t c = 0; c < nch; ++c) {
+                check32(K[c]);
+                P.segs.push_back((int32_t)K[c]);  // klen
+                P.segs.push_back(0);              // window [0, klen)
+                P.segs.push_back((int32_t)K[c]);
+                for (const auto* list : {&pr.x, &pr.y})
+                    for (const XTerm& u : *list) {
+                        check32(u.rvend[c]);
+                        P.segs.push_back((int32_t)u.row[c]);
+                        P.segs.push_back((int32_t)u.rvend[c]);
+                    }
+            }
+            t.dst = 1;
+            t.beta = 0;
+            t.dM = (int32_t)Mp;
+            t.dN = (int32_t)Np;
+            t.ws_off = ws_base + (int64_t)s * Mp * Np;
+            t.tiles_m = (int32_t)((Mp + kGemmTile - 1) / kGemmTile);
+            t.tiles_n = (int32_t)((Np + kGemmTile - 1) / kGemmTile);
+            P.mults += Mp * Np * kfull;
+            P.str_mults += Mp * Np * kfull;
+            const int32_t id = (int32_t)P.tasks.size();
+            P.tasks.push_back(t);
+            for (int32_t a = 0; a < t.tiles_m; ++a)
+                for (int32_t b = 0; b < t.tiles_n; ++b) ph(gphase).tg_items.push_back(WorkItem{id, a, b, 0});
+            ph(gphase).tg_tmax = std::max(ph(gphase).tg_tmax, std::max(t.nx, t.ny));
+            ++P.str_tasks;
+        }
+        for (size_t s = 0; !tiled && s < prods.size(); ++s) {
             const Product& pr = prods[s];
             if ((int)pr.x.size() > kMaxTerms || (int)pr.y.size() > kMaxTerms)
                 throw std::length_error("Strassen depth needs more operand terms than supported");
@@ -360,7 +409,7 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             DevCombine cb{};
             cb.M = (int32_t)M;
             cb.N = (int32_t)N;
-            cb.levels = d - 1;
+            cb.levels = expand;
             cb.variant = o.variant;
             cb.r0 = (int32_t)xc;
             cb.q0 = (int32_t)yc;
@@ -425,7 +474,7 @@ void split_k(Plan& P) {
     if (o.split_target <= 0) return;
     for (size_t pi = 0; pi < P.phases.size(); ++pi) {
         Phase& ph = P.phases[pi];
-        const int64_t items = (int64_t)(ph.str_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
+        const int64_t items = (int64_t)(ph.str_items.size() + ph.tg_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
         if (items == 0 || items >= o.split_target) continue;
         const int64_t want = std::min<int64_t>(64, o.split_target / items);
         if (want < 2) continue;
@@ -436,7 +485,7 @@ void split_k(Plan& P) {
             const int64_t k = task_k(P, P.tasks[id]);
             parts[id] = (int)std::max<int64_t>(1, std::min<int64_t>(want, k / o.split_min_k));
         };
-        for (auto* items_v : {&ph.str_items, &ph.gemm_items, &ph.syrk_items})
+        for (auto* items_v : {&ph.str_items, &ph.tg_items, &ph.gemm_items, &ph.syrk_items})
             for (const WorkItem& w : *items_v) decide(w.task);
         // products of one workspace block must share the part count
         for (DevCombine& cb : ph.combines) {
@@ -517,7 +566,7 @@ void split_k(Plan& P) {
                 P.tasks.push_back(t);
             }
         }
-        for (auto* items_v : {&ph.str_items, &ph.gemm_items, &ph.syrk_items}) {
+        for (auto* items_v : {&ph.str_items, &ph.tg_items, &ph.gemm_items, &ph.syrk_items}) {
             std::vector<WorkItem> out;
             for (const WorkItem& w : *items_v) {
                 auto it = newids.find(w.task);
@@ -558,12 +607,12 @@ Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
             const DevTask& t = P.tasks[w.task];
             const double k = (double)task_k(P, t);
             if (t.kind == TK_STR) return 2.0 * k * (1.0 + 0.1 * (t.nx + t.ny));
-            return k;
+            return k * (1.0 + 0.1 * (t.nx + t.ny - 2));
         };
-        for (auto* items : {&ph.str_items, &ph.gemm_items, &ph.syrk_items})
+        for (auto* items : {&ph.str_items, &ph.tg_items, &ph.gemm_items, &ph.syrk_items})
             std::stable_sort(items->begin(), items->end(),
                              [&](const WorkItem& a, const WorkItem& b) { return cost(a) > cost(b); });
-        P.work_items += (int64_t)(ph.str_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
+        P.work_items += (int64_t)(ph.str_items.size() + ph.tg_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
     }
     return P;
 }

@@ -98,14 +98,26 @@ struct PlanOptions {
     // workgroups whose partial results a combination sums in part order.
     int split_target = 768;
     int split_min_k = 2048;
+    // Where the last Strassen level of an off-diagonal product runs.  false:
+    // every level is expanded into signed operand terms and each of the 7^d
+    // products is a classical tile task (TK_GEMM with terms) writing a
+    // workspace slot, summed by a combination.  true: the last level runs
+    // inside each workgroup tile (TK_STR).  Products deeper than
+    // kMaxExpandDepth levels (one for Winograd) always use the in-tile form.
+    bool intile = false;
 };
+
+constexpr int kMaxExpandDepth = 2;
 
 // Launch group: everything that may run after the previous group finished.
 struct Phase {
-    std::vector<WorkItem> str_items, gemm_items, syrk_items;
+    // str: in-tile Strassen tiles; tg: Strassen product tiles (classical
+    // tiles with operand terms); gemm, syrk: classical tiles of the base case
+    std::vector<WorkItem> str_items, tg_items, gemm_items, syrk_items;
     std::vector<DevCombine> combines;
     int64_t combine_elems = 0;
     int str_tmax = 0;  // most operand terms of any TK_STR task in this phase
+    int tg_tmax = 0;   // most operand terms of any product tile task
 };
 
 struct Plan {
@@ -127,6 +139,9 @@ struct Plan {
 // Tile sizes the kernels use (output tile per workgroup).
 constexpr int kGemmTile = 128;  // TK_GEMM / TK_SYRK
 constexpr int kStrTile = 64;    // TK_STR quadrant tile (4 quadrants per workgroup)
+// Largest row stride in bytes: kernels address a staged slab of rows with
+// 32-bit offsets.
+constexpr int64_t kMaxRowBytes = (int64_t)1 << 26;
 constexpr int kMaxTerms = 8;    // max terms per operand (2^(levels staged))
 
 // Build the plan.  Throws std::invalid_argument for impossible inputs.

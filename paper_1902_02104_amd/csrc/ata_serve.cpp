@@ -215,7 +215,8 @@ bool ata_server::admit(Req* q, int pass_stream) {
     ++st.admitted;
     if (sim()) return true;
     const Plan& P = q->plan->plan;
-    q->small = P.phases.size() == 1 && P.phases[0].str_items.empty() && P.phases[0].gemm_items.empty() &&
+    q->small = P.phases.size() == 1 && P.phases[0].str_items.empty() && P.phases[0].tg_items.empty() &&
+               P.phases[0].gemm_items.empty() &&
                P.phases[0].combines.empty();
     q->stream = q->small ? pass_stream : (int)((pass + q->id) % streams.size());
     hipStream_t s = streams[q->stream];
@@ -409,6 +410,7 @@ int validate_request(const ata_request* r) {
     if (r->src != ATA_SRC_NORMAL && r->m > 0 && !r->a) return -2;
     if (r->reserved != 0 || (r->keep_a != 0 && r->keep_a != 1)) return -2;
     if (r->m > INT32_MAX || r->n > INT32_MAX) return ATA_EUNSUPPORTED;
+    if (r->n * (r->dtype == ATA_F64 ? 8 : 4) > kMaxRowBytes) return ATA_EUNSUPPORTED;
     return 0;
 }
 
@@ -487,7 +489,7 @@ int ata_server_submit(ata_server* srv, const ata_request* req, uint64_t* ticket)
     // footprint from the host plan (no device work on the caller's thread)
     std::shared_ptr<PlanDev> hp;
     if (req->m > 0) {
-        rc = get_plan(req->m, req->n, q->cutoff, q->variant, q->depth, false, hp);
+        rc = get_plan(req->m, req->n, q->cutoff, q->variant, q->depth, 0, false, hp);
         if (rc != ATA_OK) return rc;
         q->L = ws_layout(req->m, req->n, req->dtype, hp->plan.ws_elems);
         q->plan = hp;

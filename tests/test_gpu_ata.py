@@ -60,12 +60,15 @@ def test_c1_uniform_fp64(env, orc):
         assert orc.rel_fro(C, lit, 192) <= FP64_TOL
 
 
+@pytest.mark.parametrize("intile", [False, True])
 @pytest.mark.parametrize("var,depth", [("strassen", 0), ("strassen", 1), ("strassen", 2), ("strassen", 3),
                                        ("winograd", 1), ("winograd", 2)])
-def test_variants_depths_integer(env, orc, var, depth):
-    _say("case: 517x301 integer cutoff 40", var, depth)
+def test_variants_depths_integer(env, orc, var, depth, intile):
+    """Both forms of the last Strassen level: product tiles summed by a
+    combination pass, and the in-tile form."""
+    _say("case: 517x301 integer cutoff 40", var, depth, intile)
     A = synthetic.integer(517, 301, 21)
-    C = _run(env, A, cutoff=40, variant=var, max_depth=depth)
+    C = _run(env, A, cutoff=40, variant=var, max_depth=depth, intile=intile)
     assert np.array_equal(C, orc.classical(A))
 
 
@@ -87,12 +90,14 @@ def test_fuzz_shapes_integer(env, orc):
                 P.plan_info(m, n, c, max_depth=-1)
             except P.AtaError:  # natural depth needs more operand terms than supported
                 d = 3
-        _say("fuzz", case, m, n, c, d, var, lda)
         buf = synthetic.with_lda(A, lda, fill=1e300)
         At = torch.from_numpy(buf).cuda()[:, :n]
-        Cg = P.gram(At, cutoff=c, max_depth=d, variant=var)
-        torch.cuda.synchronize()
-        assert np.array_equal(Cg.cpu().numpy(), orc.classical(A)), (m, n, c, d, var, lda)
+        ref = orc.classical(A)
+        for intile in (False, True):
+            _say("fuzz", case, m, n, c, d, var, lda, intile)
+            Cg = P.gram(At, cutoff=c, max_depth=d, variant=var, intile=intile)
+            torch.cuda.synchronize()
+            assert np.array_equal(Cg.cpu().numpy(), ref), (m, n, c, d, var, lda, intile)
 
 
 def test_fuzz_shapes_uniform(env, orc):
@@ -101,10 +106,13 @@ def test_fuzz_shapes_uniform(env, orc):
         m = int(rng.integers(50, 900))
         n = int(rng.integers(50, 700))
         c = int(rng.choice([16, 32, 64, 128]))
-        _say("fuzz-u", case, m, n, c)
         A = synthetic.uniform(m, n, 300 + case)
-        C = _run(env, A, cutoff=c, max_depth=int(rng.choice([1, 2, 3])))
-        assert orc.rel_fro(C, orc.classical(A), n) <= FP64_TOL
+        d = int(rng.choice([1, 2, 3]))
+        ref = orc.classical(A)
+        for intile in (False, True):
+            _say("fuzz-u", case, m, n, c, d, intile)
+            C = _run(env, A, cutoff=c, max_depth=d, intile=intile)
+            assert orc.rel_fro(C, ref, n) <= FP64_TOL
 
 
 def test_non_uniform_tree(env, orc):
@@ -205,17 +213,17 @@ def _sampled_check(orc, A_np, C, pairs, tol):
     return worst
 
 
-@pytest.mark.parametrize("n,cutoff,depth", [(5000, 256, 2), (5000, 512, 1)] +
-                         [(10000, c, d) for c in (128, 256, 512) for d in (1, 2)])
-def test_square_full_size_sampled(env, orc, n, cutoff, depth):
+@pytest.mark.parametrize("n,cutoff,depth,intile", [(5000, 256, 2, False), (5000, 512, 1, True)] +
+                         [(10000, c, d, it) for c in (128, 256, 512) for d in (1, 2) for it in (False, True)])
+def test_square_full_size_sampled(env, orc, n, cutoff, depth, intile):
     """Full-size square workload in every configuration the benchmark's
     tuning may choose: sampled entries against the oracle, the diagonal
     against squared column norms, and a Freivalds product check."""
     torch, P = env
-    _say("case: square", n, cutoff, depth)
+    _say("case: square", n, cutoff, depth, intile)
     A_np = synthetic.uniform(n, n, synthetic.SEED_SQUARE)
     A = torch.from_numpy(A_np).cuda()
-    C = P.gram(A, cutoff=cutoff, max_depth=depth)
+    C = P.gram(A, cutoff=cutoff, max_depth=depth, intile=intile)
     torch.cuda.synchronize()
     Cn = C.cpu().numpy()
     rng = np.random.default_rng(5)

@@ -54,9 +54,10 @@ def test_plan_multiplications_match_oracle_recursion(lib, orc, m, n, c, d):
     """The device plan forms exactly the scalar products of Algorithm 1 with
     HASA (same count as the oracle's literal recursion with the same cutoff
     and Strassen depth cap)."""
-    st = P.plan_info(m, n, c, max_depth=d)
-    assert st["mults"] == orc.ata_mult_count(m, n, c, d)
-    assert st["classical_mults"] == m * n * (n + 1) // 2
+    for intile in (False, True):
+        st = P.plan_info(m, n, c, max_depth=d, intile=intile)
+        assert st["mults"] == orc.ata_mult_count(m, n, c, d)
+        assert st["classical_mults"] == m * n * (n + 1) // 2
 
 
 def test_plan_depth_zero_is_classical_count(lib, orc):
@@ -80,18 +81,29 @@ def test_plan_non_uniform_tree_uses_ordered_phases(lib, orc):
 
 
 def test_winograd_depth_limits(lib, orc):
-    st = P.plan_info(2048, 2048, 64, variant="winograd", max_depth=2)
-    assert st["mults"] == orc.ata_mult_count(2048, 2048, 64, 2)
+    for intile in (False, True):
+        st = P.plan_info(2048, 2048, 64, variant="winograd", max_depth=2, intile=intile)
+        assert st["mults"] == orc.ata_mult_count(2048, 2048, 64, 2)
     with pytest.raises(P.AtaError):
         P.plan_info(4096, 4096, 64, variant="winograd", max_depth=3)  # 16 operand terms
 
 
 def test_workspace_size(lib):
-    assert P.workspace_bytes(256, 192, 32, max_depth=1) == 0
-    ws = P.workspace_bytes(10000, 10000, 256, max_depth=2)
-    # 7 products per off-diagonal block of levels 0..3, each a quarter block
+    # in-tile form: one-level blocks write C directly; two-level blocks keep
+    # the 7 products of their first level, each a quarter block
+    assert P.workspace_bytes(256, 192, 32, max_depth=1, intile=True) == 0
+    ws = P.workspace_bytes(10000, 10000, 256, max_depth=2, intile=True)
     expect = 8 * 7 * (2500 ** 2 + 2 * 1250 ** 2 + 4 * 625 ** 2 + 8 * 313 ** 2)
     assert expect <= ws < expect + 256  # rounded up to 256-byte alignment
+    # product tiles: a block of d levels keeps all 7^d products, each of the
+    # block's size halved (ceil) d times.  Off-diagonal blocks of 10000^2 at
+    # cutoff 256: 5000^2, 2 x 2500^2, 4 x 1250^2, 8 x 625^2 (two levels each)
+    # and 16 x (312 x 313) (one level; K = 625 rows)
+    ws = P.workspace_bytes(10000, 10000, 256, max_depth=2)
+    expect = 8 * (49 * 1250 ** 2 + 2 * 49 * 625 ** 2 + 4 * 49 * 313 ** 2 + 8 * 49 * 157 ** 2 + 16 * 7 * 156 * 157)
+    assert expect <= ws < expect + 256
+    ws1 = P.workspace_bytes(256, 192, 32, max_depth=1)
+    assert ws1 > 0
 
 
 def test_workspace_size_reduced_precision(lib):
