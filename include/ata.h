@@ -83,6 +83,14 @@ typedef struct ata_opts {
  * sums the terms, written to the workspace and combined by a separate pass
  * (deeper products use the in-tile form either way). */
 #define ATA_OPT_INTILE 0x1
+/* ata_opts.flags: column equilibration.  Columns of A are scaled by powers
+ * of two (each column's largest magnitude into [1, 2)) before the product
+ * and C is scaled back, both exactly unless entries underflow.  The error of
+ * each C_ij then scales with its own two columns, which matters for Strassen
+ * levels when column sizes span many orders of magnitude.  Costs one pass
+ * over A and m x n elements of workspace.  FP64 and FP32 only (the reduced-
+ * precision forms scale columns themselves). */
+#define ATA_OPT_EQUILIBRATE 0x2
 
 #define ATA_DEFAULT_MAX_DEPTH 2
 #define ATA_MAX_DEPTH_LIMIT 4 /* deepest supported Strassen level count */

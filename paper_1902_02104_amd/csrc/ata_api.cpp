@@ -119,7 +119,7 @@ int resolve_opts(const ata_opts* opts, int& variant, int& max_depth, int& flags)
         variant = opts->variant;
         max_depth = opts->max_depth;
         flags = opts->flags;
-        if (flags & ~ATA_OPT_INTILE) return -1;
+        if (flags & ~(ATA_OPT_INTILE | ATA_OPT_EQUILIBRATE)) return -1;
     }
     if (variant != ATA_VARIANT_STRASSEN && variant != ATA_VARIANT_WINOGRAD) return -1;
     if (max_depth < -1) return -1;
@@ -142,19 +142,23 @@ bool dtype_lp(int dtype) { return (dtype & 0xff) == ATA_F32_BF16X3 || (dtype & 0
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems) {
+WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate) {
     WsLayout L;
     size_t off = (size_t)ws_elems * sizeof(double);
     off = (off + 255) & ~(size_t)255;
-    if (dtype_lp(dtype) && n > 0) {
-        const bool fp8 = (dtype & 0xff) == ATA_F32_FP8;
-        L.ldt = round_up(m > 0 ? m : 1, 128);
+    const bool lp = dtype_lp(dtype);
+    if ((lp || equilibrate) && n > 0) {
+        const size_t eb = lp ? sizeof(float) : (size_t)elem_bytes_in(dtype);
         L.scale = off;
-        off += (size_t)n * sizeof(float);
+        off += (size_t)n * eb;
         off = (off + 255) & ~(size_t)255;
         L.part = off;
-        off += (size_t)((m + 255) / 256) * n * sizeof(float);
+        off += (size_t)((m + 255) / 256) * n * eb;
         off = (off + 255) & ~(size_t)255;
+    }
+    if (lp && n > 0) {
+        const bool fp8 = (dtype & 0xff) == ATA_F32_FP8;
+        L.ldt = round_up(m > 0 ? m : 1, 128);
         const size_t plane = (size_t)n * L.ldt * (fp8 ? 1 : 2);
         L.t0 = off;
         off += plane;
@@ -164,6 +168,12 @@ WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems) {
             off += plane;
             off = (off + 255) & ~(size_t)255;
         }
+    }
+    if (equilibrate && !lp && n > 0 && m > 0) {
+        L.eq = true;
+        L.eqa = off;
+        off += (size_t)m * n * elem_bytes_in(dtype);
+        off = (off + 255) & ~(size_t)255;
     }
     L.total = off;
     return L;
@@ -319,6 +329,13 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
     const DevTables tb{(const DevTask*)(pd->blob + pd->off_tasks), (const DevTerm*)(pd->blob + pd->off_terms),
                        (const int32_t*)(pd->blob + pd->off_segs)};
     hipError_t err = hipSuccess;
+    if (L.eq) {
+        // every product below runs on the column-equilibrated copy of A
+        ProfScope ps(ATA_KERNEL_OTHER, s);
+        err = launch_equilibrate(f32, A, lda, (int)m, (int)n, ws + L.part, ws + L.scale, ws + L.eqa, s);
+        A = ws + L.eqa;
+        lda = n;
+    }
     const int lp_mode = (dtype & 0xff) == ATA_F32_FP8 ? 1 : 0;
     if (lp) {
         ProfScope ps(ATA_KERNEL_OTHER, s);
@@ -389,6 +406,10 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W, C_lower, s);
         }
     }
+    if (err == hipSuccess && L.eq) {
+        ProfScope ps(ATA_KERNEL_OTHER, s);
+        err = launch_descale(f32, out64, C_lower, (int)n, ws + L.scale, s);
+    }
     return err;
 }
 
@@ -431,11 +452,12 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     if (!out) return -6;
     if (dtype_lp(dtype)) {
         if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
+        if (flags & ATA_OPT_EQUILIBRATE) return ATA_EUNSUPPORTED;
         max_depth = 0;
     }
     const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
     std::shared_ptr<PlanDev> pd;
-    const int rc = get_plan(m, n, c, variant, max_depth, flags, false, pd);
+    const int rc = get_plan(m, n, c, variant, max_depth, flags & ATA_OPT_INTILE, false, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
     std::memset(out, 0, sizeof(*out));
@@ -449,7 +471,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     out->phases = (int64_t)P.phases.size();
     out->ata_depth = P.ata_depth;
     out->max_hasa_depth = P.max_hasa_depth;
-    out->workspace_bytes = (int64_t)ws_layout(m, n, dtype, P.ws_elems).total;
+    out->workspace_bytes = (int64_t)ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0).total;
     out->cutoff = c;
     out->strassen_mults = P.str_mults;
     out->gemm_mults = P.gemm_mults;
@@ -477,6 +499,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     if (lp) {
         // reduced-precision leaves: classical off-diagonal products only
         if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
+        if (flags & ATA_OPT_EQUILIBRATE) return ATA_EUNSUPPORTED;
         max_depth = 0;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -495,10 +518,10 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     }
     const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
     std::shared_ptr<PlanDev> pd;
-    rc = get_plan(m, n, c, variant, max_depth, flags, true, pd);
+    rc = get_plan(m, n, c, variant, max_depth, flags & ATA_OPT_INTILE, true, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
-    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems);
+    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0);
     if (L.ldt > INT32_MAX) return ATA_EUNSUPPORTED;
     char* ws = nullptr;
     bool owned = false;

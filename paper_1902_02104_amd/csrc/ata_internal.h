@@ -38,10 +38,13 @@ struct PlanDev {
 };
 
 // Device workspace layout: [FP64 Strassen products][scales][column-max
-// partials][converted copy plane 0][plane 1], each 256-byte aligned.
+// partials][converted copy plane 0][plane 1][equilibrated copy of A], each
+// 256-byte aligned.  The scale and partial areas serve the FP8 scales or the
+// equilibration scales (never both).
 struct WsLayout {
-    size_t w = 0, scale = 0, part = 0, t0 = 0, t1 = 0, total = 0;
+    size_t w = 0, scale = 0, part = 0, t0 = 0, t1 = 0, eqa = 0, total = 0;
     int64_t ldt = 0;
+    bool eq = false;
 };
 
 int hip_fail(hipError_t e);
@@ -50,7 +53,7 @@ bool dtype_lp(int dtype);
 int elem_bytes_in(int dtype);
 int elem_bytes_out(int dtype);
 int64_t default_cutoff(int64_t m, int64_t n, int dtype);
-WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems);
+WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate);
 int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, int flags, bool need_device,
              std::shared_ptr<PlanDev>& out);
 // dblob: device copy of pd.host_blob (pd.blob, or a copy the caller made)

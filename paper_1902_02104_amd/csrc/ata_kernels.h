@@ -59,6 +59,13 @@ hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1
                           const float* scale, const DevTables& tb, const WorkItem* items, int nitems,
                           void* C, double* W, hipStream_t s);
 
+// Column equilibration (power-of-two column scales into `scale`, the scaled
+// copy of A into `out` with row stride n; `part` holds ceil(m/256) x n
+// partial maxima) and its inverse on packed lower C.
+hipError_t launch_equilibrate(bool f32, const void* A, int64_t lda, int m, int n, void* part, void* scale, void* out,
+                              hipStream_t s);
+hipError_t launch_descale(bool f32, bool out_f64, void* C, int n, const void* scale, hipStream_t s);
+
 // Element conversions exposed for verification: mode 0 -> bfloat16 hi/lo
 // (uint16 pairs), mode 1 -> OCP e4m3 bytes (no scaling).
 hipError_t launch_convert(int mode, const float* x, int64_t count, void* out0, void* out1, hipStream_t s);

@@ -43,7 +43,10 @@ __device__ __forceinline__ int64_t packed_index(int64_t r, int64_t q) { return r
 // whose offset lies at or past num_records returns zero without touching
 // memory.  This gives the zero padding of ragged quadrants and K tails
 // without branches.  Offsets are 32-bit: a slab spans at most kStageRows
-// rows of at most kMaxRowBytes (checked at the API).
+// rows of at most kMaxRowBytes (checked at the API).  The compiler merges
+// adjacent 8-byte loads into 16-byte ones; the range check of a multi-dword
+// raw buffer load applies per dword, so a pair straddling the end of a slab
+// still returns its in-range half (exercised by the odd-stride tests).
 // ---------------------------------------------------------------------------
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 constexpr uint32_t kOOB = 0x80000000u;  // an offset past every record count used here
@@ -123,8 +126,8 @@ __device__ __forceinline__ void store_out(OUT* p, int beta, double v) {
 //   TMAX > 1:  Strassen product tiles: each operand is a signed sum of up to
 //              TMAX terms (quadrant blocks of A), summed in term order while
 //              staging; a term's columns past its end (padding) stage as
-//              zero.  Four-term operands stage 8 rows at a time to bound the
-//              registers that hold the terms in flight.
+//              zero.  K staged 8 rows at a time to bound the registers that
+//              hold the terms in flight.
 // ---------------------------------------------------------------------------
 constexpr int GT = kGemmTile;  // 128
 
@@ -138,7 +141,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
     typedef Eng<T> E;
     constexpr bool F32 = std::is_same<T, float>::value;
     constexpr int BR = 64 / E::RM, BC = 64 / E::RN;
-    constexpr int GK = (TMAX == 1 || (TMAX == 2 && !F32)) ? 16 : 8;  // k rows per stage
+    constexpr int GK = TMAX == 1 ? 16 : 8;  // k rows per stage
     constexpr int EPT = GK * GT / 256;           // elements per thread, term and side
     constexpr int TPR = GT / EPT;                // threads per staged row
     __shared__ T Xs[2][GK][GT + E::PAD];
@@ -169,16 +172,15 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
     const int lk = tid / TPR, lc = (tid % TPR) * EPT;
     const int64_t row_bytes = lda * (int64_t)sizeof(T);
     constexpr uint32_t ES = (uint32_t)sizeof(T);
-    // per term: byte offset of the thread's first column inside a slab and
-    // the number of its columns inside the term (later ones are padding)
-    uint32_t xo[TMAX], yo[TMAX];
-    int xcv[TMAX], ycv[TMAX];
+    // per term and element: byte offset inside a slab; a term's padding
+    // columns get kOOB and stage as zero
+    uint32_t xo[TMAX][EPT], yo[TMAX][EPT];
     T xsgn[TMAX], ysgn[TMAX];
 #pragma unroll
     for (int u = 0; u < TMAX; ++u) {
         xsgn[u] = ysgn[u] = T(0);
-        xo[u] = yo[u] = 0;
-        xcv[u] = ycv[u] = 0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) xo[u][e] = yo[u][e] = kOOB;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int nt = side == 0 ? t.nx : t.ny;
@@ -186,16 +188,14 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
             const DevTerm tm = terms[t.term_off + (side == 0 ? u : t.nx + u)];
             const int col = tm.col + (side == 0 ? i0 : j0) + lc;
             const uint32_t base = (uint32_t)(lk * row_bytes) + (uint32_t)col * ES;
-            const int cv = TMAX == 1 ? EPT : tm.cvend - col;
-            if (side == 0) {
-                xo[u] = base;
-                xcv[u] = cv;
-                xsgn[u] = (T)tm.sign;
-            } else {
-                yo[u] = base;
-                ycv[u] = cv;
-                ysgn[u] = (T)tm.sign;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t off = (TMAX == 1 || col + e < tm.cvend) ? base + e * ES : kOOB;
+                if (side == 0) xo[u][e] = off;
+                else yo[u][e] = off;
             }
+            if (side == 0) xsgn[u] = (T)tm.sign;
+            else ysgn[u] = (T)tm.sign;
         }
     }
 
@@ -241,12 +241,10 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
                 int nv = rvend - base < krem ? rvend - base : krem;
                 nv = nv < GK ? nv : GK;
                 const rsrc_t rs = slab_rsrc(A + (int64_t)base * lda, u < nt ? nv : 0, row_bytes);
-                // unmasked: reads stay inside the slab or return zero; term
-                // padding is zeroed when the terms are summed
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) {
-                    if (side == 0) xr[u][e] = bload<T>(rs, xo[u] + e * ES);
-                    else yr[u][e] = bload<T>(rs, yo[u] + e * ES);
+                    if (side == 0) xr[u][e] = bload<T>(rs, xo[u][e]);
+                    else yr[u][e] = bload<T>(rs, yo[u][e]);
                 }
             }
         }
@@ -272,12 +270,12 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
                 x = xr[0][e];
                 y = yr[0][e];
             } else {
-                x = xsgn[0] * (e < xcv[0] ? xr[0][e] : T(0));
-                y = ysgn[0] * (e < ycv[0] ? yr[0][e] : T(0));
+                x = xsgn[0] * xr[0][e];
+                y = ysgn[0] * yr[0][e];
 #pragma unroll
                 for (int u = 1; u < TMAX; ++u) {
-                    x += xsgn[u] * (e < xcv[u] ? xr[u][e] : T(0));
-                    y += ysgn[u] * (e < ycv[u] ? yr[u][e] : T(0));
+                    x += xsgn[u] * xr[u][e];
+                    y += ysgn[u] * yr[u][e];
                 }
             }
             Xs[buf][lk][lc + e] = x;
@@ -649,53 +647,77 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
 
 // ---------------------------------------------------------------------------
 // Combination of workspace products into an off-diagonal block of packed C.
-// One thread per output element; fixed summation order; FP64.
+// Each output element sums the workspace slots of its Strassen path with the
+// signs of the combination formulas, over the K parts in part order, in
+// FP64.  A workgroup covers kCbChunk consecutive elements (coalesced: thread
+// t handles elements t, t + 256, ...); one binary search per workgroup finds
+// the first block, threads step forward from there.
 // ---------------------------------------------------------------------------
 __constant__ int c_dcoef[2][7][4] = ATA_D_COEF;
+constexpr int kCbChunk = 1024;
 
 template <typename OUT>
 __global__ void __launch_bounds__(256) k_combine(const DevCombine* __restrict__ cbs, int ncb, int64_t total,
                                                  const double* __restrict__ W, OUT* __restrict__ C) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
-    int lo = 0, hi = ncb - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (cbs[mid].elem_off <= e) lo = mid;
-        else hi = mid - 1;
-    }
-    const DevCombine cb = cbs[lo];
-    const int64_t loc = e - cb.elem_off;
-    const int i = (int)(loc / cb.N), j = (int)(loc % cb.N);
-    if (cb.lower && j > i) return;
-    int ii = i, jj = j, Mc = cb.M, Nc = cb.N;
-    int quad[4];
-    for (int l = 0; l < cb.levels; ++l) {
-        const int MH = (Mc + 1) >> 1, NH = (Nc + 1) >> 1;
-        const int a = ii >= MH, c = jj >= NH;
-        ii -= a * MH;
-        jj -= c * NH;
-        quad[l] = a * 2 + c;
-        Mc = MH;
-        Nc = NH;
-    }
-    const int64_t slot_elems = (int64_t)cb.Mp * cb.Np;
-    const double* base = W + cb.ws_off + (int64_t)ii * cb.Np + jj;
-    double s = 0.0;
-    int npaths = 1;
-    for (int l = 0; l < cb.levels; ++l) npaths *= 7;
-    for (int part = 0; part < cb.nparts; ++part) {
-        const double* pb = base + (int64_t)part * cb.part_stride;
-        for (int path = 0; path < npaths; ++path) {
-            int rem = path, coef = 1;
-            for (int l = cb.levels - 1; l >= 0; --l) {
-                coef *= c_dcoef[cb.variant][rem % 7][quad[l]];
-                rem /= 7;
-            }
-            if (coef) s += coef > 0 ? pb[path * slot_elems] : -pb[path * slot_elems];
+    __shared__ int first;
+    const int64_t e0 = (int64_t)blockIdx.x * kCbChunk;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = ncb - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cbs[mid].elem_off <= e0) lo = mid;
+            else hi = mid - 1;
         }
+        first = lo;
     }
-    store_out(C + packed_index((int64_t)cb.r0 + i, cb.q0) + j, cb.beta, s);
+    __syncthreads();
+    int idx = first;
+    for (int r = 0; r < kCbChunk / 256; ++r) {
+        const int64_t e = e0 + r * 256 + threadIdx.x;
+        if (e >= total) return;
+        while (idx + 1 < ncb && cbs[idx + 1].elem_off <= e) ++idx;
+        const DevCombine& cb = cbs[idx];
+        const int64_t loc = e - cb.elem_off;
+        int i, j;
+        if (loc < 0x100000000ll) {
+            const uint32_t l32 = (uint32_t)loc, n32 = (uint32_t)cb.N;
+            i = (int)(l32 / n32);
+            j = (int)(l32 - (uint32_t)i * n32);
+        } else {
+            i = (int)(loc / cb.N);
+            j = (int)(loc - (int64_t)i * cb.N);
+        }
+        if (cb.lower && j > i) continue;
+        // quadrant path of (i, j), first level in the most significant digit
+        int ii = i, jj = j, Mc = cb.M, Nc = cb.N, qcode = 0;
+        for (int l = 0; l < cb.levels; ++l) {
+            const int MH = (Mc + 1) >> 1, NH = (Nc + 1) >> 1;
+            const int a = ii >= MH, c = jj >= NH;
+            ii -= a * MH;
+            jj -= c * NH;
+            qcode = qcode * 4 + a * 2 + c;
+            Mc = MH;
+            Nc = NH;
+        }
+        const int64_t slot_elems = (int64_t)cb.Mp * cb.Np;
+        const double* base = W + cb.ws_off + (int64_t)ii * cb.Np + jj;
+        int npaths = 1;
+        for (int l = 0; l < cb.levels; ++l) npaths *= 7;
+        double sum = 0.0;
+        for (int part = 0; part < cb.nparts; ++part) {
+            const double* pb = base + (int64_t)part * cb.part_stride;
+            for (int path = 0; path < npaths; ++path) {
+                int rem = path, qc = qcode, coef = 1;
+                for (int l = 0; l < cb.levels; ++l) {  // last level first
+                    coef *= c_dcoef[cb.variant][rem % 7][qc & 3];
+                    rem /= 7;
+                    qc >>= 2;
+                }
+                if (coef) sum += coef > 0 ? pb[path * slot_elems] : -pb[path * slot_elems];
+            }
+        }
+        store_out(C + packed_index((int64_t)cb.r0 + i, cb.q0) + j, cb.beta, sum);
+    }
 }
 
 template <typename T>
@@ -781,6 +803,61 @@ __global__ void __launch_bounds__(256) k_colscale(const float* __restrict__ part
         if (s * mx > 448.0f) s *= 0.5f;  // guard against the rounding of 448 / mx
     }
     scale[j] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Column equilibration: A' = A diag(s) with s_j a power of two putting the
+// largest |A_kj| of column j in [1, 2) (s_j = 1 for a zero column), and
+// C = diag(s)^-1 C' diag(s)^-1 afterwards.  Multiplying by powers of two is
+// exact barring underflow, so the product of A' differs from that of A only
+// in rounding; fast (Strassen) products then bound every entry's error by
+// the sizes of its own two columns instead of the largest columns of A.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_colmax_t(const T* __restrict__ A, int64_t lda, int m, int n,
+                                                  T* __restrict__ part) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int chunk = blockIdx.y;
+    if (j >= n) return;
+    const int r0 = chunk * 256, r1 = min(m, r0 + 256);
+    T mx = T(0);
+    for (int r = r0; r < r1; ++r) mx = fmax(mx, fabs(A[(int64_t)r * lda + j]));
+    part[(int64_t)chunk * n + j] = mx;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_eqscale(const T* __restrict__ part, int nchunks, int n,
+                                                 T* __restrict__ scale) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    T mx = T(0);
+    for (int c = 0; c < nchunks; ++c) mx = fmax(mx, part[(int64_t)c * n + j]);
+    T s = T(1);
+    if (mx > T(0) && isfinite(mx)) {
+        int e;  // mx = f 2^e with f in [0.5, 1): mx 2^(1 - e) in [1, 2)
+        (void)frexp(mx, &e);
+        s = ldexp(T(1), 1 - e);
+    }
+    scale[j] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_scale_cols(const T* __restrict__ A, int64_t lda, int m, int n,
+                                                    const T* __restrict__ scale, T* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)m * n) return;
+    const int64_t r = e / n;
+    const int j = (int)(e - r * n);
+    out[e] = A[r * lda + j] * scale[j];
+}
+
+// C_ij / (s_i s_j) over packed lower C: one workgroup per row.
+template <typename OUT, typename S>
+__global__ void __launch_bounds__(256) k_descale(OUT* __restrict__ C, const S* __restrict__ scale) {
+    const int i = blockIdx.x;
+    const double si = 1.0 / (double)scale[i];
+    OUT* row = C + packed_index(i, 0);
+    for (int j = threadIdx.x; j <= i; j += 256) row[j] = (OUT)((double)row[j] * si / (double)scale[j]);
 }
 
 // Transposed, converted copy of A: out[i * ldt + k] for column i of A and
@@ -1189,7 +1266,7 @@ hipError_t launch_str(bool f32, bool out_f64, int variant, int tmax, const void*
 hipError_t launch_combine(bool out_f64, const DevCombine* cbs, int ncb, int64_t total, const double* W, void* C,
                           hipStream_t s) {
     if (ncb <= 0 || total <= 0) return hipSuccess;
-    const int64_t blocks = (total + 255) / 256;
+    const int64_t blocks = (total + kCbChunk - 1) / kCbChunk;
     if (out_f64)
         hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, (double*)C);
     else
@@ -1214,6 +1291,37 @@ hipError_t launch_colscale(const float* A, int64_t lda, int m, int n, float* par
     const int nch = m > 0 ? (m + 255) / 256 : 0;
     if (nch > 0) hipLaunchKernelGGL(k_colmax_part, dim3((n + 255) / 256, nch), dim3(256), 0, s, A, lda, m, n, part);
     hipLaunchKernelGGL(k_colscale, dim3((n + 255) / 256), dim3(256), 0, s, part, nch, n, scale);
+    return hipGetLastError();
+}
+
+template <typename T>
+static void launch_equilibrate_t(const T* A, int64_t lda, int m, int n, T* part, T* scale, T* out, hipStream_t s) {
+    const int nch = (m + 255) / 256;
+    hipLaunchKernelGGL(k_colmax_t<T>, dim3((n + 255) / 256, nch), dim3(256), 0, s, A, lda, m, n, part);
+    hipLaunchKernelGGL(k_eqscale<T>, dim3((n + 255) / 256), dim3(256), 0, s, part, nch, n, scale);
+    const int64_t total = (int64_t)m * n;
+    hipLaunchKernelGGL(k_scale_cols<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, A, lda, m, n, scale,
+                       out);
+}
+
+hipError_t launch_equilibrate(bool f32, const void* A, int64_t lda, int m, int n, void* part, void* scale, void* out,
+                              hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    if (f32)
+        launch_equilibrate_t<float>((const float*)A, lda, m, n, (float*)part, (float*)scale, (float*)out, s);
+    else
+        launch_equilibrate_t<double>((const double*)A, lda, m, n, (double*)part, (double*)scale, (double*)out, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_descale(bool f32, bool out_f64, void* C, int n, const void* scale, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (!f32)
+        hipLaunchKernelGGL((k_descale<double, double>), dim3(n), dim3(256), 0, s, (double*)C, (const double*)scale);
+    else if (out_f64)
+        hipLaunchKernelGGL((k_descale<double, float>), dim3(n), dim3(256), 0, s, (double*)C, (const float*)scale);
+    else
+        hipLaunchKernelGGL((k_descale<float, float>), dim3(n), dim3(256), 0, s, (float*)C, (const float*)scale);
     return hipGetLastError();
 }
 

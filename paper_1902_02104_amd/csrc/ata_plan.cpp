@@ -612,6 +612,19 @@ Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
         for (auto* items : {&ph.str_items, &ph.tg_items, &ph.gemm_items, &ph.syrk_items})
             std::stable_sort(items->begin(), items->end(),
                              [&](const WorkItem& a, const WorkItem& b) { return cost(a) > cost(b); });
+        // Workgroups are dispatched round-robin over the eight XCDs, each with
+        // its own L2: within every window of 64 items, place eight consecutive
+        // items (neighbouring tiles of one task, sharing operand strips) at
+        // positions that land on the same XCD.
+        for (auto* items : {&ph.str_items, &ph.tg_items, &ph.gemm_items, &ph.syrk_items}) {
+            std::vector<WorkItem>& v = *items;
+            for (size_t base = 0; base + 64 <= v.size(); base += 64) {
+                WorkItem tmp[64];
+                for (int g = 0; g < 8; ++g)
+                    for (int j = 0; j < 8; ++j) tmp[j * 8 + g] = v[base + g * 8 + j];
+                std::copy(tmp, tmp + 64, v.begin() + base);
+            }
+        }
         P.work_items += (int64_t)(ph.str_items.size() + ph.tg_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
     }
     return P;

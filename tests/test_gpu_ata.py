@@ -289,24 +289,28 @@ def tall_full(env):
 # entry at its own scale; a Strassen level adds and subtracts columns of
 # very different size before the product, so small entries inherit the
 # rounding of large ones (error growth of fast products, measured here).
-TALL_BOUNDS = {("f64", 0): 1e-13, ("f64", 1): 1e-9, ("f64", 2): 1e-9,
-               ("f32", 0): 1e-6, ("f32", 1): 2e-2, ("f32", 2): 2e-2}
+# Column equilibration (power-of-two scales, exact) removes that growth.
+TALL_BOUNDS = {("f64", 0, False): 1e-13, ("f64", 1, False): 1e-9, ("f64", 2, False): 1e-9,
+               ("f32", 0, False): 1e-6, ("f32", 1, False): 2e-2, ("f32", 2, False): 2e-2,
+               ("f64", 1, True): 1e-13, ("f64", 2, True): 1e-13,
+               ("f32", 1, True): 2e-5, ("f32", 2, True): 2e-5}
 
 
-@pytest.mark.parametrize("dtype_name,depth", sorted(TALL_BOUNDS))
-def test_tall_full_size_sampled(env, orc, tall_full, dtype_name, depth):
+@pytest.mark.parametrize("dtype_name,depth,eq", sorted(TALL_BOUNDS))
+def test_tall_full_size_sampled(env, orc, tall_full, dtype_name, depth, eq):
     """The 262144 x 2048 least-squares shape at full size in the benchmark's
-    configurations (cutoff 256, 0-2 Strassen levels): sampled scaled errors
-    against the oracle and a normwise Freivalds check."""
+    configurations (cutoff 256, 0-2 Strassen levels, with and without column
+    equilibration): sampled scaled errors against the oracle and a normwise
+    Freivalds check."""
     torch, P = env
     A64, A64d = tall_full
-    _say("case: tall full", dtype_name, depth)
+    _say("case: tall full", dtype_name, depth, eq)
     if dtype_name == "f64":
         Ad, Ah, dt = A64d, A64, P.F64
     else:
         Ad = A64d.float()
         Ah, dt = Ad.cpu().numpy().astype(np.float64), P.F32 | P.OUT_F64
-    C = P.gram(Ad, dtype=dt, cutoff=256, max_depth=depth)
+    C = P.gram(Ad, dtype=dt, cutoff=256, max_depth=depth, equilibrate=eq)
     torch.cuda.synchronize()
     Cn = C.cpu().numpy()
     n = Ah.shape[1]
@@ -320,7 +324,7 @@ def test_tall_full_size_sampled(env, orc, tall_full, dtype_name, depth):
         ref = orc.classical(cols)
         cij = ref[1] if i != j else ref[0]
         worst = max(worst, abs(Cn[i * (i + 1) // 2 + j] - cij) / np.sqrt(ref[0] * ref[2]))
-    assert worst <= TALL_BOUNDS[(dtype_name, depth)], worst
+    assert worst <= TALL_BOUNDS[(dtype_name, depth, eq)], worst
     # normwise: || C x - A^t (A x) || / (||A||_F^2 ||x||), FP64 on the GPU
     x = torch.from_numpy(rng.standard_normal(n)).cuda()
     full = torch.zeros(n, n, dtype=torch.float64, device="cuda")
@@ -330,3 +334,22 @@ def test_tall_full_size_sampled(env, orc, tall_full, dtype_name, depth):
     Ad64 = torch.from_numpy(Ah).cuda() if dtype_name == "f32" else A64d
     res = ((full @ x) - Ad64.T @ (Ad64 @ x)).norm().item() / (Ad64.norm().item() ** 2 * x.norm().item())
     assert res <= (1e-14 if dtype_name == "f64" else 1e-6), res
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+@pytest.mark.parametrize("intile", [False, True])
+def test_equilibrated_integer_bit_exact(env, orc, dtype_name, intile):
+    """Equilibration multiplies columns by powers of two and C back by their
+    inverses: on small integers (with columns scaled by powers of two, so the
+    scales differ) every step is exact, at every depth and in both forms."""
+    torch, P = env
+    rng = np.random.default_rng(31)
+    A = synthetic.integer(700, 333, 41) * np.ldexp(1.0, rng.integers(-6, 7, size=333))[None, :]
+    ref = orc.classical(A)
+    At = torch.from_numpy(A.astype(np.float64 if dtype_name == "f64" else np.float32)).cuda()
+    dt = P.F64 if dtype_name == "f64" else P.F32 | P.OUT_F64
+    for d in (0, 1, 2):
+        _say("case: equilibrated integer", dtype_name, intile, d)
+        C = P.gram(At, dtype=dt, cutoff=48, max_depth=d, intile=intile, equilibrate=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(C.cpu().numpy(), ref), (dtype_name, intile, d)

@@ -149,3 +149,20 @@ def test_binding_refuses_host_tensors(lib):
     torch = pytest.importorskip("torch")
     with pytest.raises(ValueError):
         P.gram(torch.zeros(4, 4, dtype=torch.float64))
+
+
+def test_equilibration_workspace_and_options(lib):
+    m, n = 1000, 300
+    base = P.workspace_bytes(m, n, 64, max_depth=1)
+    eq = P.workspace_bytes(m, n, 64, max_depth=1, equilibrate=True)
+    # scales + per-256-row partial maxima + the scaled copy of A
+    assert eq - base >= 8 * (n + 4 * n + m * n)
+    assert eq - base < 8 * (n + 4 * n + m * n) + 3 * 256
+    eq32 = P.workspace_bytes(m, n, 64, dtype=P.F32, max_depth=1, equilibrate=True)
+    assert eq32 - P.workspace_bytes(m, n, 64, dtype=P.F32, max_depth=1) >= 4 * (n + 4 * n + m * n)
+    with pytest.raises(P.AtaError):  # the reduced-precision forms scale columns themselves
+        P.plan_info(m, n, 64, dtype=P.F32_FP8, equilibrate=True)
+    o = P.Opts()
+    o.flags = 0x100  # unknown flag
+    st = P.PlanStats()
+    assert lib.ata_plan_info(m, n, P.F64, 64, ctypes.byref(o), ctypes.byref(st)) != 0
