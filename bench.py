@@ -26,13 +26,13 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
 
 
-def _profiled_traffic(kernel: str, n: int, cutoff: int, depth: int):
-    """HBM bytes per launch of `kernel` from the committed counter summary
+def _profiled_traffic(kernel: str, n: int, cutoff: int, depth: int, form: str):
+    """HBM bytes per launch of `kernel` from its committed counter summary
     (two rocprofv3 --pmc passes scaled by a plain copy), or None when the
     summary was taken on other kernel sources or another configuration."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(root, "profiles", "k_str_f64_10000_traffic.md")
+    path = os.path.join(root, "profiles", "%s_%d_traffic.md" % (kernel, n))
     try:
         kv = dict(line.strip().split(": ", 1) for line in open(path) if line.startswith("    ") and ": " in line
                   and not line.strip().startswith("cd "))
@@ -41,8 +41,7 @@ def _profiled_traffic(kernel: str, n: int, cutoff: int, depth: int):
         return None
     if kv.get("kernels_source_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    if not kernel.startswith("k_str") or (kv.get("n"), kv.get("cutoff"), kv.get("max_depth")) != \
-            (str(n), str(cutoff), str(depth)):
+    if (kv.get("n"), kv.get("cutoff"), kv.get("max_depth"), kv.get("form")) != (str(n), str(cutoff), str(depth), form):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -385,7 +384,7 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] else None
     roof["kernel"] = {"strassen": "k_str_f64" if intile else "k_gemm_terms_f64", "gemm": "k_gemm_f64",
                       "syrk": "k_gemm_f64", "combine": "k_combine_f64"}.get(dom, dom)
-    roof["traffic"] = _profiled_traffic(roof["kernel"], n, cutoff, depth)
+    roof["traffic"] = _profiled_traffic(roof["kernel"], n, cutoff, depth, "intile" if intile else "tiles")
     roof["avg_launch_ms"] = avg_ms
 
     if args.copy_bytes > 0:

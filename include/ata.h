@@ -76,13 +76,13 @@ typedef struct ata_opts {
     int32_t reserved;
 } ata_opts;
 
-/* ata_opts.flags: run the last Strassen level of each off-diagonal product
- * inside the workgroup tile (seven products in registers, combined in the
- * epilogue).  Without it every level up to two is expanded into signed
- * operand terms: each of the 7^d products is a classical tile whose staging
- * sums the terms, written to the workspace and combined by a separate pass
- * (deeper products use the in-tile form either way). */
-#define ATA_OPT_INTILE 0x1
+/* ata_opts.flags: Strassen product tiles.  By default the last Strassen
+ * level of each off-diagonal product runs inside the workgroup tile (seven
+ * products in registers, combined in the epilogue).  With this flag every
+ * level up to two (one for Winograd) is expanded into signed operand terms
+ * instead: each of the 7^d products is a classical tile whose staging sums
+ * the terms, written to the workspace and combined by a separate pass. */
+#define ATA_OPT_PRODUCT_TILES 0x1
 /* ata_opts.flags: column equilibration.  Columns of A are scaled by powers
  * of two (each column's largest magnitude into [1, 2)) before the product
  * and C is scaled back, both exactly unless entries underflow.  The error of

@@ -24,7 +24,7 @@ OUT_F64 = 0x100
 STRASSEN = 0
 WINOGRAD = 1
 DEFAULT_MAX_DEPTH = 2
-OPT_INTILE = 0x1
+OPT_PRODUCT_TILES = 0x1
 OPT_EQUILIBRATE = 0x2
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -107,19 +107,19 @@ def tri(n: int) -> int:
     return n * (n + 1) // 2
 
 
-def _opts(variant, max_depth, dtype=F64, intile=False, equilibrate=False):
+def _opts(variant, max_depth, dtype=F64, intile=True, equilibrate=False):
     o = Opts()
     o.variant = {"strassen": STRASSEN, "winograd": WINOGRAD}.get(variant, variant)
     if max_depth is None:
         # reduced-precision leaves are classical; other forms fuse two Strassen levels
         max_depth = 0 if (dtype & 0xff) in (F32_BF16X3, F32_FP8) else DEFAULT_MAX_DEPTH
     o.max_depth = int(max_depth)
-    o.flags = (OPT_INTILE if intile else 0) | (OPT_EQUILIBRATE if equilibrate else 0)
+    o.flags = (0 if intile else OPT_PRODUCT_TILES) | (OPT_EQUILIBRATE if equilibrate else 0)
     return o
 
 
 def plan_info(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None,
-              intile=False, equilibrate=False) -> dict:
+              intile=True, equilibrate=False) -> dict:
     """Host-only description of the device plan (no GPU needed)."""
     st = PlanStats()
     o = _opts(variant, max_depth, dtype, intile, equilibrate)
@@ -130,7 +130,7 @@ def plan_info(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strass
 
 
 def workspace_bytes(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None,
-                    intile=False, equilibrate=False) -> int:
+                    intile=True, equilibrate=False) -> int:
     out = ctypes.c_size_t(0)
     o = _opts(variant, max_depth, dtype, intile, equilibrate)
     rc = load().ata_workspace_bytes(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(out))
@@ -196,11 +196,12 @@ def _stream_handle(stream):
 
 
 def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_depth=None, out=None,
-         workspace=None, stream=None, intile=False, equilibrate=False):
+         workspace=None, stream=None, intile=True, equilibrate=False):
     """Packed lower triangle of A^t A for a 2-D CUDA tensor A (row-major rows,
     unit column stride, row stride >= n).  Asynchronous on `stream` (default:
     torch's current stream).  Returns the packed output tensor.  intile: run
-    the last Strassen level inside each workgroup tile (OPT_INTILE);
+    the last Strassen level inside each workgroup tile (default), else as
+    product tiles summed by a combination pass (OPT_PRODUCT_TILES);
     equilibrate: power-of-two column scaling around the product
     (OPT_EQUILIBRATE)."""
     import torch

@@ -119,7 +119,7 @@ int resolve_opts(const ata_opts* opts, int& variant, int& max_depth, int& flags)
         variant = opts->variant;
         max_depth = opts->max_depth;
         flags = opts->flags;
-        if (flags & ~(ATA_OPT_INTILE | ATA_OPT_EQUILIBRATE)) return -1;
+        if (flags & ~(ATA_OPT_PRODUCT_TILES | ATA_OPT_EQUILIBRATE)) return -1;
     }
     if (variant != ATA_VARIANT_STRASSEN && variant != ATA_VARIANT_WINOGRAD) return -1;
     if (max_depth < -1) return -1;
@@ -207,7 +207,7 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
     po.cutoff = cutoff;
     po.variant = variant;
     po.max_depth = max_depth;
-    po.intile = (flags & ATA_OPT_INTILE) != 0;
+    po.intile = (flags & ATA_OPT_PRODUCT_TILES) == 0;
     try {
         pd->plan = build_plan(m, n, po);
     } catch (const std::length_error&) {
@@ -457,7 +457,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     }
     const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
     std::shared_ptr<PlanDev> pd;
-    const int rc = get_plan(m, n, c, variant, max_depth, flags & ATA_OPT_INTILE, false, pd);
+    const int rc = get_plan(m, n, c, variant, max_depth, flags & ATA_OPT_PRODUCT_TILES, false, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
     std::memset(out, 0, sizeof(*out));
@@ -518,7 +518,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     }
     const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
     std::shared_ptr<PlanDev> pd;
-    rc = get_plan(m, n, c, variant, max_depth, flags & ATA_OPT_INTILE, true, pd);
+    rc = get_plan(m, n, c, variant, max_depth, flags & ATA_OPT_PRODUCT_TILES, true, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
     const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0);

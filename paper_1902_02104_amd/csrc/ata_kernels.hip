@@ -339,10 +339,13 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
 // K per segment) is split once more into quadrants; a workgroup owns the
 // 64 x 64 tile at (ti, tj) of all four result quadrants and keeps the seven
 // products in registers (eight waves of 16 x 32 each).  While a k tile is
-// staged, each thread sums the operand terms of higher levels, forms the
-// seven left and seven right operands of this level from the four quadrant
-// values it holds, and writes them to fourteen LDS planes; the MFMA loop
-// then reads operands directly.  The products are combined in FP64.
+// staged, each thread sums the operand terms of higher levels.  With
+// single-term operands it also forms the seven left and seven right
+// operands of this level from the four quadrant values it holds and writes
+// them to fourteen LDS planes, which the MFMA loop reads directly; with
+// multi-term operands (whose staging registers leave no room for that) it
+// writes the four quadrant planes and the MFMA loop forms the sums in
+// registers.  The products are combined in FP64.
 // ---------------------------------------------------------------------------
 constexpr int ST = kStrTile;  // 64
 
@@ -418,8 +421,10 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
     typedef Eng<T> E;
     constexpr bool F32 = std::is_same<T, float>::value;
     constexpr int BR = 16 / E::RM, BC = 32 / E::RN;
-    __shared__ T Xs[2][7][SK][ST + E::PAD];
-    __shared__ T Ys[2][7][SK][ST + E::PAD];
+    constexpr bool STAGED = TMAX == 1;  // operand sums formed while staging
+    constexpr int NPL = STAGED ? 7 : 4;  // LDS planes per operand
+    __shared__ T Xs[2][NPL][SK][ST + E::PAD];
+    __shared__ T Ys[2][NPL][SK][ST + E::PAD];
 
     const WorkItem w = items[blockIdx.x];
     const DevTask t = tasks[w.task];
@@ -548,13 +553,21 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
                     }
                 }
             }
-            T lo[7], ro[7];
-            left_operands<VAR>(x[0], x[1], x[2], x[3], lo);
-            right_operands<VAR>(y[0], y[1], y[2], y[3], ro);
+            if constexpr (STAGED) {
+                T lo[7], ro[7];
+                left_operands<VAR>(x[0], x[1], x[2], x[3], lo);
+                right_operands<VAR>(y[0], y[1], y[2], y[3], ro);
 #pragma unroll
-            for (int p = 0; p < 7; ++p) {
-                Xs[buf][p][lk + 8 * r][lc] = lo[p];
-                Ys[buf][p][lk + 8 * r][lc] = ro[p];
+                for (int p = 0; p < 7; ++p) {
+                    Xs[buf][p][lk + 8 * r][lc] = lo[p];
+                    Ys[buf][p][lk + 8 * r][lc] = ro[p];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    Xs[buf][q][lk + 8 * r][lc] = x[q];
+                    Ys[buf][q][lk + 8 * r][lc] = y[q];
+                }
             }
         }
     };
@@ -586,15 +599,25 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
 #pragma unroll
             for (int cf = 0; cf < BC; ++cf) {
                 const int cc = wn * 32 + cf * E::RN + (lane & 15);
+                if constexpr (STAGED) {
 #pragma unroll
-                for (int p = 0; p < 7; ++p) ro[cf][p] = Ys[buf][p][kr][cc];
+                    for (int p = 0; p < 7; ++p) ro[cf][p] = Ys[buf][p][kr][cc];
+                } else {
+                    right_operands<VAR>(Ys[buf][0][kr][cc], Ys[buf][1][kr][cc], Ys[buf][2][kr][cc],
+                                        Ys[buf][3][kr][cc], ro[cf]);
+                }
             }
 #pragma unroll
             for (int rb = 0; rb < BR; ++rb) {
                 const int rr = wm * 16 + rb * E::RM + E::arow(lane);
                 T lo[7];
+                if constexpr (STAGED) {
 #pragma unroll
-                for (int p = 0; p < 7; ++p) lo[p] = Xs[buf][p][kr][rr];
+                    for (int p = 0; p < 7; ++p) lo[p] = Xs[buf][p][kr][rr];
+                } else {
+                    left_operands<VAR>(Xs[buf][0][kr][rr], Xs[buf][1][kr][rr], Xs[buf][2][kr][rr],
+                                       Xs[buf][3][kr][rr], lo);
+                }
 #pragma unroll
                 for (int p = 0; p < 7; ++p)
 #pragma unroll
@@ -649,18 +672,39 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
 // Combination of workspace products into an off-diagonal block of packed C.
 // Each output element sums the workspace slots of its Strassen path with the
 // signs of the combination formulas, over the K parts in part order, in
-// FP64.  A workgroup covers kCbChunk consecutive elements (coalesced: thread
-// t handles elements t, t + 256, ...); one binary search per workgroup finds
-// the first block, threads step forward from there.
+// FP64 (path order within a part).  One thread per element; one binary
+// search per workgroup finds the block of its first element.
 // ---------------------------------------------------------------------------
 __constant__ int c_dcoef[2][7][4] = ATA_D_COEF;
-constexpr int kCbChunk = 1024;
+
+// For one expanded level: the (at most four) products that enter result
+// quadrant q, in product order, with their signs (0 pads the list).
+struct QuadSlots {
+    int path[2][4][4];
+    int sign[2][4][4];
+};
+constexpr QuadSlots make_quad_slots() {
+    QuadSlots t{};
+    constexpr int d[2][7][4] = ATA_D_COEF;
+    for (int v = 0; v < 2; ++v)
+        for (int q = 0; q < 4; ++q) {
+            int k = 0;
+            for (int p = 0; p < 7; ++p)
+                if (d[v][p][q] != 0 && k < 4) {
+                    t.path[v][q][k] = p;
+                    t.sign[v][q][k] = d[v][p][q];
+                    ++k;
+                }
+        }
+    return t;
+}
+__constant__ QuadSlots c_qslots = make_quad_slots();
 
 template <typename OUT>
 __global__ void __launch_bounds__(256) k_combine(const DevCombine* __restrict__ cbs, int ncb, int64_t total,
                                                  const double* __restrict__ W, OUT* __restrict__ C) {
     __shared__ int first;
-    const int64_t e0 = (int64_t)blockIdx.x * kCbChunk;
+    const int64_t e0 = (int64_t)blockIdx.x * 256;
     if (threadIdx.x == 0) {
         int lo = 0, hi = ncb - 1;
         while (lo < hi) {
@@ -671,39 +715,49 @@ __global__ void __launch_bounds__(256) k_combine(const DevCombine* __restrict__ 
         first = lo;
     }
     __syncthreads();
+    const int64_t e = e0 + threadIdx.x;
+    if (e >= total) return;
     int idx = first;
-    for (int r = 0; r < kCbChunk / 256; ++r) {
-        const int64_t e = e0 + r * 256 + threadIdx.x;
-        if (e >= total) return;
-        while (idx + 1 < ncb && cbs[idx + 1].elem_off <= e) ++idx;
-        const DevCombine& cb = cbs[idx];
-        const int64_t loc = e - cb.elem_off;
-        int i, j;
-        if (loc < 0x100000000ll) {
-            const uint32_t l32 = (uint32_t)loc, n32 = (uint32_t)cb.N;
-            i = (int)(l32 / n32);
-            j = (int)(l32 - (uint32_t)i * n32);
-        } else {
-            i = (int)(loc / cb.N);
-            j = (int)(loc - (int64_t)i * cb.N);
+    while (idx + 1 < ncb && cbs[idx + 1].elem_off <= e) ++idx;
+    const DevCombine& cb = cbs[idx];
+    const int64_t loc = e - cb.elem_off;
+    int i, j;
+    if (loc < 0x100000000ll) {
+        const uint32_t l32 = (uint32_t)loc, n32 = (uint32_t)cb.N;
+        i = (int)(l32 / n32);
+        j = (int)(l32 - (uint32_t)i * n32);
+    } else {
+        i = (int)(loc / cb.N);
+        j = (int)(loc - (int64_t)i * cb.N);
+    }
+    if (cb.lower && j > i) return;
+    // quadrant path of (i, j), first level in the most significant digit
+    int ii = i, jj = j, Mc = cb.M, Nc = cb.N, qcode = 0;
+    for (int l = 0; l < cb.levels; ++l) {
+        const int MH = (Mc + 1) >> 1, NH = (Nc + 1) >> 1;
+        const int a = ii >= MH, c = jj >= NH;
+        ii -= a * MH;
+        jj -= c * NH;
+        qcode = qcode * 4 + a * 2 + c;
+        Mc = MH;
+        Nc = NH;
+    }
+    const int64_t slot_elems = (int64_t)cb.Mp * cb.Np;
+    const double* base = W + cb.ws_off + (int64_t)ii * cb.Np + jj;
+    double sum = 0.0;
+    if (cb.levels == 1 && cb.nparts == 1) {
+        // one level: load the quadrant's products together, then sum in order
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = base[c_qslots.path[cb.variant][qcode][k] * slot_elems];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int sg = c_qslots.sign[cb.variant][qcode][k];
+            if (sg) sum += sg > 0 ? v[k] : -v[k];
         }
-        if (cb.lower && j > i) continue;
-        // quadrant path of (i, j), first level in the most significant digit
-        int ii = i, jj = j, Mc = cb.M, Nc = cb.N, qcode = 0;
-        for (int l = 0; l < cb.levels; ++l) {
-            const int MH = (Mc + 1) >> 1, NH = (Nc + 1) >> 1;
-            const int a = ii >= MH, c = jj >= NH;
-            ii -= a * MH;
-            jj -= c * NH;
-            qcode = qcode * 4 + a * 2 + c;
-            Mc = MH;
-            Nc = NH;
-        }
-        const int64_t slot_elems = (int64_t)cb.Mp * cb.Np;
-        const double* base = W + cb.ws_off + (int64_t)ii * cb.Np + jj;
+    } else {
         int npaths = 1;
         for (int l = 0; l < cb.levels; ++l) npaths *= 7;
-        double sum = 0.0;
         for (int part = 0; part < cb.nparts; ++part) {
             const double* pb = base + (int64_t)part * cb.part_stride;
             for (int path = 0; path < npaths; ++path) {
@@ -716,8 +770,8 @@ __global__ void __launch_bounds__(256) k_combine(const DevCombine* __restrict__ 
                 if (coef) sum += coef > 0 ? pb[path * slot_elems] : -pb[path * slot_elems];
             }
         }
-        store_out(C + packed_index((int64_t)cb.r0 + i, cb.q0) + j, cb.beta, sum);
     }
+    store_out(C + packed_index((int64_t)cb.r0 + i, cb.q0) + j, cb.beta, sum);
 }
 
 template <typename T>
@@ -1266,7 +1320,7 @@ hipError_t launch_str(bool f32, bool out_f64, int variant, int tmax, const void*
 hipError_t launch_combine(bool out_f64, const DevCombine* cbs, int ncb, int64_t total, const double* W, void* C,
                           hipStream_t s) {
     if (ncb <= 0 || total <= 0) return hipSuccess;
-    const int64_t blocks = (total + kCbChunk - 1) / kCbChunk;
+    const int64_t blocks = (total + 255) / 256;
     if (out_f64)
         hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, (double*)C);
     else

@@ -96,15 +96,16 @@ struct PlanOptions {
     // K splitting: a launch with fewer workgroup tiles than split_target
     // splits long K ranges (at least split_min_k each part) over several
     // workgroups whose partial results a combination sums in part order.
-    int split_target = 768;
-    int split_min_k = 2048;
-    // Where the last Strassen level of an off-diagonal product runs.  false:
-    // every level is expanded into signed operand terms and each of the 7^d
-    // products is a classical tile task (TK_GEMM with terms) writing a
-    // workspace slot, summed by a combination.  true: the last level runs
-    // inside each workgroup tile (TK_STR).  Products deeper than
-    // kMaxExpandDepth levels (one for Winograd) always use the in-tile form.
-    bool intile = false;
+    // (12 workgroups per CU: the last wave of a launch is a small fraction)
+    int split_target = 6144;
+    int split_min_k = 1024;
+    // Where the last Strassen level of an off-diagonal product runs.  true:
+    // inside each workgroup tile (TK_STR).  false: every level is expanded
+    // into signed operand terms and each of the 7^d products is a classical
+    // tile task (TK_GEMM with terms) writing a workspace slot, summed by a
+    // combination.  Products deeper than kMaxExpandDepth levels (one for
+    // Winograd) always use the in-tile form.
+    bool intile = true;
 };
 
 constexpr int kMaxExpandDepth = 2;

@@ -99,10 +99,10 @@ def test_workspace_size(lib):
     # block's size halved (ceil) d times.  Off-diagonal blocks of 10000^2 at
     # cutoff 256: 5000^2, 2 x 2500^2, 4 x 1250^2, 8 x 625^2 (two levels each)
     # and 16 x (312 x 313) (one level; K = 625 rows)
-    ws = P.workspace_bytes(10000, 10000, 256, max_depth=2)
+    ws = P.workspace_bytes(10000, 10000, 256, max_depth=2, intile=False)
     expect = 8 * (49 * 1250 ** 2 + 2 * 49 * 625 ** 2 + 4 * 49 * 313 ** 2 + 8 * 49 * 157 ** 2 + 16 * 7 * 156 * 157)
     assert expect <= ws < expect + 256
-    ws1 = P.workspace_bytes(256, 192, 32, max_depth=1)
+    ws1 = P.workspace_bytes(256, 192, 32, max_depth=1, intile=False)
     assert ws1 > 0
 
 
