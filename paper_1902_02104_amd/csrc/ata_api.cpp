@@ -127,6 +127,13 @@ int resolve_opts(const ata_opts* opts, int& variant, int& max_depth, int& flags)
 }
 
 int elem_bytes_in(int dtype) { return (dtype & 0xff) == ATA_F64 ? 8 : 4; }
+
+// Plan-shaping bits of the option flags plus the dtype class (the plan cache
+// key): tables differ between the product-tile and in-tile forms and in the
+// split-K target of the reduced-precision forms.
+int plan_flags(int flags, int dtype) {
+    return (flags & ATA_OPT_PRODUCT_TILES) | (dtype_lp(dtype) ? kPlanReducedPrecision : 0);
+}
 int elem_bytes_out(int dtype) {
     if ((dtype & 0xff) == ATA_F64) return 8;
     return (dtype & ATA_OUT_F64) ? 8 : 4;
@@ -208,6 +215,9 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
     po.variant = variant;
     po.max_depth = max_depth;
     po.intile = (flags & ATA_OPT_PRODUCT_TILES) == 0;
+    // reduced-precision tiles run several times faster: splitting K for a
+    // fuller last wave costs them more (partials and their sum) than it saves
+    if (flags & kPlanReducedPrecision) po.split_target = 768;
     try {
         pd->plan = build_plan(m, n, po);
     } catch (const std::length_error&) {
@@ -457,7 +467,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     }
     const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
     std::shared_ptr<PlanDev> pd;
-    const int rc = get_plan(m, n, c, variant, max_depth, flags & ATA_OPT_PRODUCT_TILES, false, pd);
+    const int rc = get_plan(m, n, c, variant, max_depth, plan_flags(flags, dtype), false, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
     std::memset(out, 0, sizeof(*out));
@@ -518,7 +528,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     }
     const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
     std::shared_ptr<PlanDev> pd;
-    rc = get_plan(m, n, c, variant, max_depth, flags & ATA_OPT_PRODUCT_TILES, true, pd);
+    rc = get_plan(m, n, c, variant, max_depth, plan_flags(flags, dtype), true, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
     const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0);

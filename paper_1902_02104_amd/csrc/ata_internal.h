@@ -54,6 +54,9 @@ int elem_bytes_in(int dtype);
 int elem_bytes_out(int dtype);
 int64_t default_cutoff(int64_t m, int64_t n, int dtype);
 WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate);
+// Internal plan flag (beside ATA_OPT_* bits): reduced-precision dtype.
+constexpr int kPlanReducedPrecision = 0x10000;
+int plan_flags(int flags, int dtype);
 int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, int flags, bool need_device,
              std::shared_ptr<PlanDev>& out);
 // dblob: device copy of pd.host_blob (pd.blob, or a copy the caller made)
