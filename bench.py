@@ -283,8 +283,9 @@ def main():
     ap.add_argument("--cutoff", type=int, default=0, help="0: tune over {128,256,512}")
     ap.add_argument("--max-depth", type=int, default=None, help="default: tune over {1, 2}")
     ap.add_argument("--variant", default="strassen")
-    ap.add_argument("--form", default="tune", choices=("tune", "tiles", "intile"),
-                    help="last Strassen level as product tiles + combination, in-tile, or tuned")
+    ap.add_argument("--form", default="tune", choices=("tune", "intile", "tiles", "opsums"),
+                    help="last Strassen level: in-tile, product tiles (fused sums), product tiles on operand sums "
+                         "formed in a memory pass, or tuned over the three")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classical", action="store_true")
@@ -317,8 +318,9 @@ def main():
     A = torch.from_numpy(A_np).to(dev)
     C = torch.empty(P.tri(n), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
-    def run(cutoff, d, intile=False, variant=args.variant):
-        P.gram(A, cutoff=cutoff, max_depth=d, variant=variant, out=C, stream=stream, intile=intile)
+    def run(cutoff, d, form="intile", variant=args.variant):
+        P.gram(A, cutoff=cutoff, max_depth=d, variant=variant, out=C, stream=stream, intile=form == "intile",
+               operand_sums=form == "opsums")
 
     def time_steps(fn, steps):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -332,28 +334,30 @@ def main():
         return e0.elapsed_time(e1) / steps
 
     # tuning of the leaf cutoff over the set the workload names, of the
-    # number of Strassen levels per off-diagonal product, and of where the
-    # last level runs (product tiles + combination, or inside the tile)
+    # number of Strassen levels per off-diagonal product, and of the form of
+    # the last level (inside the tile; product tiles with operand sums formed
+    # while staging; product tiles on operand sums formed in a memory pass)
     sweep = {}
     cutoffs = (128, 256, 512) if args.cutoff == 0 else (args.cutoff,)
     depths = (1, 2) if args.max_depth is None else (args.max_depth,)
-    forms = (False, True) if args.form == "tune" else (args.form == "intile",)
+    forms = ("intile", "tiles", "opsums") if args.form == "tune" else (args.form,)
     for c in cutoffs:
         for d in depths:
-            for it in forms:
-                key = "c%d_d%d_%s" % (c, d, "intile" if it else "tiles")
-                run(c, d, it)
-                sweep[key] = time_steps(lambda: run(c, d, it), 3)
+            for f in forms:
+                key = "c%d_d%d_%s" % (c, d, f)
+                run(c, d, f)
+                sweep[key] = time_steps(lambda: run(c, d, f), 3)
                 _log("sweep %s: %.2f ms" % (key, sweep[key]))
     best = min(sweep, key=sweep.get)
     cutoff, depth = (int(x[1:]) for x in best.split("_")[:2])
-    intile = best.endswith("intile")
+    form = best.split("_")[2]
+    intile = form == "intile"
 
     for _ in range(args.warmup):
-        run(cutoff, depth, intile)
+        run(cutoff, depth, form)
     P.profile_enable(True)
     P.profile_collect()
-    ms = time_steps(lambda: run(cutoff, depth, intile), args.steps)
+    ms = time_steps(lambda: run(cutoff, depth, form), args.steps)
     prof = P.profile_collect()
     P.profile_enable(False)
     _log("timed %d steps: %.3f ms/step" % (args.steps, ms))
@@ -364,7 +368,8 @@ def main():
     norms = (A * A).sum(dim=0)
     diag_err = float(((diag - norms).abs() / norms).max())
 
-    st = P.plan_info(m, n, cutoff, max_depth=depth, variant=args.variant, intile=intile)
+    st = P.plan_info(m, n, cutoff, max_depth=depth, variant=args.variant, intile=intile,
+                     operand_sums=form == "opsums")
     flops_mn2 = float(m) * n * n
     value = flops_mn2 / (ms * 1e-3) / 1e12
 
@@ -382,9 +387,9 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] else None
-    roof["kernel"] = {"strassen": "k_str_f64" if intile else "k_gemm_terms_f64", "gemm": "k_gemm_f64",
-                      "syrk": "k_gemm_f64", "combine": "k_combine_f64"}.get(dom, dom)
-    roof["traffic"] = _profiled_traffic(roof["kernel"], n, cutoff, depth, "intile" if intile else "tiles")
+    roof["kernel"] = {"strassen": {"intile": "k_str_f64", "tiles": "k_gemm_terms_f64", "opsums": "k_gemm_f64"}[form],
+                      "gemm": "k_gemm_f64", "syrk": "k_gemm_f64", "combine": "k_combine_f64"}.get(dom, dom)
+    roof["traffic"] = _profiled_traffic(roof["kernel"], n, cutoff, depth, form)
     roof["avg_launch_ms"] = avg_ms
 
     if args.copy_bytes > 0:
@@ -437,7 +442,8 @@ def main():
             "workload": "square FP64 A %dx%d, i.i.d. uniform[-1,1] (seed %d), packed lower C = A^tA"
                         % (m, n, synthetic.SEED_SQUARE),
             "m": m, "n": n, "cutoff": cutoff, "tuning_sweep_ms": sweep, "variant": args.variant,
-            "max_strassen_depth": depth, "last_level": "in-tile" if intile else "product tiles",
+            "max_strassen_depth": depth, "last_level": {"intile": "in-tile", "tiles": "product tiles",
+                                                        "opsums": "product tiles on operand sums"}[form],
             "phases": st["phases"], "ata_depth": st["ata_depth"],
             "mults_over_classical": st["mults"] / st["classical_mults"],
         },

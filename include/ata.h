@@ -83,6 +83,12 @@ typedef struct ata_opts {
  * instead: each of the 7^d products is a classical tile whose staging sums
  * the terms, written to the workspace and combined by a separate pass. */
 #define ATA_OPT_PRODUCT_TILES 0x1
+/* ata_opts.flags: with product tiles, form each product's operand sums in a
+ * memory pass (the explicit sums of the paper's HASA listing) into the
+ * workspace and run the products as plain classical tiles on them.  Trades
+ * one pass over the operands for classical-tile efficiency of the products.
+ * Implies ATA_OPT_PRODUCT_TILES. */
+#define ATA_OPT_OPERAND_SUMS 0x4
 /* ata_opts.flags: column equilibration.  Columns of A are scaled by powers
  * of two (each column's largest magnitude into [1, 2)) before the product
  * and C is scaled back, both exactly unless entries underflow.  The error of

@@ -26,6 +26,7 @@ WINOGRAD = 1
 DEFAULT_MAX_DEPTH = 2
 OPT_PRODUCT_TILES = 0x1
 OPT_EQUILIBRATE = 0x2
+OPT_OPERAND_SUMS = 0x4
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _lib = None
@@ -107,22 +108,23 @@ def tri(n: int) -> int:
     return n * (n + 1) // 2
 
 
-def _opts(variant, max_depth, dtype=F64, intile=True, equilibrate=False):
+def _opts(variant, max_depth, dtype=F64, intile=True, equilibrate=False, operand_sums=False):
     o = Opts()
     o.variant = {"strassen": STRASSEN, "winograd": WINOGRAD}.get(variant, variant)
     if max_depth is None:
         # reduced-precision leaves are classical; other forms fuse two Strassen levels
         max_depth = 0 if (dtype & 0xff) in (F32_BF16X3, F32_FP8) else DEFAULT_MAX_DEPTH
     o.max_depth = int(max_depth)
-    o.flags = (0 if intile else OPT_PRODUCT_TILES) | (OPT_EQUILIBRATE if equilibrate else 0)
+    o.flags = ((0 if intile else OPT_PRODUCT_TILES) | (OPT_EQUILIBRATE if equilibrate else 0)
+               | (OPT_OPERAND_SUMS if operand_sums else 0))
     return o
 
 
 def plan_info(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None,
-              intile=True, equilibrate=False) -> dict:
+              intile=True, equilibrate=False, operand_sums=False) -> dict:
     """Host-only description of the device plan (no GPU needed)."""
     st = PlanStats()
-    o = _opts(variant, max_depth, dtype, intile, equilibrate)
+    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums)
     rc = load().ata_plan_info(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(st))
     if rc:
         raise AtaError(rc, "ata_plan_info")
@@ -130,9 +132,9 @@ def plan_info(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strass
 
 
 def workspace_bytes(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None,
-                    intile=True, equilibrate=False) -> int:
+                    intile=True, equilibrate=False, operand_sums=False) -> int:
     out = ctypes.c_size_t(0)
-    o = _opts(variant, max_depth, dtype, intile, equilibrate)
+    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums)
     rc = load().ata_workspace_bytes(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(out))
     if rc:
         raise AtaError(rc, "ata_workspace_bytes")
@@ -196,14 +198,15 @@ def _stream_handle(stream):
 
 
 def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_depth=None, out=None,
-         workspace=None, stream=None, intile=True, equilibrate=False):
+         workspace=None, stream=None, intile=True, equilibrate=False, operand_sums=False):
     """Packed lower triangle of A^t A for a 2-D CUDA tensor A (row-major rows,
     unit column stride, row stride >= n).  Asynchronous on `stream` (default:
     torch's current stream).  Returns the packed output tensor.  intile: run
     the last Strassen level inside each workgroup tile (default), else as
     product tiles summed by a combination pass (OPT_PRODUCT_TILES);
     equilibrate: power-of-two column scaling around the product
-    (OPT_EQUILIBRATE)."""
+    (OPT_EQUILIBRATE); operand_sums: product tiles on operand sums formed in
+    a memory pass (OPT_OPERAND_SUMS)."""
     import torch
     lib = load()
     if A.dim() != 2:
@@ -224,7 +227,7 @@ def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_d
         out = torch.empty(tri(n), dtype=out_t, device=A.device)
     elif out.dtype != out_t or out.numel() < tri(n) or not out.is_contiguous():
         raise ValueError("bad output tensor")
-    o = _opts(variant, max_depth, dtype, intile, equilibrate)
+    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums)
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()

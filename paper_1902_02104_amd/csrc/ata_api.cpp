@@ -72,6 +72,8 @@ void serialize(PlanDev& pd) {
         d.str_tmax = ph.str_tmax;
         d.n_tg = (int)ph.tg_items.size();
         d.tg_tmax = ph.tg_tmax;
+        d.n_ops = (int)ph.opsums.size();
+        d.ops_rows = ph.opsum_rows;
         d.n_gemm = (int)ph.gemm_items.size();
         d.n_syrk = (int)ph.syrk_items.size();
         d.n_cb = (int)ph.combines.size();
@@ -86,6 +88,8 @@ void serialize(PlanDev& pd) {
         off = align256(off + ph.syrk_items.size() * sizeof(WorkItem));
         d.off_cb = off;
         off = align256(off + ph.combines.size() * sizeof(DevCombine));
+        d.off_ops = off;
+        off = align256(off + ph.opsums.size() * sizeof(DevOpSum));
     }
     std::vector<char>& host = pd.host_blob;
     host.assign(off ? off : 256, 0);
@@ -100,6 +104,7 @@ void serialize(PlanDev& pd) {
         std::memcpy(host.data() + d.off_gemm, ph.gemm_items.data(), ph.gemm_items.size() * sizeof(WorkItem));
         std::memcpy(host.data() + d.off_syrk, ph.syrk_items.data(), ph.syrk_items.size() * sizeof(WorkItem));
         std::memcpy(host.data() + d.off_cb, ph.combines.data(), ph.combines.size() * sizeof(DevCombine));
+        std::memcpy(host.data() + d.off_ops, ph.opsums.data(), ph.opsums.size() * sizeof(DevOpSum));
     }
 }
 
@@ -119,7 +124,7 @@ int resolve_opts(const ata_opts* opts, int& variant, int& max_depth, int& flags)
         variant = opts->variant;
         max_depth = opts->max_depth;
         flags = opts->flags;
-        if (flags & ~(ATA_OPT_PRODUCT_TILES | ATA_OPT_EQUILIBRATE)) return -1;
+        if (flags & ~(ATA_OPT_PRODUCT_TILES | ATA_OPT_EQUILIBRATE | ATA_OPT_OPERAND_SUMS)) return -1;
     }
     if (variant != ATA_VARIANT_STRASSEN && variant != ATA_VARIANT_WINOGRAD) return -1;
     if (max_depth < -1) return -1;
@@ -132,7 +137,7 @@ int elem_bytes_in(int dtype) { return (dtype & 0xff) == ATA_F64 ? 8 : 4; }
 // key): tables differ between the product-tile and in-tile forms and in the
 // split-K target of the reduced-precision forms.
 int plan_flags(int flags, int dtype) {
-    return (flags & ATA_OPT_PRODUCT_TILES) | (dtype_lp(dtype) ? kPlanReducedPrecision : 0);
+    return (flags & (ATA_OPT_PRODUCT_TILES | ATA_OPT_OPERAND_SUMS)) | (dtype_lp(dtype) ? kPlanReducedPrecision : 0);
 }
 int elem_bytes_out(int dtype) {
     if ((dtype & 0xff) == ATA_F64) return 8;
@@ -149,7 +154,7 @@ bool dtype_lp(int dtype) { return (dtype & 0xff) == ATA_F32_BF16X3 || (dtype & 0
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate) {
+WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate, int64_t opsum_elems) {
     WsLayout L;
     size_t off = (size_t)ws_elems * sizeof(double);
     off = (off + 255) & ~(size_t)255;
@@ -175,6 +180,11 @@ WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equil
             off += plane;
             off = (off + 255) & ~(size_t)255;
         }
+    }
+    if (opsum_elems > 0 && !lp) {
+        L.ops = off;
+        off += (size_t)opsum_elems * elem_bytes_in(dtype);
+        off = (off + 255) & ~(size_t)255;
     }
     if (equilibrate && !lp && n > 0 && m > 0) {
         L.eq = true;
@@ -214,7 +224,8 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
     po.cutoff = cutoff;
     po.variant = variant;
     po.max_depth = max_depth;
-    po.intile = (flags & ATA_OPT_PRODUCT_TILES) == 0;
+    po.opsums = (flags & ATA_OPT_OPERAND_SUMS) != 0;
+    po.intile = (flags & (ATA_OPT_PRODUCT_TILES | ATA_OPT_OPERAND_SUMS)) == 0;
     // reduced-precision tiles run several times faster: splitting K for a
     // fuller last wave costs them more (partials and their sum) than it saves
     if (flags & kPlanReducedPrecision) po.split_target = 768;
@@ -390,10 +401,19 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             err = launch_str(f32, out64, variant, ph.str_tmax, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_str),
                              ph.n_str, C_lower, W, s);
         }
+        if (err == hipSuccess && ph.n_ops) {
+            ProfScope ps(ATA_KERNEL_OTHER, s);
+            err = launch_opsum(f32, A, lda, tb, (const DevOpSum*)(pd->blob + ph.off_ops), ph.n_ops, ph.ops_rows,
+                               ws + L.ops, s);
+        }
         if (err == hipSuccess && ph.n_tg) {
             ProfScope ps(ATA_KERNEL_STRASSEN, s);
-            err = launch_gemm_terms(f32, out64, ph.tg_tmax, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_tg),
-                                    ph.n_tg, C_lower, W, s);
+            if (ph.tg_tmax <= 1)  // products on operand-sum buffers
+                err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_tg), ph.n_tg, C_lower, W,
+                                  s, ws + L.ops);
+            else
+                err = launch_gemm_terms(f32, out64, ph.tg_tmax, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_tg),
+                                        ph.n_tg, C_lower, W, s);
         }
         hipStream_t s_small = split ? fc.s2 : s;
         if (err == hipSuccess && ph.n_gemm) {
@@ -481,7 +501,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     out->phases = (int64_t)P.phases.size();
     out->ata_depth = P.ata_depth;
     out->max_hasa_depth = P.max_hasa_depth;
-    out->workspace_bytes = (int64_t)ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0).total;
+    out->workspace_bytes = (int64_t)ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0, P.opsum_elems).total;
     out->cutoff = c;
     out->strassen_mults = P.str_mults;
     out->gemm_mults = P.gemm_mults;
@@ -531,7 +551,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     rc = get_plan(m, n, c, variant, max_depth, plan_flags(flags, dtype), true, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
-    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0);
+    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0, P.opsum_elems);
     if (L.ldt > INT32_MAX) return ATA_EUNSUPPORTED;
     char* ws = nullptr;
     bool owned = false;

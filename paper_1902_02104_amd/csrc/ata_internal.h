@@ -14,9 +14,9 @@ namespace detail {
 
 // Device copy of one plan's tables.
 struct PhaseDev {
-    int n_str = 0, n_tg = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, str_tmax = 0, tg_tmax = 0;
-    int64_t cb_elems = 0;
-    size_t off_str = 0, off_tg = 0, off_gemm = 0, off_syrk = 0, off_cb = 0;
+    int n_str = 0, n_tg = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, n_ops = 0, str_tmax = 0, tg_tmax = 0;
+    int64_t cb_elems = 0, ops_rows = 0;
+    size_t off_str = 0, off_tg = 0, off_gemm = 0, off_syrk = 0, off_cb = 0, off_ops = 0;
 };
 
 struct PlanDev {
@@ -38,11 +38,11 @@ struct PlanDev {
 };
 
 // Device workspace layout: [FP64 Strassen products][scales][column-max
-// partials][converted copy plane 0][plane 1][equilibrated copy of A], each
-// 256-byte aligned.  The scale and partial areas serve the FP8 scales or the
+// partials][converted copy plane 0][plane 1][operand-sum buffers]
+// [equilibrated copy of A], each 256-byte aligned.  The scale and partial areas serve the FP8 scales or the
 // equilibration scales (never both).
 struct WsLayout {
-    size_t w = 0, scale = 0, part = 0, t0 = 0, t1 = 0, eqa = 0, total = 0;
+    size_t w = 0, scale = 0, part = 0, t0 = 0, t1 = 0, ops = 0, eqa = 0, total = 0;
     int64_t ldt = 0;
     bool eq = false;
 };
@@ -53,7 +53,7 @@ bool dtype_lp(int dtype);
 int elem_bytes_in(int dtype);
 int elem_bytes_out(int dtype);
 int64_t default_cutoff(int64_t m, int64_t n, int dtype);
-WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate);
+WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate, int64_t opsum_elems);
 // Internal plan flag (beside ATA_OPT_* bits): reduced-precision dtype.
 constexpr int kPlanReducedPrecision = 0x10000;
 int plan_flags(int flags, int dtype);

@@ -18,8 +18,15 @@ struct DevTables {
 
 // Classical tiles (TK_SYRK / TK_GEMM) on FP64 or FP32 MFMA.  out_f64 selects
 // a double C for float input.
+// Aops: base of the operand-sum buffers read by tasks with src == 1.
 hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
-                       const WorkItem* items, int nitems, void* C, double* W, hipStream_t s);
+                       const WorkItem* items, int nitems, void* C, double* W, hipStream_t s,
+                       const void* Aops = nullptr);
+
+// Operand sums of the product tasks in `recs` (one workgroup per buffer row;
+// rows = total rows of the records) into `out`, in the input type.
+hipError_t launch_opsum(bool f32, const void* A, int64_t lda, const DevTables& tb, const DevOpSum* recs, int nrec,
+                        int64_t rows, void* out, hipStream_t s);
 
 // Strassen product tiles: classical tiles whose operands are signed sums of
 // up to tmax terms (column padding reads as zero), written to the workspace.

@@ -137,7 +137,8 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
                                                  const DevTerm* __restrict__ terms_,
                                                  const int32_t* __restrict__ segs_,
                                                  const WorkItem* __restrict__ items, OUT* __restrict__ C_,
-                                                 double* __restrict__ W, const BatchEntry* __restrict__ batch) {
+                                                 double* __restrict__ W, const BatchEntry* __restrict__ batch,
+                                                 const T* __restrict__ Aops) {
     typedef Eng<T> E;
     constexpr bool F32 = std::is_same<T, float>::value;
     constexpr int BR = 64 / E::RM, BC = 64 / E::RN;
@@ -164,6 +165,10 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
         lda = be.lda;
     }
     const DevTask t = tasks[w.task];
+    if (!BATCH && t.src == 1) {  // operands from the task's operand-sum buffer
+        A = Aops + t.src_off;
+        lda = (int64_t)t.M + t.N;
+    }
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int i0 = w.ti * GT, j0 = w.tj * GT;
@@ -286,6 +291,8 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
             advance();
             load();
         }
+        // issue priority for the MFMA section over the other workgroup's staging
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < GK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
@@ -299,6 +306,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
                 for (int cf = 0; cf < BC; ++cf) E::mma(av, bv[cf], acc[rb][cf]);
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         if (F32 && (((it + 1) * GK) % KFLUSH == 0 || it + 1 == ntiles)) {
 #pragma unroll
             for (int a = 0; a < BR; ++a)
@@ -592,6 +600,7 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
             advance();
             load();
         }
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < SK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
@@ -624,6 +633,7 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
                     for (int cf = 0; cf < BC; ++cf) E::mma(lo[p], ro[cf][p], acc[p][rb][cf]);
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         if (F32 && (((it + 1) * SK) % KFLUSH == 0 || it + 1 == ntiles)) {
 #pragma unroll
             for (int p = 0; p < 7; ++p)
@@ -665,6 +675,62 @@ __global__ void __launch_bounds__(512, 1) k_str(const T* __restrict__ A, int64_t
                 }
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Operand sums (operand-sum form): one workgroup per buffer row.  Row k of a
+// record's buffer is row k of the concatenated chunk windows of its product;
+// column c < M sums the X terms at column c of their quadrants, c >= M the Y
+// terms at c - M, in term order and in the element type, zero where a term
+// is padding (past its columns or rows).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_opsum(const T* __restrict__ A, int64_t lda,
+                                               const DevTask* __restrict__ tasks,
+                                               const DevTerm* __restrict__ terms,
+                                               const int32_t* __restrict__ segs,
+                                               const DevOpSum* __restrict__ recs, int nrec, T* __restrict__ out) {
+    __shared__ int rsel;
+    const int64_t g = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = nrec - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (recs[mid].row_off <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        rsel = lo;
+    }
+    __syncthreads();
+    const DevOpSum rec = recs[rsel];
+    const DevTask t = tasks[rec.task];
+    // chunk (segment) of row k and the row inside its window
+    int k = (int)(g - rec.row_off);
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
+    int s = 0;
+    for (; s + 1 < t.nseg; ++s) {
+        const int len = segs[t.seg_off + s * stride + 2] - segs[t.seg_off + s * stride + 1];
+        if (k < len) break;
+        k -= len;
+    }
+    const int32_t* sg = segs + t.seg_off + s * stride;
+    const int kk = sg[1] + k;
+    T* orow = out + rec.out_off + (int64_t)(g - rec.row_off) * (rec.M + rec.N);
+    for (int c = threadIdx.x; c < rec.M + rec.N; c += 256) {
+        const bool xs = c < rec.M;
+        const int cc = xs ? c : c - rec.M;
+        const int nt = xs ? t.nx : t.ny;
+        const int u0 = xs ? 0 : t.nx;
+        T v = T(0);
+        for (int u = 0; u < nt; ++u) {
+            const DevTerm tm = terms[t.term_off + u0 + u];
+            const int row = sg[kSegHdr + 2 * (u0 + u)] + kk;
+            const int col = tm.col + cc;
+            const T a = (row < sg[kSegHdr + 2 * (u0 + u) + 1] && col < tm.cvend) ? A[(int64_t)row * lda + col] : T(0);
+            v = u == 0 ? (T)tm.sign * a : v + (T)tm.sign * a;
+        }
+        orow[c] = v;
     }
 }
 
@@ -1173,19 +1239,19 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
 // Host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
-                       const WorkItem* items, int nitems, void* C, double* W, hipStream_t s) {
+                       const WorkItem* items, int nitems, void* C, double* W, hipStream_t s, const void* Aops) {
     if (nitems <= 0) return hipSuccess;
     const dim3 g(nitems), b(256);
     const BatchEntry* nb = nullptr;
     if (!f32)
         hipLaunchKernelGGL((k_gemm<double, double, false, 1>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (double*)C, W, nb);
+                           tb.segs, items, (double*)C, W, nb, (const double*)Aops);
     else if (out_f64)
         hipLaunchKernelGGL((k_gemm<float, double, false, 1>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (double*)C, W, nb);
+                           tb.segs, items, (double*)C, W, nb, (const float*)Aops);
     else
         hipLaunchKernelGGL((k_gemm<float, float, false, 1>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (float*)C, W, nb);
+                           tb.segs, items, (float*)C, W, nb, (const float*)Aops);
     return hipGetLastError();
 }
 
@@ -1196,13 +1262,13 @@ static void launch_gemm_terms_t(bool f32, bool out_f64, dim3 g, const void* A, i
     const BatchEntry* nb = nullptr;
     if (!f32)
         hipLaunchKernelGGL((k_gemm<double, double, false, TM>), g, b, 0, s, (const double*)A, lda, tb.tasks,
-                           tb.terms, tb.segs, items, (double*)C, W, nb);
+                           tb.terms, tb.segs, items, (double*)C, W, nb, nullptr);
     else if (out_f64)
         hipLaunchKernelGGL((k_gemm<float, double, false, TM>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (double*)C, W, nb);
+                           tb.segs, items, (double*)C, W, nb, nullptr);
     else
         hipLaunchKernelGGL((k_gemm<float, float, false, TM>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (float*)C, W, nb);
+                           tb.segs, items, (float*)C, W, nb, nullptr);
 }
 
 hipError_t launch_gemm_terms(bool f32, bool out_f64, int tmax, const void* A, int64_t lda, const DevTables& tb,
@@ -1224,13 +1290,13 @@ hipError_t launch_gemm_batch(bool f32, bool out_f64, const BatchEntry* batch, co
     const dim3 g(nitems), b(256);
     if (!f32)
         hipLaunchKernelGGL((k_gemm<double, double, true, 1>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
-                           nullptr, nullptr, batch);
+                           nullptr, nullptr, batch, nullptr);
     else if (out_f64)
         hipLaunchKernelGGL((k_gemm<float, double, true, 1>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
-                           nullptr, nullptr, batch);
+                           nullptr, nullptr, batch, nullptr);
     else
         hipLaunchKernelGGL((k_gemm<float, float, true, 1>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
-                           nullptr, nullptr, batch);
+                           nullptr, nullptr, batch, nullptr);
     return hipGetLastError();
 }
 
@@ -1325,6 +1391,18 @@ hipError_t launch_combine(bool out_f64, const DevCombine* cbs, int ncb, int64_t 
         hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, (double*)C);
     else
         hipLaunchKernelGGL(k_combine<float>, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, (float*)C);
+    return hipGetLastError();
+}
+
+hipError_t launch_opsum(bool f32, const void* A, int64_t lda, const DevTables& tb, const DevOpSum* recs, int nrec,
+                        int64_t rows, void* out, hipStream_t s) {
+    if (nrec <= 0 || rows <= 0) return hipSuccess;
+    if (f32)
+        hipLaunchKernelGGL(k_opsum<float>, dim3((unsigned)rows), dim3(256), 0, s, (const float*)A, lda, tb.tasks,
+                           tb.terms, tb.segs, recs, nrec, (float*)out);
+    else
+        hipLaunchKernelGGL(k_opsum<double>, dim3((unsigned)rows), dim3(256), 0, s, (const double*)A, lda, tb.tasks,
+                           tb.terms, tb.segs, recs, nrec, (double*)out);
     return hipGetLastError();
 }
 

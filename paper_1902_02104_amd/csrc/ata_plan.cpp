@@ -347,6 +347,27 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             t.tiles_n = (int32_t)((Np + kGemmTile - 1) / kGemmTile);
             P.mults += Mp * Np * kfull;
             P.str_mults += Mp * Np * kfull;
+            if (o.opsums) {
+                // t only describes the sums; the launched task is classical on them
+                const int32_t dsc = (int32_t)P.tasks.size();
+                P.tasks.push_back(t);
+                check32(kfull);
+                check32(Mp + Np);
+                DevOpSum os{dsc, (int32_t)kfull, (int32_t)Mp, (int32_t)Np, P.opsum_elems, ph(gphase).opsum_rows};
+                P.opsum_elems += kfull * (Mp + Np);
+                ph(gphase).opsum_rows += kfull;
+                ph(gphase).opsums.push_back(os);
+                DevTask g = t;
+                g.nx = g.ny = 1;
+                g.term_off = push_terms({XTerm{1, 0, Mp, {}, {}}}, {XTerm{1, Mp, Mp + Np, {}, {}}});
+                g.seg_off = (int32_t)P.segs.size();
+                g.nseg = 1;
+                for (int32_t v : {(int32_t)kfull, 0, (int32_t)kfull, 0, (int32_t)kfull, 0, (int32_t)kfull})
+                    P.segs.push_back(v);
+                g.src = 1;
+                g.src_off = os.out_off;
+                t = g;
+            }
             const int32_t id = (int32_t)P.tasks.size();
             P.tasks.push_back(t);
             for (int32_t a = 0; a < t.tiles_m; ++a)

@@ -50,8 +50,23 @@ struct DevTask {
     int32_t dM, dN;    // valid destination extent (crop)
     int32_t r0, q0;    // packed-C origin: rows of D -> C rows r0.., cols q0..
     int32_t tiles_m, tiles_n;
-    int32_t pad;
+    int32_t src;       // 0: operands are columns of A; 1: of an operand-sum buffer
     int64_t ws_off;    // element offset into the workspace
+    int64_t src_off;   // src 1: element offset of the task's buffer (K rows of
+                       // M + N: X columns, then Y columns)
+};
+
+// Operand sums of one product (operand-sum form): rows [0, K) of a buffer of
+// row length M + N at out_off hold the product's signed sums of X terms
+// (first M columns) and of Y terms (last N), zero where every term is
+// padding.  `task` describes the terms and their per-chunk rows (a TK_GEMM
+// task with nx, ny terms that is never launched); row_off is the record's
+// first row in its launch.
+struct DevOpSum {
+    int32_t task;
+    int32_t K, M, N;
+    int64_t out_off;
+    int64_t row_off;
 };
 
 // Combination of workspace products into an off-diagonal block of C.
@@ -106,6 +121,9 @@ struct PlanOptions {
     // combination.  Products deeper than kMaxExpandDepth levels (one for
     // Winograd) always use the in-tile form.
     bool intile = true;
+    // With product tiles: form each product's operand sums in a memory pass
+    // (DevOpSum) and run the products as classical tiles on those buffers.
+    bool opsums = false;
 };
 
 constexpr int kMaxExpandDepth = 2;
@@ -116,7 +134,9 @@ struct Phase {
     // tiles with operand terms); gemm, syrk: classical tiles of the base case
     std::vector<WorkItem> str_items, tg_items, gemm_items, syrk_items;
     std::vector<DevCombine> combines;
+    std::vector<DevOpSum> opsums;  // run before the product tiles
     int64_t combine_elems = 0;
+    int64_t opsum_rows = 0;
     int str_tmax = 0;  // most operand terms of any TK_STR task in this phase
     int tg_tmax = 0;   // most operand terms of any product tile task
 };
@@ -129,6 +149,7 @@ struct Plan {
     std::vector<int32_t> segs;
     std::vector<Phase> phases;
     int64_t ws_elems = 0;
+    int64_t opsum_elems = 0;  // operand-sum buffers, in elements of A's type
     // statistics
     int64_t mults = 0;
     int64_t str_mults = 0, gemm_mults = 0, syrk_mults = 0, combine_elems = 0;

@@ -491,7 +491,7 @@ int ata_server_submit(ata_server* srv, const ata_request* req, uint64_t* ticket)
     if (req->m > 0) {
         rc = get_plan(req->m, req->n, q->cutoff, q->variant, q->depth, 0, false, hp);
         if (rc != ATA_OK) return rc;
-        q->L = ws_layout(req->m, req->n, req->dtype, hp->plan.ws_elems, false);
+        q->L = ws_layout(req->m, req->n, req->dtype, hp->plan.ws_elems, false, hp->plan.opsum_elems);
         q->plan = hp;
     }
     const size_t eb = elem_bytes(req->dtype);

@@ -353,3 +353,37 @@ def test_equilibrated_integer_bit_exact(env, orc, dtype_name, intile):
         C = P.gram(At, dtype=dt, cutoff=48, max_depth=d, intile=intile, equilibrate=True)
         torch.cuda.synchronize()
         assert np.array_equal(C.cpu().numpy(), ref), (dtype_name, intile, d)
+
+
+@pytest.mark.parametrize("var,depth", [("strassen", 1), ("strassen", 2), ("winograd", 1)])
+def test_operand_sums_integer(env, orc, var, depth):
+    """Operand-sum form: the products' operand sums are formed in a memory
+    pass and the products run as classical tiles on them; exact on integers,
+    also with a row stride, split K and equilibration."""
+    torch, P = env
+    A = synthetic.integer(517, 301, 21)
+    ref = orc.classical(A)
+    _say("case: operand sums", var, depth)
+    C = _run(env, A, cutoff=40, variant=var, max_depth=depth, operand_sums=True)
+    assert np.array_equal(C, ref)
+    buf = synthetic.with_lda(A, 307, fill=1e300)
+    At = torch.from_numpy(buf).cuda()[:, :301]
+    Cg = P.gram(At, cutoff=40, variant=var, max_depth=depth, operand_sums=True, equilibrate=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(Cg.cpu().numpy(), ref)
+    A2 = synthetic.integer(24000, 300, 77)
+    assert P.plan_info(24000, 300, 64, max_depth=depth, variant=var, operand_sums=True)["combine_tasks"] >= 1
+    C2 = _run(env, A2, cutoff=64, variant=var, max_depth=depth, operand_sums=True)
+    assert np.array_equal(C2, orc.classical(A2))
+
+
+def test_operand_sums_uniform_fp32(env, orc):
+    torch, P = env
+    A = synthetic.uniform(900, 700, 55)
+    ref = orc.classical(A)
+    C = _run(env, A, cutoff=64, max_depth=2, operand_sums=True)
+    assert orc.rel_fro(C, ref, 700) <= FP64_TOL
+    A32 = A.astype(np.float32)
+    C32 = P.gram(torch.from_numpy(A32).cuda(), dtype=P.F32 | P.OUT_F64, cutoff=64, max_depth=1, operand_sums=True)
+    torch.cuda.synchronize()
+    assert orc.rel_fro(C32.cpu().numpy(), orc.classical(A32.astype(np.float64)), 700) <= 2e-5

@@ -54,8 +54,8 @@ def test_plan_multiplications_match_oracle_recursion(lib, orc, m, n, c, d):
     """The device plan forms exactly the scalar products of Algorithm 1 with
     HASA (same count as the oracle's literal recursion with the same cutoff
     and Strassen depth cap)."""
-    for intile in (False, True):
-        st = P.plan_info(m, n, c, max_depth=d, intile=intile)
+    for intile, opsums in ((False, False), (True, False), (False, True)):
+        st = P.plan_info(m, n, c, max_depth=d, intile=intile, operand_sums=opsums)
         assert st["mults"] == orc.ata_mult_count(m, n, c, d)
         assert st["classical_mults"] == m * n * (n + 1) // 2
 
