@@ -189,7 +189,10 @@ int ata_last_hip_error(void);
 /* Library version as "major.minor.patch" (static storage). */
 const char *ata_version(void);
 
-/* Release cached plans and device task tables (all devices). */
+/* Release cached plans, device task tables and the library's helper
+ * streams (all devices).  Waits for every device holding such tables to go
+ * idle first, since queued products read them.  Products of the serving
+ * loop keep their own references and are not affected. */
 void ata_release_caches(void);
 
 /*

@@ -186,6 +186,12 @@ def profile_collect() -> dict:
     return {name: (ms[i], int(cnt[i])) for i, name in enumerate(KERNEL_KINDS)}
 
 
+def release_caches() -> None:
+    """Free cached plans, their device tables and helper streams (waits for
+    the devices that hold them to go idle)."""
+    load().ata_release_caches()
+
+
 def default_cutoff(m: int, n: int, dtype: int = F64) -> int:
     return int(load().ata_default_cutoff(int(m), int(n), int(dtype)))
 

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
@@ -270,9 +271,15 @@ int fork_get(int dev, ForkCtx& c) {
             return ATA_OK;
         }
     }
-    HIP_TRY(hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&c.join, hipEventDisableTiming));
+    hipError_t e = hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.join, hipEventDisableTiming);
+    if (e != hipSuccess) {  // release what was made
+        if (c.fork) (void)hipEventDestroy(c.fork);
+        if (c.s2) (void)hipStreamDestroy(c.s2);
+        c = ForkCtx{};
+        return hip_fail(e);
+    }
     return ATA_OK;
 }
 
@@ -625,7 +632,31 @@ int ata_profile_collect(double* ms, int64_t* launches, int kinds) {
 }
 
 void ata_release_caches(void) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
     std::lock_guard<std::mutex> lk(g_mu);
+    std::set<int> devs;
+    for (const auto& kv : g_plans)
+        if (kv.second->device >= 0) devs.insert(kv.second->device);
+    {
+        std::lock_guard<std::mutex> fk(g_fork_mu);
+        for (auto& kv : g_fork_pool) {
+            devs.insert(kv.first);
+            (void)hipSetDevice(kv.first);
+            (void)hipDeviceSynchronize();
+            for (ForkCtx& c : kv.second) {
+                (void)hipEventDestroy(c.fork);
+                (void)hipEventDestroy(c.join);
+                (void)hipStreamDestroy(c.s2);
+            }
+        }
+        g_fork_pool.clear();
+    }
+    for (int d : devs) {
+        (void)hipSetDevice(d);
+        (void)hipDeviceSynchronize();
+    }
+    (void)hipSetDevice(cur);
     g_plans.clear();
 }
 

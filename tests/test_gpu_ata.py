@@ -147,6 +147,19 @@ def test_hadamard(env, orc):
     assert np.array_equal(C, orc.pack(256.0 * np.eye(192)))
 
 
+def test_release_caches_between_products(env, orc):
+    """Products queued before ata_release_caches finish on the tables they
+    read; later products rebuild the plans and give identical results."""
+    torch, P = env
+    _say("case: release caches")
+    A = torch.from_numpy(synthetic.uniform(1500, 1200, 8)).cuda()
+    C1 = P.gram(A, cutoff=100, max_depth=2)
+    P.release_caches()
+    C2 = P.gram(A, cutoff=100, max_depth=2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+
+
 def test_deterministic(env):
     torch, P = env
     _say("case: determinism")

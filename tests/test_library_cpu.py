@@ -166,3 +166,10 @@ def test_equilibration_workspace_and_options(lib):
     o.flags = 0x100  # unknown flag
     st = P.PlanStats()
     assert lib.ata_plan_info(m, n, P.F64, 64, ctypes.byref(o), ctypes.byref(st)) != 0
+
+
+def test_release_caches_without_device(lib):
+    """Host-only plans (plan_info) are dropped and rebuilt identically."""
+    before = P.plan_info(777, 333, 40, max_depth=2)
+    P.release_caches()
+    assert P.plan_info(777, 333, 40, max_depth=2) == before
