@@ -378,15 +378,30 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
         if (lp) {
             const float* scale = (const float*)(ws + L.scale);
             const void* t1 = lp_mode == 0 ? (const void*)(ws + L.t1) : nullptr;
-            if (ph.n_gemm) {
+            // diagonal tiles overlap the off-diagonal ones on a forked stream
+            const bool split = ph.n_gemm > 0 && ph.n_syrk > 0;
+            ForkCtx fc;
+            if (split) {
+                rc = fork_get(dev, fc);
+                if (rc != ATA_OK) return hipErrorOutOfMemory;
+                err = hipEventRecord(fc.fork, s);
+                if (err == hipSuccess) err = hipStreamWaitEvent(fc.s2, fc.fork, 0);
+            }
+            if (err == hipSuccess && ph.n_gemm) {
                 ProfScope ps(ATA_KERNEL_GEMM, s);
                 err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
                                      (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower, W, s);
             }
+            hipStream_t s_small = split ? fc.s2 : s;
             if (err == hipSuccess && ph.n_syrk) {
-                ProfScope ps(ATA_KERNEL_SYRK, s);
+                ProfScope ps(ATA_KERNEL_SYRK, s_small);
                 err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
-                                     (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, W, s);
+                                     (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, W, s_small);
+            }
+            if (split) {
+                if (err == hipSuccess) err = hipEventRecord(fc.join, fc.s2);
+                if (err == hipSuccess) err = hipStreamWaitEvent(s, fc.join, 0);
+                fork_put(dev, fc);
             }
             if (err == hipSuccess && ph.n_cb) {  // sums of split K parts
                 ProfScope ps(ATA_KERNEL_COMBINE, s);

@@ -1019,26 +1019,31 @@ __global__ void __launch_bounds__(256) k_prep_lp(const float* __restrict__ A, in
 // Reduced-precision classical tiles (TK_SYRK / TK_GEMM) on the transposed
 // copy: 128 x 128 output tile, four waves of 64 x 64 (4 x 4 blocks of
 // 16 x 16), FP32 MFMA accumulation added into FP64 every KFLUSH rows.
-//   MODE 0: bfloat16 split, hi^t hi + hi^t lo + lo^t hi per block; 64 k per stage
-//   MODE 1: e4m3, 128 k per stage; result de-scaled by 1 / (s_i s_j)
+//   MODE 0: bfloat16 split, hi^t hi + hi^t lo + lo^t hi per block; 128 k per stage
+//   MODE 1: e4m3, 512 k per stage; result de-scaled by 1 / (s_i s_j)
 // Rows of the copy are columns of A; the k range of a segment is its row range.
 // ---------------------------------------------------------------------------
+// One workgroup per CU (the FP64 flush accumulators need more than half
+// the registers), so each stage carries a long k range: more MFMA work per
+// barrier and per load round trip (KFLUSH must be a multiple of KT).
 template <int MODE>
 struct LpCfg;
 template <>
 struct LpCfg<0> {
-    static constexpr int KT = 64;              // k per LDS stage (elements)
+    static constexpr int KT = 128;             // k per LDS stage (elements)
     static constexpr int EB = 2;               // bytes per element
     static constexpr int PLANES = 2;           // hi, lo
     static constexpr int ROWB = KT * EB + 16;  // LDS row stride in bytes (padded)
 };
 template <>
 struct LpCfg<1> {
-    static constexpr int KT = 128;
+    static constexpr int KT = 512;
     static constexpr int EB = 1;
     static constexpr int PLANES = 1;
     static constexpr int ROWB = KT * EB + 16;
 };
+
+static_assert(KFLUSH % LpCfg<0>::KT == 0 && KFLUSH % LpCfg<1>::KT == 0, "flush on stage boundaries");
 
 template <int MODE, typename OUT>
 __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0, const uint8_t* __restrict__ T1,
@@ -1182,21 +1187,24 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
                 }
             }
         } else {
-            const int kb = kq * 32;
-            i8_t bq[4];
 #pragma unroll
-            for (int cf = 0; cf < 4; ++cf) {
-                const int rr = wn * 64 + cf * 16 + rsel;
-                bq[cf] = *(const i8_t*)(&Ys[0][rr * ROWB + kb]);
-            }
+            for (int ks = 0; ks < KT / 128; ++ks) {
+                const int kb = ks * 128 + kq * 32;
+                i8_t bq[4];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                const int rr = wm * 64 + rb * 16 + rsel;
-                const i8_t aq = *(const i8_t*)(&Xs[0][rr * ROWB + kb]);
+                for (int cf = 0; cf < 4; ++cf) {
+                    const int rr = wn * 64 + cf * 16 + rsel;
+                    bq[cf] = *(const i8_t*)(&Ys[0][rr * ROWB + kb]);
+                }
 #pragma unroll
-                for (int cf = 0; cf < 4; ++cf)
-                    acc[rb][cf] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aq, bq[cf], acc[rb][cf], 0, 0, 0,
-                                                                                  0, 0, 0);
+                for (int rb = 0; rb < 4; ++rb) {
+                    const int rr = wm * 64 + rb * 16 + rsel;
+                    const i8_t aq = *(const i8_t*)(&Xs[0][rr * ROWB + kb]);
+#pragma unroll
+                    for (int cf = 0; cf < 4; ++cf)
+                        acc[rb][cf] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aq, bq[cf], acc[rb][cf], 0, 0,
+                                                                                      0, 0, 0, 0);
+                }
             }
         }
         if (((it + 1) * KT) % KFLUSH == 0 || it + 1 == ntiles) {
