@@ -1018,14 +1018,19 @@ __global__ void __launch_bounds__(256) k_prep_lp(const float* __restrict__ A, in
 // ---------------------------------------------------------------------------
 // Reduced-precision classical tiles (TK_SYRK / TK_GEMM) on the transposed
 // copy: 128 x 128 output tile, four waves of 64 x 64 (4 x 4 blocks of
-// 16 x 16), FP32 MFMA accumulation added into FP64 every KFLUSH rows.
-//   MODE 0: bfloat16 split, hi^t hi + hi^t lo + lo^t hi per block; 128 k per stage
-//   MODE 1: e4m3, 512 k per stage; result de-scaled by 1 / (s_i s_j)
+// 16 x 16), FP32 MFMA accumulation.
+//   MODE 0: bfloat16 split, hi^t hi + hi^t lo + lo^t hi per block; 128 k per
+//           stage; the FP32 accumulators are added into FP64 every KFLUSH
+//           rows (the split's accuracy is near FP32's)
+//   MODE 1: e4m3, 256 k per stage; FP32 accumulation over the whole K (the
+//           e4m3 rounding, about 1e-2, dwarfs it), which leaves room for two
+//           workgroups per CU; result de-scaled by 1 / (s_i s_j)
 // Rows of the copy are columns of A; the k range of a segment is its row range.
 // ---------------------------------------------------------------------------
-// One workgroup per CU (the FP64 flush accumulators need more than half
-// the registers), so each stage carries a long k range: more MFMA work per
-// barrier and per load round trip (KFLUSH must be a multiple of KT).
+// Stage lengths: bfloat16 runs one workgroup per CU (its FP64 flush
+// accumulators need more than half the registers), so a stage carries a
+// long k range: more MFMA work per barrier and per load round trip (KFLUSH
+// must be a multiple of KT); e4m3 runs two per CU with half the LDS each.
 template <int MODE>
 struct LpCfg;
 template <>
@@ -1037,7 +1042,7 @@ struct LpCfg<0> {
 };
 template <>
 struct LpCfg<1> {
-    static constexpr int KT = 512;
+    static constexpr int KT = 256;
     static constexpr int EB = 1;
     static constexpr int PLANES = 1;
     static constexpr int ROWB = KT * EB + 16;
@@ -1046,7 +1051,7 @@ struct LpCfg<1> {
 static_assert(KFLUSH % LpCfg<0>::KT == 0 && KFLUSH % LpCfg<1>::KT == 0, "flush on stage boundaries");
 
 template <int MODE, typename OUT>
-__global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0, const uint8_t* __restrict__ T1,
+__global__ void __launch_bounds__(256, MODE == 1 ? 2 : 1) k_gemm_lp(const uint8_t* __restrict__ T0, const uint8_t* __restrict__ T1,
                                                     int ldt, const float* __restrict__ scale,
                                                     const DevTask* __restrict__ tasks,
                                                     const DevTerm* __restrict__ terms,
@@ -1070,15 +1075,17 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
     const int i0 = w.ti * GT, j0 = w.tj * GT;
     const int stride = kSegHdr + 2 * (t.nx + t.ny);
 
+    constexpr bool FL = MODE == 0;  // FP64 flush accumulators
     f4_t acc[4][4];
-    double acc64[4][4][4];
+    double acc64[FL ? 4 : 1][FL ? 4 : 1][FL ? 4 : 1];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+            if (FL)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc64[a][b][e] = 0.0;
+                for (int e = 0; e < 4; ++e) acc64[FL ? a : 0][FL ? b : 0][FL ? e : 0] = 0.0;
         }
 
     int ntiles = 0;
@@ -1207,13 +1214,13 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
                 }
             }
         }
-        if (((it + 1) * KT) % KFLUSH == 0 || it + 1 == ntiles) {
+        if (FL && (((it + 1) * KT) % KFLUSH == 0 || it + 1 == ntiles)) {
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) acc64[a][b][e] += (double)acc[a][b][e];
+                    for (int e = 0; e < 4; ++e) acc64[FL ? a : 0][FL ? b : 0][FL ? e : 0] += (double)acc[a][b][e];
                     acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
                 }
         }
@@ -1232,7 +1239,7 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const uint8_t* __restrict__ T0,
             for (int cf = 0; cf < 4; ++cf) {
                 const int gj = j0 + wn * 64 + cf * 16 + (lane & 15);
                 if (gj >= t.dN || (syrk && gj > gi)) continue;
-                double v = acc64[rb][cf][e];
+                double v = FL ? acc64[FL ? rb : 0][FL ? cf : 0][FL ? e : 0] : (double)acc[rb][cf][e];
                 if (MODE == 1) v = v * si / (double)scale[ty.col + gj];  // exact power-of-two de-scale
                 if (t.dst == 0)
                     store_out(C + rowbase + gj, t.beta, v);
