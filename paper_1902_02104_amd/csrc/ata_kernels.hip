@@ -343,6 +343,181 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
 }
 
 // ---------------------------------------------------------------------------
+// FP64 classical tile kernel with direct-to-LDS staging: the one-term tasks
+// and 128 x 128 tiles of k_gemm (TK_SYRK / TK_GEMM leaves and operand-sum
+// products, not batched), two workgroups of four 64 x 64 waves per CU.
+// Operand rows are copied from global memory straight into LDS by buffer
+// loads that write LDS (one dword per lane; rows outside the slab read as
+// zero, columns past an operand's end feed only outputs that are never
+// stored).  The copies of stage s + 1 are spread over the MFMA steps of
+// stage s, so no registers hold staged data and the loop never waits on
+// global memory except at the stage barrier.  Plane columns are
+// XOR-swizzled by k row (left operand in 32-byte, right operand in 128-byte
+// units) so that the four k rows an MFMA step reads fall in different banks.
+// ---------------------------------------------------------------------------
+constexpr int GKD = 16;  // k rows per stage
+
+__global__ void __launch_bounds__(256, 2) k_gemmd(const double* __restrict__ A_, int64_t lda_,
+                                                 const DevTask* __restrict__ tasks,
+                                                 const int32_t* __restrict__ segs,
+                                                 const WorkItem* __restrict__ items, double* __restrict__ C,
+                                                 double* __restrict__ W, const DevTerm* __restrict__ terms,
+                                                 const double* __restrict__ Aops) {
+    typedef Eng<double> E;
+    static_assert(GKD % 8 == 0 && GKD <= kStageRows, "stage rows");
+    constexpr int BR = 64 / E::RM, BC = 64 / E::RN;
+    constexpr int PLANE = GKD * GT;  // doubles per operand plane (k rows x 128 columns)
+    constexpr int NP = GKD / 4;      // MFMA steps per stage = copy parts per stage
+    __shared__ __attribute__((aligned(16))) double lds[2][2][PLANE];  // [buffer][operand]
+
+    const WorkItem w = items[blockIdx.x];
+    const DevTask t = tasks[w.task];
+    const double* __restrict__ A = A_;
+    int64_t lda = lda_;
+    if (t.src == 1) {  // operands from the task's operand-sum buffer
+        A = Aops + t.src_off;
+        lda = (int64_t)t.M + t.N;
+    }
+    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    const int i0 = w.ti * GT, j0 = w.tj * GT;
+    const int64_t row_bytes = lda * (int64_t)sizeof(double);
+
+    // Copy role: operand cs (0: left X, 1: right Y), k rows of parity cpar.
+    // Byte offset of this lane's dword per row residue (mod 4, the two of
+    // this parity) and per copy (four 256-byte copies per 128-column row).
+    const int cs = wave >> 1, cpar = wave & 1;
+    uint32_t doff[2][4];
+    {
+        const DevTerm tm = terms[t.term_off + (cs == 0 ? 0 : t.nx)];
+        const int colbase = tm.col + (cs == 0 ? i0 : j0);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r4 = cpar + 2 * q;
+            const int sw = cs == 0 ? r4 << 2 : r4 << 4;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int s = h * 64 + lane;  // dword within the 1 KB row
+                const int c = (s >> 1) ^ sw;  // column that dword belongs to
+                doff[q][h] = (uint32_t)(colbase + c) * 8u + 4u * (uint32_t)(s & 1);
+            }
+        }
+    }
+
+    typename E::accv_t acc[BR][BC];
+#pragma unroll
+    for (int a = 0; a < BR; ++a)
+#pragma unroll
+        for (int b = 0; b < BC; ++b) E::zero(acc[a][b]);
+
+    // k cursor over the segments: rows row_u + k for k in [kbeg, kend)
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
+    int seg = 0;
+    int k0 = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
+    int kend = t.nseg > 0 ? segs[t.seg_off + 2] : 0;
+    int ntiles = 0;
+    for (int s = 0; s < t.nseg; ++s)
+        ntiles += (segs[t.seg_off + s * stride + 2] - segs[t.seg_off + s * stride + 1] + GKD - 1) / GKD;
+
+    // Slab of this wave's operand for the stage at k0: rows below both the
+    // window end and the operand's row end; the rest read as zero.  Past the
+    // last stage (live false) the slab is empty and the copies write zeros
+    // into the spare buffer.
+    rsrc_t rs;
+    auto slab = [&](bool live) {
+        const int32_t* sg = segs + t.seg_off + (live ? seg : 0) * stride;
+        const int h = cs == 0 ? 0 : 2 * t.nx;
+        const int base = (live ? sg[kSegHdr + h] : 0) + k0;
+        const int rvend = live ? sg[kSegHdr + 1 + h] : 0;
+        int nv = rvend - base < kend - k0 ? rvend - base : kend - k0;
+        nv = nv < GKD ? nv : GKD;
+        if (!live) nv = 0;
+        rs = slab_rsrc(A + (int64_t)base * lda, nv, row_bytes);
+    };
+    // Copy part j of the stage into buffer `buf`: this wave's k rows
+    // 2(2j) + cpar and 2(2j + 1) + cpar.  (The operand always has a term;
+    // the test also keeps the copies in a block of their own, which bounds
+    // how far the scheduler moves the next step's reads.)
+    const int cnt = cs == 0 ? t.nx : t.ny;
+    auto copy_part = [&](int buf, int j) {
+        if (cnt <= 0) return;
+        double* pl = lds[buf][cs];
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
+            const int r = 2 * (2 * j + ii) + cpar;
+            const int q = (r >> 1) & 1;  // (r & 3) == cpar + 2 q
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs, (__attribute__((address_space(3))) void*)(pl + r * GT + h * 32), 4,
+                    (uint32_t)(r * row_bytes) + doff[q][h], 0, 0, 0);
+        }
+    };
+    auto advance = [&]() {
+        k0 += GKD;
+        if (k0 >= kend) {
+            ++seg;
+            if (seg < t.nseg) {
+                k0 = segs[t.seg_off + seg * stride + 1];
+                kend = segs[t.seg_off + seg * stride + 2];
+            }
+        }
+    };
+
+    if (ntiles > 0) {
+        slab(true);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) copy_part(0, j);
+    }
+    for (int it = 0; it < ntiles; ++it) {
+        const int buf = it & 1;
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of stage it have landed
+        __syncthreads();                // every copy of stage it landed; stage it-1 fully read
+        const bool next = it + 1 < ntiles;
+        if (next) advance();
+        slab(next);
+        const double* xp = lds[buf][0];
+        const double* yp = lds[buf][1];
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int ks = 0; ks < NP; ++ks) {
+            const int kr = (ks * 4 + g) * GT;
+            double av[BR], bv[BC];
+#pragma unroll
+            for (int cf = 0; cf < BC; ++cf) bv[cf] = yp[kr + ((wn * 64 + cf * E::RN + (lane & 15)) ^ (g << 4))];
+#pragma unroll
+            for (int rb = 0; rb < BR; ++rb) av[rb] = xp[kr + ((wm * 64 + rb * E::RM + E::arow(lane)) ^ (g << 2))];
+            copy_part(buf ^ 1, ks);
+#pragma unroll
+            for (int rb = 0; rb < BR; ++rb)
+#pragma unroll
+                for (int cf = 0; cf < BC; ++cf) E::mma(av[rb], bv[cf], acc[rb][cf]);
+        }
+        __builtin_amdgcn_s_setprio(0);
+    }
+
+    // epilogue: rows of D go to C rows r0 + gi, columns to C columns q0 + gj
+    const bool syrk = t.kind == TK_SYRK;
+#pragma unroll
+    for (int rb = 0; rb < BR; ++rb) {
+        const int gi = i0 + wm * 64 + rb * E::RM + E::orow(lane, 0);
+        if (gi >= t.dM) continue;
+        const int64_t rowbase = packed_index((int64_t)t.r0 + gi, t.q0);
+#pragma unroll
+        for (int cf = 0; cf < BC; ++cf) {
+            const int gj = j0 + wn * 64 + cf * E::RN + (lane & 15);
+            if (gj >= t.dN || (syrk && gj > gi)) continue;
+            const double v = E::elem(acc[rb][cf], 0);
+            if (t.dst == 0)
+                store_out(C + rowbase + gj, t.beta, v);
+            else
+                W[t.ws_off + (int64_t)gi * t.N + gj] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // In-tile Strassen kernel (TK_STR).  The product P = Xop^t Yop (padded M x N,
 // K per segment) is split once more into quadrants; a workgroup owns the
 // 64 x 64 tile at (ti, tj) of all four result quadrants and keeps the seven
@@ -717,20 +892,38 @@ __global__ void __launch_bounds__(256) k_opsum(const T* __restrict__ A, int64_t 
     const int32_t* sg = segs + t.seg_off + s * stride;
     const int kk = sg[1] + k;
     T* orow = out + rec.out_off + (int64_t)(g - rec.row_off) * (rec.M + rec.N);
-    for (int c = threadIdx.x; c < rec.M + rec.N; c += 256) {
-        const bool xs = c < rec.M;
-        const int cc = xs ? c : c - rec.M;
-        const int nt = xs ? t.nx : t.ny;
-        const int u0 = xs ? 0 : t.nx;
-        T v = T(0);
-        for (int u = 0; u < nt; ++u) {
-            const DevTerm tm = terms[t.term_off + u0 + u];
-            const int row = sg[kSegHdr + 2 * (u0 + u)] + kk;
-            const int col = tm.col + cc;
-            const T a = (row < sg[kSegHdr + 2 * (u0 + u) + 1] && col < tm.cvend) ? A[(int64_t)row * lda + col] : T(0);
-            v = u == 0 ? (T)tm.sign * a : v + (T)tm.sign * a;
+    // Left operand (first M entries of the row), then the right one.  Terms
+    // are the outer loop (uniform over the workgroup) and each thread keeps
+    // the running sums of eight elements, so eight loads are in flight; every
+    // element still adds its terms in term order.
+    constexpr int CH = 8;
+    for (int side = 0; side < 2; ++side) {
+        const int nt = side == 0 ? t.nx : t.ny, u0 = side == 0 ? 0 : t.nx;
+        const int width = side == 0 ? rec.M : rec.N;
+        T* o = orow + (side == 0 ? 0 : rec.M);
+        for (int c0 = 0; c0 < width; c0 += 256 * CH) {
+            T v[CH];
+            for (int u = 0; u < nt; ++u) {
+                const DevTerm tm = terms[t.term_off + u0 + u];
+                const int row = sg[kSegHdr + 2 * (u0 + u)] + kk;
+                const bool rok = row < sg[kSegHdr + 2 * (u0 + u) + 1];
+                const T sgn = (T)tm.sign;
+                const T* src = A + (int64_t)row * lda + tm.col;
+                T a[CH];
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    const int c = c0 + e * 256 + (int)threadIdx.x;
+                    a[e] = (rok && c < width && tm.col + c < tm.cvend) ? src[c] : T(0);
+                }
+#pragma unroll
+                for (int e = 0; e < CH; ++e) v[e] = u == 0 ? sgn * a[e] : v[e] + sgn * a[e];
+            }
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const int c = c0 + e * 256 + (int)threadIdx.x;
+                if (c < width) o[c] = v[e];
+            }
         }
-        orow[c] = v;
     }
 }
 
@@ -1259,8 +1452,8 @@ hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const
     const dim3 g(nitems), b(256);
     const BatchEntry* nb = nullptr;
     if (!f32)
-        hipLaunchKernelGGL((k_gemm<double, double, false, 1>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (double*)C, W, nb, (const double*)Aops);
+        hipLaunchKernelGGL(k_gemmd, g, b, 0, s, (const double*)A, lda, tb.tasks, tb.segs, items, (double*)C, W,
+                           tb.terms, (const double*)Aops);
     else if (out_f64)
         hipLaunchKernelGGL((k_gemm<float, double, false, 1>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
                            tb.segs, items, (double*)C, W, nb, (const float*)Aops);
