@@ -387,8 +387,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] else None
-    roof["kernel"] = {"strassen": {"intile": "k_str_f64", "tiles": "k_gemm_terms_f64", "opsums": "k_gemm_f64"}[form],
-                      "gemm": "k_gemm_f64", "syrk": "k_gemm_f64", "combine": "k_combine_f64"}.get(dom, dom)
+    roof["kernel"] = {"strassen": {"intile": "k_str_f64", "tiles": "k_gemm_terms_f64", "opsums": "k_gemmd_f64"}[form],
+                      "gemm": "k_gemmd_f64", "syrk": "k_gemmd_f64", "combine": "k_combine_f64"}.get(dom, dom)
     roof["traffic"] = _profiled_traffic(roof["kernel"], n, cutoff, depth, form)
     roof["avg_launch_ms"] = avg_ms
 
@@ -442,7 +442,7 @@ def main():
             "workload": "square FP64 A %dx%d, i.i.d. uniform[-1,1] (seed %d), packed lower C = A^tA"
                         % (m, n, synthetic.SEED_SQUARE),
             "m": m, "n": n, "cutoff": cutoff, "tuning_sweep_ms": sweep, "variant": args.variant,
-            "max_strassen_depth": depth, "last_level": {"intile": "in-tile", "tiles": "product tiles",
+            "max_strassen_depth": depth, "form": form, "last_level": {"intile": "in-tile", "tiles": "product tiles",
                                                         "opsums": "product tiles on operand sums"}[form],
             "phases": st["phases"], "ata_depth": st["ata_depth"],
             "mults_over_classical": st["mults"] / st["classical_mults"],
