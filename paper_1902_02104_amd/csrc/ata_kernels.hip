@@ -117,58 +117,35 @@ __device__ __forceinline__ void store_out(OUT* p, int beta, double v) {
 }
 
 // ---------------------------------------------------------------------------
-// Classical tile kernel: TK_SYRK (lower triangle of a diagonal block) and
-// TK_GEMM (dense off-diagonal block).  128 x 128 output tile per workgroup,
-// four waves of 64 x 64, double-buffered LDS, two workgroups per CU.
-//   TMAX == 1: base-case tiles; K staged 16 rows at a time.  Columns past an
-//              operand's end only feed outputs that are never stored, so they
-//              load unmasked.
-//   TMAX > 1:  Strassen product tiles: each operand is a signed sum of up to
-//              TMAX terms (quadrant blocks of A), summed in term order while
-//              staging; a term's columns past its end (padding) stage as
-//              zero.  K staged 8 rows at a time to bound the registers that
-//              hold the terms in flight.
+// Strassen product tiles (ATA_OPT_PRODUCT_TILES): TK_GEMM tasks whose
+// operands are signed sums of up to TMAX terms (quadrant blocks of A),
+// summed in term order while staging through registers; a term's columns
+// past its end (padding) stage as zero.  128 x 128 output tile per
+// workgroup, four waves of 64 x 64, double-buffered LDS, two workgroups per
+// CU, K staged 8 rows at a time to bound the registers that hold the terms
+// in flight.  (One-term tiles run on k_gemmd below.)
 // ---------------------------------------------------------------------------
 constexpr int GT = kGemmTile;  // 128
 
-template <typename T, typename OUT, bool BATCH, int TMAX>
-__global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64_t lda_,
-                                                 const DevTask* __restrict__ tasks_,
-                                                 const DevTerm* __restrict__ terms_,
-                                                 const int32_t* __restrict__ segs_,
-                                                 const WorkItem* __restrict__ items, OUT* __restrict__ C_,
-                                                 double* __restrict__ W, const BatchEntry* __restrict__ batch,
-                                                 const T* __restrict__ Aops) {
+template <typename T, typename OUT, int TMAX>
+__global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A, int64_t lda,
+                                                 const DevTask* __restrict__ tasks,
+                                                 const DevTerm* __restrict__ terms,
+                                                 const int32_t* __restrict__ segs,
+                                                 const WorkItem* __restrict__ items, OUT* __restrict__ C,
+                                                 double* __restrict__ W) {
     typedef Eng<T> E;
+    static_assert(TMAX > 1, "multi-term operands");
     constexpr bool F32 = std::is_same<T, float>::value;
     constexpr int BR = 64 / E::RM, BC = 64 / E::RN;
-    constexpr int GK = TMAX == 1 ? 16 : 8;  // k rows per stage
-    constexpr int EPT = GK * GT / 256;           // elements per thread, term and side
-    constexpr int TPR = GT / EPT;                // threads per staged row
+    constexpr int GK = 8;                 // k rows per stage
+    constexpr int EPT = GK * GT / 256;    // elements per thread, term and side
+    constexpr int TPR = GT / EPT;         // threads per staged row
     __shared__ T Xs[2][GK][GT + E::PAD];
     __shared__ T Ys[2][GK][GT + E::PAD];
 
     const WorkItem w = items[blockIdx.x];
-    const T* __restrict__ A = A_;
-    OUT* __restrict__ C = C_;
-    const DevTask* __restrict__ tasks = tasks_;
-    const DevTerm* __restrict__ terms = terms_;
-    const int32_t* __restrict__ segs = segs_;
-    int64_t lda = lda_;
-    if (BATCH) {
-        const BatchEntry be = batch[w.slot];
-        A = (const T*)be.A;
-        C = (OUT*)be.C;
-        tasks = be.tasks;
-        terms = be.terms;
-        segs = be.segs;
-        lda = be.lda;
-    }
     const DevTask t = tasks[w.task];
-    if (!BATCH && t.src == 1) {  // operands from the task's operand-sum buffer
-        A = Aops + t.src_off;
-        lda = (int64_t)t.M + t.N;
-    }
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int i0 = w.ti * GT, j0 = w.tj * GT;
@@ -195,7 +172,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
             const uint32_t base = (uint32_t)(lk * row_bytes) + (uint32_t)col * ES;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                const uint32_t off = (TMAX == 1 || col + e < tm.cvend) ? base + e * ES : kOOB;
+                const uint32_t off = col + e < tm.cvend ? base + e * ES : kOOB;
                 if (side == 0) xo[u][e] = off;
                 else yo[u][e] = off;
             }
@@ -270,18 +247,12 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
         const int buf = it & 1;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            T x, y;
-            if (TMAX == 1) {
-                x = xr[0][e];
-                y = yr[0][e];
-            } else {
-                x = xsgn[0] * xr[0][e];
-                y = ysgn[0] * yr[0][e];
+            T x = xsgn[0] * xr[0][e];
+            T y = ysgn[0] * yr[0][e];
 #pragma unroll
-                for (int u = 1; u < TMAX; ++u) {
-                    x += xsgn[u] * xr[u][e];
-                    y += ysgn[u] * yr[u][e];
-                }
+            for (int u = 1; u < TMAX; ++u) {
+                x += xsgn[u] * xr[u][e];
+                y += ysgn[u] * yr[u][e];
             }
             Xs[buf][lk][lc + e] = x;
             Ys[buf][lk][lc + e] = y;
@@ -343,38 +314,86 @@ __global__ void __launch_bounds__(256, 2) k_gemm(const T* __restrict__ A_, int64
 }
 
 // ---------------------------------------------------------------------------
-// FP64 classical tile kernel with direct-to-LDS staging: the one-term tasks
-// and 128 x 128 tiles of k_gemm (TK_SYRK / TK_GEMM leaves and operand-sum
-// products, not batched), two workgroups of four 64 x 64 waves per CU.
-// Operand rows are copied from global memory straight into LDS by buffer
-// loads that write LDS (one dword per lane; rows outside the slab read as
-// zero, columns past an operand's end feed only outputs that are never
-// stored).  The copies of stage s + 1 are spread over the MFMA steps of
-// stage s, so no registers hold staged data and the loop never waits on
-// global memory except at the stage barrier.  Plane columns are
-// XOR-swizzled by k row (left operand in 32-byte, right operand in 128-byte
-// units) so that the four k rows an MFMA step reads fall in different banks.
+// Classical tile kernel with direct-to-LDS staging: the one-term tasks and
+// 128 x 128 tiles of k_gemm (TK_SYRK / TK_GEMM leaves and operand-sum
+// products; BATCH: tiles of several requests in one launch), two workgroups
+// of four 64 x 64 waves per CU.  Operand rows are copied from global memory
+// straight into LDS by buffer loads that write LDS (one dword per lane; rows
+// outside the slab read as zero, columns past an operand's end feed only
+// outputs that are never stored).  The copies of stage s + 1 are spread over
+// the MFMA steps of stage s, so no registers hold staged data and the loop
+// never waits on global memory except at the stage barrier.  Plane columns
+// are XOR-swizzled by k row so that the four k rows an MFMA step reads fall
+// in different LDS banks (FP64: left operand in 32-byte, right operand in
+// 128-byte units; FP32: both in 64-byte units).  FP32 accumulates in FP32
+// MFMA and adds into FP64 every KFLUSH rows, as k_gemm does.
 // ---------------------------------------------------------------------------
-constexpr int GKD = 16;  // k rows per stage
+// Copy of a table record addressed through a global-memory pointer, read as
+// 32-bit words (the records are multiples of four bytes).
+template <typename S>
+__device__ __forceinline__ S load_rec(const __attribute__((address_space(1))) S* p) {
+    static_assert(sizeof(S) % 4 == 0, "record size");
+    S v;
+    const __attribute__((address_space(1))) int32_t* q = (const __attribute__((address_space(1))) int32_t*)p;
+    int32_t* d = reinterpret_cast<int32_t*>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(S) / 4); ++i) d[i] = q[i];
+    return v;
+}
 
-__global__ void __launch_bounds__(256, 2) k_gemmd(const double* __restrict__ A_, int64_t lda_,
-                                                 const DevTask* __restrict__ tasks,
-                                                 const int32_t* __restrict__ segs,
-                                                 const WorkItem* __restrict__ items, double* __restrict__ C,
-                                                 double* __restrict__ W, const DevTerm* __restrict__ terms,
-                                                 const double* __restrict__ Aops) {
-    typedef Eng<double> E;
-    static_assert(GKD % 8 == 0 && GKD <= kStageRows, "stage rows");
+template <typename T>
+struct DmaCfg;
+template <>
+struct DmaCfg<double> {
+    static constexpr int GK = 16;  // k rows per stage (64 KB of LDS, two workgroups per CU)
+};
+template <>
+struct DmaCfg<float> {
+    static constexpr int GK = 16;
+};
+
+template <typename T, typename OUT, bool BATCH>
+__global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int64_t lda_,
+                                                 const DevTask* __restrict__ tasks_,
+                                                 const int32_t* __restrict__ segs_,
+                                                 const WorkItem* __restrict__ items, OUT* __restrict__ C_,
+                                                 double* __restrict__ W, const DevTerm* __restrict__ terms_,
+                                                 const T* __restrict__ Aops, const BatchEntry* __restrict__ batch) {
+    typedef Eng<T> E;
+    constexpr bool F32 = std::is_same<T, float>::value;
+    constexpr int GK = DmaCfg<T>::GK;
+    static_assert(GK % 8 == 0 && GK <= 2 * kStageRows, "stage rows");
     constexpr int BR = 64 / E::RM, BC = 64 / E::RN;
-    constexpr int PLANE = GKD * GT;  // doubles per operand plane (k rows x 128 columns)
-    constexpr int NP = GKD / 4;      // MFMA steps per stage = copy parts per stage
-    __shared__ __attribute__((aligned(16))) double lds[2][2][PLANE];  // [buffer][operand]
+    constexpr int PLANE = GK * GT;                 // elements per operand plane (k rows x 128 columns)
+    constexpr int NP = GK / 4;                     // MFMA steps per stage = copy parts per stage
+    constexpr int CPR = GT * (int)sizeof(T) / 256;  // 256-byte copies per plane row
+    constexpr int NSL = (GK + kStageRows - 1) / kStageRows;  // slabs of at most kStageRows rows
+    __shared__ __attribute__((aligned(16))) T lds[2][2][PLANE];  // [buffer][operand]
 
+    // Table pointers typed as global memory: loads through a generic
+    // pointer count as divergent (it could address per-lane memory), which
+    // would put every resource built from the loaded values in a loop.
+    typedef const __attribute__((address_space(1))) DevTask* TaskP;
+    typedef const __attribute__((address_space(1))) DevTerm* TermP;
+    typedef const __attribute__((address_space(1))) int32_t* SegP;
     const WorkItem w = items[blockIdx.x];
-    const DevTask t = tasks[w.task];
-    const double* __restrict__ A = A_;
+    const T* __restrict__ A = A_;
+    OUT* __restrict__ C = C_;
+    TaskP tasks = (TaskP)tasks_;
+    TermP terms = (TermP)terms_;
+    SegP segs = (SegP)segs_;
     int64_t lda = lda_;
-    if (t.src == 1) {  // operands from the task's operand-sum buffer
+    if (BATCH) {
+        const BatchEntry be = batch[w.slot];
+        A = (const T*)be.A;
+        C = (OUT*)be.C;
+        tasks = (TaskP)be.tasks;
+        terms = (TermP)be.terms;
+        segs = (SegP)be.segs;
+        lda = be.lda;
+    }
+    const DevTask t = load_rec(tasks + w.task);
+    if (!BATCH && t.src == 1) {  // operands from the task's operand-sum buffer
         A = Aops + t.src_off;
         lda = (int64_t)t.M + t.N;
     }
@@ -382,34 +401,41 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const double* __restrict__ A_,
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
     const int i0 = w.ti * GT, j0 = w.tj * GT;
-    const int64_t row_bytes = lda * (int64_t)sizeof(double);
+    const int64_t row_bytes = lda * (int64_t)sizeof(T);
 
     // Copy role: operand cs (0: left X, 1: right Y), k rows of parity cpar.
     // Byte offset of this lane's dword per row residue (mod 4, the two of
-    // this parity) and per copy (four 256-byte copies per 128-column row).
+    // this parity) and per 256-byte copy of the row.
     const int cs = wave >> 1, cpar = wave & 1;
-    uint32_t doff[2][4];
+    const int swx = F32 ? 4 : 2, swy = 4;  // swizzle unit: 1 << swx (left) / 1 << swy (right) elements
+    uint32_t doff[2][CPR];
     {
-        const DevTerm tm = terms[t.term_off + (cs == 0 ? 0 : t.nx)];
+        const DevTerm tm = load_rec(terms + t.term_off + (cs == 0 ? 0 : t.nx));
         const int colbase = tm.col + (cs == 0 ? i0 : j0);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int r4 = cpar + 2 * q;
-            const int sw = cs == 0 ? r4 << 2 : r4 << 4;
+            const int sw = r4 << (cs == 0 ? swx : swy);
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int s = h * 64 + lane;  // dword within the 1 KB row
-                const int c = (s >> 1) ^ sw;  // column that dword belongs to
-                doff[q][h] = (uint32_t)(colbase + c) * 8u + 4u * (uint32_t)(s & 1);
+            for (int h = 0; h < CPR; ++h) {
+                const int s = h * 64 + lane;            // dword within the row
+                const int c = (F32 ? s : s >> 1) ^ sw;  // column that dword belongs to
+                doff[q][h] = (uint32_t)(colbase + c) * (uint32_t)sizeof(T) + (F32 ? 0u : 4u * (uint32_t)(s & 1));
             }
         }
     }
 
     typename E::accv_t acc[BR][BC];
+    double acc64[F32 ? BR : 1][F32 ? BC : 1][F32 ? E::NA : 1];
 #pragma unroll
     for (int a = 0; a < BR; ++a)
 #pragma unroll
-        for (int b = 0; b < BC; ++b) E::zero(acc[a][b]);
+        for (int b = 0; b < BC; ++b) {
+            E::zero(acc[a][b]);
+            if (F32)
+#pragma unroll
+                for (int e = 0; e < E::NA; ++e) acc64[F32 ? a : 0][F32 ? b : 0][F32 ? e : 0] = 0.0;
+        }
 
     // k cursor over the segments: rows row_u + k for k in [kbeg, kend)
     const int stride = kSegHdr + 2 * (t.nx + t.ny);
@@ -418,22 +444,28 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const double* __restrict__ A_,
     int kend = t.nseg > 0 ? segs[t.seg_off + 2] : 0;
     int ntiles = 0;
     for (int s = 0; s < t.nseg; ++s)
-        ntiles += (segs[t.seg_off + s * stride + 2] - segs[t.seg_off + s * stride + 1] + GKD - 1) / GKD;
+        ntiles += (segs[t.seg_off + s * stride + 2] - segs[t.seg_off + s * stride + 1] + GK - 1) / GK;
 
-    // Slab of this wave's operand for the stage at k0: rows below both the
-    // window end and the operand's row end; the rest read as zero.  Past the
-    // last stage (live false) the slab is empty and the copies write zeros
-    // into the spare buffer.
-    rsrc_t rs;
+    // Slabs of this wave's operand for the stage at k0 (kStageRows rows each,
+    // so every in-slab offset stays below kOOB): rows below both the window
+    // end and the operand's row end; the rest read as zero.  Past the last
+    // stage (live false) the slabs are empty and the copies write zeros into
+    // the spare buffer.
+    rsrc_t rs[NSL];
     auto slab = [&](bool live) {
-        const int32_t* sg = segs + t.seg_off + (live ? seg : 0) * stride;
+        const SegP sg = segs + t.seg_off + (live ? seg : 0) * stride;
         const int h = cs == 0 ? 0 : 2 * t.nx;
         const int base = (live ? sg[kSegHdr + h] : 0) + k0;
         const int rvend = live ? sg[kSegHdr + 1 + h] : 0;
         int nv = rvend - base < kend - k0 ? rvend - base : kend - k0;
-        nv = nv < GKD ? nv : GKD;
+        nv = nv < GK ? nv : GK;
         if (!live) nv = 0;
-        rs = slab_rsrc(A + (int64_t)base * lda, nv, row_bytes);
+#pragma unroll
+        for (int b = 0; b < NSL; ++b) {
+            const int ns = nv - b * kStageRows;
+            rs[b] = slab_rsrc(A + (int64_t)(base + b * kStageRows) * lda, ns < kStageRows ? ns : kStageRows,
+                              row_bytes);
+        }
     };
     // Copy part j of the stage into buffer `buf`: this wave's k rows
     // 2(2j) + cpar and 2(2j + 1) + cpar.  (The operand always has a term;
@@ -442,20 +474,20 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const double* __restrict__ A_,
     const int cnt = cs == 0 ? t.nx : t.ny;
     auto copy_part = [&](int buf, int j) {
         if (cnt <= 0) return;
-        double* pl = lds[buf][cs];
+        T* pl = lds[buf][cs];
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii) {
             const int r = 2 * (2 * j + ii) + cpar;
             const int q = (r >> 1) & 1;  // (r & 3) == cpar + 2 q
 #pragma unroll
-            for (int h = 0; h < 4; ++h)
+            for (int h = 0; h < CPR; ++h)
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                    rs, (__attribute__((address_space(3))) void*)(pl + r * GT + h * 32), 4,
-                    (uint32_t)(r * row_bytes) + doff[q][h], 0, 0, 0);
+                    rs[r / kStageRows], (__attribute__((address_space(3))) void*)(pl + r * GT + h * (256 / (int)sizeof(T))),
+                    4, (uint32_t)((r % kStageRows) * row_bytes) + doff[q][h], 0, 0, 0);
         }
     };
     auto advance = [&]() {
-        k0 += GKD;
+        k0 += GK;
         if (k0 >= kend) {
             ++seg;
             if (seg < t.nseg) {
@@ -477,17 +509,19 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const double* __restrict__ A_,
         const bool next = it + 1 < ntiles;
         if (next) advance();
         slab(next);
-        const double* xp = lds[buf][0];
-        const double* yp = lds[buf][1];
+        const T* xp = lds[buf][0];
+        const T* yp = lds[buf][1];
         __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < NP; ++ks) {
             const int kr = (ks * 4 + g) * GT;
-            double av[BR], bv[BC];
+            T av[BR], bv[BC];
 #pragma unroll
-            for (int cf = 0; cf < BC; ++cf) bv[cf] = yp[kr + ((wn * 64 + cf * E::RN + (lane & 15)) ^ (g << 4))];
+            for (int cf = 0; cf < BC; ++cf)
+                bv[cf] = yp[kr + ((wn * 64 + cf * E::RN + (lane & 15)) ^ (g << swy))];
 #pragma unroll
-            for (int rb = 0; rb < BR; ++rb) av[rb] = xp[kr + ((wm * 64 + rb * E::RM + E::arow(lane)) ^ (g << 2))];
+            for (int rb = 0; rb < BR; ++rb)
+                av[rb] = xp[kr + ((wm * 64 + rb * E::RM + E::arow(lane)) ^ (g << swx))];
             copy_part(buf ^ 1, ks);
 #pragma unroll
             for (int rb = 0; rb < BR; ++rb)
@@ -495,24 +529,38 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const double* __restrict__ A_,
                 for (int cf = 0; cf < BC; ++cf) E::mma(av[rb], bv[cf], acc[rb][cf]);
         }
         __builtin_amdgcn_s_setprio(0);
+        if (F32 && (((it + 1) * GK) % KFLUSH == 0 || it + 1 == ntiles)) {
+#pragma unroll
+            for (int a = 0; a < BR; ++a)
+#pragma unroll
+                for (int b = 0; b < BC; ++b) {
+#pragma unroll
+                    for (int e = 0; e < E::NA; ++e)
+                        acc64[F32 ? a : 0][F32 ? b : 0][F32 ? e : 0] += E::elem(acc[a][b], e);
+                    E::zero(acc[a][b]);
+                }
+        }
     }
 
     // epilogue: rows of D go to C rows r0 + gi, columns to C columns q0 + gj
     const bool syrk = t.kind == TK_SYRK;
 #pragma unroll
     for (int rb = 0; rb < BR; ++rb) {
-        const int gi = i0 + wm * 64 + rb * E::RM + E::orow(lane, 0);
-        if (gi >= t.dM) continue;
-        const int64_t rowbase = packed_index((int64_t)t.r0 + gi, t.q0);
 #pragma unroll
-        for (int cf = 0; cf < BC; ++cf) {
-            const int gj = j0 + wn * 64 + cf * E::RN + (lane & 15);
-            if (gj >= t.dN || (syrk && gj > gi)) continue;
-            const double v = E::elem(acc[rb][cf], 0);
-            if (t.dst == 0)
-                store_out(C + rowbase + gj, t.beta, v);
-            else
-                W[t.ws_off + (int64_t)gi * t.N + gj] = v;
+        for (int e = 0; e < E::NA; ++e) {
+            const int gi = i0 + wm * 64 + rb * E::RM + E::orow(lane, e);
+            if (gi >= t.dM) continue;
+            const int64_t rowbase = packed_index((int64_t)t.r0 + gi, t.q0);
+#pragma unroll
+            for (int cf = 0; cf < BC; ++cf) {
+                const int gj = j0 + wn * 64 + cf * E::RN + (lane & 15);
+                if (gj >= t.dN || (syrk && gj > gi)) continue;
+                const double v = F32 ? acc64[F32 ? rb : 0][F32 ? cf : 0][F32 ? e : 0] : E::elem(acc[rb][cf], e);
+                if (t.dst == 0)
+                    store_out(C + rowbase + gj, t.beta, v);
+                else
+                    W[t.ws_off + (int64_t)gi * t.N + gj] = v;
+            }
         }
     }
 }
@@ -1452,14 +1500,14 @@ hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const
     const dim3 g(nitems), b(256);
     const BatchEntry* nb = nullptr;
     if (!f32)
-        hipLaunchKernelGGL(k_gemmd, g, b, 0, s, (const double*)A, lda, tb.tasks, tb.segs, items, (double*)C, W,
-                           tb.terms, (const double*)Aops);
+        hipLaunchKernelGGL((k_gemmd<double, double, false>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.segs,
+                           items, (double*)C, W, tb.terms, (const double*)Aops, nb);
     else if (out_f64)
-        hipLaunchKernelGGL((k_gemm<float, double, false, 1>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (double*)C, W, nb, (const float*)Aops);
+        hipLaunchKernelGGL((k_gemmd<float, double, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.segs,
+                           items, (double*)C, W, tb.terms, (const float*)Aops, nb);
     else
-        hipLaunchKernelGGL((k_gemm<float, float, false, 1>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (float*)C, W, nb, (const float*)Aops);
+        hipLaunchKernelGGL((k_gemmd<float, float, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.segs,
+                           items, (float*)C, W, tb.terms, (const float*)Aops, nb);
     return hipGetLastError();
 }
 
@@ -1467,16 +1515,15 @@ template <int TM>
 static void launch_gemm_terms_t(bool f32, bool out_f64, dim3 g, const void* A, int64_t lda, const DevTables& tb,
                                 const WorkItem* items, void* C, double* W, hipStream_t s) {
     const dim3 b(256);
-    const BatchEntry* nb = nullptr;
     if (!f32)
-        hipLaunchKernelGGL((k_gemm<double, double, false, TM>), g, b, 0, s, (const double*)A, lda, tb.tasks,
-                           tb.terms, tb.segs, items, (double*)C, W, nb, nullptr);
+        hipLaunchKernelGGL((k_gemm<double, double, TM>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.terms,
+                           tb.segs, items, (double*)C, W);
     else if (out_f64)
-        hipLaunchKernelGGL((k_gemm<float, double, false, TM>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (double*)C, W, nb, nullptr);
+        hipLaunchKernelGGL((k_gemm<float, double, TM>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
+                           tb.segs, items, (double*)C, W);
     else
-        hipLaunchKernelGGL((k_gemm<float, float, false, TM>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
-                           tb.segs, items, (float*)C, W, nb, nullptr);
+        hipLaunchKernelGGL((k_gemm<float, float, TM>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.terms,
+                           tb.segs, items, (float*)C, W);
 }
 
 hipError_t launch_gemm_terms(bool f32, bool out_f64, int tmax, const void* A, int64_t lda, const DevTables& tb,
@@ -1497,14 +1544,14 @@ hipError_t launch_gemm_batch(bool f32, bool out_f64, const BatchEntry* batch, co
     if (nitems <= 0) return hipSuccess;
     const dim3 g(nitems), b(256);
     if (!f32)
-        hipLaunchKernelGGL((k_gemm<double, double, true, 1>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
-                           nullptr, nullptr, batch, nullptr);
+        hipLaunchKernelGGL((k_gemmd<double, double, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, items, nullptr,
+                           nullptr, nullptr, nullptr, batch);
     else if (out_f64)
-        hipLaunchKernelGGL((k_gemm<float, double, true, 1>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
-                           nullptr, nullptr, batch, nullptr);
+        hipLaunchKernelGGL((k_gemmd<float, double, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, items, nullptr,
+                           nullptr, nullptr, nullptr, batch);
     else
-        hipLaunchKernelGGL((k_gemm<float, float, true, 1>), g, b, 0, s, nullptr, 0, nullptr, nullptr, nullptr, items,
-                           nullptr, nullptr, batch, nullptr);
+        hipLaunchKernelGGL((k_gemmd<float, float, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, items, nullptr,
+                           nullptr, nullptr, nullptr, batch);
     return hipGetLastError();
 }
 
