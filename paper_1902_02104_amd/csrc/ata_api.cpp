@@ -55,6 +55,23 @@ int check_device(int dev) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// True when every segment window [row + kbeg, row + kend) of the plan's
+// classical tasks starts and ends on a multiple of `q` elements: the
+// transposed converted copy (rows padded to a multiple of 128 elements) can
+// then be staged in whole dwords (q = 2 for bfloat16, 4 for e4m3).
+bool lp_windows_aligned(const Plan& P, int q) {
+    for (const DevTask& t : P.tasks) {
+        if (t.kind != TK_SYRK && t.kind != TK_GEMM) continue;
+        const int stride = kSegHdr + 2 * (t.nx + t.ny);
+        for (int sg = 0; sg < t.nseg; ++sg) {
+            const int32_t* g = P.segs.data() + t.seg_off + (int64_t)sg * stride;
+            const int64_t row = g[kSegHdr];
+            if ((row + g[1]) % q != 0 || (row + g[2]) % q != 0) return false;
+        }
+    }
+    return true;
+}
+
 // Lay out a plan's tables in one host image (offsets recorded in pd).
 void serialize(PlanDev& pd) {
     const Plan& P = pd.plan;
@@ -107,6 +124,7 @@ void serialize(PlanDev& pd) {
         std::memcpy(host.data() + d.off_cb, ph.combines.data(), ph.combines.size() * sizeof(DevCombine));
         std::memcpy(host.data() + d.off_ops, ph.opsums.data(), ph.opsums.size() * sizeof(DevOpSum));
     }
+    for (int mode = 0; mode < 2; ++mode) pd.lp_aligned[mode] = lp_windows_aligned(P, mode == 0 ? 2 : 4);
 }
 
 // Copy a serialized plan into one device allocation.
@@ -390,13 +408,15 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             if (err == hipSuccess && ph.n_gemm) {
                 ProfScope ps(ATA_KERNEL_GEMM, s);
                 err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
-                                     (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower, W, s);
+                                     (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower, W, s,
+                                     pdr.lp_aligned[lp_mode]);
             }
             hipStream_t s_small = split ? fc.s2 : s;
             if (err == hipSuccess && ph.n_syrk) {
                 ProfScope ps(ATA_KERNEL_SYRK, s_small);
                 err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
-                                     (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, W, s_small);
+                                     (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, W, s_small,
+                                     pdr.lp_aligned[lp_mode]);
             }
             if (split) {
                 if (err == hipSuccess) err = hipEventRecord(fc.join, fc.s2);

@@ -26,6 +26,7 @@ struct PlanDev {
     std::vector<char> host_blob;  // the same tables on the host
     size_t off_tasks = 0, off_terms = 0, off_segs = 0;
     std::vector<PhaseDev> phases;
+    bool lp_aligned[2] = {false, false};  // reduced-precision modes: windows dword-aligned in the copy
     ~PlanDev() {
         if (blob) {
             int cur = 0;

@@ -62,9 +62,12 @@ hipError_t launch_colscale(const float* A, int64_t lda, int m, int n, float* par
                            hipStream_t s);
 hipError_t launch_prep_lp(int mode, const float* A, int64_t lda, int m, int n, int ldt, const float* scale,
                           void* out0, void* out1, hipStream_t s);
+// aligned: every segment window of the plan starts and ends on a dword of
+// the copy (see lp_windows_aligned), which lets the tiles stage through
+// direct-to-LDS copies.
 hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1, int ldt,
                           const float* scale, const DevTables& tb, const WorkItem* items, int nitems,
-                          void* C, double* W, hipStream_t s);
+                          void* C, double* W, hipStream_t s, bool aligned);
 
 // Column equilibration (power-of-two column scales into `scale`, the scaled
 // copy of A into `out` with row stride n; `part` holds ceil(m/256) x n

@@ -1492,6 +1492,225 @@ __global__ void __launch_bounds__(256, MODE == 1 ? 2 : 1) k_gemm_lp(const uint8_
 }
 
 // ---------------------------------------------------------------------------
+// Reduced-precision tiles with direct-to-LDS staging: the tasks of k_gemm_lp
+// (classical tiles on the transposed converted copy), with every stage's rows
+// of the copy moved from global memory straight into LDS by buffer loads that
+// write LDS, one dword per lane, two 128-byte tile rows per copy.  The copies
+// of stage s + 1 are issued while stage s is multiplied (double-buffered
+// LDS), so the loop waits on global memory only at the stage barrier.  Wave w
+// copies operand w / 2, tile rows [64 (w % 2), 64 (w % 2) + 64).  The copies
+// need every segment window of the plan to start and end on a dword of the
+// copy (checked on the host; otherwise k_gemm_lp runs).  The 16-byte chunks
+// of tile row r are XOR-swizzled by (r / 2) mod 8, which puts the sixteen
+// rows an MFMA operand read touches in sixteen different bank groups.
+// Copies past the window end or the operand's last row get an out-of-range
+// offset and write zeros.
+// ---------------------------------------------------------------------------
+template <int MODE>
+struct LpdCfg;
+template <>
+struct LpdCfg<0> {  // bfloat16 hi and lo planes; FP64 flush needs the whole register file
+    static constexpr int KT = 64, EB = 2, PL = 2, OCC = 1;
+};
+template <>
+struct LpdCfg<1> {  // e4m3
+    static constexpr int KT = 128, EB = 1, PL = 1, OCC = 2;
+};
+
+template <int MODE, typename OUT>
+__global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8_t* __restrict__ T0,
+                                                                    const uint8_t* __restrict__ T1, int ldt,
+                                                                    const float* __restrict__ scale,
+                                                                    const DevTask* __restrict__ tasks,
+                                                                    const DevTerm* __restrict__ terms,
+                                                                    const int32_t* __restrict__ segs,
+                                                                    const WorkItem* __restrict__ items,
+                                                                    OUT* __restrict__ C, double* __restrict__ W) {
+    typedef LpdCfg<MODE> L;
+    constexpr int KT = L::KT, EB = L::EB, PL = L::PL;
+    constexpr int RB = KT * EB;  // bytes of one tile row per stage
+    static_assert(RB == 128, "two tile rows per 256-byte copy");
+    constexpr int PLANE = GT * RB;
+    constexpr int NCP = 32;  // copies per plane and wave (64 rows, two per copy)
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2][PL][2][PLANE];  // [buffer][plane][operand]
+
+    const WorkItem w = items[blockIdx.x];
+    const DevTask t = tasks[w.task];
+    const DevTerm tx = terms[t.term_off];
+    const DevTerm ty = terms[t.term_off + 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    const int i0 = w.ti * GT, j0 = w.tj * GT;
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
+    const int64_t rowb = (int64_t)ldt * EB;  // bytes between rows of the copy
+
+    // Copy role: operand cop, tile rows half * 64 + [0, 64).  Copy i moves
+    // rows 2i (lanes 0-31) and 2i + 1 (lanes 32-63) of that range; lane
+    // dword d of a row holds logical chunk (d / 4) ^ (i mod 8).  Per i mod 8:
+    // the lane's byte offset inside the row block and its first k element.
+    const int cop = wave >> 1, half = wave & 1;
+    const int hb = lane >> 5, d = lane & 31;
+    uint32_t vb[8];
+    int ke[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int lc = (d >> 2) ^ q;
+        const int byte = lc * 16 + (d & 3) * 4;
+        vb[q] = (uint32_t)(hb * rowb) + (uint32_t)byte;
+        ke[q] = byte / EB;
+    }
+    const DevTerm& tc = cop == 0 ? tx : ty;
+    const int row0 = tc.col + (cop == 0 ? i0 : j0) + half * 64;  // first row of the copy this wave reads
+    const int nrv = tc.cvend - row0;                              // rows of the range that exist
+    const int ilim = nrv >= 64 ? NCP : (nrv - hb + 1 > 0 ? (nrv - hb + 1) / 2 : 0);  // copies with this lane's row
+
+    constexpr bool FL = MODE == 0;  // FP64 flush accumulators
+    f4_t acc[4][4];
+    double acc64[FL ? 4 : 1][FL ? 4 : 1][FL ? 4 : 1];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+            if (FL)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc64[FL ? a : 0][FL ? b : 0][FL ? e : 0] = 0.0;
+        }
+
+    int ntiles = 0;
+    for (int s = 0; s < t.nseg; ++s)
+        ntiles += (segs[t.seg_off + s * stride + 2] - segs[t.seg_off + s * stride + 1] + KT - 1) / KT;
+    int seg = 0;
+    int k0 = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
+    int kend = t.nseg > 0 ? segs[t.seg_off + 2] : 0;  // window end
+    int krow = t.nseg > 0 ? segs[t.seg_off + kSegHdr] : 0;
+
+    // Copies of the stage at k0 into buffer `buf` (live false: past the last
+    // stage, every copy is out of range and writes zeros).
+    auto copy_stage = [&](int buf, bool live) {
+        const int krem = live ? kend - k0 : 0;
+        const bool full = krem >= KT && nrv >= 64;  // uniform: every copy of the stage in range
+#pragma unroll
+        for (int p = 0; p < PL; ++p) {
+            const uint8_t* base = (p == 0 ? T0 : T1) + ((int64_t)row0 * ldt + krow + k0) * EB;
+            const rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), (short)0, 0x7fffffff,
+                                                                0x00020000);
+            uint8_t* dst = &lds[buf][p][cop][half * 64 * RB];
+#pragma unroll
+            for (int i = 0; i < NCP; ++i) {
+                const uint32_t off = full || (i < ilim && ke[i & 7] < krem) ? vb[i & 7] : kOOB;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(dst + 2 * i * RB),
+                                                         4, off, (int)(2 * i * rowb), 0, 0);
+            }
+        }
+    };
+    auto advance = [&]() {
+        k0 += KT;
+        if (k0 >= kend) {
+            ++seg;
+            if (seg < t.nseg) {
+                k0 = segs[t.seg_off + seg * stride + 1];
+                kend = segs[t.seg_off + seg * stride + 2];
+                krow = segs[t.seg_off + seg * stride + kSegHdr];
+            }
+        }
+    };
+    // byte address of logical 16-byte chunk kc of tile row r inside a plane
+    auto chunk = [](int r, int kc) { return r * RB + ((kc ^ ((r >> 1) & 7)) << 4); };
+
+    if (ntiles > 0) copy_stage(0, true);
+    for (int it = 0; it < ntiles; ++it) {
+        const int buf = it & 1;
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of stage it have landed
+        __syncthreads();                // every copy of stage it landed; stage it-1 fully read
+        const bool next = it + 1 < ntiles;
+        if (next) advance();
+        copy_stage(buf ^ 1, next);
+        const int rsel = lane & 15, kq = lane >> 4;
+        if (MODE == 0) {
+#pragma unroll
+            for (int ks = 0; ks < KT / 32; ++ks) {
+                const int kc = ks * 4 + kq;
+                bf8_t bh[4], bl[4];
+#pragma unroll
+                for (int cf = 0; cf < 4; ++cf) {
+                    const int rr = wn * 64 + cf * 16 + rsel;
+                    bh[cf] = *(const bf8_t*)(&lds[buf][0][1][chunk(rr, kc)]);
+                    bl[cf] = *(const bf8_t*)(&lds[buf][PL - 1][1][chunk(rr, kc)]);
+                }
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const int rr = wm * 64 + rb * 16 + rsel;
+                    const bf8_t ah = *(const bf8_t*)(&lds[buf][0][0][chunk(rr, kc)]);
+                    const bf8_t al = *(const bf8_t*)(&lds[buf][PL - 1][0][chunk(rr, kc)]);
+#pragma unroll
+                    for (int cf = 0; cf < 4; ++cf) {
+                        acc[rb][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cf], acc[rb][cf], 0, 0, 0);
+                        acc[rb][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cf], acc[rb][cf], 0, 0, 0);
+                        acc[rb][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cf], acc[rb][cf], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            const int kc = 2 * kq;  // 32 bytes: logical chunks kc, kc + 1
+            i8_t bq[4];
+#pragma unroll
+            for (int cf = 0; cf < 4; ++cf) {
+                const int rr = wn * 64 + cf * 16 + rsel;
+                const u4_t lo = *(const u4_t*)(&lds[buf][0][1][chunk(rr, kc)]);
+                const u4_t hi = *(const u4_t*)(&lds[buf][0][1][chunk(rr, kc + 1)]);
+                bq[cf] = i8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+            }
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int rr = wm * 64 + rb * 16 + rsel;
+                const u4_t lo = *(const u4_t*)(&lds[buf][0][0][chunk(rr, kc)]);
+                const u4_t hi = *(const u4_t*)(&lds[buf][0][0][chunk(rr, kc + 1)]);
+                const i8_t aq = i8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+#pragma unroll
+                for (int cf = 0; cf < 4; ++cf)
+                    acc[rb][cf] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aq, bq[cf], acc[rb][cf], 0, 0, 0, 0,
+                                                                                  0, 0);
+            }
+        }
+        if (FL && (((it + 1) * KT) % KFLUSH == 0 || it + 1 == ntiles)) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc64[FL ? a : 0][FL ? b : 0][FL ? e : 0] += (double)acc[a][b][e];
+                    acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+    }
+
+    const bool syrk = t.kind == TK_SYRK;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int gi = i0 + wm * 64 + rb * 16 + 4 * (lane >> 4) + e;
+            if (gi >= t.dM) continue;
+            const int64_t rowbase = packed_index((int64_t)t.r0 + gi, t.q0);
+            const double si = MODE == 1 ? 1.0 / (double)scale[tx.col + gi] : 1.0;
+#pragma unroll
+            for (int cf = 0; cf < 4; ++cf) {
+                const int gj = j0 + wn * 64 + cf * 16 + (lane & 15);
+                if (gj >= t.dN || (syrk && gj > gi)) continue;
+                double v = FL ? acc64[FL ? rb : 0][FL ? cf : 0][FL ? e : 0] : (double)acc[rb][cf][e];
+                if (MODE == 1) v = v * si / (double)scale[ty.col + gj];  // exact power-of-two de-scale
+                if (t.dst == 0)
+                    store_out(C + rowbase + gj, t.beta, v);
+                else
+                    W[t.ws_off + (int64_t)gi * t.N + gj] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
@@ -1725,26 +1944,29 @@ hipError_t launch_prep_lp(int mode, const float* A, int64_t lda, int m, int n, i
 
 hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1, int ldt, const float* scale,
                           const DevTables& tb, const WorkItem* items, int nitems, void* C, double* W,
-                          hipStream_t s) {
+                          hipStream_t s, bool aligned) {
     if (nitems <= 0) return hipSuccess;
     const dim3 g(nitems), b(256);
     const uint8_t* t0 = (const uint8_t*)T0;
     const uint8_t* t1 = (const uint8_t*)(T1 ? T1 : T0);
+    // direct-to-LDS copies: dword-aligned windows, row offsets of one copy
+    // block below 2^31
+    const int eb = mode == 0 ? 2 : 1;
+    const bool dma = aligned && (int64_t)64 * ldt * eb < ((int64_t)1 << 31);
+#define ATA_LP_LAUNCH(K, M, O)                                                                                       \
+    hipLaunchKernelGGL((K<M, O>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs, items, (O*)C, W)
     if (mode == 0) {
-        if (out_f64)
-            hipLaunchKernelGGL((k_gemm_lp<0, double>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
-                               items, (double*)C, W);
-        else
-            hipLaunchKernelGGL((k_gemm_lp<0, float>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
-                               items, (float*)C, W);
+        if (dma && out_f64) ATA_LP_LAUNCH(k_gemm_lpd, 0, double);
+        else if (dma) ATA_LP_LAUNCH(k_gemm_lpd, 0, float);
+        else if (out_f64) ATA_LP_LAUNCH(k_gemm_lp, 0, double);
+        else ATA_LP_LAUNCH(k_gemm_lp, 0, float);
     } else {
-        if (out_f64)
-            hipLaunchKernelGGL((k_gemm_lp<1, double>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
-                               items, (double*)C, W);
-        else
-            hipLaunchKernelGGL((k_gemm_lp<1, float>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
-                               items, (float*)C, W);
+        if (dma && out_f64) ATA_LP_LAUNCH(k_gemm_lpd, 1, double);
+        else if (dma) ATA_LP_LAUNCH(k_gemm_lpd, 1, float);
+        else if (out_f64) ATA_LP_LAUNCH(k_gemm_lp, 1, double);
+        else ATA_LP_LAUNCH(k_gemm_lp, 1, float);
     }
+#undef ATA_LP_LAUNCH
     return hipGetLastError();
 }
 

@@ -484,6 +484,8 @@ void restrict_window(Plan& P, DevTask& t, int64_t a, int64_t b) {
     P.segs.insert(P.segs.end(), out.begin(), out.end());
 }
 
+constexpr int64_t kSplitAlign = 16;
+
 // Split long K ranges of launches that have too few tiles to fill the GPU.
 // A task writing C becomes nparts tasks writing dense partial blocks to the
 // workspace plus a combination that sums them (in part order) into C; the
@@ -573,9 +575,13 @@ void split_k(Plan& P) {
                     if (cb.nparts == np && t0.ws_off >= cb.ws_off && t0.ws_off < cb.ws_off + cb.part_stride)
                         pstride = cb.part_stride;
             }
+            // interior part boundaries on multiples of kSplitAlign rows, so that
+            // windows stay aligned wherever the row chunks are (the reduced-
+            // precision tiles stage whole dwords of a converted copy)
+            auto cut = [&](int p) -> int64_t { return p == np ? k : (k * p / np) / kSplitAlign * kSplitAlign; };
             for (int p = 0; p < np; ++p) {
                 DevTask t = t0;
-                restrict_window(P, t, k * p / np, k * (p + 1) / np);
+                restrict_window(P, t, cut(p), cut(p + 1));
                 if (t0.dst == 0) {
                     t.dst = 1;
                     t.beta = 0;

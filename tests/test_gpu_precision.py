@@ -183,3 +183,26 @@ def test_reduced_precision_split_k(env, orc):
         assert P.plan_info(20000, 200, 64, dtype=dt)["combine_tasks"] >= 1
         C = _gram(env, A, dt | P.OUT_F64, cutoff=64)
         assert orc.rel_fro(C, ref, 200) <= tol
+
+
+def test_reduced_precision_copy_paths(env, orc):
+    """Plans whose segment windows all start and end on a dword of the
+    converted copy stage it through direct-to-LDS copies; other plans stage
+    through registers.  Both are exact on small-integer inputs.  Row counts:
+    2048 (every window aligned for both forms), 2047 (odd windows: register
+    staging), 4102 (aligned for bfloat16 pairs, not for e4m3 quadruples);
+    with a 200000-row matrix split-K parts (boundaries on multiples of 16
+    rows) keep the windows aligned."""
+    torch, P = env
+    print("case: lp copy paths", flush=True)
+    for m in (2048, 2047, 4102):
+        Ai = synthetic.integer(m, 130, m).astype(np.float32)
+        exact = orc.classical(Ai.astype(np.float64))
+        for dt in (P.F32_BF16X3, P.F32_FP8):
+            for c in (64, 10 ** 6):
+                assert np.array_equal(_gram(env, Ai, dt | P.OUT_F64, cutoff=c), exact), (m, dt, c)
+    Ai = synthetic.integer(200000, 64, 5).astype(np.float32)
+    exact = orc.classical(Ai.astype(np.float64))
+    for dt in (P.F32_BF16X3, P.F32_FP8):
+        assert P.plan_info(200000, 64, 10 ** 6, dtype=dt)["combine_tasks"] >= 1
+        assert np.array_equal(_gram(env, Ai, dt | P.OUT_F64, cutoff=10 ** 6), exact), dt
