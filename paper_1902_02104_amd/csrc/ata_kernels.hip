@@ -449,8 +449,7 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
     // Slabs of this wave's operand for the stage at k0 (kStageRows rows each,
     // so every in-slab offset stays below kOOB): rows below both the window
     // end and the operand's row end; the rest read as zero.  Past the last
-    // stage (live false) the slabs are empty and the copies write zeros into
-    // the spare buffer.
+    // stage (live false) the slabs are empty and nothing is copied.
     rsrc_t rs[NSL];
     auto slab = [&](bool live) {
         const SegP sg = segs + t.seg_off + (live ? seg : 0) * stride;
@@ -468,12 +467,14 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
         }
     };
     // Copy part j of the stage into buffer `buf`: this wave's k rows
-    // 2(2j) + cpar and 2(2j + 1) + cpar.  (The operand always has a term;
-    // the test also keeps the copies in a block of their own, which bounds
-    // how far the scheduler moves the next step's reads.)
+    // 2(2j) + cpar and 2(2j + 1) + cpar.  Nothing is copied past the last
+    // stage, so no copy is in flight when the workgroup ends.  (The test also
+    // keeps the copies in a block of their own, which bounds how far the
+    // scheduler moves the next step's reads.)
     const int cnt = cs == 0 ? t.nx : t.ny;
+    bool copying = false;  // the stage being copied exists
     auto copy_part = [&](int buf, int j) {
-        if (cnt <= 0) return;
+        if (cnt <= 0 || !copying) return;
         T* pl = lds[buf][cs];
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii) {
@@ -499,6 +500,7 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
 
     if (ntiles > 0) {
         slab(true);
+        copying = true;
 #pragma unroll
         for (int j = 0; j < NP; ++j) copy_part(0, j);
     }
@@ -509,6 +511,7 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
         const bool next = it + 1 < ntiles;
         if (next) advance();
         slab(next);
+        copying = next;
         const T* xp = lds[buf][0];
         const T* yp = lds[buf][1];
         __builtin_amdgcn_s_setprio(1);
@@ -1587,7 +1590,8 @@ __global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8
     int krow = t.nseg > 0 ? segs[t.seg_off + kSegHdr] : 0;
 
     // Copies of the stage at k0 into buffer `buf` (live false: past the last
-    // stage, every copy is out of range and writes zeros).
+    // stage, every copy is out of range and writes zeros into the spare
+    // buffer; they are waited for before the workgroup ends).
     auto copy_stage = [&](int buf, bool live) {
         const int krem = live ? kend - k0 : 0;
         const bool full = krem >= KT && nrv >= 64;  // uniform: every copy of the stage in range
@@ -1685,6 +1689,9 @@ __global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8
                 }
         }
     }
+
+    // no copy may land after the workgroup's LDS is released
+    __builtin_amdgcn_s_waitcnt(0);
 
     const bool syrk = t.kind == TK_SYRK;
 #pragma unroll
