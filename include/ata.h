@@ -98,7 +98,10 @@ typedef struct ata_opts {
  * precision forms scale columns themselves). */
 #define ATA_OPT_EQUILIBRATE 0x2
 
-#define ATA_DEFAULT_MAX_DEPTH 2
+/* One Strassen level per off-diagonal product: on gfx950 FP64 and FP32 a
+ * second level costs more in operand-sum traffic than its 1/8 saving in
+ * multiplications. */
+#define ATA_DEFAULT_MAX_DEPTH 1
 #define ATA_MAX_DEPTH_LIMIT 4 /* deepest supported Strassen level count */
 
 /*
@@ -177,7 +180,8 @@ typedef struct ata_plan_stats {
 int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts *opts,
                   ata_plan_stats *out);
 
-/* Default cutoff chosen for a shape when cutoff == 0. */
+/* Default cutoff chosen for a shape when cutoff == 0: 128 when
+ * min(m, n) <= 1024, 256 up to 4096, 512 above. */
 int ata_default_cutoff(int64_t m, int64_t n, int dtype);
 
 /* Text for a status code (static storage). */

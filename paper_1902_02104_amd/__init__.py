@@ -23,7 +23,7 @@ F32_FP8 = 3
 OUT_F64 = 0x100
 STRASSEN = 0
 WINOGRAD = 1
-DEFAULT_MAX_DEPTH = 2
+DEFAULT_MAX_DEPTH = 1
 OPT_PRODUCT_TILES = 0x1
 OPT_EQUILIBRATE = 0x2
 OPT_OPERAND_SUMS = 0x4

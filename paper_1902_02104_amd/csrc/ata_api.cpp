@@ -218,10 +218,13 @@ WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equil
 int64_t default_cutoff(int64_t m, int64_t n, int dtype) {
     (void)dtype;
     // Leaves of a few hundred columns keep every workgroup tile busy while the
-    // top levels (where nearly all the work is) still split.
+    // top levels (where nearly all the work is) still split.  Large shapes
+    // take 512-column leaves, the fastest of {128, 256, 512} on gfx950 for a
+    // square 10000-column FP64 product at one Strassen level.
     const int64_t mn = m < n ? m : n;
     if (mn <= 1024) return 128;
-    return 256;
+    if (mn <= 4096) return 256;
+    return 512;
 }
 
 // Build (or fetch) the plan for the current device.
