@@ -12,6 +12,12 @@ Functions
                             returns (C, counts)
   hasa(X, Y, cutoff, ...)   the rectangular Strassen/Winograd routine alone
   ata_mult_count(m, n, c)   multiplication count of Algorithm 1 (no data)
+  potrf(Cp, n)              Cholesky factor of packed C (row by row), with
+                            LAPACK's info (first non-positive pivot + 1)
+  potrs(L, n, B)            L L^t X = B by forward and back substitution
+  atb(A, B)                 A^t B, the normal equations' right-hand side
+                            (these three follow Section 1's least-squares use
+                            of A^t A and their textbook definitions)
   bf16_round, bf16_split, e4m3_round, pow2_column_scales
                             number-format conversions used by the reduced
                             precision forms, written from the format
@@ -31,6 +37,7 @@ __all__ = [
     "classical", "classical_mt", "ata", "hasa", "ata_mult_count", "unpack", "pack",
     "tri", "rel_fro", "scaled_err", "freivalds_residual", "bf16_round", "bf16_split",
     "e4m3_round", "pow2_column_scales", "gram_bf16x3", "gram_fp8", "STRASSEN", "WINOGRAD", "load",
+    "potrf", "potrs", "atb",
 ]
 
 STRASSEN = 0
@@ -77,6 +84,12 @@ def load():
     lib.ora_hasa.restype = None
     lib.ora_ata_mult_count.argtypes = [i64, i64, i64, ctypes.c_int]
     lib.ora_ata_mult_count.restype = i64
+    lib.ora_potrf.argtypes = [dp, i64]
+    lib.ora_potrf.restype = i64
+    lib.ora_potrs.argtypes = [dp, i64, dp, i64, i64]
+    lib.ora_potrs.restype = None
+    lib.ora_atb.argtypes = [dp, i64, i64, i64, dp, i64, i64, dp, i64]
+    lib.ora_atb.restype = None
     _lib = lib
     return lib
 
@@ -164,6 +177,41 @@ def hasa(X: np.ndarray, Y: np.ndarray, cutoff: int = 32, variant="strassen", max
 def ata_mult_count(m: int, n: int, cutoff: int, max_depth: int = -1) -> int:
     """Scalar multiplications of Algorithm 1 for an m x n input."""
     return int(load().ora_ata_mult_count(int(m), int(n), int(cutoff), int(max_depth)))
+
+
+def potrf(Cp: np.ndarray, n: int):
+    """Cholesky factor of the packed lower SPD matrix Cp (a copy is factored).
+    Returns (packed L, info): info 0, or p + 1 for the first row p whose pivot
+    is not positive (rows from p on are then unspecified)."""
+    L = np.array(Cp, dtype=np.float64, copy=True)
+    if L.shape != (tri(n),):
+        raise ValueError("packed length must be n(n+1)/2")
+    info = int(load().ora_potrf(_dptr(L), n)) if n else 0
+    return L, info
+
+
+def potrs(L: np.ndarray, n: int, B: np.ndarray) -> np.ndarray:
+    """X with L L^t X = B for packed lower L; B is n x nrhs (or length n)."""
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    X = np.array(B, dtype=np.float64, copy=True, order="C")
+    vec = X.ndim == 1
+    X2 = X.reshape(n, -1)
+    if n and X2.shape[1]:
+        load().ora_potrs(_dptr(L), n, _dptr(X2), X2.shape[1], X2.shape[1])
+    return X2.reshape(-1) if vec else X2
+
+
+def atb(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """A^t B for A m x n and B m x nrhs (or length m), i ascending."""
+    A, m, n, lda = _as_rows(A)
+    Bv = np.ascontiguousarray(B, dtype=np.float64)
+    vec = Bv.ndim == 1
+    B2 = Bv.reshape(m, -1)
+    r = B2.shape[1]
+    out = np.zeros((n, r))
+    if n and r:
+        load().ora_atb(_dptr(A), m, n, lda, _dptr(B2), r, r, _dptr(out), r)
+    return out.reshape(-1) if vec else out
 
 
 # -------------------------------------------------------------------------

@@ -20,6 +20,11 @@
  *   ora_hasa           HASA alone: D = X Y for X (M x K), Y (K x N), Strassen
  *                      (1969) or Winograd (1971) seven-product recursion with
  *                      zero padding of odd quadrants.
+ *   ora_potrf, ora_potrs, ora_atb
+ *                      consumers of the product for the normal equations of
+ *                      least squares (Section 1): the Cholesky factor of packed
+ *                      C, the two triangular solves, and A^t b, each by its
+ *                      textbook definition.
  *
  * Build with -O2 -ffp-contract=off: no fused multiply-add, IEEE round to
  * nearest even on every operation, so results are reproducible.
@@ -37,6 +42,7 @@
  *     (A11 + A22)(B11 + B22) and (A12 - A22)(B21 + B22): as printed those two
  *     do not reproduce A B with the printed quadrant sums.
  */
+#include <math.h>
 #include <pthread.h>
 #include <stdint.h>
 
@@ -424,4 +430,68 @@ i64 ora_ata_mult_count(i64 m, i64 n, i64 cutoff, int max_depth)
     ora_cfg cfg = {cutoff, ORA_STRASSEN, max_depth};
     if (m <= 0 || n <= 0) return 0;
     return ata_count(m, n, &cfg);
+}
+
+/* ------------------------------------------------------------------------
+ * Consumers of the product (Section 1 names the normal equations of least
+ * squares as a use of A^t A).  Textbook definitions, no blocking.
+ * ------------------------------------------------------------------------ */
+
+/* Cholesky factor of the packed lower SPD matrix C, in place, row by row
+ * (Cholesky-Banachiewicz): for j < i,
+ *   L[i][j] = (C[i][j] - sum_{k<j} L[i][k] L[j][k]) / L[j][j],
+ *   L[i][i] = sqrt(C[i][i] - sum_{k<i} L[i][k]^2),
+ * each sum taken with k ascending.  Returns 0, or p + 1 for the first row p
+ * whose pivot C[p][p] - sum is not positive; the rows from p on are then
+ * left as they stand. */
+i64 ora_potrf(double *C, i64 n)
+{
+    for (i64 i = 0; i < n; ++i) {
+        double *Li = C + tri(i);
+        for (i64 j = 0; j < i; ++j) {
+            const double *Lj = C + tri(j);
+            double s = 0.0;
+            for (i64 k = (ORA_MUTANT == 9 && j > 0) ? 1 : 0; k < j; ++k) s += Li[k] * Lj[k];
+            Li[j] = (Li[j] - s) / (ORA_MUTANT == 10 ? Li[i] : Lj[j]);
+        }
+        double s = 0.0;
+        for (i64 k = 0; k < i; ++k) s += Li[k] * Li[k];
+        const double d = Li[i] - s;
+        if (!(d > 0.0)) return i + 1;
+        Li[i] = sqrt(d);
+    }
+    return 0;
+}
+
+/* Solve L L^t X = B in place for the packed lower factor L (n x n) and the
+ * row-major n x nrhs right-hand sides B (row stride ldb): forward
+ * substitution L Y = B, then back substitution L^t X = Y. */
+void ora_potrs(const double *L, i64 n, double *B, i64 nrhs, i64 ldb)
+{
+    for (i64 r = 0; r < nrhs; ++r) {
+        for (i64 i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (i64 k = 0; k < i; ++k) s += L[tri(i) + k] * B[k * ldb + r];
+            B[i * ldb + r] = (B[i * ldb + r] - s) / L[tri(i) + i];
+        }
+        for (i64 i = n - 1; i >= 0; --i) {
+            double s = 0.0;
+            for (i64 k = i + 1; k < n; ++k) s += L[tri(k) + i] * B[k * ldb + r];
+            const double num = B[i * ldb + r] - s;
+            B[i * ldb + r] = ORA_MUTANT == 11 ? num : num / L[tri(i) + i];
+        }
+    }
+}
+
+/* out[j][r] = sum_i A[i][j] B[i][r], i ascending: the right-hand side A^t b
+ * of the normal equations (A m x n row stride lda, B m x nrhs row stride ldb,
+ * out n x nrhs row stride ldo). */
+void ora_atb(const double *A, i64 m, i64 n, i64 lda, const double *B, i64 nrhs, i64 ldb, double *out, i64 ldo)
+{
+    for (i64 j = 0; j < n; ++j)
+        for (i64 r = 0; r < nrhs; ++r) {
+            double s = 0.0;
+            for (i64 i = (ORA_MUTANT == 12 && m > 1) ? 1 : 0; i < m; ++i) s += A[i * lda + j] * B[i * ldb + r];
+            out[j * ldo + r] = s;
+        }
 }

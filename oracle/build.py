@@ -23,7 +23,7 @@ def build(verbose: bool = False, mutant: int = 0, out: str | None = None) -> str
     tmp = out + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
            "-Wall", "-Wno-unused-function", "-pthread", "-DORA_MUTANT=%d" % int(mutant),
-           os.path.join(HERE, "ata_oracle.c"), "-o", tmp]
+           os.path.join(HERE, "ata_oracle.c"), "-lm", "-o", tmp]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -21,6 +21,7 @@ SEED_TALL_Z = 3
 SEED_TALL_SCALES = 4
 SEED_PRECISION = 5
 SEED_STREAM = 6
+SEED_FACTOR = 7
 SEED_REQUEST_BASE = 1000
 
 
@@ -41,6 +42,17 @@ def integer(m: int, n: int, seed: int, lo: int = -3, hi: int = 3, dtype=np.float
 def normal(m: int, n: int, seed: int, dtype=np.float64) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.ascontiguousarray(rng.standard_normal(size=(m, n)).astype(dtype, copy=False))
+
+
+def integer_factor(n: int, seed: int, lo: int = -2, hi: int = 2) -> np.ndarray:
+    """Dense n x n lower-triangular integer matrix with diagonal entries drawn
+    from {1, 2, 4} and off-diagonal entries uniform in {lo..hi}.  Its Gram
+    L L^t has integer entries and a Cholesky factor (L itself) that every
+    summation order reaches exactly while partial sums stay below 2^24."""
+    rng = np.random.default_rng(seed)
+    L = np.tril(rng.integers(lo, hi + 1, size=(n, n)), -1).astype(np.float64)
+    L[np.arange(n), np.arange(n)] = rng.choice([1.0, 2.0, 4.0], size=n)
+    return L
 
 
 def column_scales(n: int, seed: int, lo_exp: float = -3.0, hi_exp: float = 3.0) -> np.ndarray:

@@ -281,6 +281,95 @@ def test_empty_and_degenerate(orc):
 
 
 # ---------------------------------------------------------------------------
+# Normal-equation consumers: Cholesky factor, triangular solves, A^t b
+# ---------------------------------------------------------------------------
+
+def _binom_lower(n):
+    """Lower Pascal triangle, L[i][j] = C(i, j)."""
+    from math import comb
+    return np.array([[comb(i, j) if j <= i else 0 for j in range(n)] for i in range(n)], dtype=np.float64)
+
+
+def _pascal(n):
+    """Symmetric Pascal matrix, P[i][j] = C(i + j, i)."""
+    from math import comb
+    return np.array([[comb(i + j, i) for j in range(n)] for i in range(n)], dtype=np.float64)
+
+
+def test_potrf_pascal_closed_form(orc):
+    # The symmetric Pascal matrix factors as (lower Pascal)(lower Pascal)^t,
+    # every intermediate an integer: the factor is exact.
+    for n in (1, 2, 7, 20):
+        L, info = orc.potrf(orc.pack(_pascal(n)), n)
+        assert info == 0
+        assert np.array_equal(L, orc.pack(_binom_lower(n)))
+
+
+def test_potrf_integer_factor_exact(orc):
+    for n, seed in [(1, 0), (5, 1), (33, 2), (90, 3)]:
+        L0 = synthetic.integer_factor(n, seed)
+        L, info = orc.potrf(orc.pack(L0 @ L0.T), n)  # small integers: BLAS exact
+        assert info == 0
+        assert np.array_equal(L, orc.pack(L0))
+
+
+def test_potrf_two_by_two_closed_form(orc):
+    a, b, c = 3.0, 1.25, 7.5
+    L, info = orc.potrf(np.array([a, b, c]), 2)
+    l11 = np.sqrt(a)
+    expect = np.array([l11, b / l11, np.sqrt(c - (b / l11) ** 2)])
+    assert info == 0
+    np.testing.assert_allclose(L, expect, rtol=4e-16, atol=0)
+
+
+def test_potrf_matches_lapack_on_gram(orc):
+    A = synthetic.uniform(400, 120, 11)
+    C = orc.classical(A)
+    L, info = orc.potrf(C, 120)
+    ref = np.linalg.cholesky(orc.unpack(C, 120))  # LAPACK dpotrf
+    assert info == 0
+    np.testing.assert_allclose(orc.unpack(L, 120)[np.tril_indices(120)], ref[np.tril_indices(120)],
+                               rtol=1e-12, atol=1e-12 * float(np.max(np.abs(ref))))
+
+
+def test_potrf_info_names_first_bad_pivot(orc):
+    n = 12
+    L0 = synthetic.integer_factor(n, 4)
+    for p in (0, 5, 11):
+        C = L0 @ L0.T
+        C[p, p] -= L0[p, p] ** 2 + 1.0  # pivot p becomes exactly -1
+        _, info = orc.potrf(orc.pack(C), n)
+        assert info == p + 1
+    _, info = orc.potrf(orc.pack(np.diag([1.0, 1.0, 0.0, 1.0])), 4)
+    assert info == 3
+
+
+def test_potrs_exact_and_residual(orc):
+    for n, r, seed in [(1, 1, 0), (17, 3, 1), (60, 2, 2)]:
+        L0 = synthetic.integer_factor(n, seed)
+        X0 = synthetic.integer(n, r, seed + 100)
+        B = (L0 @ L0.T) @ X0  # small integers: exact
+        X = orc.potrs(orc.pack(L0), n, B)
+        assert np.array_equal(X, X0)
+    A = synthetic.uniform(300, 80, 12)
+    C = orc.unpack(orc.classical(A), 80)
+    L, _ = orc.potrf(orc.pack(C), 80)
+    B = synthetic.uniform(80, 4, 13)
+    X = orc.potrs(L, 80, B)
+    np.testing.assert_allclose(X, np.linalg.solve(C, B), rtol=1e-10, atol=1e-12)
+    assert np.linalg.norm(C @ X - B) <= 1e-13 * np.linalg.norm(C) * np.linalg.norm(X)
+    x1 = orc.potrs(L, 80, B[:, 0])
+    assert x1.shape == (80,) and np.array_equal(x1, X[:, 0])
+
+
+def test_atb_definition(orc):
+    A = synthetic.integer(70, 23, 5)
+    B = synthetic.integer(70, 3, 6)
+    assert np.array_equal(orc.atb(A, B), A.T @ B)  # small integers: exact
+    assert np.array_equal(orc.atb(A, B[:, 1]), A.T @ B[:, 1])
+
+
+# ---------------------------------------------------------------------------
 # Planted mistakes must be caught
 # ---------------------------------------------------------------------------
 
@@ -293,6 +382,10 @@ MUTANTS = {
     6: "M7 as misprinted",
     7: "Winograd U3 sign flipped",
     8: "first term of the base-case sum dropped",
+    9: "first term of the Cholesky sum dropped",
+    10: "Cholesky column divided by the wrong diagonal",
+    11: "back substitution without the diagonal division",
+    12: "first row of A^t b dropped",
 }
 
 
@@ -315,6 +408,24 @@ def _run_pins(lib_path):
             lib.ora_ata(A.ctypes.data_as(dp), m, n, n, C.ctypes.data_as(dp), 2, var, -1,
                         ctypes.byref(cnt))
             ok &= bool(np.array_equal(C, ref))
+    # normal-equation consumers: exact integer factor, solve and right-hand side
+    lib.ora_potrf.argtypes = [dp, i64]
+    lib.ora_potrf.restype = i64
+    lib.ora_potrs.argtypes = [dp, i64, dp, i64, i64]
+    lib.ora_atb.argtypes = [dp, i64, i64, i64, dp, i64, i64, dp, i64]
+    n = 20
+    L0 = synthetic.integer_factor(n, 9)
+    L = orc.pack(L0 @ L0.T)
+    ok &= lib.ora_potrf(L.ctypes.data_as(dp), n) == 0 and bool(np.array_equal(L, orc.pack(L0)))
+    X0 = synthetic.integer(n, 2, 10)
+    B = np.ascontiguousarray((L0 @ L0.T) @ X0)
+    lib.ora_potrs(orc.pack(L0).ctypes.data_as(dp), n, B.ctypes.data_as(dp), 2, 2)
+    ok &= bool(np.array_equal(B, X0))
+    A = synthetic.integer(30, 7, 11)
+    Bv = synthetic.integer(30, 2, 12)
+    out = np.zeros((7, 2))
+    lib.ora_atb(A.ctypes.data_as(dp), 30, 7, 7, Bv.ctypes.data_as(dp), 2, 2, out.ctypes.data_as(dp), 2)
+    ok &= bool(np.array_equal(out, A.T @ Bv))
     return ok
 
 
