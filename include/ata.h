@@ -304,6 +304,55 @@ double ata_server_now(ata_server *srv);
 /* Stop the loop after in-flight work completes and free everything. */
 int ata_server_destroy(ata_server *srv);
 
+/*
+ * Normal equations of least squares.  The paper's introduction names them
+ * (with projections and least squares) as a use of A^t A; these calls take
+ * the packed product to a solution:  x = (A^t A)^-1 A^t b.  All four work in
+ * the storage of ata's output (row-major packed lower triangle), on device
+ * memory, asynchronously on `stream`, in FP64 (dtype ATA_F64) or FP32
+ * (ATA_F32) arithmetic and storage throughout.  Return codes as above:
+ * -k for an invalid k-th argument, ATA_EUNSUPPORTED for another device or
+ * n > 2^22.
+ *
+ * ata_potrf: Cholesky factor of the symmetric positive definite matrix in
+ *   C_lower (n x n, packed), in place: on return C_lower holds L, lower
+ *   triangular with positive diagonal and L L^t = C.  Right-looking in
+ *   64-column blocks: per block one launch for the diagonal block, one for
+ *   the rows below it and one MFMA launch for the trailing update.
+ *   info: device int32 or NULL.  The call sets it to 0, and a kernel sets it
+ *   to p + 1 for the first column p whose pivot is not positive (LAPACK's
+ *   convention); L is then unspecified from column p on.  Read it after the
+ *   stream has synchronised.
+ */
+int ata_potrf(void *C_lower, int64_t n, int dtype, int32_t *info, void *stream);
+
+/*
+ * ata_potrs: solve L L^t X = B in place for the factor L from ata_potrf.
+ *   B: row-major n x nrhs, row stride ldb >= nrhs, overwritten by X.  One
+ *   launch per 64-row block for each of the forward and back substitutions;
+ *   suited to a few right-hand sides (each is solved in turn inside a block).
+ */
+int ata_potrs(const void *L_lower, int64_t n, void *B, int64_t nrhs, int64_t ldb, int dtype, void *stream);
+
+/*
+ * ata_atb: out = A^t B, the right-hand side of the normal equations.
+ *   A: row-major m x n (row stride lda >= n); B: row-major m x nrhs (row
+ *   stride ldb >= nrhs); out: row-major n x nrhs (row stride ldo >= nrhs).
+ *   Sums in FP64 over fixed row chunks, then the chunks in order, so results
+ *   are reproducible.  Allocates its partial sums stream-ordered on `stream`.
+ */
+int ata_atb(const void *A, int64_t m, int64_t n, int64_t lda, const void *B, int64_t nrhs, int64_t ldb, void *out,
+            int64_t ldo, int dtype, void *stream);
+
+/*
+ * ata_normal_solve: X = (A^t A)^-1 A^t B by ata (cutoff as for ata, 0 =
+ *   default; default options), ata_potrf, ata_atb and ata_potrs.  X: row-major
+ *   n x nrhs (row stride ldx >= nrhs).  The packed product and the partial
+ *   sums are allocated stream-ordered on `stream`.  info as for ata_potrf.
+ */
+int ata_normal_solve(const void *A, int64_t m, int64_t n, int64_t lda, const void *B, int64_t nrhs, int64_t ldb,
+                     void *X, int64_t ldx, int dtype, int cutoff, int32_t *info, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -195,7 +195,7 @@ def potrs(L: np.ndarray, n: int, B: np.ndarray) -> np.ndarray:
     L = np.ascontiguousarray(L, dtype=np.float64)
     X = np.array(B, dtype=np.float64, copy=True, order="C")
     vec = X.ndim == 1
-    X2 = X.reshape(n, -1)
+    X2 = X.reshape(n, 1) if vec else X
     if n and X2.shape[1]:
         load().ora_potrs(_dptr(L), n, _dptr(X2), X2.shape[1], X2.shape[1])
     return X2.reshape(-1) if vec else X2
@@ -206,7 +206,7 @@ def atb(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     A, m, n, lda = _as_rows(A)
     Bv = np.ascontiguousarray(B, dtype=np.float64)
     vec = Bv.ndim == 1
-    B2 = Bv.reshape(m, -1)
+    B2 = Bv.reshape(m, 1) if vec else Bv
     r = B2.shape[1]
     out = np.zeros((n, r))
     if n and r:

@@ -8,6 +8,7 @@ library is missing: there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 __all__ = [
@@ -96,6 +97,14 @@ def load():
     lib.ata_profile_enable.restype = ci
     lib.ata_profile_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ci]
     lib.ata_profile_collect.restype = ci
+    lib.ata_potrf.argtypes = [vp, i64, ci, vp, vp]
+    lib.ata_potrf.restype = ci
+    lib.ata_potrs.argtypes = [vp, i64, vp, i64, i64, ci, vp]
+    lib.ata_potrs.restype = ci
+    lib.ata_atb.argtypes = [vp, i64, i64, i64, vp, i64, i64, vp, i64, ci, vp]
+    lib.ata_atb.restype = ci
+    lib.ata_normal_solve.argtypes = [vp, i64, i64, i64, vp, i64, i64, vp, i64, ci, ci, vp, vp]
+    lib.ata_normal_solve.restype = ci
     _lib = lib
     return lib
 
@@ -244,3 +253,132 @@ def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_d
     if rc:
         raise AtaError(rc, "ata_ex")
     return out
+
+
+# -------------------------------------------------------------------------
+# Normal equations: Cholesky factor, triangular solves, A^t B
+# -------------------------------------------------------------------------
+
+def _solve_dtype(t):
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("float64 or float32 tensors only")
+
+
+def _rows2d(B, n, dtype, what):
+    """(tensor, rows, nrhs, row stride) of a length-n vector or n x r matrix
+    with unit column stride on the device."""
+    if not B.is_cuda:
+        raise ValueError("%s must be a device tensor" % what)
+    if _solve_dtype(B) != dtype:
+        raise TypeError("%s must have the factor's dtype" % what)
+    if B.dim() == 1:
+        if B.shape[0] != n or (n > 1 and B.stride(0) != 1):
+            raise ValueError("%s must be a contiguous vector of length %d" % (what, n))
+        return B, n, 1, 1
+    if B.dim() != 2 or B.shape[0] != n:
+        raise ValueError("%s must have %d rows" % (what, n))
+    r = B.shape[1]
+    if n > 0 and r > 0 and B.stride(1) != 1:
+        raise ValueError("%s needs unit column stride" % what)
+    return B, n, r, (B.stride(0) if n > 1 else max(r, 1))
+
+
+def _order(packed, n):
+    if n is None:
+        n = int((math.isqrt(8 * packed.numel() + 1) - 1) // 2)
+    if packed.dim() != 1 or packed.numel() < tri(n) or not packed.is_contiguous():
+        raise ValueError("packed triangle must be a contiguous vector of n(n+1)/2 entries")
+    return n
+
+
+def cholesky(C, n: int | None = None, info=None, stream=None):
+    """Cholesky factor of the packed lower SPD matrix C (device tensor), in
+    place: C then holds L with L L^t = C.  info: optional int32 device tensor
+    of one element that receives 0, or p + 1 for the first column p whose
+    pivot is not positive.  Returns C."""
+    import torch
+    lib = load()
+    if not C.is_cuda:
+        raise ValueError("C must be a device tensor")
+    n = _order(C, n)
+    if info is not None and (info.dtype != torch.int32 or not info.is_cuda or info.numel() < 1):
+        raise ValueError("info must be an int32 device tensor")
+    with torch.cuda.device(C.device):
+        rc = lib.ata_potrf(ctypes.c_void_p(C.data_ptr()), n, _solve_dtype(C),
+                           ctypes.c_void_p(info.data_ptr()) if info is not None else None, _stream_handle(stream))
+    if rc:
+        raise AtaError(rc, "ata_potrf")
+    return C
+
+
+def cholesky_solve(L, B, n: int | None = None, stream=None):
+    """Solve L L^t X = B in place (B: length-n vector or n x r matrix on the
+    device, unit column stride) for the packed factor L.  Returns B."""
+    import torch
+    lib = load()
+    n = _order(L, n)
+    dt = _solve_dtype(L)
+    B, _, r, ldb = _rows2d(B, n, dt, "B")
+    with torch.cuda.device(L.device):
+        rc = lib.ata_potrs(ctypes.c_void_p(L.data_ptr()), n, ctypes.c_void_p(B.data_ptr()), r, ldb, dt,
+                           _stream_handle(stream))
+    if rc:
+        raise AtaError(rc, "ata_potrs")
+    return B
+
+
+def atb(A, B, out=None, stream=None):
+    """A^t B for device tensors A (m x n) and B (length m or m x r)."""
+    import torch
+    lib = load()
+    if A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor")
+    m, n = A.shape
+    if m > 0 and n > 0 and A.stride(1) != 1:
+        raise ValueError("A needs unit column stride")
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    dt = _solve_dtype(A)
+    B, _, r, ldb = _rows2d(B, m, dt, "B")
+    shape = (n,) if B.dim() == 1 else (n, r)
+    if out is None:
+        out = torch.empty(shape, dtype=A.dtype, device=A.device)
+    out, _, _, ldo = _rows2d(out, n, dt, "out")
+    with torch.cuda.device(A.device):
+        rc = lib.ata_atb(ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.c_void_p(B.data_ptr()), r, ldb,
+                         ctypes.c_void_p(out.data_ptr()), ldo, dt, _stream_handle(stream))
+    if rc:
+        raise AtaError(rc, "ata_atb")
+    return out
+
+
+def normal_solve(A, B, cutoff: int = 0, X=None, info=None, stream=None):
+    """Least-squares solution X = (A^t A)^-1 A^t B through the normal
+    equations: the packed product, its Cholesky factor, A^t B and the two
+    triangular solves, all on the device.  info as for cholesky().  Returns X."""
+    import torch
+    lib = load()
+    if A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor")
+    m, n = A.shape
+    if m > 0 and n > 0 and A.stride(1) != 1:
+        raise ValueError("A needs unit column stride")
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    dt = _solve_dtype(A)
+    B, _, r, ldb = _rows2d(B, m, dt, "B")
+    if X is None:
+        X = torch.empty((n,) if B.dim() == 1 else (n, r), dtype=A.dtype, device=A.device)
+    X, _, _, ldx = _rows2d(X, n, dt, "X")
+    if info is not None and (info.dtype != torch.int32 or not info.is_cuda or info.numel() < 1):
+        raise ValueError("info must be an int32 device tensor")
+    with torch.cuda.device(A.device):
+        rc = lib.ata_normal_solve(ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.c_void_p(B.data_ptr()), r, ldb,
+                                  ctypes.c_void_p(X.data_ptr()), ldx, dt, int(cutoff),
+                                  ctypes.c_void_p(info.data_ptr()) if info is not None else None,
+                                  _stream_handle(stream))
+    if rc:
+        raise AtaError(rc, "ata_normal_solve")
+    return X

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libata.so")
 
-SOURCES = ["ata_plan.cpp", "ata_api.cpp", "ata_serve.cpp", "ata_kernels.hip"]
+SOURCES = ["ata_plan.cpp", "ata_api.cpp", "ata_serve.cpp", "ata_solve.cpp", "ata_kernels.hip", "ata_chol.hip"]
 
 
 def hipcc() -> str:

@@ -53,6 +53,13 @@ int check_device(int dev) {
     return ok;
 }
 
+int current_device_ok() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return check_device(dev);
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // True when every segment window [row + kbeg, row + kend) of the plan's

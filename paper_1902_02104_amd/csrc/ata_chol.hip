@@ -1,0 +1,508 @@
+// Consumers of the packed product on gfx950: the Cholesky factor of the
+// packed lower C, the two triangular solves with it, and the right-hand side
+// A^t b of the normal equations (Section 1 names least squares through the
+// normal equations as a use of A^t A).
+//
+// Storage: row-major packed lower triangle, element (i, j), j <= i, at
+// i (i + 1) / 2 + j, so a row's entries left of the diagonal are contiguous.
+// The factorization is right-looking over 64-column blocks: per block, one
+// launch factors the diagonal block, one solves the rows below it, and one
+// MFMA launch applies the rank-64 update to the trailing lower triangle.  The
+// solves take one launch per 64-row block in each direction.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ata_kernels.h"
+
+namespace atalib {
+
+namespace {
+
+constexpr int NB = 64;  // block width of the factorization and the solves
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int64_t pidx(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
+
+// ---------------------------------------------------------------------------
+// Diagonal block of the factorization at block column kb (width w <= 64), one
+// workgroup, in place.  Thread t owns column l = t & 63 and rows
+// i = (t >> 6) + 4 q (q < 16) of the block.  Column j of the step is scaled by
+// its owners (times 1 / pivot, as LAPACK's unblocked factor does) and
+// broadcast through LDS; every thread then applies the rank-one update to the
+// entries it owns (right-looking, unblocked).  A pivot that is not positive is
+// reported once through `info` (first failing column + 1, LAPACK's
+// convention); the factorization carries on with the resulting NaNs.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ C, int64_t kb, int w, int32_t* __restrict__ info) {
+    __shared__ T col[NB];
+    __shared__ T dg;
+    const int t = threadIdx.x, l = t & 63, wv = t >> 6;
+    T d[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = wv + 4 * q;
+        d[q] = (i < w && l <= i) ? C[pidx(kb + i, kb + l)] : T(0);
+    }
+    if (t == 0) dg = d[0];
+    __syncthreads();
+    for (int j = 0; j < w; ++j) {
+        const T dj = dg;
+        const T piv = sqrt(dj);
+        const T rp = T(1) / piv;
+        if (t == 0 && !(dj > T(0)) && info) atomicCAS(info, 0, (int32_t)(kb + j + 1));
+        if (l == j) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = wv + 4 * q;
+                if (i > j) {
+                    d[q] *= rp;
+                    col[i] = d[q];
+                } else if (i == j) {
+                    d[q] = piv;
+                }
+            }
+        }
+        __syncthreads();
+        if (l > j && l < w) {
+            const T lj = col[l];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = wv + 4 * q;
+                if (i >= l) {
+                    d[q] -= col[i] * lj;
+                    if (i == j + 1 && l == j + 1) dg = d[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = wv + 4 * q;
+        if (i < w && l <= i) C[pidx(kb + i, kb + l)] = d[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rows below the diagonal block: L21 = C21 L11^-t for rows
+// R0 = kb + w + 64 b ... R0 + 63 (workgroup b), with the factored L11 staged
+// in LDS.  Same ownership and step order as the diagonal block, so an entry
+// sees the same operations as if it had been factored with it.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_chol_rows(T* __restrict__ C, int64_t n, int64_t kb, int w) {
+    __shared__ T ld[NB * (NB + 1)];
+    __shared__ T col[NB];
+    const int t = threadIdx.x, l = t & 63, wv = t >> 6;
+    const int64_t R0 = kb + w + (int64_t)NB * blockIdx.x;
+    for (int e = t; e < NB * NB; e += 256) {
+        const int row = e >> 6, c = e & 63;
+        ld[row * (NB + 1) + c] = (row < w && c <= row) ? C[pidx(kb + row, kb + c)] : T(0);
+    }
+    T r[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = wv + 4 * q;
+        r[q] = (R0 + i < n && l < w) ? C[pidx(R0 + i, kb + l)] : T(0);
+    }
+    __syncthreads();
+    for (int j = 0; j < w; ++j) {
+        if (l == j) {
+            const T rp = T(1) / ld[j * (NB + 1) + j];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                r[q] *= rp;
+                col[wv + 4 * q] = r[q];
+            }
+        }
+        __syncthreads();
+        if (l > j && l < w) {
+            const T lj = ld[l * (NB + 1) + j];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) r[q] -= col[wv + 4 * q] * lj;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = wv + 4 * q;
+        if (R0 + i < n && l < w) C[pidx(R0 + i, kb + l)] = r[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Trailing update: C[i][j] -= sum_{k < w} L[i][kb + k] L[j][kb + k] for
+// s <= j <= i < n, s = kb + w, over the 64 x 64 tiles (ti, tj), tj <= ti, of
+// the trailing lower triangle (tile from the linear workgroup index).  Both
+// panel slices are staged transposed in LDS ([k][row], row stride 68: 4 mod
+// 16 doubles, so the broadcast operand reads of the FP64 form fall on
+// distinct banks) and four waves each form a 32 x 32 quarter on MFMA; on a
+// diagonal tile the quarter above the diagonal is skipped.
+//   FP64: v_mfma_f64_4x4x4f64 with the left operand broadcast to the four
+//         blocks, a 4 x 16 x 4 product: left lane l = X[row l & 3][k l >> 4],
+//         right lane l = Y[k l >> 4][col l & 15], result lane l =
+//         D[row l >> 4][col l & 15].
+//   FP32: v_mfma_f32_16x16x4f32: left lane l = X[row l & 15][k l >> 4],
+//         right as above, result element e of lane l = D[row 4 (l >> 4) + e]
+//         [col l & 15].
+// ---------------------------------------------------------------------------
+constexpr int UP = NB + 4;
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_chol_update(T* __restrict__ C, int64_t n, int64_t kb, int w, int tiles) {
+    __shared__ T Pi[NB * UP];
+    __shared__ T Pj[NB * UP];
+    const int64_t b = blockIdx.x;
+    int64_t ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > b) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    const int64_t tj = b - ti * (ti + 1) / 2;
+    if (ti >= tiles) return;
+    const int64_t s = kb + w;
+    const int64_t r0 = s + NB * ti, c0 = s + NB * tj;
+    const bool diag = ti == tj;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wr = wv >> 1, wc = wv & 1;
+#pragma unroll 4
+    for (int e = t; e < NB * NB; e += 256) {
+        const int row = e >> 6, k = e & 63;
+        const int64_t gi = r0 + row, gj = c0 + row;
+        Pi[k * UP + row] = (gi < n && k < w) ? C[pidx(gi, kb + k)] : T(0);
+        if (!diag) Pj[k * UP + row] = (gj < n && k < w) ? C[pidx(gj, kb + k)] : T(0);
+    }
+    __syncthreads();
+    if (diag && wr < wc) return;
+    const T* Y = diag ? Pi : Pj;
+    if constexpr (sizeof(T) == 8) {
+        double acc[8][2];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) acc[g][0] = acc[g][1] = 0.0;
+        for (int k0 = 0; k0 < NB; k0 += 4) {
+            const int kr = (k0 + (lane >> 4)) * UP;
+            double a[8], bb[2];
+#pragma unroll
+            for (int g = 0; g < 8; ++g) a[g] = Pi[kr + 32 * wr + 4 * g + (lane & 3)];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) bb[h] = Y[kr + 32 * wc + 16 * h + (lane & 15)];
+#pragma unroll
+            for (int g = 0; g < 8; ++g)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) acc[g][h] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[g], bb[h], acc[g][h], 0, 0, 0);
+        }
+#pragma unroll
+        for (int g = 0; g < 8; ++g)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t i = r0 + 32 * wr + 4 * g + (lane >> 4);
+                const int64_t j = c0 + 32 * wc + 16 * h + (lane & 15);
+                if (i < n && j <= i) {
+                    T* p = C + pidx(i, j);
+                    *p = *p - acc[g][h];
+                }
+            }
+    } else {
+        f4_t acc[2][2];
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc[g][h] = f4_t{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < NB; k0 += 4) {
+            const int kr = (k0 + (lane >> 4)) * UP;
+            float a[2], bb[2];
+#pragma unroll
+            for (int g = 0; g < 2; ++g) a[g] = Pi[kr + 32 * wr + 16 * g + (lane & 15)];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) bb[h] = Y[kr + 32 * wc + 16 * h + (lane & 15)];
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g], bb[h], acc[g][h], 0, 0, 0);
+        }
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t i = r0 + 32 * wr + 16 * g + 4 * (lane >> 4) + e;
+                    const int64_t j = c0 + 32 * wc + 16 * h + (lane & 15);
+                    if (i < n && j <= i) {
+                        T* p = C + pidx(i, j);
+                        *p = *p - acc[g][h][e];
+                    }
+                }
+    }
+}
+
+// Sum of v over the 64 lanes of the wave (every lane receives it).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+constexpr int RC = 8;  // right-hand sides per pass of the solve updates
+
+// Stage the diagonal block d (width wd) of L in LDS, row stride NB + 1.
+template <typename T>
+__device__ void stage_diag(const T* __restrict__ L, int64_t d0, int wd, T* ld) {
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int row = e >> 6, c = e & 63;
+        ld[row * (NB + 1) + c] = (row < wd && c <= row) ? L[pidx(d0 + row, d0 + c)] : T(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward substitution L Y = B, one launch per block (B row-major n x nrhs,
+// row stride ldb, overwritten by Y).  Launch k = -1 solves diagonal block 0.
+// Launch k >= 0 (block k already solved): workgroup b subtracts
+// L[block k+1+b rows][block k] Y_k from its 64 rows (one wave per row at a
+// time, lane = column of block k, wave-wide sums); workgroup 0 then solves
+// diagonal block k+1 with wave 0 (lane = row; column by column, each solved
+// value broadcast from its lane).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_fwd(const T* __restrict__ L, int64_t n, T* __restrict__ B, int64_t nrhs,
+                                                  int64_t ldb, int64_t k) {
+    __shared__ T ld[NB * (NB + 1)];
+    __shared__ T ys[NB * RC];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t tb = k + 1 + blockIdx.x;  // target block
+    const int64_t t0 = NB * tb;
+    if (k >= 0) {
+        const int64_t y0 = NB * k;
+        for (int64_t r0 = 0; r0 < nrhs; r0 += RC) {
+            const int rc = (int)(nrhs - r0 < RC ? nrhs - r0 : RC);
+            __syncthreads();
+            for (int e = t; e < NB * RC; e += 256) {
+                const int c = e / RC, rr = e % RC;
+                ys[e] = rr < rc ? B[(y0 + c) * ldb + r0 + rr] : T(0);
+            }
+            __syncthreads();
+            for (int q = wv; q < NB; q += 4) {
+                const int64_t i = t0 + q;
+                if (i >= n) break;
+                const T lv = L[pidx(i, y0 + lane)];
+                for (int rr = 0; rr < rc; ++rr) {
+                    const T s = wave_sum(lv * ys[lane * RC + rr]);
+                    if (lane == 0) B[i * ldb + r0 + rr] -= s;
+                }
+            }
+        }
+    }
+    if (blockIdx.x != 0) return;
+    const int wd = (int)(n - t0 < NB ? n - t0 : NB);
+    __syncthreads();  // the rows just updated are read below
+    stage_diag(L, t0, wd, ld);
+    __syncthreads();
+    if (wv != 0) return;
+    for (int64_t r = 0; r < nrhs; ++r) {
+        T x = lane < wd ? B[(t0 + lane) * ldb + r] : T(0);
+        for (int c = 0; c < wd; ++c) {
+            if (lane == c) x = x / ld[c * (NB + 1) + c];
+            const T xc = __shfl(x, c, 64);
+            if (lane > c) x -= ld[lane * (NB + 1) + c] * xc;
+        }
+        if (lane < wd) B[(t0 + lane) * ldb + r] = x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Back substitution L^t X = Y, one launch per block, last block first.
+// Launch k = nblk solves the last diagonal block.  Launch k (block k solved)
+// has k workgroups: workgroup b subtracts L[block k][block k-1-b]^t X_k from
+// the rows of block k-1-b (lane = row of the target block, so the reads of a
+// row of L are contiguous; the four waves split the rows of block k and their
+// sums are added in a fixed order); workgroup 0 then solves diagonal block
+// k-1 with wave 0, last column first.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_bwd(const T* __restrict__ L, int64_t n, T* __restrict__ B, int64_t nrhs,
+                                                  int64_t ldb, int64_t k, int64_t nblk) {
+    __shared__ T ld[NB * (NB + 1)];
+    __shared__ T xs[NB * RC];
+    __shared__ T red[4 * NB * RC];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int64_t d;  // diagonal block solved by workgroup 0
+    if (k < nblk) {
+        const int64_t x0 = NB * k;
+        const int wk = (int)(n - x0 < NB ? n - x0 : NB);
+        const int64_t tb = k - 1 - blockIdx.x;
+        const int64_t c0 = NB * tb;
+        for (int64_t r0 = 0; r0 < nrhs; r0 += RC) {
+            const int rc = (int)(nrhs - r0 < RC ? nrhs - r0 : RC);
+            __syncthreads();
+            for (int e = t; e < NB * RC; e += 256) {
+                const int j = e / RC, rr = e % RC;
+                xs[e] = (j < wk && rr < rc) ? B[(x0 + j) * ldb + r0 + rr] : T(0);
+            }
+            __syncthreads();
+            T acc[RC];
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr) acc[rr] = T(0);
+            for (int j = wv; j < wk; j += 4) {
+                const T lv = L[pidx(x0 + j, c0 + lane)];
+#pragma unroll
+                for (int rr = 0; rr < RC; ++rr) acc[rr] += lv * xs[j * RC + rr];
+            }
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr) red[(wv * NB + lane) * RC + rr] = acc[rr];
+            __syncthreads();
+            if (wv == 0) {
+                for (int rr = 0; rr < rc; ++rr) {
+                    const T s = ((red[lane * RC + rr] + red[(NB + lane) * RC + rr]) + red[(2 * NB + lane) * RC + rr]) +
+                                red[(3 * NB + lane) * RC + rr];
+                    B[(c0 + lane) * ldb + r0 + rr] -= s;
+                }
+            }
+        }
+        if (blockIdx.x != 0) return;
+        d = k - 1;
+    } else {
+        d = nblk - 1;
+    }
+    const int64_t d0 = NB * d;
+    const int wd = (int)(n - d0 < NB ? n - d0 : NB);
+    __syncthreads();
+    stage_diag(L, d0, wd, ld);
+    __syncthreads();
+    if (wv != 0) return;
+    for (int64_t r = 0; r < nrhs; ++r) {
+        T x = lane < wd ? B[(d0 + lane) * ldb + r] : T(0);
+        for (int c = wd - 1; c >= 0; --c) {
+            if (lane == c) x = x / ld[c * (NB + 1) + c];
+            const T xc = __shfl(x, c, 64);
+            if (lane < c) x -= ld[c * (NB + 1) + lane] * xc;
+        }
+        if (lane < wd) B[(d0 + lane) * ldb + r] = x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A^t B: partial sums over row chunks (workgroup = 256 columns x one chunk,
+// thread = column, rows ascending, FP64 accumulation), then a pass that adds
+// the chunks in order.  Each row of A is read once per eight right-hand
+// sides, contiguously across the workgroup.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_atb_part(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                                  const T* __restrict__ B, int64_t nrhs, int64_t ldb, int64_t rows,
+                                                  double* __restrict__ part) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t ch = blockIdx.y;
+    const int64_t i0 = ch * rows;
+    const int64_t i1 = i0 + rows < m ? i0 + rows : m;
+    for (int64_t r0 = 0; r0 < nrhs; r0 += RC) {
+        const int rc = (int)(nrhs - r0 < RC ? nrhs - r0 : RC);
+        double acc[RC];
+#pragma unroll
+        for (int rr = 0; rr < RC; ++rr) acc[rr] = 0.0;
+        if (j < n) {
+            for (int64_t i = i0; i < i1; ++i) {
+                const double a = (double)A[i * lda + j];
+#pragma unroll
+                for (int rr = 0; rr < RC; ++rr)
+                    if (rr < rc) acc[rr] += a * (double)B[i * ldb + r0 + rr];
+            }
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr)
+                if (rr < rc) part[(ch * n + j) * nrhs + r0 + rr] = acc[rr];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_atb_sum(const double* __restrict__ part, int64_t chunks, int64_t n,
+                                                 int64_t nrhs, T* __restrict__ out, int64_t ldo) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * nrhs) return;
+    double s = 0.0;
+    for (int64_t c = 0; c < chunks; ++c) s += part[c * n * nrhs + e];
+    out[(e / nrhs) * ldo + e % nrhs] = (T)s;
+}
+
+template <typename T>
+hipError_t potrf_t(T* C, int64_t n, int32_t* info, hipStream_t s) {
+    for (int64_t kb = 0; kb < n; kb += NB) {
+        const int w = (int)(n - kb < NB ? n - kb : NB);
+        const int64_t rest = n - kb - w;
+        const int64_t nrb = (rest + NB - 1) / NB;
+        hipLaunchKernelGGL(k_chol_diag<T>, dim3(1), dim3(256), 0, s, C, kb, w, info);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (nrb > 0) {
+            hipLaunchKernelGGL(k_chol_rows<T>, dim3((unsigned)nrb), dim3(256), 0, s, C, n, kb, w);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_chol_update<T>, dim3((unsigned)(nrb * (nrb + 1) / 2)), dim3(256), 0, s, C, n, kb, w,
+                               (int)nrb);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t potrs_t(const T* L, int64_t n, T* B, int64_t nrhs, int64_t ldb, hipStream_t s) {
+    const int64_t nblk = (n + NB - 1) / NB;
+    for (int64_t k = -1; k < nblk - 1; ++k) {
+        const int64_t grid = k < 0 ? 1 : nblk - k - 1;
+        hipLaunchKernelGGL(k_trsv_fwd<T>, dim3((unsigned)grid), dim3(256), 0, s, L, n, B, nrhs, ldb, k);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    for (int64_t k = nblk; k >= 1; --k) {
+        const int64_t grid = k == nblk ? 1 : k;
+        hipLaunchKernelGGL(k_trsv_bwd<T>, dim3((unsigned)grid), dim3(256), 0, s, L, n, B, nrhs, ldb, k, nblk);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t atb_t(const T* A, int64_t m, int64_t n, int64_t lda, const T* B, int64_t nrhs, int64_t ldb, T* out,
+                 int64_t ldo, double* part, int64_t chunks, hipStream_t s) {
+    const int64_t rows = (m + chunks - 1) / chunks;
+    hipLaunchKernelGGL(k_atb_part<T>, dim3((unsigned)((n + 255) / 256), (unsigned)chunks), dim3(256), 0, s, A, m, n,
+                       lda, B, nrhs, ldb, rows, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_atb_sum<T>, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, s, part, chunks, n, nrhs,
+                       out, ldo);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_potrf(bool f32, void* C, int64_t n, int32_t* info, hipStream_t s) {
+    return f32 ? potrf_t((float*)C, n, info, s) : potrf_t((double*)C, n, info, s);
+}
+
+hipError_t launch_potrs(bool f32, const void* L, int64_t n, void* B, int64_t nrhs, int64_t ldb, hipStream_t s) {
+    return f32 ? potrs_t((const float*)L, n, (float*)B, nrhs, ldb, s)
+               : potrs_t((const double*)L, n, (double*)B, nrhs, ldb, s);
+}
+
+int64_t atb_chunks(int64_t m, int64_t n) {
+    const int64_t ct = (n + 255) / 256;
+    int64_t ch = (2048 + ct - 1) / ct;
+    const int64_t most = (m + 255) / 256;
+    if (ch > most) ch = most;
+    return ch < 1 ? 1 : ch;
+}
+
+hipError_t launch_atb(bool f32, const void* A, int64_t m, int64_t n, int64_t lda, const void* B, int64_t nrhs,
+                      int64_t ldb, void* out, int64_t ldo, double* part, hipStream_t s) {
+    const int64_t ch = atb_chunks(m, n);
+    return f32 ? atb_t((const float*)A, m, n, lda, (const float*)B, nrhs, ldb, (float*)out, ldo, part, ch, s)
+               : atb_t((const double*)A, m, n, lda, (const double*)B, nrhs, ldb, (double*)out, ldo, part, ch, s);
+}
+
+}  // namespace atalib

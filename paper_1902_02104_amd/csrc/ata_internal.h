@@ -49,7 +49,8 @@ struct WsLayout {
 };
 
 int hip_fail(hipError_t e);
-int check_device(int dev);
+int check_device(int dev);       // caller holds the library mutex
+int current_device_ok();         // the current device is gfx950 (locks)
 bool dtype_lp(int dtype);
 int elem_bytes_in(int dtype);
 int elem_bytes_out(int dtype);

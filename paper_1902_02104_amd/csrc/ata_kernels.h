@@ -80,4 +80,15 @@ hipError_t launch_descale(bool f32, bool out_f64, void* C, int n, const void* sc
 // (uint16 pairs), mode 1 -> OCP e4m3 bytes (no scaling).
 hipError_t launch_convert(int mode, const float* x, int64_t count, void* out0, void* out1, hipStream_t s);
 
+// Consumers of the packed product (ata_chol.hip), FP64 or FP32 throughout.
+// Cholesky factor of packed lower C in place; info (device, may be null)
+// receives the first failing column + 1 if it is still 0.
+hipError_t launch_potrf(bool f32, void* C, int64_t n, int32_t* info, hipStream_t s);
+// L L^t X = B in place, B row-major n x nrhs with row stride ldb.
+hipError_t launch_potrs(bool f32, const void* L, int64_t n, void* B, int64_t nrhs, int64_t ldb, hipStream_t s);
+// out = A^t B; part holds atb_chunks(m, n) x n x nrhs doubles.
+int64_t atb_chunks(int64_t m, int64_t n);
+hipError_t launch_atb(bool f32, const void* A, int64_t m, int64_t n, int64_t lda, const void* B, int64_t nrhs,
+                      int64_t ldb, void* out, int64_t ldo, double* part, hipStream_t s);
+
 }  // namespace atalib

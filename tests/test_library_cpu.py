@@ -173,3 +173,35 @@ def test_release_caches_without_device(lib):
     before = P.plan_info(777, 333, 40, max_depth=2)
     P.release_caches()
     assert P.plan_info(777, 333, 40, max_depth=2) == before
+
+
+def test_normal_equation_argument_validation_without_gpu(lib):
+    """The factor, solve and A^t B entry points reject bad arguments before
+    any device call, with the LAPACK-style position codes of ata.h."""
+    L = P.load()
+    vp = ctypes.c_void_p
+    buf = (ctypes.c_double * 64)()
+    a = ctypes.cast(buf, vp)
+    assert L.ata_potrf(a, -1, P.F64, None, None) == -2
+    assert L.ata_potrf(None, 4, P.F64, None, None) == -1
+    assert L.ata_potrf(a, 4, P.F32_FP8, None, None) == -3
+    assert L.ata_potrf(a, 4, P.F64 | P.OUT_F64, None, None) == -3
+    assert L.ata_potrs(a, -1, a, 1, 1, P.F64, None) == -2
+    assert L.ata_potrs(a, 4, a, -1, 1, P.F64, None) == -4
+    assert L.ata_potrs(None, 4, a, 1, 1, P.F64, None) == -1
+    assert L.ata_potrs(a, 4, None, 1, 1, P.F64, None) == -3
+    assert L.ata_potrs(a, 4, a, 3, 2, P.F64, None) == -5
+    assert L.ata_potrs(a, 4, a, 1, 1, 9, None) == -6
+    assert L.ata_atb(a, -1, 4, 4, a, 1, 1, a, 1, P.F64, None) == -2
+    assert L.ata_atb(a, 4, -1, 4, a, 1, 1, a, 1, P.F64, None) == -3
+    assert L.ata_atb(a, 4, 4, 3, a, 1, 1, a, 1, P.F64, None) == -4
+    assert L.ata_atb(None, 4, 4, 4, a, 1, 1, a, 1, P.F64, None) == -1
+    assert L.ata_atb(a, 4, 4, 4, None, 1, 1, a, 1, P.F64, None) == -5
+    assert L.ata_atb(a, 4, 4, 4, a, -1, 1, a, 1, P.F64, None) == -6
+    assert L.ata_atb(a, 4, 4, 4, a, 2, 1, a, 2, P.F64, None) == -7
+    assert L.ata_atb(a, 4, 4, 4, a, 1, 1, None, 1, P.F64, None) == -8
+    assert L.ata_atb(a, 4, 4, 4, a, 2, 2, a, 1, P.F64, None) == -9
+    assert L.ata_atb(a, 4, 4, 4, a, 1, 1, a, 1, P.F32_BF16X3, None) == -10
+    assert L.ata_normal_solve(a, 4, 4, 4, a, 1, 1, a, 1, P.F64, -1, None, None) == -11
+    assert L.ata_normal_solve(a, 4, 4, 4, a, 1, 1, None, 1, P.F64, 0, None, None) == -8
+    assert L.ata_potrf(a, (1 << 22) + 1, P.F64, None, None) == 3  # ATA_EUNSUPPORTED
