@@ -275,6 +275,68 @@ def _tall_skinny(P, torch, dev, stream, m: int, n: int, steps: int):
     return out
 
 
+def _normal_equations(P, torch, dev, stream, C0, n: int, steps: int):
+    """Consumers of the product: the Cholesky factor of the headline's packed
+    C (n^3/3 flops counted) with a solve check, and the whole least-squares
+    chain (product, factor, A^t b, solves) on the 262144 x 2048 shape with
+    uniform[-1,1] data, checked through the normal-equation residual
+    ||A^t (A x - b)|| / (||A||_F^2 ||x||)."""
+    import synthetic
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize(dev)
+        return e0.elapsed_time(e1) / k
+
+    out = {}
+    Cw = torch.empty_like(C0)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    t_copy = timed(lambda: Cw.copy_(C0), steps)
+    t_fac = timed(lambda: (Cw.copy_(C0), P.cholesky(Cw, n, info=info, stream=stream)), steps) - t_copy
+    assert int(info.item()) == 0
+    full = torch.zeros((n, n), dtype=torch.float64, device=dev)
+    il = torch.tril_indices(n, n, device=dev)
+    full[il[0], il[1]] = C0
+    full = full + full.t() - torch.diag(torch.diagonal(full))
+    e = torch.ones(n, dtype=torch.float64, device=dev)
+    b = full.mv(e)
+    del full
+    t_solve = timed(lambda: P.cholesky_solve(Cw, b.clone(), stream=stream), steps)
+    x = P.cholesky_solve(Cw, b.clone(), stream=stream)
+    torch.cuda.synchronize(dev)
+    out["factor"] = {"n": n, "ms": t_fac, "tflops": n ** 3 / 3 / (t_fac * 1e-3) / 1e12,
+                     "frac_of_fp64_peak": n ** 3 / 3 / (t_fac * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "solve_ms_nrhs1": t_solve, "solve_max_err_vs_ones": float((x - 1.0).abs().max())}
+    _log("normal equations: factor n=%d %.2f ms (%.1f TF/s), solve %.2f ms"
+         % (n, t_fac, out["factor"]["tflops"], t_solve))
+    m, k = 262144, 2048
+    A = torch.from_numpy(synthetic.uniform(m, k, synthetic.SEED_TALL_Z)).to(dev)
+    bb = torch.from_numpy(synthetic.uniform(m, 1, synthetic.SEED_TALL_SCALES)[:, 0].copy()).to(dev)
+    t_chain = timed(lambda: P.normal_solve(A, bb, info=info, stream=stream), 3)
+    t_gram = timed(lambda: P.gram(A, stream=stream), 3)
+    t_atb = timed(lambda: P.atb(A, bb, stream=stream), 3)
+    xs = P.normal_solve(A, bb, info=info, stream=stream)
+    torch.cuda.synchronize(dev)
+    g = A.t().mv(A.mv(xs) - bb)
+    res = float(g.norm() / (torch.linalg.matrix_norm(A, "fro") ** 2 * xs.norm()))
+    out["least_squares"] = {"workload": "A %dx%d uniform[-1,1] (seed %d), b uniform (seed %d), one right-hand side"
+                                        % (m, k, synthetic.SEED_TALL_Z, synthetic.SEED_TALL_SCALES),
+                            "ms": t_chain, "gram_ms": t_gram, "atb_ms": t_atb,
+                            "atb_gbs": m * k * 8 / (t_atb * 1e-3) / 1e9, "info": int(info.item()),
+                            "normal_eq_residual": res}
+    _log("normal equations: least squares %dx%d %.2f ms (product %.2f ms, A^t b %.3f ms), residual %.1e"
+         % (m, k, t_chain, t_gram, t_atb, res))
+    del A
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,6 +359,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=5000)
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--no-tall", action="store_true")
+    ap.add_argument("--no-normal", action="store_true", help="skip the Cholesky / least-squares leg")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed steps, copy this many bytes device to device three times "
                          "(a plain copy of known size for scaling hardware byte counters)")
@@ -425,6 +488,10 @@ def main():
     if not args.no_tall:
         tall = _tall_skinny(P, torch, dev, stream, 262144, 2048, 3)
 
+    normal = None
+    if not args.no_normal:
+        normal = _normal_equations(P, torch, dev, stream, C, n, 5)
+
     cpu = None
     if not args.no_cpu:
         _log("oracle CPU baseline")
@@ -460,6 +527,7 @@ def main():
         "precision_forms": forms,
         "serving": serving,
         "tall_skinny": tall,
+        "normal_equations": normal,
         "check": {"diag_max_rel_err": diag_err},
     }
     print(json.dumps(out), flush=True)

@@ -48,35 +48,34 @@ __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ C, int64_t kb
     }
     if (t == 0) dg = d[0];
     __syncthreads();
+    // The step body is branch-free apart from the owners' part: selects keep
+    // the entries a step must not change (the LDS values they read then are
+    // stale but defined, and discarded).
     for (int j = 0; j < w; ++j) {
-        const T dj = dg;
-        const T piv = sqrt(dj);
-        const T rp = T(1) / piv;
-        if (t == 0 && !(dj > T(0)) && info) atomicCAS(info, 0, (int32_t)(kb + j + 1));
         if (l == j) {
+            const T dj = dg;
+            const T piv = sqrt(dj);
+            const T rp = T(1) / piv;
+            if (wv == 0 && !(dj > T(0)) && info) atomicCAS(info, 0, (int32_t)(kb + j + 1));
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int i = wv + 4 * q;
-                if (i > j) {
-                    d[q] *= rp;
-                    col[i] = d[q];
-                } else if (i == j) {
-                    d[q] = piv;
-                }
+                d[q] = i > j ? d[q] * rp : (i == j ? piv : d[q]);
+                col[i] = d[q];
             }
         }
         __syncthreads();
-        if (l > j && l < w) {
-            const T lj = col[l];
+        const bool act = l > j && l < w;
+        const T lj = col[l];
+        T dnext = T(0);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int i = wv + 4 * q;
-                if (i >= l) {
-                    d[q] -= col[i] * lj;
-                    if (i == j + 1 && l == j + 1) dg = d[q];
-                }
-            }
+        for (int q = 0; q < 16; ++q) {
+            const int i = wv + 4 * q;
+            const T v = d[q] - col[i] * lj;
+            d[q] = (act && i >= l) ? v : d[q];
+            dnext = i == l ? d[q] : dnext;
         }
+        if (l == j + 1 && l < w && wv == (l & 3)) dg = dnext;
         __syncthreads();
     }
 #pragma unroll
@@ -96,12 +95,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_chol_rows(T* __restrict__ C, int64_t n, int64_t kb, int w) {
     __shared__ T ld[NB * (NB + 1)];
     __shared__ T col[NB];
+    __shared__ T rcp[NB];
     const int t = threadIdx.x, l = t & 63, wv = t >> 6;
     const int64_t R0 = kb + w + (int64_t)NB * blockIdx.x;
     for (int e = t; e < NB * NB; e += 256) {
         const int row = e >> 6, c = e & 63;
         ld[row * (NB + 1) + c] = (row < w && c <= row) ? C[pidx(kb + row, kb + c)] : T(0);
     }
+    if (t < w) rcp[t] = T(1) / C[pidx(kb + t, kb + t)];
     T r[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(256) void k_chol_rows(T* __restrict__ C, int64_t n,
     __syncthreads();
     for (int j = 0; j < w; ++j) {
         if (l == j) {
-            const T rp = T(1) / ld[j * (NB + 1) + j];
+            const T rp = rcp[j];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 r[q] *= rp;
@@ -136,11 +137,15 @@ __global__ __launch_bounds__(256) void k_chol_rows(T* __restrict__ C, int64_t n,
 // ---------------------------------------------------------------------------
 // Trailing update: C[i][j] -= sum_{k < w} L[i][kb + k] L[j][kb + k] for
 // s <= j <= i < n, s = kb + w, over the 64 x 64 tiles (ti, tj), tj <= ti, of
-// the trailing lower triangle (tile from the linear workgroup index).  Both
-// panel slices are staged transposed in LDS ([k][row], row stride 68: 4 mod
-// 16 doubles, so the broadcast operand reads of the FP64 form fall on
-// distinct banks) and four waves each form a 32 x 32 quarter on MFMA; on a
-// diagonal tile the quarter above the diagonal is skipped.
+// the trailing lower triangle.  part 0 takes every tile, part 1 only the
+// first tile column (tj = 0: the next diagonal block and the rows below it),
+// part 2 the others; the tile comes from the linear workgroup index.  Each
+// wave first loads its quarter of the C tile (those loads complete under the
+// staging and the MFMAs), then both panel slices are staged transposed in
+// LDS ([k][row], row stride 68: 4 mod 16 doubles, so the broadcast operand
+// reads of the FP64 form fall on distinct banks) and four waves each form a
+// 32 x 32 quarter on MFMA; on a diagonal tile the quarter above the diagonal
+// is skipped.
 //   FP64: v_mfma_f64_4x4x4f64 with the left operand broadcast to the four
 //         blocks, a 4 x 16 x 4 product: left lane l = X[row l & 3][k l >> 4],
 //         right lane l = Y[k l >> 4][col l & 15], result lane l =
@@ -151,15 +156,30 @@ __global__ __launch_bounds__(256) void k_chol_rows(T* __restrict__ C, int64_t n,
 // ---------------------------------------------------------------------------
 constexpr int UP = NB + 4;
 
+// Row a and column c of linear index b in a lower triangle of tiles.
+__device__ __forceinline__ void tri_decode(int64_t b, int64_t& a, int64_t& c) {
+    a = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while (a * (a + 1) / 2 > b) --a;
+    while ((a + 1) * (a + 2) / 2 <= b) ++a;
+    c = b - a * (a + 1) / 2;
+}
+
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_chol_update(T* __restrict__ C, int64_t n, int64_t kb, int w, int tiles) {
+__global__ __launch_bounds__(256, 2) void k_chol_update(T* __restrict__ C, int64_t n, int64_t kb, int w, int tiles,
+                                                        int part) {
     __shared__ T Pi[NB * UP];
     __shared__ T Pj[NB * UP];
-    const int64_t b = blockIdx.x;
-    int64_t ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
-    while (ti * (ti + 1) / 2 > b) --ti;
-    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
-    const int64_t tj = b - ti * (ti + 1) / 2;
+    int64_t ti, tj;
+    if (part == 1) {
+        ti = blockIdx.x;
+        tj = 0;
+    } else if (part == 2) {
+        tri_decode(blockIdx.x, ti, tj);
+        ++ti;
+        ++tj;
+    } else {
+        tri_decode(blockIdx.x, ti, tj);
+    }
     if (ti >= tiles) return;
     const int64_t s = kb + w;
     const int64_t r0 = s + NB * ti, c0 = s + NB * tj;
@@ -167,15 +187,40 @@ __global__ __launch_bounds__(256, 2) void k_chol_update(T* __restrict__ C, int64
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wr = wv >> 1, wc = wv & 1;
-#pragma unroll 4
-    for (int e = t; e < NB * NB; e += 256) {
-        const int row = e >> 6, k = e & 63;
+    const bool active = !(diag && wr < wc);
+    // C values of this wave's quarter, in the result layout of the MFMA form
+    constexpr int NV = 16;
+    T cv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        int64_t i, j;
+        if constexpr (sizeof(T) == 8) {
+            i = r0 + 32 * wr + 4 * (v >> 1) + (lane >> 4);
+            j = c0 + 32 * wc + 16 * (v & 1) + (lane & 15);
+        } else {
+            i = r0 + 32 * wr + 16 * (v >> 3) + 4 * (lane >> 4) + (v & 3);
+            j = c0 + 32 * wc + 16 * ((v >> 2) & 1) + (lane & 15);
+        }
+        cv[v] = (active && i < n && j <= i) ? C[pidx(i, j)] : T(0);
+    }
+    // panel slices: all 32 loads of a thread in flight before the LDS stores
+    // (row (t >> 6) + 4 u, k = lane: one 512-byte row segment per wave load)
+    T pv[16], qv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int row = (t >> 6) + 4 * u;
         const int64_t gi = r0 + row, gj = c0 + row;
-        Pi[k * UP + row] = (gi < n && k < w) ? C[pidx(gi, kb + k)] : T(0);
-        if (!diag) Pj[k * UP + row] = (gj < n && k < w) ? C[pidx(gj, kb + k)] : T(0);
+        pv[u] = (gi < n && lane < w) ? C[pidx(gi, kb + lane)] : T(0);
+        qv[u] = (!diag && gj < n && lane < w) ? C[pidx(gj, kb + lane)] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int row = (t >> 6) + 4 * u;
+        Pi[lane * UP + row] = pv[u];
+        if (!diag) Pj[lane * UP + row] = qv[u];
     }
     __syncthreads();
-    if (diag && wr < wc) return;
+    if (!active) return;
     const T* Y = diag ? Pi : Pj;
     if constexpr (sizeof(T) == 8) {
         double acc[8][2];
@@ -194,16 +239,11 @@ __global__ __launch_bounds__(256, 2) void k_chol_update(T* __restrict__ C, int64
                 for (int h = 0; h < 2; ++h) acc[g][h] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[g], bb[h], acc[g][h], 0, 0, 0);
         }
 #pragma unroll
-        for (int g = 0; g < 8; ++g)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int64_t i = r0 + 32 * wr + 4 * g + (lane >> 4);
-                const int64_t j = c0 + 32 * wc + 16 * h + (lane & 15);
-                if (i < n && j <= i) {
-                    T* p = C + pidx(i, j);
-                    *p = *p - acc[g][h];
-                }
-            }
+        for (int v = 0; v < NV; ++v) {
+            const int64_t i = r0 + 32 * wr + 4 * (v >> 1) + (lane >> 4);
+            const int64_t j = c0 + 32 * wc + 16 * (v & 1) + (lane & 15);
+            if (i < n && j <= i) C[pidx(i, j)] = cv[v] - acc[v >> 1][v & 1];
+        }
     } else {
         f4_t acc[2][2];
 #pragma unroll
@@ -223,18 +263,11 @@ __global__ __launch_bounds__(256, 2) void k_chol_update(T* __restrict__ C, int64
                 for (int h = 0; h < 2; ++h) acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g], bb[h], acc[g][h], 0, 0, 0);
         }
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int64_t i = r0 + 32 * wr + 16 * g + 4 * (lane >> 4) + e;
-                    const int64_t j = c0 + 32 * wc + 16 * h + (lane & 15);
-                    if (i < n && j <= i) {
-                        T* p = C + pidx(i, j);
-                        *p = *p - acc[g][h][e];
-                    }
-                }
+        for (int v = 0; v < NV; ++v) {
+            const int64_t i = r0 + 32 * wr + 16 * (v >> 3) + 4 * (lane >> 4) + (v & 3);
+            const int64_t j = c0 + 32 * wc + 16 * ((v >> 2) & 1) + (lane & 15);
+            if (i < n && j <= i) C[pidx(i, j)] = cv[v] - acc[v >> 3][(v >> 2) & 1][v & 3];
+        }
     }
 }
 
@@ -248,13 +281,26 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 constexpr int RC = 8;  // right-hand sides per pass of the solve updates
 
-// Stage the diagonal block d (width wd) of L in LDS, row stride NB + 1.
+// Stage the diagonal block d (width wd) of L in LDS, row stride NB + 1, with
+// the reciprocal of each diagonal entry in place of the entry.
 template <typename T>
 __device__ void stage_diag(const T* __restrict__ L, int64_t d0, int wd, T* ld) {
     for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
         const int row = e >> 6, c = e & 63;
-        ld[row * (NB + 1) + c] = (row < wd && c <= row) ? L[pidx(d0 + row, d0 + c)] : T(0);
+        const T v = (row < wd && c <= row) ? L[pidx(d0 + row, d0 + c)] : T(0);
+        ld[row * (NB + 1) + c] = (c == row && row < wd) ? T(1) / v : v;
     }
+}
+
+// Value of v in lane src (uniform) for every lane, through scalar registers.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
 }
 
 // ---------------------------------------------------------------------------
@@ -264,7 +310,8 @@ __device__ void stage_diag(const T* __restrict__ L, int64_t d0, int wd, T* ld) {
 // L[block k+1+b rows][block k] Y_k from its 64 rows (one wave per row at a
 // time, lane = column of block k, wave-wide sums); workgroup 0 then solves
 // diagonal block k+1 with wave 0 (lane = row; column by column, each solved
-// value broadcast from its lane).
+// value broadcast from its lane through scalar registers and scaled by the
+// staged reciprocal of the diagonal entry).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsv_fwd(const T* __restrict__ L, int64_t n, T* __restrict__ B, int64_t nrhs,
@@ -304,8 +351,8 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const T* __restrict__ L, int64
     for (int64_t r = 0; r < nrhs; ++r) {
         T x = lane < wd ? B[(t0 + lane) * ldb + r] : T(0);
         for (int c = 0; c < wd; ++c) {
-            if (lane == c) x = x / ld[c * (NB + 1) + c];
-            const T xc = __shfl(x, c, 64);
+            const T xc = lane_bcast(x, c) * ld[c * (NB + 1) + c];
+            if (lane == c) x = xc;
             if (lane > c) x -= ld[lane * (NB + 1) + c] * xc;
         }
         if (lane < wd) B[(t0 + lane) * ldb + r] = x;
@@ -375,8 +422,8 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(const T* __restrict__ L, int64
     for (int64_t r = 0; r < nrhs; ++r) {
         T x = lane < wd ? B[(d0 + lane) * ldb + r] : T(0);
         for (int c = wd - 1; c >= 0; --c) {
-            if (lane == c) x = x / ld[c * (NB + 1) + c];
-            const T xc = __shfl(x, c, 64);
+            const T xc = lane_bcast(x, c) * ld[c * (NB + 1) + c];
+            if (lane == c) x = xc;
             if (lane < c) x -= ld[c * (NB + 1) + lane] * xc;
         }
         if (lane < wd) B[(d0 + lane) * ldb + r] = x;
@@ -426,25 +473,48 @@ __global__ __launch_bounds__(256) void k_atb_sum(const double* __restrict__ part
     out[(e / nrhs) * ldo + e % nrhs] = (T)s;
 }
 
+// Right-looking factorization.  With a helper stream s2 and two events the
+// update of block k is split: its first tile column (what block k + 1 needs)
+// runs on s, the rest on s2, so the diagonal factor and row solve of block
+// k + 1 overlap the bulk of the update.  Ordering: the rest of update k waits
+// for the row solve and first column of k (event e); the first column of
+// update k + 1 waits for the rest of update k (event f), whose tiles it
+// overlaps; s joins s2 at the end.
 template <typename T>
-hipError_t potrf_t(T* C, int64_t n, int32_t* info, hipStream_t s) {
+hipError_t potrf_t(T* C, int64_t n, int32_t* info, hipStream_t s, hipStream_t s2, hipEvent_t e, hipEvent_t f) {
+    bool rest_pending = false;
+    hipError_t err;
     for (int64_t kb = 0; kb < n; kb += NB) {
         const int w = (int)(n - kb < NB ? n - kb : NB);
         const int64_t rest = n - kb - w;
         const int64_t nrb = (rest + NB - 1) / NB;
         hipLaunchKernelGGL(k_chol_diag<T>, dim3(1), dim3(256), 0, s, C, kb, w, info);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        if (nrb > 0) {
-            hipLaunchKernelGGL(k_chol_rows<T>, dim3((unsigned)nrb), dim3(256), 0, s, C, n, kb, w);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_chol_update<T>, dim3((unsigned)(nrb * (nrb + 1) / 2)), dim3(256), 0, s, C, n, kb, w,
-                               (int)nrb);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if (nrb == 0) continue;
+        hipLaunchKernelGGL(k_chol_rows<T>, dim3((unsigned)nrb), dim3(256), 0, s, C, n, kb, w);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if (!s2 || nrb == 1) {
+            if (rest_pending) {
+                if ((err = hipStreamWaitEvent(s, f, 0)) != hipSuccess) return err;
+                rest_pending = false;
+            }
+            hipLaunchKernelGGL(k_chol_update<T>, dim3((unsigned)(nrb * (nrb + 1) / 2)), dim3(256), 0, s, C, n, kb,
+                               w, (int)nrb, 0);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+            continue;
         }
+        if (rest_pending && (err = hipStreamWaitEvent(s, f, 0)) != hipSuccess) return err;
+        hipLaunchKernelGGL(k_chol_update<T>, dim3((unsigned)nrb), dim3(256), 0, s, C, n, kb, w, (int)nrb, 1);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if ((err = hipEventRecord(e, s)) != hipSuccess) return err;
+        if ((err = hipStreamWaitEvent(s2, e, 0)) != hipSuccess) return err;
+        hipLaunchKernelGGL(k_chol_update<T>, dim3((unsigned)((nrb - 1) * nrb / 2)), dim3(256), 0, s2, C, n, kb, w,
+                           (int)nrb, 2);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if ((err = hipEventRecord(f, s2)) != hipSuccess) return err;
+        rest_pending = true;
     }
+    if (rest_pending && (err = hipStreamWaitEvent(s, f, 0)) != hipSuccess) return err;
     return hipSuccess;
 }
 
@@ -481,8 +551,9 @@ hipError_t atb_t(const T* A, int64_t m, int64_t n, int64_t lda, const T* B, int6
 
 }  // namespace
 
-hipError_t launch_potrf(bool f32, void* C, int64_t n, int32_t* info, hipStream_t s) {
-    return f32 ? potrf_t((float*)C, n, info, s) : potrf_t((double*)C, n, info, s);
+hipError_t launch_potrf(bool f32, void* C, int64_t n, int32_t* info, hipStream_t s, hipStream_t s2, hipEvent_t e,
+                        hipEvent_t f) {
+    return f32 ? potrf_t((float*)C, n, info, s, s2, e, f) : potrf_t((double*)C, n, info, s, s2, e, f);
 }
 
 hipError_t launch_potrs(bool f32, const void* L, int64_t n, void* B, int64_t nrhs, int64_t ldb, hipStream_t s) {

@@ -82,8 +82,11 @@ hipError_t launch_convert(int mode, const float* x, int64_t count, void* out0, v
 
 // Consumers of the packed product (ata_chol.hip), FP64 or FP32 throughout.
 // Cholesky factor of packed lower C in place; info (device, may be null)
-// receives the first failing column + 1 if it is still 0.
-hipError_t launch_potrf(bool f32, void* C, int64_t n, int32_t* info, hipStream_t s);
+// receives the first failing column + 1 if it is still 0.  s2 (may be null):
+// helper stream for the lookahead, with two events e and f; the work on s2 is
+// joined back into s before the call returns.
+hipError_t launch_potrf(bool f32, void* C, int64_t n, int32_t* info, hipStream_t s, hipStream_t s2, hipEvent_t e,
+                        hipEvent_t f);
 // L L^t X = B in place, B row-major n x nrhs with row stride ldb.
 hipError_t launch_potrs(bool f32, const void* L, int64_t n, void* B, int64_t nrhs, int64_t ldb, hipStream_t s);
 // out = A^t B; part holds atb_chunks(m, n) x n x nrhs doubles.

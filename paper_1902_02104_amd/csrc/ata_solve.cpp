@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "ata.h"
 #include "ata_internal.h"
@@ -25,10 +27,32 @@ int64_t max1(int64_t x) { return x > 1 ? x : 1; }
         if (_e != hipSuccess) return hip_fail(_e); \
     } while (0)
 
+// Lookahead helper of the factorization, one per device, created on first
+// use and kept until the process ends: a stream at the default priority and
+// two events.  The mutex is held while a factorization is enqueued, so calls
+// from several threads never interleave their event records.
+struct Lookahead {
+    hipStream_t s2 = nullptr;
+    hipEvent_t e = nullptr, f = nullptr;
+};
+std::mutex g_look_mu;
+std::map<int, Lookahead> g_look;
+
 int potrf_checked(void* C, int64_t n, int dtype, int32_t* info, hipStream_t s) {
     if (info) SOLVE_TRY(launch_fill_zero(info, 1, 4, s));
     if (n == 0) return ATA_OK;
-    SOLVE_TRY(launch_potrf(dtype == ATA_F32, C, n, info, s));
+    int dev = 0;
+    SOLVE_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_look_mu);
+    Lookahead& la = g_look[dev];
+    if (!la.s2) {
+        Lookahead nl;
+        SOLVE_TRY(hipStreamCreateWithFlags(&nl.s2, hipStreamNonBlocking));
+        SOLVE_TRY(hipEventCreateWithFlags(&nl.e, hipEventDisableTiming));
+        SOLVE_TRY(hipEventCreateWithFlags(&nl.f, hipEventDisableTiming));
+        la = nl;
+    }
+    SOLVE_TRY(launch_potrf(dtype == ATA_F32, C, n, info, s, la.s2, la.e, la.f));
     return ATA_OK;
 }
 
