@@ -125,6 +125,16 @@ int ata(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int dty
         int cutoff, void *stream);
 
 /*
+ * ata_aat: the companion product C_lower = lower(A A^t), m x m packed, for
+ *   the same row-major A (m x n, row stride lda >= n).  A A^t is the product
+ *   of the n x m matrix A^t with itself, so the call writes A^t into a
+ *   stream-ordered workspace (n x m elements, one pass over A) and runs ata
+ *   on it with default options; every dtype of ata is accepted.  Argument
+ *   codes as for ata (C_lower holds m (m + 1) / 2 elements).
+ */
+int ata_aat(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int dtype, int cutoff, void *stream);
+
+/*
  * ata_ex: as ata, with options and an optional caller workspace.
  *   opts       NULL for defaults
  *   workspace  device memory of ws_bytes, or NULL: the library then

@@ -97,6 +97,8 @@ def load():
     lib.ata_profile_enable.restype = ci
     lib.ata_profile_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ci]
     lib.ata_profile_collect.restype = ci
+    lib.ata_aat.argtypes = [vp, i64, i64, i64, vp, ci, ci, vp]
+    lib.ata_aat.restype = ci
     lib.ata_potrf.argtypes = [vp, i64, ci, vp, vp]
     lib.ata_potrf.restype = ci
     lib.ata_potrs.argtypes = [vp, i64, vp, i64, i64, ci, vp]
@@ -252,6 +254,35 @@ def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_d
                         ctypes.c_void_p(ws_ptr) if ws_ptr else None, ws_bytes)
     if rc:
         raise AtaError(rc, "ata_ex")
+    return out
+
+
+def gram_rows(A, cutoff: int = 0, dtype: int | None = None, out=None, stream=None):
+    """Packed lower triangle of the companion product A A^t (m x m) for a 2-D
+    device tensor A, through the product of A^t with itself (ata_aat)."""
+    import torch
+    lib = load()
+    if A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor")
+    m, n = A.shape
+    if n > 0 and m > 0 and A.stride(1) != 1:
+        raise ValueError("A needs unit column stride")
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    if dtype is None:
+        dtype = F64 if A.dtype == torch.float64 else F32
+    want_in = torch.float64 if (dtype & 0xff) == F64 else torch.float32
+    if A.dtype != want_in:
+        raise TypeError("A must be %s for dtype %#x" % (want_in, dtype))
+    out_t = torch.float64 if ((dtype & 0xff) == F64 or dtype & OUT_F64) else torch.float32
+    if out is None:
+        out = torch.empty(tri(m), dtype=out_t, device=A.device)
+    elif out.dtype != out_t or out.numel() < tri(m) or not out.is_contiguous():
+        raise ValueError("bad output tensor")
+    with torch.cuda.device(A.device):
+        rc = lib.ata_aat(ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.c_void_p(out.data_ptr()), int(dtype),
+                         int(cutoff), _stream_handle(stream))
+    if rc:
+        raise AtaError(rc, "ata_aat")
     return out
 
 

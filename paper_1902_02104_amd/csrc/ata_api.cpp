@@ -642,6 +642,39 @@ int ata(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int dty
     return ata_ex(A, m, n, lda, C_lower, dtype, cutoff, stream, nullptr, nullptr, 0);
 }
 
+int ata_aat(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int dtype, int cutoff, void* stream) {
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (!dtype_valid(dtype)) return -6;
+    if (cutoff < 0) return -7;
+    if (m > 0 && n > 0 && !A) return -1;
+    if (m > 0 && !C_lower) return -5;
+    const int eb = elem_bytes_in(dtype);
+    if ((uintptr_t)A % eb) return -1;
+    if ((uintptr_t)C_lower % elem_bytes_out(dtype)) return -5;
+    if ((m + 63) / 64 > 65535 || n > INT32_MAX) return ATA_EUNSUPPORTED;
+    if (!current_device_ok()) return ATA_EUNSUPPORTED;
+    if (m == 0) return ATA_OK;
+    hipStream_t s = (hipStream_t)stream;
+    void* At = nullptr;
+    if (n > 0) {
+        HIP_TRY(hipMallocAsync(&At, (size_t)n * (size_t)m * eb, s));
+        const hipError_t e = launch_transpose(eb, A, m, n, lda, At, s);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(At, s);
+            return hip_fail(e);
+        }
+    }
+    // A A^t is the product of the n x m matrix A^t with itself: C = (A^t)^t A^t
+    int rc = ata_ex(At, n, m, m, C_lower, dtype, cutoff, stream, nullptr, nullptr, 0);
+    if (At) {
+        const hipError_t e2 = hipFreeAsync(At, s);
+        if (rc == ATA_OK && e2 != hipSuccess) rc = hip_fail(e2);
+    }
+    return rc;
+}
+
 int ata_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;

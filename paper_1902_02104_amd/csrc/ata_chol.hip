@@ -1,7 +1,8 @@
 // Consumers of the packed product on gfx950: the Cholesky factor of the
 // packed lower C, the two triangular solves with it, and the right-hand side
 // A^t b of the normal equations (Section 1 names least squares through the
-// normal equations as a use of A^t A).
+// normal equations as a use of A^t A); and the transpose that gives the
+// companion product A A^t.
 //
 // Storage: row-major packed lower triangle, element (i, j), j <= i, at
 // i (i + 1) / 2 + j, so a row's entries left of the diagonal are contiguous.
@@ -549,7 +550,44 @@ hipError_t atb_t(const T* A, int64_t m, int64_t n, int64_t lda, const T* B, int6
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Transpose for the companion product A A^t: out (n x m, row stride m) =
+// A^t for A (m x n, row stride lda), 64 x 64 tiles through LDS so that both
+// the reads of A's rows and the writes of out's rows are contiguous.
+// E: element type of 4 or 8 bytes (moved as raw bits).
+// ---------------------------------------------------------------------------
+template <typename E>
+__global__ __launch_bounds__(256) void k_transpose(const E* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                                   E* __restrict__ out) {
+    __shared__ E tile[64][65];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int r = wv + 4 * u;
+        if (r0 + r < m && c0 + lane < n) tile[r][lane] = A[(r0 + r) * lda + c0 + lane];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = wv + 4 * u;
+        if (c0 + c < n && r0 + lane < m) out[(c0 + c) * m + r0 + lane] = tile[lane][c];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_transpose(int elem_bytes, const void* A, int64_t m, int64_t n, int64_t lda, void* out,
+                            hipStream_t s) {
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 63) / 64));
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_transpose<uint64_t>, grid, dim3(256), 0, s, (const uint64_t*)A, m, n, lda,
+                           (uint64_t*)out);
+    else
+        hipLaunchKernelGGL(k_transpose<uint32_t>, grid, dim3(256), 0, s, (const uint32_t*)A, m, n, lda,
+                           (uint32_t*)out);
+    return hipGetLastError();
+}
 
 hipError_t launch_potrf(bool f32, void* C, int64_t n, int32_t* info, hipStream_t s, hipStream_t s2, hipEvent_t e,
                         hipEvent_t f) {

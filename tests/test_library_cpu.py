@@ -205,3 +205,19 @@ def test_normal_equation_argument_validation_without_gpu(lib):
     assert L.ata_normal_solve(a, 4, 4, 4, a, 1, 1, a, 1, P.F64, -1, None, None) == -11
     assert L.ata_normal_solve(a, 4, 4, 4, a, 1, 1, None, 1, P.F64, 0, None, None) == -8
     assert L.ata_potrf(a, (1 << 22) + 1, P.F64, None, None) == 3  # ATA_EUNSUPPORTED
+
+
+def test_aat_argument_validation_without_gpu(lib):
+    L = P.load()
+    vp = ctypes.c_void_p
+    buf = (ctypes.c_double * 64)()
+    a = ctypes.cast(buf, vp)
+    assert L.ata_aat(a, -1, 4, 4, a, P.F64, 0, None) == -2
+    assert L.ata_aat(a, 4, -1, 4, a, P.F64, 0, None) == -3
+    assert L.ata_aat(a, 4, 4, 3, a, P.F64, 0, None) == -4
+    assert L.ata_aat(None, 4, 4, 4, a, P.F64, 0, None) == -1
+    assert L.ata_aat(a, 4, 4, 4, None, P.F64, 0, None) == -5
+    assert L.ata_aat(a, 4, 4, 4, a, 7, 0, None) == -6
+    assert L.ata_aat(a, 4, 4, 4, a, P.F64, -1, None) == -7
+    mis = ctypes.c_void_p(ctypes.addressof(buf) + 4)
+    assert L.ata_aat(mis, 4, 4, 4, a, P.F64, 0, None) == -1
