@@ -26,20 +26,38 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int64_t pidx(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
 
+// Value of v in lane src (uniform) for every lane, through scalar registers.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+
+// Orders the LDS accesses of one wave (no instruction needed: a wave's LDS
+// operations complete in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
 // ---------------------------------------------------------------------------
 // Diagonal block of the factorization at block column kb (width w <= 64), one
 // workgroup, in place.  Thread t owns column l = t & 63 and rows
-// i = (t >> 6) + 4 q (q < 16) of the block.  Column j of the step is scaled by
-// its owners (times 1 / pivot, as LAPACK's unblocked factor does) and
-// broadcast through LDS; every thread then applies the rank-one update to the
-// entries it owns (right-looking, unblocked).  A pivot that is not positive is
-// reported once through `info` (first failing column + 1, LAPACK's
-// convention); the factorization carries on with the resulting NaNs.
+// i = (t >> 6) + 4 q (q < 16) of the block, and keeps a running copy of its
+// column's diagonal entry (updated by the same operation as the entry
+// itself), so the owners of step j take the pivot from their own copy.
+// Step j: the owners scale column j by 1 / pivot (as LAPACK's unblocked
+// factor does) and publish it in LDS; after one barrier every thread applies
+// the rank-one update to its entries with selects.  The column buffer
+// alternates between two halves by step parity: the barrier of step j + 1
+// separates the reads of step j from the writes of step j + 2.  A pivot that
+// is not positive is reported once through `info` (first failing column + 1,
+// LAPACK's convention); the factorization carries on with the resulting NaNs.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ C, int64_t kb, int w, int32_t* __restrict__ info) {
-    __shared__ T col[NB];
-    __shared__ T dg;
+    __shared__ T col[2][NB];
     const int t = threadIdx.x, l = t & 63, wv = t >> 6;
     T d[16];
 #pragma unroll
@@ -47,37 +65,30 @@ __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ C, int64_t kb
         const int i = wv + 4 * q;
         d[q] = (i < w && l <= i) ? C[pidx(kb + i, kb + l)] : T(0);
     }
-    if (t == 0) dg = d[0];
-    __syncthreads();
-    // The step body is branch-free apart from the owners' part: selects keep
-    // the entries a step must not change (the LDS values they read then are
-    // stale but defined, and discarded).
+    T dd = l < w ? C[pidx(kb + l, kb + l)] : T(1);
     for (int j = 0; j < w; ++j) {
+        T* cb = col[j & 1];
         if (l == j) {
-            const T dj = dg;
-            const T piv = sqrt(dj);
+            const T piv = sqrt(dd);
             const T rp = T(1) / piv;
-            if (wv == 0 && !(dj > T(0)) && info) atomicCAS(info, 0, (int32_t)(kb + j + 1));
+            if (wv == 0 && !(dd > T(0)) && info) atomicCAS(info, 0, (int32_t)(kb + j + 1));
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int i = wv + 4 * q;
                 d[q] = i > j ? d[q] * rp : (i == j ? piv : d[q]);
-                col[i] = d[q];
+                cb[i] = d[q];
             }
         }
         __syncthreads();
         const bool act = l > j && l < w;
-        const T lj = col[l];
-        T dnext = T(0);
+        const T lj = cb[l];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int i = wv + 4 * q;
-            const T v = d[q] - col[i] * lj;
+            const T v = d[q] - cb[i] * lj;
             d[q] = (act && i >= l) ? v : d[q];
-            dnext = i == l ? d[q] : dnext;
         }
-        if (l == j + 1 && l < w && wv == (l & 3)) dg = dnext;
-        __syncthreads();
+        if (act) dd -= lj * lj;
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -89,8 +100,9 @@ __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ C, int64_t kb
 // ---------------------------------------------------------------------------
 // Rows below the diagonal block: L21 = C21 L11^-t for rows
 // R0 = kb + w + 64 b ... R0 + 63 (workgroup b), with the factored L11 staged
-// in LDS.  Same ownership and step order as the diagonal block, so an entry
-// sees the same operations as if it had been factored with it.
+// in LDS.  Thread t owns column l = t & 63 and rows i = (t >> 6) + 4 q; each
+// step scales column j (times the staged 1 / L11[j][j]) and subtracts its
+// multiples from the later columns, the order the diagonal block uses.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_chol_rows(T* __restrict__ C, int64_t n, int64_t kb, int w) {
@@ -111,6 +123,9 @@ __global__ __launch_bounds__(256) void k_chol_rows(T* __restrict__ C, int64_t n,
         r[q] = (R0 + i < n && l < w) ? C[pidx(R0 + i, kb + l)] : T(0);
     }
     __syncthreads();
+    // The rows of a wave (i = wv + 4 q) depend only on each other and on L11,
+    // and the column entries col[wv + 4 q] are written and read by that wave
+    // alone: the steps need wave-level ordering only.
     for (int j = 0; j < w; ++j) {
         if (l == j) {
             const T rp = rcp[j];
@@ -120,13 +135,13 @@ __global__ __launch_bounds__(256) void k_chol_rows(T* __restrict__ C, int64_t n,
                 col[wv + 4 * q] = r[q];
             }
         }
-        __syncthreads();
+        wave_lds_fence();
         if (l > j && l < w) {
             const T lj = ld[l * (NB + 1) + j];
 #pragma unroll
             for (int q = 0; q < 16; ++q) r[q] -= col[wv + 4 * q] * lj;
         }
-        __syncthreads();
+        wave_lds_fence();
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -291,17 +306,6 @@ __device__ void stage_diag(const T* __restrict__ L, int64_t d0, int wd, T* ld) {
         const T v = (row < wd && c <= row) ? L[pidx(d0 + row, d0 + c)] : T(0);
         ld[row * (NB + 1) + c] = (c == row && row < wd) ? T(1) / v : v;
     }
-}
-
-// Value of v in lane src (uniform) for every lane, through scalar registers.
-__device__ __forceinline__ double lane_bcast(double v, int src) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ float lane_bcast(float v, int src) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
 }
 
 // ---------------------------------------------------------------------------
