@@ -736,6 +736,7 @@ void ata_release_caches(void) {
     }
     (void)hipSetDevice(cur);
     g_plans.clear();
+    release_lookahead();
 }
 
 }  // extern "C"

@@ -51,6 +51,7 @@ struct WsLayout {
 int hip_fail(hipError_t e);
 int check_device(int dev);       // caller holds the library mutex
 int current_device_ok();         // the current device is gfx950 (locks)
+void release_lookahead();        // helper streams of the Cholesky factor (waits for their devices)
 bool dtype_lp(int dtype);
 int elem_bytes_in(int dtype);
 int elem_bytes_out(int dtype);

@@ -28,8 +28,8 @@ int64_t max1(int64_t x) { return x > 1 ? x : 1; }
     } while (0)
 
 // Lookahead helper of the factorization, one per device, created on first
-// use and kept until the process ends: a stream at the default priority and
-// two events.  The mutex is held while a factorization is enqueued, so calls
+// use and kept until ata_release_caches or the end of the process: a stream
+// at the default priority and two events.  The mutex is held while a factorization is enqueued, so calls
 // from several threads never interleave their event records.
 struct Lookahead {
     hipStream_t s2 = nullptr;
@@ -69,6 +69,22 @@ int atb_checked(const void* A, int64_t m, int64_t n, int64_t lda, const void* B,
 }
 
 }  // namespace
+
+void atalib::detail::release_lookahead() {
+    std::lock_guard<std::mutex> lk(g_look_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_look) {
+        if (!kv.second.s2) continue;
+        (void)hipSetDevice(kv.first);
+        (void)hipDeviceSynchronize();
+        (void)hipEventDestroy(kv.second.e);
+        (void)hipEventDestroy(kv.second.f);
+        (void)hipStreamDestroy(kv.second.s2);
+    }
+    g_look.clear();
+    (void)hipSetDevice(cur);
+}
 
 extern "C" {
 

@@ -233,3 +233,18 @@ def test_edges(env, orc):
     assert float(C.item()) == 2.0
     with pytest.raises(TypeError):
         P.cholesky_solve(C, torch.zeros(1, dtype=torch.float32, device="cuda"))
+
+
+def test_factor_after_releasing_caches(env, orc):
+    """The lookahead stream of the factor is released with the other caches
+    and created again on the next call."""
+    torch, P = env
+    _say("case: potrf around release_caches")
+    n = 200
+    Cp, L0 = _exact_case(orc, n, 77)
+    for _ in range(2):
+        C = _dev(torch, Cp, torch.float64)
+        P.cholesky(C, n)
+        torch.cuda.synchronize()
+        assert np.array_equal(C.cpu().numpy(), orc.pack(L0))
+        P.release_caches()
