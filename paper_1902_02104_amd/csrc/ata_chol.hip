@@ -58,6 +58,9 @@ __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOM
 template <typename T>
 __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ C, int64_t kb, int w, int32_t* __restrict__ info) {
     __shared__ T col[2][NB];
+    // on the critical path while the helper stream's update fills the CUs:
+    // raise this wave's issue priority on its SIMD
+    __builtin_amdgcn_s_setprio(3);
     const int t = threadIdx.x, l = t & 63, wv = t >> 6;
     T d[16];
 #pragma unroll
@@ -109,6 +112,7 @@ __global__ __launch_bounds__(256) void k_chol_rows(T* __restrict__ C, int64_t n,
     __shared__ T ld[NB * (NB + 1)];
     __shared__ T col[NB];
     __shared__ T rcp[NB];
+    __builtin_amdgcn_s_setprio(3);  // critical path, as in k_chol_diag
     const int t = threadIdx.x, l = t & 63, wv = t >> 6;
     const int64_t R0 = kb + w + (int64_t)NB * blockIdx.x;
     for (int e = t; e < NB * NB; e += 256) {
