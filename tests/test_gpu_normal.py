@@ -248,3 +248,70 @@ def test_factor_after_releasing_caches(env, orc):
         torch.cuda.synchronize()
         assert np.array_equal(C.cpu().numpy(), orc.pack(L0))
         P.release_caches()
+
+
+def test_factor_full_order_of_least_squares_shape(env, orc):
+    """The factor at the order of the least-squares shape's product (2048
+    columns, 8192 rows here), element by element against the oracle's factor
+    of the oracle's product, within the perturbation bound."""
+    torch, P = env
+    m, n = 8192, 2048
+    _say("case: potrf full order n=%d" % n)
+    A = synthetic.uniform(m, n, 51)
+    Cp = orc.classical_mt(A, threads=16)
+    ref, info = orc.potrf(Cp, n)
+    assert info == 0
+    C = _dev(torch, Cp, torch.float64)
+    info_t = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    P.cholesky(C, n, info=info_t)
+    torch.cuda.synchronize()
+    assert int(info_t.item()) == 0
+    got = C.cpu().numpy()
+    Lr = orc.unpack(ref, n)
+    err = float(np.linalg.norm(got - ref)) / float(np.linalg.norm(np.tril(Lr), 2))
+    tol = 4 * (n + 1) * U64 * _kappa(orc, Cp, n)
+    _say("   rel err %.3e tol %.3e" % (err, tol))
+    assert err <= tol
+
+
+def test_atb_full_least_squares_size_exact(env):
+    """A^t B at the full least-squares shape (262144 x 2048, the launch
+    configuration the benchmark times), through properties exact at any size:
+    with integer A, B = [e_k, ones] must give row k of A and the column sums
+    (checked in int64).  A is drawn on the device from a seeded generator."""
+    torch, P = env
+    m, n, k = 262144, 2048, 123457
+    _say("case: atb full size %dx%d" % (m, n))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(61)
+    Ai = torch.randint(-3, 4, (m, n), generator=g, device="cuda", dtype=torch.int64)
+    A = Ai.double()
+    B = torch.zeros((m, 2), dtype=torch.float64, device="cuda")
+    B[k, 0] = 1.0
+    B[:, 1] = 1.0
+    out = P.atb(A, B)
+    torch.cuda.synchronize()
+    assert torch.equal(out[:, 0], A[k])
+    assert torch.equal(out[:, 1].long(), Ai.sum(0))
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_factor_and_solve_full_order_exact(env, orc, f32):
+    """Factor and solve at the full order of the least-squares product (2048),
+    on the exactly factorable integer case: bit-exact against the oracle."""
+    torch, P = env
+    dt = torch.float32 if f32 else torch.float64
+    n, r = 2048, 2
+    _say("case: potrf + potrs exact n=%d f32=%s" % (n, f32))
+    Cp, L0 = _exact_case(orc, n, 71)
+    ref, info = orc.potrf(Cp, n)
+    assert info == 0 and np.array_equal(ref, orc.pack(L0))
+    X0 = synthetic.integer(n, r, 72)
+    Bn = orc.unpack(Cp, n) @ X0  # exact
+    C = _dev(torch, Cp, dt)
+    P.cholesky(C, n)
+    B = _dev(torch, Bn, dt)
+    P.cholesky_solve(C, B, n)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().double().numpy(), ref)
+    assert np.array_equal(B.cpu().double().numpy(), X0)
