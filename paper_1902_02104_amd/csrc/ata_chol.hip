@@ -332,6 +332,13 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const T* __restrict__ L, int64
     const int64_t t0 = NB * tb;
     if (k >= 0) {
         const int64_t y0 = NB * k;
+        // this wave's 16 rows of L[.][block k], all loads in flight at once
+        T lv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int64_t i = t0 + wv + 4 * u;
+            lv[u] = i < n ? L[pidx(i, y0 + lane)] : T(0);
+        }
         for (int64_t r0 = 0; r0 < nrhs; r0 += RC) {
             const int rc = (int)(nrhs - r0 < RC ? nrhs - r0 : RC);
             __syncthreads();
@@ -340,13 +347,13 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const T* __restrict__ L, int64
                 ys[e] = rr < rc ? B[(y0 + c) * ldb + r0 + rr] : T(0);
             }
             __syncthreads();
-            for (int q = wv; q < NB; q += 4) {
-                const int64_t i = t0 + q;
-                if (i >= n) break;
-                const T lv = L[pidx(i, y0 + lane)];
-                for (int rr = 0; rr < rc; ++rr) {
-                    const T s = wave_sum(lv * ys[lane * RC + rr]);
-                    if (lane == 0) B[i * ldb + r0 + rr] -= s;
+            for (int rr = 0; rr < rc; ++rr) {
+                const T y = ys[lane * RC + rr];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int64_t i = t0 + wv + 4 * u;
+                    const T s = wave_sum(lv[u] * y);
+                    if (lane == 0 && i < n) B[i * ldb + r0 + rr] -= s;
                 }
             }
         }
@@ -390,6 +397,13 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(const T* __restrict__ L, int64
         const int wk = (int)(n - x0 < NB ? n - x0 : NB);
         const int64_t tb = k - 1 - blockIdx.x;
         const int64_t c0 = NB * tb;
+        // this wave's 16 rows of L[block k][block tb], all loads in flight at once
+        T lv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int j = wv + 4 * u;
+            lv[u] = j < wk ? L[pidx(x0 + j, c0 + lane)] : T(0);
+        }
         for (int64_t r0 = 0; r0 < nrhs; r0 += RC) {
             const int rc = (int)(nrhs - r0 < RC ? nrhs - r0 : RC);
             __syncthreads();
@@ -401,10 +415,11 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(const T* __restrict__ L, int64
             T acc[RC];
 #pragma unroll
             for (int rr = 0; rr < RC; ++rr) acc[rr] = T(0);
-            for (int j = wv; j < wk; j += 4) {
-                const T lv = L[pidx(x0 + j, c0 + lane)];
 #pragma unroll
-                for (int rr = 0; rr < RC; ++rr) acc[rr] += lv * xs[j * RC + rr];
+            for (int u = 0; u < 16; ++u) {
+                const int j = wv + 4 * u;  // xs rows past wk hold zeros
+#pragma unroll
+                for (int rr = 0; rr < RC; ++rr) acc[rr] += lv[u] * xs[j * RC + rr];
             }
 #pragma unroll
             for (int rr = 0; rr < RC; ++rr) red[(wv * NB + lane) * RC + rr] = acc[rr];
