@@ -321,7 +321,8 @@ int ata_server_destroy(ata_server *srv);
  * the storage of ata's output (row-major packed lower triangle), on device
  * memory, asynchronously on `stream`, in FP64 (dtype ATA_F64) or FP32
  * (ATA_F32) arithmetic and storage throughout.  Return codes as above:
- * -k for an invalid k-th argument, ATA_EUNSUPPORTED for another device or
+ * -k for an invalid k-th argument (a null pointer where data is needed, or a
+ * pointer not aligned to its element), ATA_EUNSUPPORTED for another device or
  * n > 2^22.
  *
  * ata_potrf: Cholesky factor of the symmetric positive definite matrix in

@@ -21,6 +21,9 @@ bool solve_dtype(int dtype) { return dtype == ATA_F64 || dtype == ATA_F32; }
 
 int64_t max1(int64_t x) { return x > 1 ? x : 1; }
 
+// A device pointer must be aligned to its element (4 or 8 bytes).
+bool misaligned(const void* p, int dtype) { return (uintptr_t)p % (dtype == ATA_F32 ? 4 : 8) != 0; }
+
 #define SOLVE_TRY(expr)                            \
     do {                                           \
         hipError_t _e = (expr);                    \
@@ -92,6 +95,8 @@ int ata_potrf(void* C_lower, int64_t n, int dtype, int32_t* info, void* stream) 
     if (n < 0) return -2;
     if (n > 0 && !C_lower) return -1;
     if (!solve_dtype(dtype)) return -3;
+    if (misaligned(C_lower, dtype)) return -1;
+    if ((uintptr_t)info % 4) return -4;
     if (n > kMaxOrder) return ATA_EUNSUPPORTED;
     if (!current_device_ok()) return ATA_EUNSUPPORTED;
     return potrf_checked(C_lower, n, dtype, info, (hipStream_t)stream);
@@ -104,6 +109,8 @@ int ata_potrs(const void* L_lower, int64_t n, void* B, int64_t nrhs, int64_t ldb
     if (n > 0 && nrhs > 0 && !B) return -3;
     if (ldb < max1(nrhs)) return -5;
     if (!solve_dtype(dtype)) return -6;
+    if (misaligned(L_lower, dtype)) return -1;
+    if (misaligned(B, dtype)) return -3;
     if (n > kMaxOrder) return ATA_EUNSUPPORTED;
     if (!current_device_ok()) return ATA_EUNSUPPORTED;
     if (n == 0 || nrhs == 0) return ATA_OK;
@@ -123,6 +130,9 @@ int ata_atb(const void* A, int64_t m, int64_t n, int64_t lda, const void* B, int
     if (m > 0 && nrhs > 0 && !B) return -5;
     if (n > 0 && nrhs > 0 && !out) return -8;
     if (!solve_dtype(dtype)) return -10;
+    if (misaligned(A, dtype)) return -1;
+    if (misaligned(B, dtype)) return -5;
+    if (misaligned(out, dtype)) return -8;
     if (!current_device_ok()) return ATA_EUNSUPPORTED;
     return atb_checked(A, m, n, lda, B, nrhs, ldb, out, ldo, dtype, (hipStream_t)stream);
 }
@@ -140,6 +150,10 @@ int ata_normal_solve(const void* A, int64_t m, int64_t n, int64_t lda, const voi
     if (n > 0 && nrhs > 0 && !X) return -8;
     if (!solve_dtype(dtype)) return -10;
     if (cutoff < 0) return -11;
+    if (misaligned(A, dtype)) return -1;
+    if (misaligned(B, dtype)) return -5;
+    if (misaligned(X, dtype)) return -8;
+    if ((uintptr_t)info % 4) return -12;
     if (n > kMaxOrder) return ATA_EUNSUPPORTED;
     if (!current_device_ok()) return ATA_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;

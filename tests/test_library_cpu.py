@@ -205,6 +205,12 @@ def test_normal_equation_argument_validation_without_gpu(lib):
     assert L.ata_normal_solve(a, 4, 4, 4, a, 1, 1, a, 1, P.F64, -1, None, None) == -11
     assert L.ata_normal_solve(a, 4, 4, 4, a, 1, 1, None, 1, P.F64, 0, None, None) == -8
     assert L.ata_potrf(a, (1 << 22) + 1, P.F64, None, None) == 3  # ATA_EUNSUPPORTED
+    mis = ctypes.c_void_p(ctypes.addressof(buf) + 4)
+    assert L.ata_potrf(mis, 4, P.F64, None, None) == -1
+    assert L.ata_potrf(a, 4, P.F64, ctypes.c_void_p(ctypes.addressof(buf) + 2), None) == -4
+    assert L.ata_potrs(a, 4, mis, 1, 1, P.F64, None) == -3
+    assert L.ata_atb(a, 4, 4, 4, a, 1, 1, mis, 1, P.F64, None) == -8
+    assert L.ata_normal_solve(mis, 4, 4, 4, a, 1, 1, a, 1, P.F64, 0, None, None) == -1
 
 
 def test_aat_argument_validation_without_gpu(lib):
