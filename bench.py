@@ -311,7 +311,27 @@ def _normal_equations(P, torch, dev, stream, C0, n: int, steps: int):
     t_solve = timed(lambda: P.cholesky_solve(Cw, b.clone(), stream=stream), steps)
     x = P.cholesky_solve(Cw, b.clone(), stream=stream)
     torch.cuda.synchronize(dev)
-    out["factor"] = {"n": n, "ms": t_fac, "tflops": n ** 3 / 3 / (t_fac * 1e-3) / 1e12,
+    # the update kernel, timed by events on its own launch streams: C is read
+    # and written once per trailing lower entry (16 B) for 2 w flops
+    P.profile_enable(True)
+    P.profile_collect()
+    for _ in range(steps):
+        Cw.copy_(C0)
+        P.cholesky(Cw, n, info=info, stream=stream)
+    torch.cuda.synchronize(dev)
+    prof = P.profile_collect()
+    P.profile_enable(False)
+    upd_ms, upd_launches = prof["factor_update"]
+    entries = sum((n - kb - min(64, n - kb)) * (n - kb - min(64, n - kb) + 1) // 2 for kb in range(0, n, 64))
+    upd_bytes = 16.0 * entries * steps
+    achieved = upd_bytes / (upd_ms * 1e-3) / 1e9
+    roof_fac = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_chol_update_f64",
+                "algorithmic_bytes_per_launch": upd_bytes / max(upd_launches, 1),
+                "avg_launch_ms": upd_ms / max(upd_launches, 1),
+                "mfma_tflops": 2 * 64 * entries * steps / (upd_ms * 1e-3) / 1e12,
+                "panel_ms_per_factor": prof["factor_panel"][0] / steps}
+    out["factor"] = {"n": n, "ms": t_fac, "tflops": n ** 3 / 3 / (t_fac * 1e-3) / 1e12, "roofline": roof_fac,
                      "frac_of_fp64_peak": n ** 3 / 3 / (t_fac * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                      "solve_ms_nrhs1": t_solve, "solve_max_err_vs_ones": float((x - 1.0).abs().max())}
     _log("normal equations: factor n=%d %.2f ms (%.1f TF/s), solve %.2f ms"

@@ -222,7 +222,10 @@ void ata_release_caches(void);
 #define ATA_KERNEL_SYRK 2     /* diagonal base-case tiles */
 #define ATA_KERNEL_COMBINE 3  /* workspace combinations */
 #define ATA_KERNEL_OTHER 4    /* fills and conversions */
-#define ATA_KERNEL_KINDS 5
+#define ATA_KERNEL_FACTOR_PANEL 5  /* Cholesky diagonal blocks and row solves */
+#define ATA_KERNEL_FACTOR_UPDATE 6 /* Cholesky trailing updates */
+#define ATA_KERNEL_SOLVE 7         /* triangular solves and A^t B */
+#define ATA_KERNEL_KINDS 8
 int ata_profile_enable(int on);
 int ata_profile_collect(double *ms, int64_t *launches, int kinds);
 

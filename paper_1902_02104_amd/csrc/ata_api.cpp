@@ -316,38 +316,10 @@ void fork_put(int dev, const ForkCtx& c) {
     g_fork_pool[dev].push_back(c);
 }
 
-// ---- kernel timing (measurement tools only) ----
-struct ProfRec {
-    int kind;
-    hipEvent_t a, b;
-};
+// ---- kernel timing (measurement tools only; ProfScope in ata_internal.h) ----
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
-
-// Brackets one launch with events when profiling is on.
-struct ProfScope {
-    int kind;
-    hipStream_t s;
-    hipEvent_t a = nullptr, b = nullptr;
-    bool on = false;
-    ProfScope(int k, hipStream_t st) : kind(k), s(st) {
-        {
-            std::lock_guard<std::mutex> lk(g_prof_mu);
-            on = g_prof_on;
-        }
-        if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
-            (void)hipEventRecord(a, s);
-        else
-            on = false;
-    }
-    ~ProfScope() {
-        if (!on) return;
-        (void)hipEventRecord(b, s);
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        g_prof.push_back(ProfRec{kind, a, b});
-    }
-};
 
 int common_checks(const void* A, int64_t m, int64_t n, int64_t lda, const void* C, int dtype, int cutoff) {
     if (m < 0) return -2;

@@ -14,11 +14,15 @@
 
 #include <cstdint>
 
+#include "ata.h"
+#include "ata_internal.h"
 #include "ata_kernels.h"
 
 namespace atalib {
 
 namespace {
+
+using detail::ProfScope;
 
 constexpr int NB = 64;  // block width of the factorization and the solves
 
@@ -512,29 +516,42 @@ hipError_t potrf_t(T* C, int64_t n, int32_t* info, hipStream_t s, hipStream_t s2
         const int w = (int)(n - kb < NB ? n - kb : NB);
         const int64_t rest = n - kb - w;
         const int64_t nrb = (rest + NB - 1) / NB;
-        hipLaunchKernelGGL(k_chol_diag<T>, dim3(1), dim3(256), 0, s, C, kb, w, info);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
+        {
+            ProfScope ps(ATA_KERNEL_FACTOR_PANEL, s);
+            hipLaunchKernelGGL(k_chol_diag<T>, dim3(1), dim3(256), 0, s, C, kb, w, info);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
         if (nrb == 0) continue;
-        hipLaunchKernelGGL(k_chol_rows<T>, dim3((unsigned)nrb), dim3(256), 0, s, C, n, kb, w);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
+        {
+            ProfScope ps(ATA_KERNEL_FACTOR_PANEL, s);
+            hipLaunchKernelGGL(k_chol_rows<T>, dim3((unsigned)nrb), dim3(256), 0, s, C, n, kb, w);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
         if (!s2 || nrb == 1) {
             if (rest_pending) {
                 if ((err = hipStreamWaitEvent(s, f, 0)) != hipSuccess) return err;
                 rest_pending = false;
             }
+            ProfScope ps(ATA_KERNEL_FACTOR_UPDATE, s);
             hipLaunchKernelGGL(k_chol_update<T>, dim3((unsigned)(nrb * (nrb + 1) / 2)), dim3(256), 0, s, C, n, kb,
                                w, (int)nrb, 0);
             if ((err = hipGetLastError()) != hipSuccess) return err;
             continue;
         }
         if (rest_pending && (err = hipStreamWaitEvent(s, f, 0)) != hipSuccess) return err;
-        hipLaunchKernelGGL(k_chol_update<T>, dim3((unsigned)nrb), dim3(256), 0, s, C, n, kb, w, (int)nrb, 1);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
+        {
+            ProfScope ps(ATA_KERNEL_FACTOR_UPDATE, s);
+            hipLaunchKernelGGL(k_chol_update<T>, dim3((unsigned)nrb), dim3(256), 0, s, C, n, kb, w, (int)nrb, 1);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
         if ((err = hipEventRecord(e, s)) != hipSuccess) return err;
         if ((err = hipStreamWaitEvent(s2, e, 0)) != hipSuccess) return err;
-        hipLaunchKernelGGL(k_chol_update<T>, dim3((unsigned)((nrb - 1) * nrb / 2)), dim3(256), 0, s2, C, n, kb, w,
-                           (int)nrb, 2);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
+        {
+            ProfScope ps(ATA_KERNEL_FACTOR_UPDATE, s2);
+            hipLaunchKernelGGL(k_chol_update<T>, dim3((unsigned)((nrb - 1) * nrb / 2)), dim3(256), 0, s2, C, n, kb,
+                               w, (int)nrb, 2);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
         if ((err = hipEventRecord(f, s2)) != hipSuccess) return err;
         rest_pending = true;
     }
@@ -547,12 +564,14 @@ hipError_t potrs_t(const T* L, int64_t n, T* B, int64_t nrhs, int64_t ldb, hipSt
     const int64_t nblk = (n + NB - 1) / NB;
     for (int64_t k = -1; k < nblk - 1; ++k) {
         const int64_t grid = k < 0 ? 1 : nblk - k - 1;
+        ProfScope ps(ATA_KERNEL_SOLVE, s);
         hipLaunchKernelGGL(k_trsv_fwd<T>, dim3((unsigned)grid), dim3(256), 0, s, L, n, B, nrhs, ldb, k);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     for (int64_t k = nblk; k >= 1; --k) {
         const int64_t grid = k == nblk ? 1 : k;
+        ProfScope ps(ATA_KERNEL_SOLVE, s);
         hipLaunchKernelGGL(k_trsv_bwd<T>, dim3((unsigned)grid), dim3(256), 0, s, L, n, B, nrhs, ldb, k, nblk);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -564,6 +583,7 @@ template <typename T>
 hipError_t atb_t(const T* A, int64_t m, int64_t n, int64_t lda, const T* B, int64_t nrhs, int64_t ldb, T* out,
                  int64_t ldo, double* part, int64_t chunks, hipStream_t s) {
     const int64_t rows = (m + chunks - 1) / chunks;
+    ProfScope ps(ATA_KERNEL_SOLVE, s);
     hipLaunchKernelGGL(k_atb_part<T>, dim3((unsigned)((n + 255) / 256), (unsigned)chunks), dim3(256), 0, s, A, m, n,
                        lda, B, nrhs, ldb, rows, part);
     hipError_t e = hipGetLastError();

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "ata_plan.h"
@@ -46,6 +47,42 @@ struct WsLayout {
     size_t w = 0, scale = 0, part = 0, t0 = 0, t1 = 0, ops = 0, eqa = 0, total = 0;
     int64_t ldt = 0;
     bool eq = false;
+};
+
+// Kernel timing for measurement tools (ata_profile_enable): while enabled,
+// a ProfScope brackets the launches made in its lifetime with HIP events on
+// the launch stream, recorded under its kernel kind (ATA_KERNEL_*).
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+extern std::mutex g_prof_mu;
+extern bool g_prof_on;
+extern std::vector<ProfRec> g_prof;
+
+struct ProfScope {
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on = false;
+    ProfScope(int k, hipStream_t st) : kind(k), s(st) {
+        {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            on = g_prof_on;
+        }
+        if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, s);
+        else
+            on = false;
+    }
+    ~ProfScope() {
+        if (!on) return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof.push_back(ProfRec{kind, a, b});
+    }
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
 };
 
 int hip_fail(hipError_t e);
