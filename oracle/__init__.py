@@ -18,6 +18,9 @@ Functions
   atb(A, B)                 A^t B, the normal equations' right-hand side
                             (these three follow Section 1's least-squares use
                             of A^t A and their textbook definitions)
+  project(A, B)             A (A^t A)^-1 A^t B, the projection onto the
+                            column space (Section 1's projection matrix):
+                            the steps above, then a matrix product
   bf16_round, bf16_split, e4m3_round, pow2_column_scales
                             number-format conversions used by the reduced
                             precision forms, written from the format
@@ -37,7 +40,7 @@ __all__ = [
     "classical", "classical_mt", "ata", "hasa", "ata_mult_count", "unpack", "pack",
     "tri", "rel_fro", "scaled_err", "freivalds_residual", "bf16_round", "bf16_split",
     "e4m3_round", "pow2_column_scales", "gram_bf16x3", "gram_fp8", "STRASSEN", "WINOGRAD", "load",
-    "potrf", "potrs", "atb",
+    "potrf", "potrs", "atb", "project",
 ]
 
 STRASSEN = 0
@@ -212,6 +215,19 @@ def atb(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     if n and r:
         load().ora_atb(_dptr(A), m, n, lda, _dptr(B2), r, r, _dptr(out), r)
     return out.reshape(-1) if vec else out
+
+
+def project(A: np.ndarray, B: np.ndarray, info_out: list | None = None) -> np.ndarray:
+    """P B for the projection P = A (A^t A)^-1 A^t onto the columns of A
+    (Section 1): the normal equations solved through the plain product, its
+    Cholesky factor and the two substitutions, then A X."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[1]
+    L, info = potrf(classical(A), n)
+    if info_out is not None:
+        info_out.append(info)
+    X = potrs(L, n, atb(A, B))
+    return A @ X
 
 
 # -------------------------------------------------------------------------

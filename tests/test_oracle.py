@@ -369,6 +369,30 @@ def test_atb_definition(orc):
     assert np.array_equal(orc.atb(A, B[:, 1]), A.T @ B[:, 1])
 
 
+def test_project_exact_on_orthogonal_columns(orc):
+    """Columns of a Hadamard matrix of order 256 are orthogonal with squared
+    norm 256: A^t A = 256 I, its factor 16 I, and every step is exact.  The
+    projection of A c + z, with z in the span of the other Hadamard columns,
+    is exactly A c."""
+    H = synthetic.hadamard(256)
+    n = 12
+    A = np.ascontiguousarray(H[:, :n])
+    c = synthetic.integer(n, 2, 81)
+    z = H[:, n:] @ synthetic.integer(256 - n, 2, 82)
+    P = orc.project(A, A @ c + z)
+    assert np.array_equal(P, A @ c)
+
+
+def test_project_is_idempotent_and_orthogonal(orc):
+    A = synthetic.uniform(300, 40, 83)
+    b = synthetic.uniform(300, 1, 84)[:, 0]
+    p = orc.project(A, b)
+    np.testing.assert_allclose(orc.project(A, p), p, rtol=0, atol=1e-12 * np.linalg.norm(p))
+    assert np.linalg.norm(A.T @ (b - p)) <= 1e-12 * np.linalg.norm(A) ** 2 * np.linalg.norm(b)
+    ref = A @ np.linalg.lstsq(A, b, rcond=None)[0]  # LAPACK least squares
+    np.testing.assert_allclose(p, ref, rtol=0, atol=1e-11 * np.linalg.norm(ref))
+
+
 # ---------------------------------------------------------------------------
 # Planted mistakes must be caught
 # ---------------------------------------------------------------------------
