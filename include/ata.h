@@ -367,6 +367,17 @@ int ata_atb(const void *A, int64_t m, int64_t n, int64_t lda, const void *B, int
 int ata_normal_solve(const void *A, int64_t m, int64_t n, int64_t lda, const void *B, int64_t nrhs, int64_t ldb,
                      void *X, int64_t ldx, int dtype, int cutoff, int32_t *info, void *stream);
 
+/*
+ * ata_project: out = P B for the projection P = A (A^t A)^-1 A^t onto the
+ *   column space of A, which the introduction names beside the normal
+ *   equations: ata_normal_solve into a stream-ordered n x nrhs workspace,
+ *   then A X (one wave per row of A, FP64 sums).  B, out: row-major
+ *   m x nrhs (row strides ldb, ldo >= nrhs).  info as for ata_potrf.
+ *   n = 0 gives zeros.
+ */
+int ata_project(const void *A, int64_t m, int64_t n, int64_t lda, const void *B, int64_t nrhs, int64_t ldb,
+                void *out, int64_t ldo, int dtype, int cutoff, int32_t *info, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -107,6 +107,8 @@ def load():
     lib.ata_atb.restype = ci
     lib.ata_normal_solve.argtypes = [vp, i64, i64, i64, vp, i64, i64, vp, i64, ci, ci, vp, vp]
     lib.ata_normal_solve.restype = ci
+    lib.ata_project.argtypes = [vp, i64, i64, i64, vp, i64, i64, vp, i64, ci, ci, vp, vp]
+    lib.ata_project.restype = ci
     _lib = lib
     return lib
 
@@ -413,3 +415,32 @@ def normal_solve(A, B, cutoff: int = 0, X=None, info=None, stream=None):
     if rc:
         raise AtaError(rc, "ata_normal_solve")
     return X
+
+
+def project(A, B, cutoff: int = 0, out=None, info=None, stream=None):
+    """P B for the projection P = A (A^t A)^-1 A^t onto the columns of A
+    (device tensors; B of length m or m x r): the normal equations on the
+    device, then A X.  info as for cholesky().  Returns out."""
+    import torch
+    lib = load()
+    if A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor")
+    m, n = A.shape
+    if m > 0 and n > 0 and A.stride(1) != 1:
+        raise ValueError("A needs unit column stride")
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    dt = _solve_dtype(A)
+    B, _, r, ldb = _rows2d(B, m, dt, "B")
+    if out is None:
+        out = torch.empty((m,) if B.dim() == 1 else (m, r), dtype=A.dtype, device=A.device)
+    out, _, _, ldo = _rows2d(out, m, dt, "out")
+    if info is not None and (info.dtype != torch.int32 or not info.is_cuda or info.numel() < 1):
+        raise ValueError("info must be an int32 device tensor")
+    with torch.cuda.device(A.device):
+        rc = lib.ata_project(ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.c_void_p(B.data_ptr()), r, ldb,
+                             ctypes.c_void_p(out.data_ptr()), ldo, dt, int(cutoff),
+                             ctypes.c_void_p(info.data_ptr()) if info is not None else None,
+                             _stream_handle(stream))
+    if rc:
+        raise AtaError(rc, "ata_project")
+    return out

@@ -491,6 +491,39 @@ __global__ __launch_bounds__(256) void k_atb_part(const T* __restrict__ A, int64
     }
 }
 
+// ---------------------------------------------------------------------------
+// A X for the projection A (A^t A)^-1 A^t B: one wave per row of A (four rows
+// per workgroup), lanes striding the row's n entries (contiguous loads), FP64
+// sums over lanes and a wave-wide sum per right-hand side.  X (n x nrhs) is
+// small and read through the caches.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_ax(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                            const T* __restrict__ X, int64_t nrhs, int64_t ldx, T* __restrict__ out,
+                                            int64_t ldo) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= m) return;  // whole waves leave; no barrier follows
+    const T* a = A + i * lda;
+    for (int64_t r0 = 0; r0 < nrhs; r0 += RC) {
+        const int rc = (int)(nrhs - r0 < RC ? nrhs - r0 : RC);
+        double acc[RC];
+#pragma unroll
+        for (int rr = 0; rr < RC; ++rr) acc[rr] = 0.0;
+#pragma unroll 4
+        for (int64_t j = lane; j < n; j += 64) {
+            const double v = (double)a[j];
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr)
+                if (rr < rc) acc[rr] += v * (double)X[j * ldx + r0 + rr];
+        }
+        for (int rr = 0; rr < rc; ++rr) {
+            const double sum = wave_sum(acc[rr]);
+            if (lane == 0) out[i * ldo + r0 + rr] = (T)sum;
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_atb_sum(const double* __restrict__ part, int64_t chunks, int64_t n,
                                                  int64_t nrhs, T* __restrict__ out, int64_t ldo) {
@@ -619,6 +652,19 @@ __global__ __launch_bounds__(256) void k_transpose(const E* __restrict__ A, int6
 }
 
 }  // namespace
+
+hipError_t launch_ax(bool f32, const void* A, int64_t m, int64_t n, int64_t lda, const void* X, int64_t nrhs,
+                     int64_t ldx, void* out, int64_t ldo, hipStream_t s) {
+    ProfScope ps(ATA_KERNEL_SOLVE, s);
+    const dim3 grid((unsigned)((m + 3) / 4));
+    if (f32)
+        hipLaunchKernelGGL(k_ax<float>, grid, dim3(256), 0, s, (const float*)A, m, n, lda, (const float*)X, nrhs,
+                           ldx, (float*)out, ldo);
+    else
+        hipLaunchKernelGGL(k_ax<double>, grid, dim3(256), 0, s, (const double*)A, m, n, lda, (const double*)X, nrhs,
+                           ldx, (double*)out, ldo);
+    return hipGetLastError();
+}
 
 hipError_t launch_transpose(int elem_bytes, const void* A, int64_t m, int64_t n, int64_t lda, void* out,
                             hipStream_t s) {

@@ -89,6 +89,10 @@ hipError_t launch_potrf(bool f32, void* C, int64_t n, int32_t* info, hipStream_t
                         hipEvent_t f);
 // L L^t X = B in place, B row-major n x nrhs with row stride ldb.
 hipError_t launch_potrs(bool f32, const void* L, int64_t n, void* B, int64_t nrhs, int64_t ldb, hipStream_t s);
+// out (m x nrhs, row stride ldo) = A X for A m x n (row stride lda) and X
+// n x nrhs (row stride ldx), FP64 sums.
+hipError_t launch_ax(bool f32, const void* A, int64_t m, int64_t n, int64_t lda, const void* X, int64_t nrhs,
+                     int64_t ldx, void* out, int64_t ldo, hipStream_t s);
 // out (n x m, row stride m) = A^t for A m x n with row stride lda; elements of
 // elem_bytes 4 or 8.
 hipError_t launch_transpose(int elem_bytes, const void* A, int64_t m, int64_t n, int64_t lda, void* out,

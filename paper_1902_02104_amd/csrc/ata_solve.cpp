@@ -1,5 +1,6 @@
 // C ABI of the normal-equation consumers: Cholesky factor, triangular solves,
-// A^t B, and the chained least-squares solve (declared in ata.h).
+// A^t B, the chained least-squares solve and the projection (declared in
+// ata.h).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -169,6 +170,47 @@ int ata_normal_solve(const void* A, int64_t m, int64_t n, int64_t lda, const voi
         if (e != hipSuccess) rc = hip_fail(e);
     }
     const hipError_t ef = hipFreeAsync(C, s);
+    if (rc == ATA_OK && ef != hipSuccess) rc = hip_fail(ef);
+    return rc;
+}
+
+int ata_project(const void* A, int64_t m, int64_t n, int64_t lda, const void* B, int64_t nrhs, int64_t ldb,
+                void* out, int64_t ldo, int dtype, int cutoff, int32_t* info, void* stream) {
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (lda < max1(n)) return -4;
+    if (nrhs < 0) return -6;
+    if (ldb < max1(nrhs)) return -7;
+    if (ldo < max1(nrhs)) return -9;
+    if (m > 0 && n > 0 && !A) return -1;
+    if (m > 0 && nrhs > 0 && !B) return -5;
+    if (m > 0 && nrhs > 0 && !out) return -8;
+    if (!solve_dtype(dtype)) return -10;
+    if (cutoff < 0) return -11;
+    if (misaligned(A, dtype)) return -1;
+    if (misaligned(B, dtype)) return -5;
+    if (misaligned(out, dtype)) return -8;
+    if ((uintptr_t)info % 4) return -12;
+    if (n > kMaxOrder || (m + 3) / 4 > INT32_MAX) return ATA_EUNSUPPORTED;
+    if (!current_device_ok()) return ATA_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    if (m == 0 || nrhs == 0 || n == 0) {
+        // no columns: the projection is zero; no rows or right-hand sides: nothing to write
+        int rc = potrf_checked(nullptr, 0, dtype, info, s);
+        if (rc == ATA_OK && m > 0 && nrhs > 0) {
+            const hipError_t e = launch_ax(dtype == ATA_F32, A, m, 0, lda, nullptr, nrhs, nrhs, out, ldo, s);
+            if (e != hipSuccess) rc = hip_fail(e);
+        }
+        return rc;
+    }
+    void* X = nullptr;
+    SOLVE_TRY(hipMallocAsync(&X, (size_t)n * (size_t)nrhs * (dtype == ATA_F32 ? 4 : 8), s));
+    int rc = ata_normal_solve(A, m, n, lda, B, nrhs, ldb, X, nrhs, dtype, cutoff, info, stream);
+    if (rc == ATA_OK) {
+        const hipError_t e = launch_ax(dtype == ATA_F32, A, m, n, lda, X, nrhs, nrhs, out, ldo, s);
+        if (e != hipSuccess) rc = hip_fail(e);
+    }
+    const hipError_t ef = hipFreeAsync(X, s);
     if (rc == ATA_OK && ef != hipSuccess) rc = hip_fail(ef);
     return rc;
 }

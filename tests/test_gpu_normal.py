@@ -315,3 +315,49 @@ def test_factor_and_solve_full_order_exact(env, orc, f32):
     torch.cuda.synchronize()
     assert np.array_equal(C.cpu().double().numpy(), ref)
     assert np.array_equal(B.cpu().double().numpy(), X0)
+
+
+def test_project_exact_on_orthogonal_columns(env, orc):
+    """Hadamard columns: A^t A = 256 I, so the whole chain is exact and the
+    projection of A c + z (z orthogonal to the columns) is A c, on both sides."""
+    torch, P = env
+    _say("case: project exact 256x12")
+    H = synthetic.hadamard(256)
+    n = 12
+    A = np.ascontiguousarray(H[:, :n])
+    c = synthetic.integer(n, 2, 91)
+    b = A @ c + H[:, n:] @ synthetic.integer(256 - n, 2, 92)
+    ref = orc.project(A, b)
+    assert np.array_equal(ref, A @ c)
+    for dt in (torch.float64, torch.float32):
+        out = P.project(_dev(torch, A, dt), _dev(torch, b, dt), cutoff=64)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().double().numpy(), ref)
+
+
+def test_project_uniform_and_full_shape(env, orc):
+    torch, P = env
+    m, n = 3000, 200
+    _say("case: project uniform %dx%d" % (m, n))
+    A = synthetic.uniform(m, n, 93)
+    b = synthetic.uniform(m, 1, 94)[:, 0]
+    ref = orc.project(A, b)
+    got = P.project(_dev(torch, A, torch.float64), _dev(torch, b, torch.float64)).cpu().numpy()
+    kap = _kappa(orc, orc.classical(A), n)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    tol = (8 * (n + 1) * U64 + 1e-12) * kap
+    _say("   rel err %.3e tol %.3e" % (err, tol))
+    assert err <= tol
+    # the least-squares shape at a quarter of its rows: the residual b - P b
+    # is orthogonal to the columns and P is idempotent (torch FP64 checks)
+    m, n = 65536, 2048
+    _say("case: project least-squares shape %dx%d" % (m, n))
+    At = torch.from_numpy(synthetic.uniform(m, n, 95)).cuda()
+    bt = torch.from_numpy(synthetic.uniform(m, 1, 96)[:, 0].copy()).cuda()
+    p = P.project(At, bt)
+    pp = P.project(At, p)
+    torch.cuda.synchronize()
+    fro2 = float(torch.linalg.matrix_norm(At, "fro") ** 2)
+    assert float(At.t().mv(bt - p).norm()) <= 64 * n * U64 * fro2 * float(bt.norm()) / np.sqrt(fro2)
+    assert float((pp - p).norm()) <= 64 * n * U64 * float(p.norm())
+

@@ -227,3 +227,18 @@ def test_aat_argument_validation_without_gpu(lib):
     assert L.ata_aat(a, 4, 4, 4, a, P.F64, -1, None) == -7
     mis = ctypes.c_void_p(ctypes.addressof(buf) + 4)
     assert L.ata_aat(mis, 4, 4, 4, a, P.F64, 0, None) == -1
+
+
+def test_project_argument_validation_without_gpu(lib):
+    L = P.load()
+    vp = ctypes.c_void_p
+    buf = (ctypes.c_double * 64)()
+    a = ctypes.cast(buf, vp)
+    assert L.ata_project(a, -1, 4, 4, a, 1, 1, a, 1, P.F64, 0, None, None) == -2
+    assert L.ata_project(a, 4, 4, 3, a, 1, 1, a, 1, P.F64, 0, None, None) == -4
+    assert L.ata_project(a, 4, 4, 4, None, 1, 1, a, 1, P.F64, 0, None, None) == -5
+    assert L.ata_project(a, 4, 4, 4, a, 1, 1, None, 1, P.F64, 0, None, None) == -8
+    assert L.ata_project(a, 4, 4, 4, a, 2, 2, a, 1, P.F64, 0, None, None) == -9
+    assert L.ata_project(a, 4, 4, 4, a, 1, 1, a, 1, P.F32_FP8, 0, None, None) == -10
+    assert L.ata_project(a, 4, 4, 4, a, 1, 1, a, 1, P.F64, -1, None, None) == -11
+
