@@ -191,7 +191,8 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts *o
                   ata_plan_stats *out);
 
 /* Default cutoff chosen for a shape when cutoff == 0: 128 when
- * min(m, n) <= 1024, 256 up to 4096, 512 above. */
+ * min(m, n) <= 1024; otherwise 512, except 256 for float input (dtype other
+ * than ATA_F64) with min(m, n) <= 4096 and m < 4 n. */
 int ata_default_cutoff(int64_t m, int64_t n, int dtype);
 
 /* Text for a status code (static storage). */

@@ -223,14 +223,15 @@ WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equil
 }
 
 int64_t default_cutoff(int64_t m, int64_t n, int dtype) {
-    (void)dtype;
     // Leaves of a few hundred columns keep every workgroup tile busy while the
-    // top levels (where nearly all the work is) still split.  Large shapes
-    // take 512-column leaves, the fastest of {128, 256, 512} on gfx950 for a
-    // square 10000-column FP64 product at one Strassen level.
+    // top levels (where nearly all the work is) still split.  From timings on
+    // gfx950 at one Strassen level: 512-column leaves are the fastest of
+    // {128, 256, 512} for FP64 from 2048 columns up (square and tall) and for
+    // every form above 4096 columns; float input on near-square shapes of up
+    // to 4096 columns runs faster with 256.
     const int64_t mn = m < n ? m : n;
     if (mn <= 1024) return 128;
-    if (mn <= 4096) return 256;
+    if (mn <= 4096 && (dtype & 0xff) != ATA_F64 && m < 4 * n) return 256;
     return 512;
 }
 
