@@ -354,9 +354,7 @@ def _normal_equations(P, torch, dev, stream, C0, n: int, steps: int):
                                         % (m, k, synthetic.SEED_TALL_Z, synthetic.SEED_TALL_SCALES),
                             "ms": t_chain, "gram_ms": t_gram, "atb_ms": t_atb,
                             "atb_gbs": m * k * 8 / (t_atb * 1e-3) / 1e9, "info": int(info.item()),
-                            "normal_eq_residual": res, "project_ms": t_proj,
-                            "project_ax_gbs": m * k * 8 / ((t_proj - t_chain) * 1e-3) / 1e9 if t_proj > t_chain else None,
-                            "project_orthogonality": orth}
+                            "normal_eq_residual": res, "project_ms": t_proj, "project_orthogonality": orth}
     _log("normal equations: least squares %dx%d %.2f ms (product %.2f ms, A^t b %.3f ms), residual %.1e; "
          "projection %.2f ms, orthogonality %.1e" % (m, k, t_chain, t_gram, t_atb, res, t_proj, orth))
     del A
