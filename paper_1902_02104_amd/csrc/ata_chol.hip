@@ -1,8 +1,8 @@
 // Consumers of the packed product on gfx950: the Cholesky factor of the
-// packed lower C, the two triangular solves with it, and the right-hand side
-// A^t b of the normal equations (Section 1 names least squares through the
-// normal equations as a use of A^t A); and the transpose that gives the
-// companion product A A^t.
+// packed lower C, the two triangular solves with it, the right-hand side A^t b
+// of the normal equations and the product A X that applies the projection
+// A (A^t A)^-1 A^t (Section 1 names both as uses of A^t A); and the transpose
+// that gives the companion product A A^t.
 //
 // Storage: row-major packed lower triangle, element (i, j), j <= i, at
 // i (i + 1) / 2 + j, so a row's entries left of the diagonal are contiguous.
