@@ -361,3 +361,25 @@ def test_project_uniform_and_full_shape(env, orc):
     assert float(At.t().mv(bt - p).norm()) <= 64 * n * U64 * fro2 * float(bt.norm()) / np.sqrt(fro2)
     assert float((pp - p).norm()) <= 64 * n * U64 * float(p.norm())
 
+
+
+def test_normal_solve_f32_within_bound(env, orc):
+    """The chain in FP32 throughout (FP32 product, factor, right-hand side and
+    solves) against the FP64 oracle chain: the FP32 product's own error (the
+    form's 2e-5 bound) and the FP32 solve, both amplified by kappa."""
+    torch, P = env
+    m, n = 3000, 150
+    _say("case: normal_solve f32 %dx%d" % (m, n))
+    A = synthetic.uniform(m, n, 97).astype(np.float32).astype(np.float64)
+    b = synthetic.uniform(m, 1, 98)[:, 0].astype(np.float32).astype(np.float64)
+    Cp = orc.classical(A)
+    L, _ = orc.potrf(Cp, n)
+    xr = orc.potrs(L, n, orc.atb(A, b))
+    info = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    x = P.normal_solve(_dev(torch, A, torch.float32), _dev(torch, b, torch.float32), info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    err = float(np.linalg.norm(x.cpu().double().numpy() - xr) / np.linalg.norm(xr))
+    tol = (2e-5 + 8 * (n + 1) * U32) * _kappa(orc, Cp, n)
+    _say("   rel err %.3e tol %.3e" % (err, tol))
+    assert err <= tol
