@@ -51,9 +51,10 @@ __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOM
 // i = (t >> 6) + 4 q (q < 16) of the block, and keeps a running copy of its
 // column's diagonal entry (updated by the same operation as the entry
 // itself), so the owners of step j take the pivot from their own copy.
-// Step j: the owners scale column j by 1 / pivot (as LAPACK's unblocked
-// factor does) and publish it in LDS; after one barrier every thread applies
-// the rank-one update to its entries with selects.  The column buffer
+// Step j: the owners publish column j and 1 / pivot in LDS; after one
+// barrier every thread scales the entries it reads by 1 / pivot (as LAPACK's
+// unblocked factor scales the column) and applies the rank-one update to its
+// entries with selects.  A finished column is scaled when it is stored.  The column buffer
 // alternates between two halves by step parity: the barrier of step j + 1
 // separates the reads of step j from the writes of step j + 2.  A pivot that
 // is not positive is reported once through `info` (first failing column + 1,
@@ -62,6 +63,7 @@ __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOM
 template <typename T>
 __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ C, int64_t kb, int w, int32_t* __restrict__ info) {
     __shared__ T col[2][NB];
+    __shared__ T rps[2];
     // on the critical path while the helper stream's update fills the CUs:
     // raise this wave's issue priority on its SIMD
     __builtin_amdgcn_s_setprio(3);
@@ -73,26 +75,28 @@ __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ C, int64_t kb
         d[q] = (i < w && l <= i) ? C[pidx(kb + i, kb + l)] : T(0);
     }
     T dd = l < w ? C[pidx(kb + l, kb + l)] : T(1);
+    T myrp = T(1), mypiv = T(0);  // this thread's column: 1 / pivot and pivot
     for (int j = 0; j < w; ++j) {
         T* cb = col[j & 1];
         if (l == j) {
-            const T piv = sqrt(dd);
-            const T rp = T(1) / piv;
+            // the owners publish column j unscaled with 1 / pivot; each reader
+            // forms the scaled entries it needs (the same products), and a
+            // column is scaled in place only when it is stored
+            mypiv = sqrt(dd);
+            myrp = T(1) / mypiv;
             if (wv == 0 && !(dd > T(0)) && info) atomicCAS(info, 0, (int32_t)(kb + j + 1));
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int i = wv + 4 * q;
-                d[q] = i > j ? d[q] * rp : (i == j ? piv : d[q]);
-                cb[i] = d[q];
-            }
+            for (int q = 0; q < 16; ++q) cb[wv + 4 * q] = d[q];
+            if (wv == 0) rps[j & 1] = myrp;
         }
         __syncthreads();
         const bool act = l > j && l < w;
-        const T lj = cb[l];
+        const T rpj = rps[j & 1];
+        const T lj = cb[l] * rpj;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int i = wv + 4 * q;
-            const T v = d[q] - cb[i] * lj;
+            const T v = d[q] - (cb[i] * rpj) * lj;
             d[q] = (act && i >= l) ? v : d[q];
         }
         if (act) dd -= lj * lj;
@@ -100,7 +104,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ C, int64_t kb
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int i = wv + 4 * q;
-        if (i < w && l <= i) C[pidx(kb + i, kb + l)] = d[q];
+        if (i < w && l <= i) C[pidx(kb + i, kb + l)] = i > l ? d[q] * myrp : (i == l ? mypiv : d[q]);
     }
 }
 
