@@ -138,27 +138,28 @@ __global__ __launch_bounds__(256) void k_chol_rows(T* __restrict__ C, int64_t n,
     // The rows of a wave (i = wv + 4 q) depend only on each other and on L11,
     // and the column entries col[wv + 4 q] are written and read by that wave
     // alone: the steps need wave-level ordering only.
+    // The owner lane publishes its column unscaled; readers scale by the
+    // staged 1 / L11[j][j] (the same products), and a column is scaled when
+    // it is stored.
     for (int j = 0; j < w; ++j) {
         if (l == j) {
-            const T rp = rcp[j];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                r[q] *= rp;
-                col[wv + 4 * q] = r[q];
-            }
+            for (int q = 0; q < 16; ++q) col[wv + 4 * q] = r[q];
         }
         wave_lds_fence();
         if (l > j && l < w) {
             const T lj = ld[l * (NB + 1) + j];
+            const T rj = rcp[j];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) r[q] -= col[wv + 4 * q] * lj;
+            for (int q = 0; q < 16; ++q) r[q] -= (col[wv + 4 * q] * rj) * lj;
         }
         wave_lds_fence();
     }
+    const T rl = l < w ? rcp[l] : T(0);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int i = wv + 4 * q;
-        if (R0 + i < n && l < w) C[pidx(R0 + i, kb + l)] = r[q];
+        if (R0 + i < n && l < w) C[pidx(R0 + i, kb + l)] = r[q] * rl;
     }
 }
 
