@@ -260,6 +260,93 @@ def test_invariants(orc):
     np.linalg.cholesky(orc.unpack(Cu, n))
 
 
+# ---------------------------------------------------------------------------
+# The checkers every floating-point parity test goes through: relative
+# Frobenius error, scaled error and the Freivalds residual, pinned to values
+# worked out by hand, and shown to reject planted mistakes in their source.
+# ---------------------------------------------------------------------------
+
+# Packed lower triangle of [[4, 1, 2], [1, 9, 3], [2, 3, 16]]: squared
+# Frobenius norm of the full matrix 16 + 81 + 256 + 2 (1 + 4 + 9) = 381.
+_REF3 = np.array([4.0, 1.0, 9.0, 2.0, 3.0, 16.0])
+
+
+def _checker_pins_hold(rel_fro, scaled_err, freivalds_residual):
+    """True when all three checkers give the hand-worked values below."""
+    ok = True
+    d = 0.5
+    # one off-diagonal entry (2, 1) off by d: it appears twice in the full matrix
+    C = _REF3.copy()
+    C[4] += d
+    ok &= abs(rel_fro(C, _REF3, 3) - np.sqrt(2 * d * d) / np.sqrt(381.0)) < 1e-15
+    # one diagonal entry (1, 1) off by d: it appears once
+    C = _REF3.copy()
+    C[2] += d
+    ok &= abs(rel_fro(C, _REF3, 3) - d / np.sqrt(381.0)) < 1e-15
+    ok &= rel_fro(_REF3, _REF3, 3) == 0.0
+    # scaled error of (2, 1) is d / sqrt(C_11 C_22) = d / 12, of (1, 0) d / sqrt(4 * 9) = d / 6
+    C = _REF3.copy()
+    C[4] += d
+    ok &= abs(scaled_err(C, _REF3, 3) - d / 12.0) < 1e-15
+    C[1] -= 0.25 * d
+    ok &= abs(scaled_err(C, _REF3, 3) - d / 12.0) < 1e-15  # 0.125 / 6 < 0.5 / 12
+    C[1] -= 0.75 * d
+    ok &= abs(scaled_err(C, _REF3, 3) - d / 6.0) < 1e-15
+    # Freivalds: A 4 x 3 integer, ||A||_F^2 = 15; x = (1, 2, 2), ||x|| = 3
+    A = np.array([[1.0, 2.0, 0.0], [0.0, 1.0, 1.0], [2.0, 0.0, 1.0], [1.0, 1.0, 1.0]])
+    x = np.array([1.0, 2.0, 2.0])
+    Cp = np.array([6.0, 3.0, 6.0, 3.0, 2.0, 3.0])  # A^t A = [[6, 3, 3], [3, 6, 2], [3, 2, 3]]
+    ok &= freivalds_residual(Cp, A, x) == 0.0
+    # entry (2, 0) off by 3: (C - A^t A) x = 3 (x_0 e_2 + x_2 e_0), norm 3 sqrt(5)
+    Cp[3] += 3.0
+    ok &= abs(freivalds_residual(Cp, A, x) - np.sqrt(5.0) / 15.0) < 1e-15
+    # a diagonal entry (1, 1) off by 3: (C - A^t A) x = 3 x_1 e_1, norm 6
+    Cp[3] -= 3.0
+    Cp[2] += 3.0
+    ok &= abs(freivalds_residual(Cp, A, x) - 6.0 / 45.0) < 1e-15
+    return bool(ok)
+
+
+def test_checkers_hand_values(orc):
+    assert _checker_pins_hold(orc.rel_fro, orc.scaled_err, orc.freivalds_residual)
+    # A hand-built packed matrix against numpy's norm of the unpacked difference.
+    rng = np.random.default_rng(4)
+    ref = rng.standard_normal(orc.tri(40))
+    C = ref + 1e-7 * rng.standard_normal(ref.shape)
+    want = np.linalg.norm(orc.unpack(C, 40) - orc.unpack(ref, 40)) / np.linalg.norm(orc.unpack(ref, 40))
+    assert abs(orc.rel_fro(C, ref, 40) - want) <= 1e-12 * want
+
+
+CHECKER_MUTANTS = [
+    ("rel_fro", "np.full(d.shape, 2.0)", "np.full(d.shape, 1.0)", "off-diagonal entries counted once"),
+    ("rel_fro", "w[diag] = 1.0", "w[diag] = 2.0", "diagonal entries counted twice"),
+    ("rel_fro", "np.sum(w * ref * ref)", "np.sum(w * C * C)", "normalised by the result, not the reference"),
+    ("scaled_err", "ref[tri(i + 1) - 1]", "ref[tri(i)]", "first entry of each row taken as the diagonal"),
+    ("scaled_err", "diag[ii] * diag[jj]", "diag[ii] * diag[ii]", "row diagonal used twice"),
+    ("freivalds_residual", "lhs = C @ x", "lhs = rhs = A.T @ (A @ x)", "residual that is always zero"),
+    ("freivalds_residual", "C = unpack(", "C = np.tril(unpack(", "lower triangle only"),
+    ("freivalds_residual", "float(np.linalg.norm(x))", "float(np.sum(x))", "wrong norm of x"),
+]
+
+
+def test_checker_mutants_are_caught(orc):
+    """Each planted mistake in a checker's own source breaks a hand-worked pin."""
+    import inspect
+    import oracle as mod
+    for name, old, new, what in CHECKER_MUTANTS:
+        src = inspect.getsource(getattr(mod, name))
+        assert old in src, (name, old)
+        mutated = src.replace(old, new, 1)
+        if new.startswith("C = np.tril("):
+            mutated = mutated.replace("dtype=np.float64), n)", "dtype=np.float64), n))", 1)
+        ns = {"np": np, "tri": mod.tri, "unpack": mod.unpack}
+        exec(compile(mutated, "<mutant %s>" % what, "exec"), ns)
+        fns = {"rel_fro": mod.rel_fro, "scaled_err": mod.scaled_err,
+               "freivalds_residual": mod.freivalds_residual}
+        fns[name] = ns[name]
+        assert not _checker_pins_hold(**fns), "checker mutant survived: %s" % what
+
+
 def test_power_of_two_column_scaling_is_exact_for_classical(orc):
     """Classical products commute exactly with power-of-two column scaling:
     (AD)^t (AD) = D (A^t A) D bitwise."""
