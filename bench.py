@@ -511,17 +511,21 @@ def main():
     dom = max(kt, key=lambda k: kt[k][0])
     dom_ms, dom_launches = kt[dom]
     avg_ms = dom_ms / dom_launches
-    mult_key = {"strassen": "strassen_mults", "gemm": "gemm_mults", "syrk": "syrk_mults"}.get(dom)
+    # the mixed FP64 launch runs the product tiles and the classical tiles of
+    # the phase together: its algorithmic work is all of their multiplications
+    mult_keys = {"strassen": ("strassen_mults",), "gemm": ("gemm_mults",), "syrk": ("syrk_mults",),
+                 "tiles": ("strassen_mults", "gemm_mults", "syrk_mults")}.get(dom)
     launches_per_step = dom_launches / args.steps
-    if mult_key:
-        alg_flops = 2.0 * st[mult_key] / launches_per_step
+    if mult_keys:
+        alg_flops = 2.0 * sum(st[k] for k in mult_keys) / launches_per_step
         roof = {"bound": "mfma", "achieved": alg_flops / (avg_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "algorithmic_flops_per_launch": alg_flops}
     else:
         roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] else None
-    roof["kernel"] = {"strassen": {"intile": "k_str_f64", "tiles": "k_gemm_terms_f64", "opsums": "k_gemmd_f64"}[form],
-                      "gemm": "k_gemmd_f64", "syrk": "k_gemmd_f64", "combine": "k_combine_f64"}.get(dom, dom)
+    roof["kernel"] = {"strassen": {"intile": "k_str_f64", "tiles": "k_gemm_terms_f64", "opsums": "k_tile_f64"}[form],
+                      "tiles": "k_tile2_f64" if (form == "tiles" and depth >= 1) else "k_tile_f64",
+                      "gemm": "k_tile_f64", "syrk": "k_tile_f64", "combine": "k_combine_f64"}.get(dom, dom)
     roof["traffic"] = _profiled_traffic(roof["kernel"], n, cutoff, depth, form)
     roof["avg_launch_ms"] = avg_ms
 

@@ -226,7 +226,9 @@ void ata_release_caches(void);
 #define ATA_KERNEL_FACTOR_PANEL 5  /* Cholesky diagonal blocks and row solves */
 #define ATA_KERNEL_FACTOR_UPDATE 6 /* Cholesky trailing updates */
 #define ATA_KERNEL_SOLVE 7         /* triangular solves and A^t B */
-#define ATA_KERNEL_KINDS 8
+#define ATA_KERNEL_TILES 8         /* FP64 product tiles and classical tiles of a
+                                      phase in one launch */
+#define ATA_KERNEL_KINDS 9
 int ata_profile_enable(int on);
 int ata_profile_collect(double *ms, int64_t *launches, int kinds);
 

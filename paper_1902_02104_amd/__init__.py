@@ -180,7 +180,7 @@ def precision_convert(x, dtype: int, stream=None):
     return (o0, o1) if o1 is not None else o0
 
 
-KERNEL_KINDS = ("strassen", "gemm", "syrk", "combine", "other", "factor_panel", "factor_update", "solve")
+KERNEL_KINDS = ("strassen", "gemm", "syrk", "combine", "other", "factor_panel", "factor_update", "solve", "tiles")
 
 
 def profile_enable(on: bool = True) -> None:

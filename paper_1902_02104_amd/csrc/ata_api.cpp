@@ -115,6 +115,9 @@ void serialize(PlanDev& pd) {
         off = align256(off + ph.combines.size() * sizeof(DevCombine));
         d.off_ops = off;
         off = align256(off + ph.opsums.size() * sizeof(DevOpSum));
+        d.n_mix = (int)ph.mix_items.size();
+        d.off_mix = off;
+        off = align256(off + ph.mix_items.size() * sizeof(WorkItem));
     }
     std::vector<char>& host = pd.host_blob;
     host.assign(off ? off : 256, 0);
@@ -130,6 +133,7 @@ void serialize(PlanDev& pd) {
         std::memcpy(host.data() + d.off_syrk, ph.syrk_items.data(), ph.syrk_items.size() * sizeof(WorkItem));
         std::memcpy(host.data() + d.off_cb, ph.combines.data(), ph.combines.size() * sizeof(DevCombine));
         std::memcpy(host.data() + d.off_ops, ph.opsums.data(), ph.opsums.size() * sizeof(DevOpSum));
+        std::memcpy(host.data() + d.off_mix, ph.mix_items.data(), ph.mix_items.size() * sizeof(WorkItem));
     }
     for (int mode = 0; mode < 2; ++mode) pd.lp_aligned[mode] = lp_windows_aligned(P, mode == 0 ? 2 : 4);
 }
@@ -413,6 +417,27 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             }
             continue;
         }
+        if (!f32 && ph.n_mix > 0 && ph.n_str == 0) {
+            // FP64 product tiles and classical tiles in one launch, heaviest
+            // first, then the combination of the products
+            if (ph.n_ops) {
+                ProfScope ps(ATA_KERNEL_OTHER, s);
+                err = launch_opsum(f32, A, lda, tb, (const DevOpSum*)(pd->blob + ph.off_ops), ph.n_ops, ph.ops_rows,
+                                   ws + L.ops, s);
+            }
+            if (err == hipSuccess) {
+                ProfScope ps(ATA_KERNEL_TILES, s);
+                err = launch_tile(ph.tg_tmax <= 1 ? 1 : 2, (const double*)A, lda, tb,
+                                  (const WorkItem*)(pd->blob + ph.off_mix), ph.n_mix, (double*)C_lower, W, s,
+                                  (const double*)(ws + L.ops));
+            }
+            if (err == hipSuccess && ph.n_cb) {
+                ProfScope ps(ATA_KERNEL_COMBINE, s);
+                err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W,
+                                     C_lower, s);
+            }
+            continue;
+        }
         const bool split = (ph.n_str + ph.n_tg) > 0 && (ph.n_gemm + ph.n_syrk) > 0;
         ForkCtx fc;
         if (split) {
@@ -433,23 +458,27 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
         }
         if (err == hipSuccess && ph.n_tg) {
             ProfScope ps(ATA_KERNEL_STRASSEN, s);
-            if (ph.tg_tmax <= 1)  // products on operand-sum buffers
-                err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_tg), ph.n_tg, C_lower, W,
-                                  s, ws + L.ops);
+            const WorkItem* it = (const WorkItem*)(pd->blob + ph.off_tg);
+            if (!f32 && ph.tg_tmax <= 2)  // FP64: one-term (operand-sum buffers) or two-term tiles
+                err = launch_tile(ph.tg_tmax <= 1 ? 1 : 2, (const double*)A, lda, tb, it, ph.n_tg, (double*)C_lower, W,
+                                  s, (const double*)(ws + L.ops));
+            else if (ph.tg_tmax <= 1)  // products on operand-sum buffers
+                err = launch_gemm(f32, out64, A, lda, tb, it, ph.n_tg, C_lower, W, s, ws + L.ops);
             else
-                err = launch_gemm_terms(f32, out64, ph.tg_tmax, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_tg),
-                                        ph.n_tg, C_lower, W, s);
+                err = launch_gemm_terms(f32, out64, ph.tg_tmax, A, lda, tb, it, ph.n_tg, C_lower, W, s);
         }
         hipStream_t s_small = split ? fc.s2 : s;
         if (err == hipSuccess && ph.n_gemm) {
             ProfScope ps(ATA_KERNEL_GEMM, s_small);
-            err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower,
-                              W, s_small);
+            const WorkItem* it = (const WorkItem*)(pd->blob + ph.off_gemm);
+            err = f32 ? launch_gemm(f32, out64, A, lda, tb, it, ph.n_gemm, C_lower, W, s_small)
+                      : launch_tile(1, (const double*)A, lda, tb, it, ph.n_gemm, (double*)C_lower, W, s_small);
         }
         if (err == hipSuccess && ph.n_syrk) {
             ProfScope ps(ATA_KERNEL_SYRK, s_small);
-            err = launch_gemm(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower,
-                              W, s_small);
+            const WorkItem* it = (const WorkItem*)(pd->blob + ph.off_syrk);
+            err = f32 ? launch_gemm(f32, out64, A, lda, tb, it, ph.n_syrk, C_lower, W, s_small)
+                      : launch_tile(1, (const double*)A, lda, tb, it, ph.n_syrk, (double*)C_lower, W, s_small);
         }
         if (split) {
             if (err == hipSuccess) err = hipEventRecord(fc.join, fc.s2);

@@ -15,9 +15,9 @@ namespace detail {
 
 // Device copy of one plan's tables.
 struct PhaseDev {
-    int n_str = 0, n_tg = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, n_ops = 0, str_tmax = 0, tg_tmax = 0;
+    int n_str = 0, n_tg = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, n_ops = 0, n_mix = 0, str_tmax = 0, tg_tmax = 0;
     int64_t cb_elems = 0, ops_rows = 0;
-    size_t off_str = 0, off_tg = 0, off_gemm = 0, off_syrk = 0, off_cb = 0, off_ops = 0;
+    size_t off_str = 0, off_tg = 0, off_gemm = 0, off_syrk = 0, off_cb = 0, off_ops = 0, off_mix = 0;
 };
 
 struct PlanDev {

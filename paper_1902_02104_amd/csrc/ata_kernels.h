@@ -23,6 +23,12 @@ hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const
                        const WorkItem* items, int nitems, void* C, double* W, hipStream_t s,
                        const void* Aops = nullptr);
 
+// FP64 tiles on 16-byte direct-to-LDS copies: nt = 1 for classical tiles
+// (TK_SYRK / TK_GEMM, and products on operand-sum buffers through Aops),
+// nt = 2 for Strassen product tiles with at most two terms per operand.
+hipError_t launch_tile(int nt, const double* A, int64_t lda, const DevTables& tb, const WorkItem* items, int nitems,
+                       double* C, double* W, hipStream_t s, const double* Aops = nullptr);
+
 // Operand sums of the product tasks in `recs` (one workgroup per buffer row;
 // rows = total rows of the records) into `out`, in the input type.
 hipError_t launch_opsum(bool f32, const void* A, int64_t lda, const DevTables& tb, const DevOpSum* recs, int nrec,

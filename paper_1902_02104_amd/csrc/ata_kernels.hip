@@ -569,6 +569,275 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
 }
 
 // ---------------------------------------------------------------------------
+// FP64 tile kernel with 16-byte direct-to-LDS copies and 128-bit operand
+// reads (k_tile): classical tiles (one term per operand: TK_SYRK / TK_GEMM
+// leaves and the products of the operand-sum form) and Strassen product
+// tiles whose operands are signed sums of two quadrant terms.  128 x 128
+// output tile, four waves of 64 x 64, 16 k rows per stage, double-buffered
+// LDS (64 KB), two workgroups per CU.
+//
+// Copies: one buffer load that writes LDS moves a whole 1 KB tile row (16
+// bytes per lane).  The 16-byte chunks of row r sit at chunk position
+// c ^ ((r & 3) << 2), so the four k rows an MFMA step reads fall in four
+// different 64-byte bank groups.
+//
+// Operand reads: a 128-bit read gives each lane two neighbouring columns, so
+// one read serves two MFMA blocks.  The FP64 4x4x4 MFMA takes the left
+// operand as 4 rows x 4 k, repeated in its four lane quads (it has no
+// broadcast of a single block), so the left side reads 4-row slots: slot
+// (block 2q + h, row i) of a wave holds column 8q + 2i + h; the right side
+// reads 16-column slots: slot (block 2u + h, column j) holds column
+// 32u + 2j + h.  The epilogue maps the slots back.
+//
+// Two-term operands: the first term is copied into the operand's plane as
+// above; the second is loaded into registers by the same wave and added into
+// the plane with LDS atomic adds (x0 + s x1 with s = +-1: one rounding, as
+// the sum in the product's definition) once the first has landed.  Each
+// element is summed once per workgroup by the LDS unit, so the MFMA loop
+// reads one plane per operand, exactly as for classical tiles, and runs no
+// FP64 vector adds.  The product's overall sign is applied to the result.
+// A term's columns past its end read as zero: whole chunks past the end get
+// an out-of-range offset, and the one chunk that straddles the end (odd
+// column counts) has its tail cleared.
+// ---------------------------------------------------------------------------
+typedef double d2_t __attribute__((ext_vector_type(2)));
+
+// One 16-byte buffer load per lane into LDS at lds + 16 * lane.  (A plain
+// device function: the host pass does not know the 16-byte form, which
+// would otherwise fail the host-side instantiation of the kernel templates.)
+__device__ __forceinline__ void lds_copy16(rsrc_t r, void* lds, uint32_t voff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, 0, 0, 0);
+}
+
+template <typename OUT, int NT>
+__global__ void __launch_bounds__(256, 2) k_tile(const double* __restrict__ A_, int64_t lda_,
+                                                const DevTask* __restrict__ tasks_,
+                                                const DevTerm* __restrict__ terms_,
+                                                const int32_t* __restrict__ segs_,
+                                                const WorkItem* __restrict__ items, OUT* __restrict__ C,
+                                                double* __restrict__ W, const double* __restrict__ Aops) {
+    constexpr int GK = 16;               // k rows per stage
+    static_assert(GK <= kStageRows, "one slab per stage");
+    constexpr int NP = GK / 4;           // MFMA steps per stage
+    constexpr int PLANE = GK * GT;       // doubles per plane
+    constexpr int RPW = GK / 2;          // rows a wave copies per stage (two waves per operand)
+    __shared__ __attribute__((aligned(16))) double lds[2][2][PLANE];  // [buffer][operand]
+
+    typedef const __attribute__((address_space(1))) DevTask* TaskP;
+    typedef const __attribute__((address_space(1))) DevTerm* TermP;
+    typedef const __attribute__((address_space(1))) int32_t* SegP;
+    const WorkItem w = items[blockIdx.x];
+    const double* __restrict__ A = A_;
+    int64_t lda = lda_;
+    const TaskP tasks = (TaskP)tasks_;
+    const TermP terms = (TermP)terms_;
+    const SegP segs = (SegP)segs_;
+    const DevTask t = load_rec(tasks + w.task);
+    if (t.src == 1) {  // operands from the task's operand-sum buffer
+        A = Aops + t.src_off;
+        lda = (int64_t)t.M + t.N;
+    }
+    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    const int i0 = w.ti * GT, j0 = w.tj * GT;
+    const int64_t row_bytes = lda * (int64_t)sizeof(double);
+
+    // Copy role: operand cs (0: left X, 1: right Y), k rows of parity cpar.
+    // Per term and per row residue (r & 3 is cpar or cpar + 2): the byte
+    // offset of the 16-byte chunk this lane copies, kOOB past the term's end.
+    const int cs = wave >> 1, cpar = wave & 1;
+    const int cnt = NT > 1 ? (cs == 0 ? t.nx : t.ny) : 1;  // terms of this wave's operand
+    uint32_t doff[NT][2];
+    int tail[NT];  // valid columns of the term in this tile when a chunk straddles its end, else 0
+    double osgn, s1 = 1.0;  // overall sign; sign of the second term relative to the first
+    {
+        const DevTerm x0 = load_rec(terms + t.term_off);
+        const DevTerm y0 = load_rec(terms + t.term_off + t.nx);
+        osgn = (double)(x0.sign * y0.sign);
+        if (NT > 1 && cnt > 1)
+            s1 = (double)((cs == 0 ? x0.sign : y0.sign) *
+                          load_rec(terms + t.term_off + (cs == 0 ? 1 : t.nx + 1)).sign);
+    }
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        doff[u][0] = doff[u][1] = kOOB;
+        tail[u] = 0;
+        if (u < cnt) {
+            const DevTerm tm = load_rec(terms + t.term_off + (cs == 0 ? u : t.nx + u));
+            const int colbase = tm.col + (cs == 0 ? i0 : j0);
+            const int nvalid = tm.cvend - colbase;  // columns of the term from the tile start on
+            if (NT > 1 && nvalid > 0 && nvalid < GT && (nvalid & 1)) tail[u] = nvalid;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int c = lane ^ ((cpar + 2 * p) << 2);  // logical chunk this lane copies
+                doff[u][p] = 2 * c < nvalid ? (uint32_t)(colbase + 2 * c) * 8u : kOOB;
+            }
+        }
+    }
+
+    double acc[16][4];
+#pragma unroll
+    for (int a = 0; a < 16; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+
+    // k cursor over the segments: rows row_u + k for k in [kbeg, kend)
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
+    int seg = 0;
+    int k0 = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
+    int kend = t.nseg > 0 ? segs[t.seg_off + 2] : 0;
+    int ntiles = 0;
+    for (int s = 0; s < t.nseg; ++s)
+        ntiles += (segs[t.seg_off + s * stride + 2] - segs[t.seg_off + s * stride + 1] + GK - 1) / GK;
+
+    // Slab of each term of this wave's operand for the stage at k0: rows
+    // below both the window end and the term's row end; the rest read as zero.
+    rsrc_t rs[NT];
+    auto slab = [&](bool live) {
+        const SegP sg = segs + t.seg_off + (live ? seg : 0) * stride;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int h = 2 * ((cs == 0 ? 0 : t.nx) + u);
+            const bool on = live && u < cnt;
+            const int base = (on ? sg[kSegHdr + h] : 0) + k0;
+            const int rvend = on ? sg[kSegHdr + 1 + h] : 0;
+            int nv = rvend - base < kend - k0 ? rvend - base : kend - k0;
+            nv = nv < GK ? nv : GK;
+            if (!on) nv = 0;
+            rs[u] = slab_rsrc(A + (int64_t)base * lda, nv, row_bytes);
+        }
+    };
+    // Row i of this wave's rows (2 i + cpar) of the current stage: the first
+    // term copied into LDS, the second loaded into registers.  Nothing is
+    // copied past the last stage, so no copy is in flight when the workgroup
+    // ends.
+    bool copying = false;
+    d2_t v1[NT > 1 ? RPW : 1];
+    auto copy_row = [&](int buf, int i) {
+        if (!copying) return;
+        const int r = 2 * i + cpar;
+        lds_copy16(rs[0], &lds[buf][cs][r * GT], (uint32_t)(r * row_bytes) + doff[0][i & 1]);
+    };
+    auto load_row = [&](int i) {
+        if (!copying || !(NT > 1 && cnt > 1)) return;
+        const int r = 2 * i + cpar;
+        v1[NT > 1 ? i : 0] = __builtin_bit_cast(
+            d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs[NT - 1], (int)((uint32_t)(r * row_bytes) + doff[NT - 1][i & 1]),
+                                                        0, 0));
+    };
+    auto advance = [&]() {
+        k0 += GK;
+        if (k0 >= kend) {
+            ++seg;
+            if (seg < t.nseg) {
+                k0 = segs[t.seg_off + seg * stride + 1];
+                kend = segs[t.seg_off + seg * stride + 2];
+            }
+        }
+    };
+
+    // Second terms: clear the tail of a straddling chunk of the first term in
+    // the rows this wave copies (before any sum lands there), then add rows
+    // [ia, ib) of the second term into the plane.  The first term's copy of
+    // those rows must have landed.
+    auto fix_tail = [&](int buf) {
+        if (NT > 1 && tail[0] && lane < RPW) {
+            const int r = 2 * lane + cpar;
+            lds[buf][cs][r * GT + 2 * ((tail[0] >> 1) ^ ((r & 3) << 2)) + 1] = 0.0;
+        }
+    };
+    auto add_rows = [&](int buf, int ia, int ib) {
+        if (!(NT > 1 && cnt > 1)) return;
+#pragma unroll
+        for (int i = ia; i < ib; ++i) {
+            const int r = 2 * i + cpar;
+            d2_t v = v1[NT > 1 ? i : 0];
+            if (tail[NT - 1] && (lane ^ ((r & 3) << 2)) == (tail[NT - 1] >> 1)) v[1] = 0.0;
+            double* dst = &lds[buf][cs][r * GT + 2 * lane];
+            __hip_atomic_fetch_add(dst, s1 * v[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(dst + 1, s1 * v[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    };
+
+    if (ntiles > 0) {
+        slab(true);
+        copying = true;
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            copy_row(0, i);
+            load_row(i);
+        }
+    }
+    for (int it = 0; it < ntiles; ++it) {
+        const int buf = it & 1;
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies and loads of stage it have landed
+        fix_tail(buf);
+        add_rows(buf, 0, RPW);
+        __syncthreads();  // every copy and sum of stage it is in LDS; stage it-1 fully read
+        const bool next = it + 1 < ntiles;
+        if (next) advance();
+        slab(next);
+        copying = next;
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int ks = 0; ks < NP; ++ks) {
+            const int kr = (ks * 4 + g) * GT;
+            const int sw = g << 2;
+            d2_t bv[2], av[8];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                bv[u] = *(const d2_t*)&lds[buf][1][kr + 2 * ((wn * 32 + 16 * u + (lane & 15)) ^ sw)];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                av[q] = *(const d2_t*)&lds[buf][0][kr + 2 * ((wm * 32 + 4 * q + (lane & 3)) ^ sw)];
+            // Every copy of the next stage goes out with the first step, so a
+            // whole stage of MFMA work covers its latency.  The register loads
+            // of second terms are spread over the steps (issued together they
+            // would be live across the whole stage and spill).
+            if (ks == 0) {
+#pragma unroll
+                for (int i = 0; i < RPW; ++i) copy_row(buf ^ 1, i);
+            }
+#pragma unroll
+            for (int i = ks * (RPW / NP); i < (ks + 1) * (RPW / NP); ++i) load_row(i);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int ha = 0; ha < 2; ++ha)
+#pragma unroll
+                    for (int cf = 0; cf < 4; ++cf)
+                        acc[2 * q + ha][cf] =
+                            __builtin_amdgcn_mfma_f64_4x4x4f64(av[q][ha], bv[cf >> 1][cf & 1], acc[2 * q + ha][cf], 0, 0, 0);
+        }
+        __builtin_amdgcn_s_setprio(0);
+    }
+
+    // epilogue: slot (2q + ha, row g) -> tile row 8q + 2g + ha of the wave,
+    // slot (2u + hb, column j) -> tile column 32u + 2j + hb
+    const bool syrk = t.kind == TK_SYRK;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+#pragma unroll
+        for (int ha = 0; ha < 2; ++ha) {
+            const int gi = i0 + wm * 64 + 8 * q + 2 * g + ha;
+            if (gi >= t.dM) continue;
+            const int64_t rowbase = packed_index((int64_t)t.r0 + gi, t.q0);
+#pragma unroll
+            for (int cf = 0; cf < 4; ++cf) {
+                const int gj = j0 + wn * 64 + 32 * (cf >> 1) + 2 * (lane & 15) + (cf & 1);
+                if (gj >= t.dN || (syrk && gj > gi)) continue;
+                const double v = osgn * acc[2 * q + ha][cf];
+                if (t.dst == 0)
+                    store_out(C + rowbase + gj, t.beta, v);
+                else
+                    W[t.ws_off + (int64_t)gi * t.N + gj] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // In-tile Strassen kernel (TK_STR).  The product P = Xop^t Yop (padded M x N,
 // K per segment) is split once more into quadrants; a workgroup owns the
 // 64 x 64 tile at (ti, tj) of all four result quadrants and keeps the seven
@@ -1734,6 +2003,19 @@ hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const
     else
         hipLaunchKernelGGL((k_gemmd<float, float, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.segs,
                            items, (float*)C, W, tb.terms, (const float*)Aops, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile(int nt, const double* A, int64_t lda, const DevTables& tb, const WorkItem* items, int nitems,
+                       double* C, double* W, hipStream_t s, const double* Aops) {
+    if (nitems <= 0) return hipSuccess;
+    const dim3 g(nitems), b(256);
+    if (nt <= 1)
+        hipLaunchKernelGGL((k_tile<double, 1>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W, Aops);
+    else if (nt == 2)
+        hipLaunchKernelGGL((k_tile<double, 2>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W, Aops);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

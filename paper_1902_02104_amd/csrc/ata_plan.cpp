@@ -311,6 +311,7 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             khalf += ceil2(K[c]);
             kfull += K[c];
         }
+        const int32_t group = tiled ? P.n_groups++ : -1;
         for (size_t s = 0; tiled && s < prods.size(); ++s) {
             // product s of the fully expanded recursion as a classical tile task
             const Product& pr = prods[s];
@@ -370,6 +371,8 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
             }
             const int32_t id = (int32_t)P.tasks.size();
             P.tasks.push_back(t);
+            P.task_group.resize(P.tasks.size(), -1);
+            P.task_group[id] = group;
             for (int32_t a = 0; a < t.tiles_m; ++a)
                 for (int32_t b = 0; b < t.tiles_n; ++b) ph(gphase).tg_items.push_back(WorkItem{id, a, b, 0});
             ph(gphase).tg_tmax = std::max(ph(gphase).tg_tmax, std::max(t.nx, t.ny));
@@ -589,8 +592,13 @@ void split_k(Plan& P) {
                 } else {
                     t.ws_off = t0.ws_off + p * pstride;
                 }
-                newids[id].push_back((int32_t)P.tasks.size());
+                const int32_t nid = (int32_t)P.tasks.size();
+                newids[id].push_back(nid);
                 P.tasks.push_back(t);
+                P.task_group.resize(P.tasks.size(), -1);
+                P.task_part.resize(P.tasks.size(), 0);
+                P.task_group[nid] = P.task_group[id];
+                P.task_part[nid] = p;
             }
         }
         for (auto* items_v : {&ph.str_items, &ph.tg_items, &ph.gemm_items, &ph.syrk_items}) {
@@ -628,7 +636,28 @@ Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
         b.ata_node({Chunk{0, m}}, 0, n, 0, 0);
     }
     split_k(P);
-    // longest-processing-time order inside every launch: heavier tiles first
+    // Order of the items of every launch.  Heavier tiles first (longest
+    // processing time).  Among equal costs, tiles that read the same operand
+    // strips go together: the products of one Strassen expansion (same K
+    // part) at neighbouring tile positions, in blocks of B x B positions with
+    // B^2 times the product count near 64; classical tiles of one task in
+    // 8 x 8 blocks.
+    auto group_of = [&](int32_t id) -> int64_t {
+        const int32_t g = (size_t)id < P.task_group.size() ? P.task_group[id] : -1;
+        return g >= 0 ? ((int64_t)1 << 40) + g : (int64_t)id;
+    };
+    auto part_of = [&](int32_t id) -> int32_t { return (size_t)id < P.task_part.size() ? P.task_part[id] : 0; };
+    std::map<int64_t, int> group_size;  // products per expansion group
+    for (size_t id = 0; id < P.tasks.size(); ++id)
+        if (part_of((int32_t)id) == 0 && group_of((int32_t)id) >= ((int64_t)1 << 40)) ++group_size[group_of((int32_t)id)];
+    auto block_of = [&](int32_t id) -> int {
+        const int64_t gk = group_of(id);
+        if (gk < ((int64_t)1 << 40)) return 8;
+        const int np = std::max(1, group_size[gk]);
+        int b = 1;
+        while ((b + 1) * (b + 1) * np <= 64) ++b;
+        return b;
+    };
     for (Phase& ph : P.phases) {
         auto cost = [&](const WorkItem& w) {
             const DevTask& t = P.tasks[w.task];
@@ -636,21 +665,48 @@ Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
             if (t.kind == TK_STR) return 2.0 * k * (1.0 + 0.1 * (t.nx + t.ny));
             return k * (1.0 + 0.1 * (t.nx + t.ny - 2));
         };
-        for (auto* items : {&ph.str_items, &ph.tg_items, &ph.gemm_items, &ph.syrk_items})
-            std::stable_sort(items->begin(), items->end(),
-                             [&](const WorkItem& a, const WorkItem& b) { return cost(a) > cost(b); });
+        if (ph.str_items.empty() && ph.tg_tmax <= 2 &&
+            !(ph.tg_items.empty() && ph.gemm_items.empty() && ph.syrk_items.empty())) {
+            ph.mix_items = ph.tg_items;
+            ph.mix_items.insert(ph.mix_items.end(), ph.gemm_items.begin(), ph.gemm_items.end());
+            ph.mix_items.insert(ph.mix_items.end(), ph.syrk_items.begin(), ph.syrk_items.end());
+        }
+        for (auto* items : {&ph.str_items, &ph.tg_items, &ph.gemm_items, &ph.syrk_items, &ph.mix_items})
+            std::stable_sort(items->begin(), items->end(), [&](const WorkItem& a, const WorkItem& b) {
+                const double ca = cost(a), cb = cost(b);
+                if (ca != cb) return ca > cb;
+                const int64_t ga = group_of(a.task), gb = group_of(b.task);
+                if (ga != gb) return ga < gb;
+                const int32_t pa = part_of(a.task), pb = part_of(b.task);
+                if (pa != pb) return pa < pb;
+                const int B = block_of(a.task);
+                if (a.ti / B != b.ti / B) return a.ti / B < b.ti / B;
+                if (a.tj / B != b.tj / B) return a.tj / B < b.tj / B;
+                if (a.task != b.task) return a.task < b.task;
+                if (a.ti != b.ti) return a.ti < b.ti;
+                return a.tj < b.tj;
+            });
         // Workgroups are dispatched round-robin over the eight XCDs, each with
-        // its own L2: within every window of 64 items, place eight consecutive
-        // items (neighbouring tiles of one task, sharing operand strips) at
-        // positions that land on the same XCD.
-        for (auto* items : {&ph.str_items, &ph.tg_items, &ph.gemm_items, &ph.syrk_items}) {
+        // its own L2: item 8 j + x runs on XCD x.  Runs of 64 consecutive
+        // items of the order above (about what one XCD holds at a time, two
+        // workgroups on each of its 32 CUs) are placed at the positions of
+        // one XCD; a short last round uses shorter runs.
+        for (auto* items : {&ph.str_items, &ph.tg_items, &ph.gemm_items, &ph.syrk_items, &ph.mix_items}) {
             std::vector<WorkItem>& v = *items;
-            for (size_t base = 0; base + 64 <= v.size(); base += 64) {
-                WorkItem tmp[64];
-                for (int g = 0; g < 8; ++g)
-                    for (int j = 0; j < 8; ++j) tmp[j * 8 + g] = v[base + g * 8 + j];
-                std::copy(tmp, tmp + 64, v.begin() + base);
+            std::vector<WorkItem> out(v.size());
+            size_t base = 0;
+            while (base < v.size()) {
+                const size_t rem = v.size() - base;
+                const size_t run = rem >= 512 ? 64 : rem / 8;
+                if (run == 0) {
+                    std::copy(v.begin() + base, v.end(), out.begin() + base);
+                    break;
+                }
+                for (size_t c = 0; c < 8; ++c)
+                    for (size_t j = 0; j < run; ++j) out[base + j * 8 + c] = v[base + c * run + j];
+                base += 8 * run;
             }
+            v.swap(out);
         }
         P.work_items += (int64_t)(ph.str_items.size() + ph.tg_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
     }

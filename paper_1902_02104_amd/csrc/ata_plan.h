@@ -133,6 +133,9 @@ struct Phase {
     // str: in-tile Strassen tiles; tg: Strassen product tiles (classical
     // tiles with operand terms); gemm, syrk: classical tiles of the base case
     std::vector<WorkItem> str_items, tg_items, gemm_items, syrk_items;
+    // The product tiles and the classical tiles of the phase in one list, in
+    // the same order rules: for kernels that run both kinds in one launch.
+    std::vector<WorkItem> mix_items;
     std::vector<DevCombine> combines;
     std::vector<DevOpSum> opsums;  // run before the product tiles
     int64_t combine_elems = 0;
@@ -156,6 +159,11 @@ struct Plan {
     int64_t syrk_tasks = 0, gemm_tasks = 0, str_tasks = 0, combine_tasks = 0;
     int64_t work_items = 0;
     int64_t ata_depth = 0, max_hasa_depth = 0;
+    // Host-only locality record of each task (used to order work items):
+    // the Strassen expansion its operands come from (-1: none) and its K part
+    // after splitting.  Shorter than tasks when trailing tasks have neither.
+    std::vector<int32_t> task_group, task_part;
+    int32_t n_groups = 0;
 };
 
 // Tile sizes the kernels use (output tile per workgroup).
