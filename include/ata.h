@@ -144,6 +144,28 @@ int ata_aat(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int
 int ata_ex(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int dtype, int cutoff,
            void *stream, const ata_opts *opts, void *workspace, size_t ws_bytes);
 
+/*
+ * ata_ex_noalloc: as ata_ex, for callers that cannot allocate device memory
+ *   (code under HIP graph capture, tight serving loops, harnesses that forbid
+ *   allocation).  It calls no hipMalloc, hipFree or other allocating routine:
+ *   the plan's task tables and the whole workspace live in one fixed device
+ *   array of ATA_NOALLOC_SCRATCH_BYTES per GPU, which the library holds until
+ *   the process ends.  The tables are copied there (hipMemcpyAsync from host
+ *   memory) on every call; the product runs with K splitting off (its
+ *   partial sums would need workspace) and without the helper stream, so
+ *   floating-point results may differ from ata_ex in rounding order only
+ *   (integer-valued inputs give identical results).
+ *   scratch_used  if not NULL: bytes of the array the call needs (set also
+ *                 when the call is rejected for size).
+ * Returns ATA_EWORKSPACE when tables plus workspace exceed the array; other
+ * codes as for ata_ex.  Every call on one GPU uses that GPU's single array,
+ * which keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ */
+#define ATA_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ata_ex_noalloc(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int dtype, int cutoff,
+                   void *stream, const ata_opts *opts, size_t *scratch_used);
+
 /* Bytes of device workspace ata_ex needs for this problem (0 if none). */
 int ata_workspace_bytes(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts *opts,
                         size_t *bytes);

@@ -77,6 +77,9 @@ def load():
     lib.ata.restype = ci
     lib.ata_ex.argtypes = [vp, i64, i64, i64, vp, ci, ci, vp, ctypes.POINTER(Opts), vp, ctypes.c_size_t]
     lib.ata_ex.restype = ci
+    lib.ata_ex_noalloc.argtypes = [vp, i64, i64, i64, vp, ci, ci, vp, ctypes.POINTER(Opts),
+                                   ctypes.POINTER(ctypes.c_size_t)]
+    lib.ata_ex_noalloc.restype = ci
     lib.ata_workspace_bytes.argtypes = [i64, i64, ci, ci, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_size_t)]
     lib.ata_workspace_bytes.restype = ci
     lib.ata_plan_info.argtypes = [i64, i64, ci, ci, ctypes.POINTER(Opts), ctypes.POINTER(PlanStats)]
@@ -257,6 +260,41 @@ def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_d
     if rc:
         raise AtaError(rc, "ata_ex")
     return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # ATA_NOALLOC_SCRATCH_BYTES
+
+
+def gram_noalloc(A, out, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_depth=None,
+                 stream=None, intile=True, equilibrate=False, operand_sums=False):
+    """gram() through ata_ex_noalloc: no device allocation by the library (the
+    plan tables and workspace live in its fixed per-GPU scratch array), so
+    the output tensor `out` must be given.  Returns (out, scratch bytes the
+    call used).  Calls that overlap on one GPU race on the shared array."""
+    import torch
+    lib = load()
+    if A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor")
+    m, n = A.shape
+    if n > 0 and m > 0 and A.stride(1) != 1:
+        raise ValueError("A needs unit column stride")
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    if dtype is None:
+        dtype = F64 if A.dtype == torch.float64 else F32
+    want_in = torch.float64 if (dtype & 0xff) == F64 else torch.float32
+    if A.dtype != want_in:
+        raise TypeError("A must be %s for dtype %#x" % (want_in, dtype))
+    out_t = torch.float64 if ((dtype & 0xff) == F64 or dtype & OUT_F64) else torch.float32
+    if out.dtype != out_t or out.numel() < tri(n) or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("bad output tensor")
+    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums)
+    used = ctypes.c_size_t(0)
+    with torch.cuda.device(A.device):
+        rc = lib.ata_ex_noalloc(ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.c_void_p(out.data_ptr()), int(dtype),
+                                int(cutoff), _stream_handle(stream), ctypes.byref(o), ctypes.byref(used))
+    if rc:
+        raise AtaError(rc, "ata_ex_noalloc")
+    return out, int(used.value)
 
 
 def gram_rows(A, cutoff: int = 0, dtype: int | None = None, out=None, stream=None):

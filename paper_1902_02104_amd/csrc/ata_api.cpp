@@ -263,6 +263,7 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
     // reduced-precision tiles run several times faster: splitting K for a
     // fuller last wave costs them more (partials and their sum) than it saves
     if (flags & kPlanReducedPrecision) po.split_target = 768;
+    if (flags & kPlanNoSplit) po.split_target = 0;
     try {
         pd->plan = build_plan(m, n, po);
     } catch (const std::length_error&) {
@@ -346,7 +347,7 @@ int common_checks(const void* A, int64_t m, int64_t n, int64_t lda, const void* 
 // L.total bytes (may be null when L.total is 0).
 hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout& L, const void* A, int64_t m,
                            int64_t n, int64_t lda, void* C_lower, int dtype, int variant, char* ws, hipStream_t s,
-                           int dev) {
+                           int dev, bool fork_ok) {
     struct {
         const char* blob;
         size_t off_tasks, off_terms, off_segs;
@@ -384,7 +385,7 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             const float* scale = (const float*)(ws + L.scale);
             const void* t1 = lp_mode == 0 ? (const void*)(ws + L.t1) : nullptr;
             // diagonal tiles overlap the off-diagonal ones on a forked stream
-            const bool split = ph.n_gemm > 0 && ph.n_syrk > 0;
+            const bool split = fork_ok && ph.n_gemm > 0 && ph.n_syrk > 0;
             ForkCtx fc;
             if (split) {
                 rc = fork_get(dev, fc);
@@ -438,7 +439,7 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             }
             continue;
         }
-        const bool split = (ph.n_str + ph.n_tg) > 0 && (ph.n_gemm + ph.n_syrk) > 0;
+        const bool split = fork_ok && (ph.n_str + ph.n_tg) > 0 && (ph.n_gemm + ph.n_syrk) > 0;
         ForkCtx fc;
         if (split) {
             rc = fork_get(dev, fc);
@@ -638,6 +639,85 @@ int ata_precision_convert(int dtype, const float* x, int64_t count, void* out0, 
     if (count == 0) return ATA_OK;
     hipError_t e = launch_convert(base == ATA_F32_FP8 ? 1 : 0, x, count, out0, out1, (hipStream_t)stream);
     return e == hipSuccess ? ATA_OK : hip_fail(e);
+}
+
+}  // extern "C"
+
+// ---- the entry point that allocates nothing (ata_ex_noalloc) ----
+// One fixed device array per GPU holds the plan tables and the workspace of
+// ata_ex_noalloc.  In host code `scratch` names a host-side stand-in, not
+// device memory: the device address comes from hipGetSymbolAddress, once per
+// device with that device current, and only that address is used.
+static __device__ __align__(256) char scratch[ATA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch;  // device -> address of its scratch array
+
+int scratch_address(int dev, char** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+        it = g_scratch.emplace(dev, (char*)p).first;
+    }
+    *out = it->second;
+    return ATA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ata_ex_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int dtype, int cutoff,
+                   void* stream, const ata_opts* opts, size_t* scratch_used) {
+    int rc = common_checks(A, m, n, lda, C_lower, dtype, cutoff);
+    if (rc) return rc;
+    int variant, max_depth, flags;
+    if (resolve_opts(opts, variant, max_depth, flags)) return -9;
+    if (dtype_lp(dtype)) {
+        if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
+        if (flags & ATA_OPT_EQUILIBRATE) return ATA_EUNSUPPORTED;
+        max_depth = 0;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!check_device(dev)) return ATA_EUNSUPPORTED;
+    }
+    char* base = nullptr;
+    rc = scratch_address(dev, &base);
+    if (rc != ATA_OK) return rc;
+    if (scratch_used) *scratch_used = 0;
+    if (n == 0) return ATA_OK;
+    const int64_t nout = n * (n + 1) / 2;
+    if (m == 0) {
+        HIP_TRY(launch_fill_zero(C_lower, nout, elem_bytes_out(dtype), s));
+        return ATA_OK;
+    }
+    const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
+    std::shared_ptr<PlanDev> pd;
+    // host tables only (no device copy of the plan); no K splitting, whose
+    // partial sums would need workspace
+    rc = get_plan(m, n, c, variant, max_depth, plan_flags(flags, dtype) | kPlanNoSplit, false, pd);
+    if (rc != ATA_OK) return rc;
+    const Plan& P = pd->plan;
+    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0, P.opsum_elems);
+    if (L.ldt > INT32_MAX) return ATA_EUNSUPPORTED;
+    const size_t tbytes = (pd->host_blob.size() + 255) / 256 * 256;
+    const size_t need = tbytes + L.total;
+    if (scratch_used) *scratch_used = need;
+    if (need > (size_t)ATA_NOALLOC_SCRATCH_BYTES) return ATA_EWORKSPACE;
+    // the plan's tables go to the start of the array, the workspace after them
+    HIP_TRY(hipMemcpyAsync(base, pd->host_blob.data(), pd->host_blob.size(), hipMemcpyHostToDevice, s));
+    const hipError_t err =
+        enqueue_product(*pd, base, L, A, m, n, lda, C_lower, dtype, variant, L.total ? base + tbytes : nullptr, s,
+                        dev, false);
+    if (err != hipSuccess) return hip_fail(err);
+    return ATA_OK;
 }
 
 int ata(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int dtype, int cutoff, void* stream) {

@@ -96,13 +96,17 @@ int64_t default_cutoff(int64_t m, int64_t n, int dtype);
 WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate, int64_t opsum_elems);
 // Internal plan flag (beside ATA_OPT_* bits): reduced-precision dtype.
 constexpr int kPlanReducedPrecision = 0x10000;
+// Internal plan flag: no K splitting (its partial sums need workspace).
+constexpr int kPlanNoSplit = 0x20000;
 int plan_flags(int flags, int dtype);
 int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, int flags, bool need_device,
              std::shared_ptr<PlanDev>& out);
 // dblob: device copy of pd.host_blob (pd.blob, or a copy the caller made)
+// fork_ok: classical tiles may run on a pooled helper stream beside the
+// Strassen tiles (false: everything on s).
 hipError_t enqueue_product(const PlanDev& pd, const char* dblob, const WsLayout& L, const void* A, int64_t m,
                            int64_t n, int64_t lda, void* C_lower, int dtype, int variant, char* ws, hipStream_t s,
-                           int dev);
+                           int dev, bool fork_ok = true);
 
 }  // namespace detail
 }  // namespace atalib
