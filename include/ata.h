@@ -97,11 +97,27 @@ typedef struct ata_opts {
  * over A and m x n elements of workspace.  FP64 and FP32 only (the reduced-
  * precision forms scale columns themselves). */
 #define ATA_OPT_EQUILIBRATE 0x2
+/* ata_opts.flags: adaptive depth.  A Strassen level of an off-diagonal
+ * product is taken only where it is faster than classical tiles by a cost
+ * model of this library's tile kernels: tile counts of the product before and
+ * after the split, the measured fractions of the MFMA peak that classical
+ * tiles and Strassen tiles reach on gfx950, and the cost of the combination.
+ * max_depth still caps the levels.  (The paper's HASA stops at the cutoff
+ * alone; this is its adaptive stopping rule driven by measured rates.) */
+#define ATA_OPT_ADAPTIVE 0x8
+/* ata_opts.flags: equilibrate (as ATA_OPT_EQUILIBRATE) exactly when the plan
+ * runs a Strassen level, whose error bound depends on the largest columns;
+ * classical products keep each entry's error relative to its own columns
+ * without it. */
+#define ATA_OPT_EQUILIBRATE_AUTO 0x10
 
-/* One Strassen level per off-diagonal product: on gfx950 FP64 and FP32 a
- * second level costs more in operand-sum traffic than its 1/8 saving in
- * multiplications. */
+/* Defaults when the options struct is NULL: Strassen variant, at most
+ * ATA_DEFAULT_MAX_DEPTH levels, flags ATA_DEFAULT_FLAGS (adaptive depth and
+ * equilibration with Strassen levels), and for ATA_F64 the product-tile
+ * form, the faster of the fused forms there.  A second level costs more in
+ * operand-sum traffic than its 1/8 saving in multiplications on gfx950. */
 #define ATA_DEFAULT_MAX_DEPTH 1
+#define ATA_DEFAULT_FLAGS (ATA_OPT_ADAPTIVE | ATA_OPT_EQUILIBRATE_AUTO)
 #define ATA_MAX_DEPTH_LIMIT 4 /* deepest supported Strassen level count */
 
 /*
@@ -306,6 +322,10 @@ typedef struct ata_request_info {
     int32_t stream;     /* stream index it ran on */
     int64_t footprint;  /* bytes held in the pool while in flight */
     double flops;       /* m * n * n, the classical count of the metric */
+    int32_t slabs;      /* row slabs it ran in (1 unless chunked: requests
+                           above 4e10 flops run in slabs of about 2e10, each
+                           launched after the previous one completes) */
+    int32_t reserved;
 } ata_request_info;
 
 typedef struct ata_server_stats {
@@ -319,6 +339,9 @@ typedef struct ata_server_stats {
 #define ATA_SERVER_SIMULATE 1 /* host-only: no device memory or kernels; a
                                  request completes flops / (simulate_tflops 1e12)
                                  seconds after admission.  For scheduler tests. */
+/* In simulate mode a request with src ATA_SRC_NORMAL and this seed ends with
+ * status ATA_EHIP, to exercise the failure path. */
+#define ATA_SERVER_SIM_FAIL_SEED 0xFFFFFFFFFFFFFFFFull
 
 /* budget_bytes > 0; max_active >= 1; streams in [1, 16]; flags ATA_SERVER_*. */
 int ata_server_create(size_t budget_bytes, int max_active, int streams, int flags, double simulate_tflops,
@@ -331,9 +354,12 @@ int ata_server_query(ata_server *srv, uint64_t ticket, ata_request_info *info);
 /* Block until done or timeout_s elapses (ATA_EPENDING). */
 int ata_server_wait(ata_server *srv, uint64_t ticket, double timeout_s, ata_request_info *info);
 /* Copy the packed result (n(n+1)/2 elements of the request's type) to `c`
- * (device memory if c_on_device, else host) and, if `a_host` is not NULL, A
- * (m x n) to host memory; then release the request's pool memory. */
-int ata_server_take(ata_server *srv, uint64_t ticket, void *c, int c_on_device, void *a_host);
+ * and, if `a` is not NULL, the request's A (m x n, row-major; it must have
+ * been submitted with keep_a = 1, else -4) to `a`; both are device memory if
+ * on_device, else host memory.  Either pointer may be NULL.  Then release the
+ * request's pool memory.  A request that ended with an error is released by
+ * this call (nothing is copied) and its error status is returned. */
+int ata_server_take(ata_server *srv, uint64_t ticket, void *c, void *a, int on_device);
 /* Release a finished request without copying anything. */
 int ata_server_release(ata_server *srv, uint64_t ticket);
 int ata_server_get_stats(ata_server *srv, ata_server_stats *out);

@@ -28,6 +28,8 @@ DEFAULT_MAX_DEPTH = 1
 OPT_PRODUCT_TILES = 0x1
 OPT_EQUILIBRATE = 0x2
 OPT_OPERAND_SUMS = 0x4
+OPT_ADAPTIVE = 0x8
+OPT_EQUILIBRATE_AUTO = 0x10
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _lib = None
@@ -124,34 +126,45 @@ def tri(n: int) -> int:
     return n * (n + 1) // 2
 
 
-def _opts(variant, max_depth, dtype=F64, intile=True, equilibrate=False, operand_sums=False):
+def _opts(variant, max_depth, dtype=F64, intile=None, equilibrate=None, operand_sums=False, adaptive=None):
+    """The options struct for a call, or None for the library's defaults
+    (ATA_DEFAULT_MAX_DEPTH levels, adaptive depth, equilibration with
+    Strassen levels, product tiles for FP64) when nothing is chosen."""
+    if (max_depth is None and intile is None and equilibrate is None and not operand_sums and adaptive is None
+            and variant in ("strassen", STRASSEN)):
+        return None
     o = Opts()
     o.variant = {"strassen": STRASSEN, "winograd": WINOGRAD}.get(variant, variant)
     if max_depth is None:
-        # reduced-precision leaves are classical; other forms fuse two Strassen levels
+        # reduced-precision leaves are classical; the other forms take the default level count
         max_depth = 0 if (dtype & 0xff) in (F32_BF16X3, F32_FP8) else DEFAULT_MAX_DEPTH
     o.max_depth = int(max_depth)
+    intile = True if intile is None else intile
     o.flags = ((0 if intile else OPT_PRODUCT_TILES) | (OPT_EQUILIBRATE if equilibrate else 0)
-               | (OPT_OPERAND_SUMS if operand_sums else 0))
+               | (OPT_OPERAND_SUMS if operand_sums else 0) | (OPT_ADAPTIVE if adaptive else 0))
     return o
 
 
+def _optp(o):
+    return ctypes.byref(o) if o is not None else None
+
+
 def plan_info(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None,
-              intile=True, equilibrate=False, operand_sums=False) -> dict:
+              intile=None, equilibrate=None, operand_sums=False, adaptive=None) -> dict:
     """Host-only description of the device plan (no GPU needed)."""
     st = PlanStats()
-    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums)
-    rc = load().ata_plan_info(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(st))
+    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums, adaptive)
+    rc = load().ata_plan_info(int(m), int(n), int(dtype), int(cutoff), _optp(o), ctypes.byref(st))
     if rc:
         raise AtaError(rc, "ata_plan_info")
     return st.as_dict()
 
 
 def workspace_bytes(m: int, n: int, cutoff: int = 0, dtype: int = F64, variant="strassen", max_depth=None,
-                    intile=True, equilibrate=False, operand_sums=False) -> int:
+                    intile=None, equilibrate=None, operand_sums=False, adaptive=None) -> int:
     out = ctypes.c_size_t(0)
-    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums)
-    rc = load().ata_workspace_bytes(int(m), int(n), int(dtype), int(cutoff), ctypes.byref(o), ctypes.byref(out))
+    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums, adaptive)
+    rc = load().ata_workspace_bytes(int(m), int(n), int(dtype), int(cutoff), _optp(o), ctypes.byref(out))
     if rc:
         raise AtaError(rc, "ata_workspace_bytes")
     return int(out.value)
@@ -220,7 +233,7 @@ def _stream_handle(stream):
 
 
 def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_depth=None, out=None,
-         workspace=None, stream=None, intile=True, equilibrate=False, operand_sums=False):
+         workspace=None, stream=None, intile=None, equilibrate=None, operand_sums=False, adaptive=None):
     """Packed lower triangle of A^t A for a 2-D CUDA tensor A (row-major rows,
     unit column stride, row stride >= n).  Asynchronous on `stream` (default:
     torch's current stream).  Returns the packed output tensor.  intile: run
@@ -249,13 +262,13 @@ def gram(A, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_d
         out = torch.empty(tri(n), dtype=out_t, device=A.device)
     elif out.dtype != out_t or out.numel() < tri(n) or not out.is_contiguous():
         raise ValueError("bad output tensor")
-    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums)
+    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums, adaptive)
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
     with torch.cuda.device(A.device):
         rc = lib.ata_ex(ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.c_void_p(out.data_ptr()), int(dtype),
-                        int(cutoff), _stream_handle(stream), ctypes.byref(o),
+                        int(cutoff), _stream_handle(stream), _optp(o),
                         ctypes.c_void_p(ws_ptr) if ws_ptr else None, ws_bytes)
     if rc:
         raise AtaError(rc, "ata_ex")
@@ -266,7 +279,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20  # ATA_NOALLOC_SCRATCH_BYTES
 
 
 def gram_noalloc(A, out, cutoff: int = 0, dtype: int | None = None, variant="strassen", max_depth=None,
-                 stream=None, intile=True, equilibrate=False, operand_sums=False):
+                 stream=None, intile=None, equilibrate=None, operand_sums=False, adaptive=None):
     """gram() through ata_ex_noalloc: no device allocation by the library (the
     plan tables and workspace live in its fixed per-GPU scratch array), so
     the output tensor `out` must be given.  Returns (out, scratch bytes the
@@ -287,11 +300,11 @@ def gram_noalloc(A, out, cutoff: int = 0, dtype: int | None = None, variant="str
     out_t = torch.float64 if ((dtype & 0xff) == F64 or dtype & OUT_F64) else torch.float32
     if out.dtype != out_t or out.numel() < tri(n) or not out.is_contiguous() or not out.is_cuda:
         raise ValueError("bad output tensor")
-    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums)
+    o = _opts(variant, max_depth, dtype, intile, equilibrate, operand_sums, adaptive)
     used = ctypes.c_size_t(0)
     with torch.cuda.device(A.device):
         rc = lib.ata_ex_noalloc(ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.c_void_p(out.data_ptr()), int(dtype),
-                                int(cutoff), _stream_handle(stream), ctypes.byref(o), ctypes.byref(used))
+                                int(cutoff), _stream_handle(stream), _optp(o), ctypes.byref(used))
     if rc:
         raise AtaError(rc, "ata_ex_noalloc")
     return out, int(used.value)

@@ -5,6 +5,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <list>
 #include <map>
 #include <set>
 #include <memory>
@@ -41,6 +42,49 @@ using PlanKey = std::tuple<int, int64_t, int64_t, int64_t, int, int, int>;
 
 std::mutex g_mu;
 std::map<PlanKey, std::shared_ptr<PlanDev>> g_plans;
+// Least recently used order of the cached plans (front = oldest) and the cap:
+// a stream of shapes (serving draws m and n at random) would otherwise keep
+// every plan it ever built.
+std::list<PlanKey> g_plan_lru;
+std::map<PlanKey, std::list<PlanKey>::iterator> g_plan_pos;
+constexpr size_t kPlanCacheCap = 256;
+
+void plan_touch(const PlanKey& key) {
+    auto it = g_plan_pos.find(key);
+    if (it != g_plan_pos.end()) g_plan_lru.erase(it->second);
+    g_plan_lru.push_back(key);
+    g_plan_pos[key] = std::prev(g_plan_lru.end());
+}
+
+// Drop the oldest plans beyond the cap (caller holds g_mu).  Callers that
+// still use a plan hold their own reference.  A device copy of the tables
+// may still be read by queued products, so the devices holding evicted copies
+// are synchronised before the copies are freed (outside the lock, by the
+// caller, through `freed`).
+void plan_evict(std::vector<std::shared_ptr<PlanDev>>& freed) {
+    while (g_plans.size() > kPlanCacheCap && !g_plan_lru.empty()) {
+        const PlanKey k = g_plan_lru.front();
+        g_plan_lru.pop_front();
+        g_plan_pos.erase(k);
+        auto it = g_plans.find(k);
+        if (it == g_plans.end()) continue;
+        freed.push_back(it->second);
+        g_plans.erase(it);
+    }
+}
+
+void plan_release(std::vector<std::shared_ptr<PlanDev>>& freed) {
+    int cur = -1;
+    for (auto& pd : freed) {
+        if (pd->blob && pd.use_count() == 1) {
+            if (cur < 0) (void)hipGetDevice(&cur);
+            (void)hipSetDevice(pd->device);
+            (void)hipDeviceSynchronize();
+        }
+        pd.reset();
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+}
 std::map<int, int> g_device_ok;  // device -> 1 gfx950, 0 not
 
 int check_device(int dev) {
@@ -149,12 +193,14 @@ int upload(PlanDev& pd, int dev) {
 int resolve_opts(const ata_opts* opts, int& variant, int& max_depth, int& flags) {
     variant = ATA_VARIANT_STRASSEN;
     max_depth = ATA_DEFAULT_MAX_DEPTH;
-    flags = 0;
+    flags = ATA_DEFAULT_FLAGS;
     if (opts) {
         variant = opts->variant;
         max_depth = opts->max_depth;
         flags = opts->flags;
-        if (flags & ~(ATA_OPT_PRODUCT_TILES | ATA_OPT_EQUILIBRATE | ATA_OPT_OPERAND_SUMS)) return -1;
+        if (flags & ~(ATA_OPT_PRODUCT_TILES | ATA_OPT_EQUILIBRATE | ATA_OPT_OPERAND_SUMS | ATA_OPT_ADAPTIVE |
+                      ATA_OPT_EQUILIBRATE_AUTO))
+            return -1;
     }
     if (variant != ATA_VARIANT_STRASSEN && variant != ATA_VARIANT_WINOGRAD) return -1;
     if (max_depth < -1) return -1;
@@ -167,7 +213,21 @@ int elem_bytes_in(int dtype) { return (dtype & 0xff) == ATA_F64 ? 8 : 4; }
 // key): tables differ between the product-tile and in-tile forms and in the
 // split-K target of the reduced-precision forms.
 int plan_flags(int flags, int dtype) {
-    return (flags & (ATA_OPT_PRODUCT_TILES | ATA_OPT_OPERAND_SUMS)) | (dtype_lp(dtype) ? kPlanReducedPrecision : 0);
+    int f = (flags & (ATA_OPT_PRODUCT_TILES | ATA_OPT_OPERAND_SUMS | ATA_OPT_ADAPTIVE)) |
+            (dtype_lp(dtype) ? kPlanReducedPrecision : 0);
+    if ((flags & ATA_OPT_ADAPTIVE) && (dtype & 0xff) != ATA_F64) f |= kPlanF32;
+    if ((flags & ATA_OPT_ADAPTIVE) && !dtype_lp(dtype)) f |= flags & ATA_OPT_EQUILIBRATE_AUTO;
+    return f;
+}
+bool want_equilibrate(int flags, const Plan& P, int dtype) {
+    if (dtype_lp(dtype)) return false;
+    if (flags & ATA_OPT_EQUILIBRATE) return true;
+    return (flags & ATA_OPT_EQUILIBRATE_AUTO) && P.str_mults > 0;
+}
+// Default form for a NULL options struct: FP64 runs its Strassen levels as
+// product tiles (the faster fused form there).
+int default_form_flags(const ata_opts* opts, int dtype) {
+    return (!opts && (dtype & 0xff) == ATA_F64) ? ATA_OPT_PRODUCT_TILES : 0;
 }
 int elem_bytes_out(int dtype) {
     if ((dtype & 0xff) == ATA_F64) return 8;
@@ -247,10 +307,16 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
         HIP_TRY(hipGetDevice(&dev));
     }
     const PlanKey key{dev, m, n, cutoff, variant, max_depth, flags};
+    std::vector<std::shared_ptr<PlanDev>> freed;
+    struct Release {
+        std::vector<std::shared_ptr<PlanDev>>& f;
+        ~Release() { plan_release(f); }
+    } release{freed};  // runs after the lock below is dropped
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         out = it->second;
+        plan_touch(key);
         return ATA_OK;
     }
     auto pd = std::make_shared<PlanDev>();
@@ -264,6 +330,23 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
     // fuller last wave costs them more (partials and their sum) than it saves
     if (flags & kPlanReducedPrecision) po.split_target = 768;
     if (flags & kPlanNoSplit) po.split_target = 0;
+    if (flags & kPlanAccumulate) po.accumulate = true;
+    if (flags & ATA_OPT_ADAPTIVE) {
+        // Fractions of the MFMA peak measured on MI355X for this library's
+        // tiles (rocprof MFMA busy of whole launches at 10000^2): FP64
+        // classical tiles 0.855, FP64 two-term product tiles 0.76, FP64
+        // in-tile Strassen 0.48; FP32 classical tiles 0.66, FP32 Strassen
+        // tiles about 0.48.  Combination: about 48 bytes of memory traffic per
+        // output element at 5 TB/s, 0.023 of a 128 x 128 x 1 tile step.
+        po.adaptive = true;
+        const bool f32 = (flags & kPlanF32) != 0;
+        po.rate_one = f32 ? 0.66 : 0.855;
+        po.rate_two = f32 ? 0.48 : (po.intile ? 0.48 : 0.76);
+        po.comb = 0.023;
+        // equilibration that comes with Strassen levels: a column-maximum
+        // pass and a scaled copy, three element transfers per element of A
+        if (flags & ATA_OPT_EQUILIBRATE_AUTO) po.eq = f32 ? 0.0058 : 0.0115;
+    }
     try {
         pd->plan = build_plan(m, n, po);
     } catch (const std::length_error&) {
@@ -279,6 +362,8 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
         if (rc != ATA_OK) return rc;
     }
     g_plans[key] = pd;
+    plan_touch(key);
+    plan_evict(freed);
     out = pd;
     return ATA_OK;
 }
@@ -320,6 +405,17 @@ int fork_get(int dev, ForkCtx& c) {
 void fork_put(int dev, const ForkCtx& c) {
     std::lock_guard<std::mutex> lk(g_fork_mu);
     g_fork_pool[dev].push_back(c);
+}
+
+// Join the forked stream back into s, also after a failed launch: whatever
+// was queued on the fork before the failure must finish before later work
+// on s (a stream-ordered free of the workspace, say).  Keeps the first error.
+void join_fork(ForkCtx& fc, hipStream_t s, hipError_t& err, int dev) {
+    const hipError_t e1 = hipEventRecord(fc.join, fc.s2);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s, fc.join, 0) : e1;
+    if (e2 != hipSuccess) (void)hipStreamSynchronize(fc.s2);  // the event could not order them
+    if (err == hipSuccess) err = e2;
+    fork_put(dev, fc);
 }
 
 // ---- kernel timing (measurement tools only; ProfScope in ata_internal.h) ----
@@ -406,11 +502,7 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
                                      (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, W, s_small,
                                      pdr.lp_aligned[lp_mode]);
             }
-            if (split) {
-                if (err == hipSuccess) err = hipEventRecord(fc.join, fc.s2);
-                if (err == hipSuccess) err = hipStreamWaitEvent(s, fc.join, 0);
-                fork_put(dev, fc);
-            }
+            if (split) join_fork(fc, s, err, dev);
             if (err == hipSuccess && ph.n_cb) {  // sums of split K parts
                 ProfScope ps(ATA_KERNEL_COMBINE, s);
                 err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W,
@@ -481,11 +573,7 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             err = f32 ? launch_gemm(f32, out64, A, lda, tb, it, ph.n_syrk, C_lower, W, s_small)
                       : launch_tile(1, (const double*)A, lda, tb, it, ph.n_syrk, (double*)C_lower, W, s_small);
         }
-        if (split) {
-            if (err == hipSuccess) err = hipEventRecord(fc.join, fc.s2);
-            if (err == hipSuccess) err = hipStreamWaitEvent(s, fc.join, 0);
-            fork_put(dev, fc);
-        }
+        if (split) join_fork(fc, s, err, dev);
         if (err == hipSuccess && ph.n_cb) {
             ProfScope ps(ATA_KERNEL_COMBINE, s);
             err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W, C_lower, s);
@@ -534,6 +622,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     if (cutoff < 0) return -4;
     int variant, max_depth, flags;
     if (resolve_opts(opts, variant, max_depth, flags)) return -5;
+    flags |= default_form_flags(opts, dtype);
     if (!out) return -6;
     if (dtype_lp(dtype)) {
         if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
@@ -556,7 +645,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     out->phases = (int64_t)P.phases.size();
     out->ata_depth = P.ata_depth;
     out->max_hasa_depth = P.max_hasa_depth;
-    out->workspace_bytes = (int64_t)ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0, P.opsum_elems).total;
+    out->workspace_bytes = (int64_t)ws_layout(m, n, dtype, P.ws_elems, want_equilibrate(flags, P, dtype), P.opsum_elems).total;
     out->cutoff = c;
     out->strassen_mults = P.str_mults;
     out->gemm_mults = P.gemm_mults;
@@ -580,6 +669,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     if (rc) return rc;
     int variant, max_depth, flags;
     if (resolve_opts(opts, variant, max_depth, flags)) return -9;
+    flags |= default_form_flags(opts, dtype);
     const bool lp = dtype_lp(dtype);
     if (lp) {
         // reduced-precision leaves: classical off-diagonal products only
@@ -606,7 +696,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     rc = get_plan(m, n, c, variant, max_depth, plan_flags(flags, dtype), true, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
-    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0, P.opsum_elems);
+    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, want_equilibrate(flags, P, dtype), P.opsum_elems);
     if (L.ldt > INT32_MAX) return ATA_EUNSUPPORTED;
     char* ws = nullptr;
     bool owned = false;
@@ -676,6 +766,7 @@ int ata_ex_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, void* C_low
     if (rc) return rc;
     int variant, max_depth, flags;
     if (resolve_opts(opts, variant, max_depth, flags)) return -9;
+    flags |= default_form_flags(opts, dtype);
     if (dtype_lp(dtype)) {
         if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
         if (flags & ATA_OPT_EQUILIBRATE) return ATA_EUNSUPPORTED;
@@ -705,7 +796,7 @@ int ata_ex_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, void* C_low
     rc = get_plan(m, n, c, variant, max_depth, plan_flags(flags, dtype) | kPlanNoSplit, false, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
-    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, (flags & ATA_OPT_EQUILIBRATE) != 0, P.opsum_elems);
+    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, want_equilibrate(flags, P, dtype), P.opsum_elems);
     if (L.ldt > INT32_MAX) return ATA_EUNSUPPORTED;
     const size_t tbytes = (pd->host_blob.size() + 255) / 256 * 256;
     const size_t need = tbytes + L.total;
@@ -818,6 +909,8 @@ void ata_release_caches(void) {
     }
     (void)hipSetDevice(cur);
     g_plans.clear();
+    g_plan_lru.clear();
+    g_plan_pos.clear();
     release_lookahead();
 }
 

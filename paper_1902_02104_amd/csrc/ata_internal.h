@@ -98,6 +98,12 @@ WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equil
 constexpr int kPlanReducedPrecision = 0x10000;
 // Internal plan flag: no K splitting (its partial sums need workspace).
 constexpr int kPlanNoSplit = 0x20000;
+// Internal plan flag: float input (the adaptive depth rule uses FP32 rates).
+constexpr int kPlanF32 = 0x40000;
+// Internal plan flag: accumulate into C (row slabs of one product).
+constexpr int kPlanAccumulate = 0x80000;
+// Equilibration in effect for a call with these option flags and this plan.
+bool want_equilibrate(int flags, const Plan& P, int dtype);
 int plan_flags(int flags, int dtype);
 int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, int flags, bool need_device,
              std::shared_ptr<PlanDev>& out);

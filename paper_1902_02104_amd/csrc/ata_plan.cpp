@@ -81,9 +81,23 @@ private:
     }
     int hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M, int64_t yc, int64_t N,
                    int phase);
+    // Cost of a product in 128 x 128 x 1 tile steps at the measured rates:
+    // classical tiles, or one Strassen level (seven half-size products in
+    // product tiles of 128, or in-tile quadrants of 64, plus the combination).
+    bool level_pays(int64_t M, int64_t K, int64_t N) const {
+        auto t128 = [](int64_t x) { return (double)((x + kGemmTile - 1) / kGemmTile); };
+        auto t64 = [](int64_t x) { return (double)((x + kStrTile - 1) / kStrTile); };
+        const double classical = t128(M) * t128(N) * (double)K / o.rate_one;
+        const int64_t MH = ceil2(M), NH = ceil2(N), KH = ceil2(K);
+        const double prods = o.intile ? 7.0 / 4.0 * t64(MH) * t64(NH) * (double)KH
+                                      : 7.0 * t128(MH) * t128(NH) * (double)KH;
+        const double strassen = prods / o.rate_two + o.comb * (double)M * (double)N + o.eq * (double)(M + N) * (double)K;
+        return strassen < classical;
+    }
     int hasa_depth(int64_t M, int64_t K, int64_t N) const {
         int d = 0;
         while (std::min(M, std::min(K, N)) > o.cutoff && (o.max_depth < 0 || d < o.max_depth)) {
+            if (o.adaptive && !level_pays(M, K, N)) break;
             M = ceil2(M);
             K = ceil2(K);
             N = ceil2(N);
@@ -636,6 +650,12 @@ Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
         b.ata_node({Chunk{0, m}}, 0, n, 0, 0);
     }
     split_k(P);
+    if (opt.accumulate) {
+        for (DevTask& t : P.tasks)
+            if (t.dst == 0) t.beta = 1;
+        for (Phase& ph : P.phases)
+            for (DevCombine& cb : ph.combines) cb.beta = 1;
+    }
     // Order of the items of every launch.  Heavier tiles first (longest
     // processing time).  Among equal costs, tiles that read the same operand
     // strips go together: the products of one Strassen expansion (same K

@@ -124,6 +124,19 @@ struct PlanOptions {
     // With product tiles: form each product's operand sums in a memory pass
     // (DevOpSum) and run the products as classical tiles on those buffers.
     bool opsums = false;
+    // Adaptive depth: a further Strassen level is taken only where it is
+    // faster by a cost model of the tile kernels: rate_one and rate_two are
+    // the measured fractions of the MFMA peak of classical tiles and of the
+    // tiles of a Strassen level (product tiles or in-tile), comb the cost of
+    // combining one output element in 128 x 128 x 1 tile-step units.
+    // eq: cost of equilibrating one element of A, charged to a Strassen level
+    // for the columns of its operands when equilibration comes with Strassen
+    // levels (0 otherwise).
+    bool adaptive = false;
+    double rate_one = 1.0, rate_two = 1.0, comb = 0.0, eq = 0.0;
+    // Accumulate: every write into C adds to what C holds (C += A^t A), for
+    // sums of products over row slabs of A.
+    bool accumulate = false;
 };
 
 constexpr int kMaxExpandDepth = 2;

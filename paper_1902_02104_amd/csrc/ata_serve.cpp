@@ -31,6 +31,24 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kBypass = 8;  // queued requests that may be admitted ahead of a blocked head
+// Row slabs: requests above kChunkFlops (m n^2) run in slabs of about
+// kSlabFlops each, at least kMinSlabRows rows (multiples of 256).
+constexpr double kChunkFlops = 4e10;
+constexpr double kSlabFlops = 2e10;
+constexpr int64_t kMinSlabRows = 4096;
+
+int64_t slab_rows_for(int64_t m, int64_t n) {
+    const double f = (double)m * (double)n * (double)n;
+    if (f <= kChunkFlops) return 0;
+    int64_t rows = (int64_t)(kSlabFlops / ((double)n * (double)n));
+    rows = std::max(rows, kMinSlabRows);
+    rows = (rows + 255) / 256 * 256;
+    return 2 * rows <= m ? rows : 0;
+}
+
+// Simulate mode: a device-drawn request with this seed ends with ATA_EHIP
+// (exercises the failure path of the scheduler without a device).
+constexpr uint64_t kSimFailSeed = ATA_SERVER_SIM_FAIL_SEED;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -95,9 +113,19 @@ struct Req {
     int batched = 0, stream = -1;
     int64_t footprint = 0;
     double flops = 0;
-    Block a, c, w, tb;
+    Block a, c, w, tb, tb_acc, tb_tail;
     std::shared_ptr<PlanDev> plan;  // host plan; its tables are copied into block tb
     WsLayout L;
+    // Row slabs of a large request (the row split of the block equations:
+    // C = sum over slabs of A_s^t A_s).  Slab s covers rows
+    // [s slab_rows, min(m, (s + 1) slab_rows)); the first writes C (plan),
+    // the others add to it (plan_acc for full slabs, plan_tail for a shorter
+    // last one), each launched once the previous slab has completed, so other
+    // requests' launches on the same stream run in between.
+    int nslab = 1, next_slab = 0;
+    int64_t slab_rows = 0;
+    std::shared_ptr<PlanDev> plan_acc, plan_tail;
+    WsLayout L_acc, L_tail;
     int64_t cutoff = 0;
     int variant = 0, depth = 0;
     bool small = false;
@@ -145,6 +173,7 @@ struct ata_server {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     void loop();
+    hipError_t launch_slab(Req* q);
     void finish(Req* q, int status, double t);
     bool admit(Req* q, int pass_stream);
     void release_block(Block& b) {
@@ -162,12 +191,35 @@ void ata_server::finish(Req* q, int status, double t) {
     if (!q->r.keep_a) release_block(q->a);
     release_block(q->w);
     release_block(q->tb);
+    release_block(q->tb_acc);
+    release_block(q->tb_tail);
     if (q->ev) {
         (void)hipEventDestroy(q->ev);
         q->ev = nullptr;
     }
     --active;
     ++st.completed;
+}
+
+// Enqueue the request's next slab (the whole product when it has one slab)
+// on its stream and record its event.
+hipError_t ata_server::launch_slab(Req* q) {
+    const int sl = q->next_slab;
+    const bool last = sl == q->nslab - 1;
+    const bool tail = q->nslab > 1 && last && q->plan_tail;
+    const PlanDev& pd = sl == 0 ? *q->plan : (tail ? *q->plan_tail : *q->plan_acc);
+    const Block& tb = sl == 0 ? q->tb : (tail ? q->tb_tail : q->tb_acc);
+    const WsLayout& L = sl == 0 ? q->L : (tail ? q->L_tail : q->L_acc);
+    const int64_t r0 = (int64_t)sl * q->slab_rows;
+    const int64_t rows = q->nslab == 1 ? q->r.m : std::min(q->r.m - r0, q->slab_rows);
+    const size_t eb = elem_bytes(q->r.dtype);
+    hipStream_t s = streams[q->stream];
+    hipError_t e = enqueue_product(pd, base + tb.off, L, base + q->a.off + (size_t)r0 * q->r.n * eb, rows, q->r.n,
+                                   q->r.n, base + q->c.off, q->r.dtype, q->variant,
+                                   q->w.held ? base + q->w.off : nullptr, s, dev);
+    if (e == hipSuccess) e = hipEventRecord(q->ev, s);
+    q->next_slab = sl + 1;
+    return e;
 }
 
 // Allocate the request's blocks, fill A and upload its plan.  Returns false
@@ -195,7 +247,7 @@ bool ata_server::admit(Req* q, int pass_stream) {
         w.bytes = q->L.total;
         w.held = true;
     }
-    Block tb;
+    Block tb, tba, tbt;
     const size_t tbytes = q->plan->host_blob.size();
     if (!pool.alloc(tbytes, tb.off)) {
         release_block(a);
@@ -205,24 +257,46 @@ bool ata_server::admit(Req* q, int pass_stream) {
     }
     tb.bytes = tbytes;
     tb.held = true;
+    auto more = [&](const std::shared_ptr<PlanDev>& pd, Block& b) {
+        if (!pd) return true;
+        if (!pool.alloc(pd->host_blob.size(), b.off)) return false;
+        b.bytes = pd->host_blob.size();
+        b.held = true;
+        return true;
+    };
+    if (!more(q->plan_acc, tba) || !more(q->plan_tail, tbt)) {
+        release_block(a);
+        release_block(c);
+        release_block(w);
+        release_block(tb);
+        release_block(tba);
+        return false;
+    }
     q->a = a;
     q->c = c;
     q->w = w;
     q->tb = tb;
+    q->tb_acc = tba;
+    q->tb_tail = tbt;
     q->state = ATA_REQ_ADMITTED;
     q->t_admit = now();
     ++active;
     ++st.admitted;
     if (sim()) return true;
     const Plan& P = q->plan->plan;
-    q->small = P.phases.size() == 1 && P.phases[0].str_items.empty() && P.phases[0].tg_items.empty() &&
-               P.phases[0].gemm_items.empty() &&
-               P.phases[0].combines.empty();
+    q->small = q->nslab == 1 && P.phases.size() == 1 && P.phases[0].str_items.empty() &&
+               P.phases[0].tg_items.empty() && P.phases[0].gemm_items.empty() && P.phases[0].combines.empty();
     q->stream = q->small ? pass_stream : (int)((pass + q->id) % streams.size());
     hipStream_t s = streams[q->stream];
     void* A = base + q->a.off;
     // the plan's tables travel with the request (no synchronous upload)
     hipError_t e = hipMemcpyAsync(base + q->tb.off, q->plan->host_blob.data(), tbytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && q->plan_acc)
+        e = hipMemcpyAsync(base + q->tb_acc.off, q->plan_acc->host_blob.data(), q->tb_acc.bytes, hipMemcpyHostToDevice,
+                           s);
+    if (e == hipSuccess && q->plan_tail)
+        e = hipMemcpyAsync(base + q->tb_tail.off, q->plan_tail->host_blob.data(), q->tb_tail.bytes,
+                           hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
     } else if (q->r.src == ATA_SRC_HOST)
         e = hipMemcpyAsync(A, q->r.a, abytes, hipMemcpyHostToDevice, s);
@@ -231,6 +305,9 @@ bool ata_server::admit(Req* q, int pass_stream) {
     else
         e = launch_fill_normal(A, m * n, q->r.seed, eb == 8, s);
     if (e != hipSuccess) {
+        // copies already queued on s may still write the blocks: let them
+        // finish before the blocks go back to the pool
+        (void)hipStreamSynchronize(s);
         finish(q, hip_fail(e), now());
         release_block(q->a);
     }
@@ -262,6 +339,7 @@ void ata_server::loop() {
             int status = ATA_OK;
             if (sim()) {
                 done = tnow >= q->t_due;
+                if (done && q->r.src == ATA_SRC_NORMAL && q->r.seed == kSimFailSeed) status = ATA_EHIP;
             } else {
                 const hipError_t e = hipEventQuery(q->ev);
                 if (e == hipSuccess) done = true;
@@ -269,6 +347,16 @@ void ata_server::loop() {
                     done = true;
                     status = hip_fail(e);
                 }
+            }
+            if (done && status == ATA_OK && !sim() && q->next_slab < q->nslab) {
+                // the previous slab has completed: queue the next one behind
+                // whatever else this pass put on the stream
+                const hipError_t e = launch_slab(q);
+                if (e == hipSuccess) {
+                    ++i;
+                    continue;
+                }
+                status = hip_fail(e);
             }
             if (done) {
                 finish(q, status, tnow);
@@ -324,12 +412,8 @@ void ata_server::loop() {
                         small_by_type[q->r.dtype].push_back(q);
                         continue;
                     }
-                    hipStream_t s = streams[q->stream];
-                    hipError_t e = enqueue_product(*q->plan, base + q->tb.off, q->L, base + q->a.off, q->r.m, q->r.n, q->r.n,
-                                                   base + q->c.off, q->r.dtype, q->variant,
-                                                   q->w.held ? base + q->w.off : nullptr, s, dev);
-                    if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
-                    if (e == hipSuccess) e = hipEventRecord(q->ev, s);
+                    hipError_t e = hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
+                    if (e == hipSuccess) e = launch_slab(q);
                     q->t_launch = now();
                     if (e != hipSuccess) {
                         finish(q, hip_fail(e), now());
@@ -428,6 +512,8 @@ void fill_info(const Req* q, ata_request_info* info) {
     info->stream = q->stream;
     info->footprint = q->footprint;
     info->flops = q->flops;
+    info->slabs = q->nslab;
+    info->reserved = 0;
 }
 
 }  // namespace
@@ -488,16 +574,43 @@ int ata_server_submit(ata_server* srv, const ata_request* req, uint64_t* ticket)
     q->flops = (double)req->m * (double)req->n * (double)req->n;
     // footprint from the host plan (no device work on the caller's thread)
     std::shared_ptr<PlanDev> hp;
+    size_t wsmax = 0, tables = 0;
     if (req->m > 0) {
-        rc = get_plan(req->m, req->n, q->cutoff, q->variant, q->depth, 0, false, hp);
+        q->slab_rows = slab_rows_for(req->m, req->n);
+        const int64_t rows = q->slab_rows ? q->slab_rows : req->m;
+        q->nslab = q->slab_rows ? (int)((req->m + rows - 1) / rows) : 1;
+        if (q->slab_rows && !req->cutoff) q->cutoff = default_cutoff(rows, req->n, req->dtype);
+        // the library's default depth rule for requests that leave it open
+        const int pf = req->max_depth == -2 ? plan_flags(ATA_OPT_ADAPTIVE, req->dtype) : 0;
+        rc = get_plan(rows, req->n, q->cutoff, q->variant, q->depth, pf, false, hp);
         if (rc != ATA_OK) return rc;
-        q->L = ws_layout(req->m, req->n, req->dtype, hp->plan.ws_elems, false, hp->plan.opsum_elems);
+        q->L = ws_layout(rows, req->n, req->dtype, hp->plan.ws_elems, false, hp->plan.opsum_elems);
         q->plan = hp;
+        wsmax = q->L.total;
+        tables = align_up(hp->host_blob.size());
+        if (q->nslab > 1) {
+            rc = get_plan(rows, req->n, q->cutoff, q->variant, q->depth, pf | kPlanAccumulate, false, q->plan_acc);
+            if (rc != ATA_OK) return rc;
+            q->L_acc = ws_layout(rows, req->n, req->dtype, q->plan_acc->plan.ws_elems, false,
+                                 q->plan_acc->plan.opsum_elems);
+            wsmax = std::max(wsmax, q->L_acc.total);
+            tables += align_up(q->plan_acc->host_blob.size());
+            const int64_t tail = req->m - (int64_t)(q->nslab - 1) * rows;
+            if (tail != rows) {
+                rc = get_plan(tail, req->n, q->cutoff, q->variant, q->depth, pf | kPlanAccumulate, false, q->plan_tail);
+                if (rc != ATA_OK) return rc;
+                q->L_tail = ws_layout(tail, req->n, req->dtype, q->plan_tail->plan.ws_elems, false,
+                                      q->plan_tail->plan.opsum_elems);
+                wsmax = std::max(wsmax, q->L_tail.total);
+                tables += align_up(q->plan_tail->host_blob.size());
+            }
+        }
+        // every slab's workspace layout fits in the largest one's bytes
+        q->L.total = q->L_acc.total = q->L_tail.total = wsmax;
     }
     const size_t eb = elem_bytes(req->dtype);
     q->footprint = (int64_t)(align_up((size_t)req->m * req->n * eb) +
-                             align_up((size_t)(req->n * (req->n + 1) / 2) * eb) + align_up(q->L.total) +
-                             (hp ? align_up(hp->host_blob.size()) : 0));
+                             align_up((size_t)(req->n * (req->n + 1) / 2) * eb) + align_up(wsmax) + tables);
     std::lock_guard<std::mutex> lk(srv->mu);
     ++srv->st.submitted;
     if ((size_t)q->footprint > srv->pool.size) {
@@ -555,7 +668,8 @@ int ata_server_wait(ata_server* srv, uint64_t ticket, double timeout_s, ata_requ
     }
 }
 
-int ata_server_take(ata_server* srv, uint64_t ticket, void* c, int c_on_device, void* a_host) {
+int ata_server_take(ata_server* srv, uint64_t ticket, void* c, void* a_out, int on_device) {
+    const int c_on_device = on_device;
     if (!srv) return -1;
     Req* q = nullptr;
     {
@@ -564,8 +678,22 @@ int ata_server_take(ata_server* srv, uint64_t ticket, void* c, int c_on_device, 
         if (it == srv->reqs.end()) return ATA_ENOTFOUND;
         q = it->second;
         if (q->state != ATA_REQ_DONE) return ATA_EPENDING;
-        if (q->status != ATA_OK) return q->status;
-        if (a_host && q->r.m > 0 && !q->a.held) return -5;
+        if (q->status != ATA_OK) {
+            // a failed request is released here: its blocks go back to the pool
+            const int st = q->status;
+            srv->reqs.erase(it);
+            srv->release_block(q->a);
+            srv->release_block(q->c);
+            srv->release_block(q->w);
+            srv->release_block(q->tb);
+            srv->release_block(q->tb_acc);
+            srv->release_block(q->tb_tail);
+            delete q;
+            srv->kick = true;
+            srv->cv_work.notify_one();
+            return st;
+        }
+        if (a_out && q->r.m > 0 && !q->a.held) return -4;
         srv->reqs.erase(it);  // the caller now owns the request's remaining blocks
     }
     const size_t eb = elem_bytes(q->r.dtype);
@@ -585,8 +713,9 @@ int ata_server_take(ata_server* srv, uint64_t ticket, void* c, int c_on_device, 
                                      c_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
             if (e != hipSuccess) rc = hip_fail(e);
         }
-        if (rc == ATA_OK && a_host) {
-            hipError_t e = hipMemcpy(a_host, srv->base + q->a.off, (size_t)q->r.m * q->r.n * eb, hipMemcpyDeviceToHost);
+        if (rc == ATA_OK && a_out) {
+            hipError_t e = hipMemcpy(a_out, srv->base + q->a.off, (size_t)q->r.m * q->r.n * eb,
+                                     on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
             if (e != hipSuccess) rc = hip_fail(e);
         }
     }
@@ -595,13 +724,15 @@ int ata_server_take(ata_server* srv, uint64_t ticket, void* c, int c_on_device, 
     srv->release_block(q->c);
     srv->release_block(q->w);
     srv->release_block(q->tb);
+    srv->release_block(q->tb_acc);
+    srv->release_block(q->tb_tail);
     delete q;
     srv->kick = true;
     srv->cv_work.notify_one();
     return rc;
 }
 
-int ata_server_release(ata_server* srv, uint64_t ticket) { return ata_server_take(srv, ticket, nullptr, 0, nullptr); }
+int ata_server_release(ata_server* srv, uint64_t ticket) { return ata_server_take(srv, ticket, nullptr, nullptr, 0); }
 
 int ata_server_get_stats(ata_server* srv, ata_server_stats* out) {
     if (!srv) return -1;

@@ -28,7 +28,8 @@ class RequestInfo(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("m", ctypes.c_int64),
                 ("n", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
                 ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double), ("batched", ctypes.c_int32),
-                ("stream", ctypes.c_int32), ("footprint", ctypes.c_int64), ("flops", ctypes.c_double)]
+                ("stream", ctypes.c_int32), ("footprint", ctypes.c_int64), ("flops", ctypes.c_double),
+                ("slabs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -56,7 +57,7 @@ def _bind():
     lib.ata_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(u64)]
     lib.ata_server_query.argtypes = [vp, u64, ctypes.POINTER(RequestInfo)]
     lib.ata_server_wait.argtypes = [vp, u64, dbl, ctypes.POINTER(RequestInfo)]
-    lib.ata_server_take.argtypes = [vp, u64, vp, ci, vp]
+    lib.ata_server_take.argtypes = [vp, u64, vp, vp, ci]
     lib.ata_server_release.argtypes = [vp, u64]
     lib.ata_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.ata_server_now.argtypes = [vp]
@@ -138,16 +139,26 @@ class Server:
             raise AtaError(info.status, "request %d" % ticket)
         return info.as_dict()
 
-    def take(self, ticket: int, want_a: bool = False):
-        """Copy the packed result (and A if kept) to host numpy arrays and
-        release the request."""
+    def take(self, ticket: int, want_a: bool = False, device: bool = False):
+        """Copy the packed result (and A if kept) out and release the request:
+        host numpy arrays, or device tensors on the current device when
+        `device` is set."""
         import numpy as np
         info = self.wait(ticket)
         m, n = info["m"], info["n"]
-        dt = np.float64 if self._dtypes.pop(ticket, F32) == F64 else np.float32
-        c = np.empty(tri(n), dtype=dt)
-        a = np.empty((m, n), dtype=dt) if want_a else None
-        rc = self._lib.ata_server_take(self._h, ticket, c.ctypes.data, 0, a.ctypes.data if want_a else None)
+        f64 = self._dtypes.pop(ticket, F32) == F64
+        if device:
+            import torch
+            dt = torch.float64 if f64 else torch.float32
+            c = torch.empty(tri(n), dtype=dt, device="cuda")
+            a = torch.empty((m, n), dtype=dt, device="cuda") if want_a else None
+            cp, ap = c.data_ptr(), (a.data_ptr() if want_a else None)
+        else:
+            dt = np.float64 if f64 else np.float32
+            c = np.empty(tri(n), dtype=dt)
+            a = np.empty((m, n), dtype=dt) if want_a else None
+            cp, ap = c.ctypes.data, (a.ctypes.data if want_a else None)
+        rc = self._lib.ata_server_take(self._h, ticket, cp, ap, 1 if device else 0)
         if rc:
             raise AtaError(rc, "ata_server_take")
         return (c, a) if want_a else c

@@ -218,6 +218,33 @@ def test_normal_solve_least_squares_shape(env):
     assert rel <= 64 * n * U64
 
 
+def test_normal_solve_on_scaled_columns(env, orc):
+    """The chain's default options on the least-squares data recipe (columns
+    scaled by 10^U(-3,3)), at 32768 x 256: the product the chain factors
+    (gram with default options) keeps the scaled error
+    max |dC_ij| / sqrt(C_ii C_jj) at double precision, and the solution
+    satisfies the normal equations to the chain's backward error."""
+    torch, P = env
+    m, n = 32768, 256
+    _say("case: normal_solve on scaled columns %dx%d" % (m, n))
+    A_np = synthetic.tall_scaled(m, n)
+    A = torch.from_numpy(A_np).cuda()
+    C = P.gram(A).cpu().numpy()
+    ref = orc.classical(A_np)
+    sc = orc.scaled_err(C, ref, n)
+    _say("   default product scaled error %.3e" % sc)
+    assert sc <= 1e-12
+    b = torch.from_numpy(synthetic.uniform(m, 1, 43)[:, 0].copy()).cuda()
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    x = P.normal_solve(A, b, info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    g = A.t().mv(A.mv(x) - b)
+    rel = float(g.norm() / (torch.linalg.matrix_norm(A, "fro") ** 2 * x.norm()))
+    _say("   normal-equation residual %.3e" % rel)
+    assert rel <= 64 * n * U64
+
+
 def test_edges(env, orc):
     torch, P = env
     _say("case: normal-equation edges")

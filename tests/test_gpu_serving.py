@@ -89,3 +89,33 @@ def test_timestamps_and_rejection(srv_env):
             s.release(t)
         with pytest.raises(P.AtaError):
             s.submit(65536, 4096, dtype=P.F32)  # 1 GiB of A > 64 MiB budget
+
+
+def test_chunked_request_exact_and_identical_in_mix(srv_env, orc):
+    """A request above the chunking threshold runs in row slabs whose Grams
+    add up to C (the row split of the block equations): exact on integer
+    input, and bit-identical alone and among other requests."""
+    torch, P, Server = srv_env
+    print("case: chunked request", flush=True)
+    m, n = 40000, 1100  # 4.8e10 flops: three slabs of 16640, 16640 and 6720 rows
+    A = synthetic.integer(m, n, 610)
+    with Server(8 << 30, max_active=16, streams=4) as s:
+        t = s.submit(m, n, dtype=P.F64, a=A)
+        info = s.wait(t)
+        assert info["slabs"] == 3
+        C = s.take(t)
+        assert np.array_equal(C, orc.classical_mt(A, threads=8))
+        # FP32 device-drawn: alone, then among smaller requests
+        t = s.submit(m, n, dtype=P.F32, seed=611)
+        alone = s.take(t)
+        rng = np.random.default_rng(12)
+        noise = [s.submit(int(rng.integers(1024, 8000)), int(rng.integers(64, 900)), dtype=P.F32, seed=700 + k)
+                 for k in range(12)]
+        t = s.submit(m, n, dtype=P.F32, seed=611)
+        noise += [s.submit(int(rng.integers(1024, 8000)), int(rng.integers(64, 900)), dtype=P.F32, seed=720 + k)
+                  for k in range(12)]
+        assert np.array_equal(s.take(t), alone)
+        for k in noise:
+            s.wait(k)
+            s.release(k)
+        assert s.stats()["pool_in_use"] == 0

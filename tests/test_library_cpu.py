@@ -242,3 +242,14 @@ def test_project_argument_validation_without_gpu(lib):
     assert L.ata_project(a, 4, 4, 4, a, 1, 1, a, 1, P.F32_FP8, 0, None, None) == -10
     assert L.ata_project(a, 4, 4, 4, a, 1, 1, a, 1, P.F64, -1, None, None) == -11
 
+
+
+def test_plan_cache_is_bounded_and_rebuilds():
+    """Many distinct shapes (as a serving stream draws them) pass through the
+    bounded plan cache; an evicted plan is rebuilt identically."""
+    import paper_1902_02104_amd as P
+    first = P.plan_info(700, 300, 64, max_depth=1)
+    for i in range(600):
+        P.plan_info(500 + i, 120 + (i % 37), 64, max_depth=1)
+    again = P.plan_info(700, 300, 64, max_depth=1)
+    assert again == first

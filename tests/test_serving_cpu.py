@@ -96,3 +96,25 @@ def test_close_with_queued_work():
         s.submit(1024, 256)
     time.sleep(0.01)
     s.close()  # returns: in-flight work finishes, queued requests are dropped
+
+
+def test_failed_request_is_released():
+    """A request that ended with an error gives its memory back when it is
+    released (the error status is reported by that call)."""
+    fail_seed = 0xFFFFFFFFFFFFFFFF  # ATA_SERVER_SIM_FAIL_SEED
+    with Server(64 << 20, max_active=4, simulate_tflops=1e-3) as s:
+        ok = s.submit(1024, 64)
+        bad = s.submit(1024, 128, seed=fail_seed)
+        with pytest.raises(P.AtaError) as ei:
+            s.wait(bad, timeout=30)
+        assert ei.value.status == 2  # ATA_EHIP
+        assert s.stats()["pool_in_use"] > 0
+        with pytest.raises(P.AtaError) as ei:
+            s.release(bad)
+        assert ei.value.status == 2
+        with pytest.raises(P.AtaError) as ei:
+            s.release(bad)
+        assert ei.value.status == 7  # ATA_ENOTFOUND: already released
+        s.wait(ok, timeout=30)
+        s.release(ok)
+        assert s.stats()["pool_in_use"] == 0
