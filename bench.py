@@ -153,8 +153,8 @@ def _precision_forms(P, torch, dev, stream, n: int, steps: int):
            "oracle": "FP64 plain definition on the FP32 input, %.1f s on the host" % ref_s}
     # (name, dtype, depths, MFMA products per classical product, MFMA peak TFLOP/s)
     for name, dt, depths, mult, peak in (("fp32", P.F32, (0, 1, 2), 1, 157.3),
-                                         ("bf16x3", P.F32_BF16X3, (0,), 3, 2500.0),
-                                         ("fp8_e4m3", P.F32_FP8, (0,), 1, 5000.0)):
+                                         ("bf16x3", P.F32_BF16X3, (0, 1, 2), 3, 2500.0),
+                                         ("fp8_e4m3", P.F32_FP8, (0, 1, 2), 1, 5000.0)):
         best = None
         for d in depths:
             fn = lambda: P.gram(At, dtype=dt | P.OUT_F64, cutoff=256, max_depth=d, out=C, stream=stream)

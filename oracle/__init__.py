@@ -40,7 +40,7 @@ __all__ = [
     "classical", "classical_mt", "ata", "hasa", "ata_mult_count", "unpack", "pack",
     "tri", "rel_fro", "scaled_err", "freivalds_residual", "bf16_round", "bf16_split",
     "e4m3_round", "pow2_column_scales", "gram_bf16x3", "gram_fp8", "STRASSEN", "WINOGRAD", "load",
-    "potrf", "potrs", "atb", "project",
+    "potrf", "potrs", "atb", "project", "ata_lowp",
 ]
 
 STRASSEN = 0
@@ -352,6 +352,125 @@ def gram_fp8(A32: np.ndarray) -> np.ndarray:
     Q = e4m3_round(A32.astype(np.float64) * s[None, :])
     full = (Q.T @ Q) / s[:, None] / s[None, :]
     return pack(full)
+
+
+def _lowp_leaf(X: np.ndarray, Y: np.ndarray, fmt: str, xs=None, ys=None) -> np.ndarray:
+    """X (M x K) Y (K x N) of binary32 operands in a reduced-precision form,
+    exactly in FP64: 'bf16x3' splits each operand (hi = bf16(x),
+    lo = bf16(x - hi)) and keeps hi hi + hi lo + lo hi; 'fp8' rounds
+    diag(xs) X and Y diag(ys) to e4m3 and scales back, with xs, ys the
+    power-of-two scales of X's rows and Y's columns (computed from the
+    operands when not given)."""
+    X = np.asarray(X, dtype=np.float32)
+    Y = np.asarray(Y, dtype=np.float32)
+    if fmt == "bf16x3":
+        xh, xl = bf16_split(X)
+        yh, yl = bf16_split(Y)
+        xh, xl, yh, yl = (v.astype(np.float64) for v in (xh, xl, yh, yl))
+        return xh @ yh + xh @ yl + xl @ yh
+    if fmt == "fp8":
+        if xs is None:
+            xs = pow2_column_scales(X.T.astype(np.float64))
+        if ys is None:
+            ys = pow2_column_scales(Y.astype(np.float64))
+        qx = e4m3_round(X.astype(np.float64) * xs[:, None])
+        qy = e4m3_round(Y.astype(np.float64) * ys[None, :])
+        return (qx @ qy) / xs[:, None] / ys[None, :]
+    raise ValueError("format must be 'bf16x3' or 'fp8'")
+
+
+# Strassen (1969) and Winograd (1971) products as (left terms, right terms):
+# each term (sign, row half, column half) of X or Y; result quadrants below.
+_LP_STRASSEN = [
+    ([(1, 0, 0), (1, 1, 1)], [(1, 0, 0), (1, 1, 1)]),  # M1 = (X11 + X22)(Y11 + Y22)
+    ([(1, 1, 0), (1, 1, 1)], [(1, 0, 0)]),             # M2 = (X21 + X22) Y11
+    ([(1, 0, 0)], [(1, 0, 1), (-1, 1, 1)]),            # M3 = X11 (Y12 - Y22)
+    ([(1, 1, 1)], [(1, 1, 0), (-1, 0, 0)]),            # M4 = X22 (Y21 - Y11)
+    ([(1, 0, 0), (1, 0, 1)], [(1, 1, 1)]),             # M5 = (X11 + X12) Y22
+    ([(1, 1, 0), (-1, 0, 0)], [(1, 0, 0), (1, 0, 1)]), # M6 = (X21 - X11)(Y11 + Y12)
+    ([(1, 0, 1), (-1, 1, 1)], [(1, 1, 0), (1, 1, 1)]), # M7 = (X12 - X22)(Y21 + Y22)
+]
+_LP_STRASSEN_D = [  # D_ac = sum of sign * M_p, in product order
+    [(1, 0), (1, 3), (-1, 4), (1, 6)], [(1, 2), (1, 4)], [(1, 1), (1, 3)], [(1, 0), (-1, 1), (1, 2), (1, 5)]]
+
+
+def _lowp_hasa(X, Y, fmt, cutoff, levels):
+    """HASA (Strassen levels down to min(M, K, N) <= cutoff or `levels`
+    levels) with every operand sum formed in binary32 and every leaf product
+    taken in the reduced-precision form; combinations in FP64."""
+    M, K = X.shape
+    N = Y.shape[1]
+    if levels == 0 or min(M, K, N) <= cutoff:
+        return _lowp_leaf(X, Y, fmt)
+    M1, K1, N1 = (M + 1) // 2, (K + 1) // 2, (N + 1) // 2
+
+    def quad(Z, a, b, R, C):
+        q = np.zeros((R, C), dtype=np.float32)
+        blk = Z[a * R:(a + 1) * R, b * C:(b + 1) * C]
+        q[:blk.shape[0], :blk.shape[1]] = blk
+        return q
+
+    Xq = {(a, b): quad(X, a, b, M1, K1) for a in (0, 1) for b in (0, 1)}
+    Yq = {(a, b): quad(Y, a, b, K1, N1) for a in (0, 1) for b in (0, 1)}
+
+    def opsum(q, terms):
+        acc = None
+        for sg, a, b in terms:
+            v = q[(a, b)] if sg > 0 else -q[(a, b)]
+            acc = v if acc is None else (acc + v).astype(np.float32)  # binary32 sum
+        return acc
+
+    P = [_lowp_hasa(opsum(Xq, xt), opsum(Yq, yt), fmt, cutoff, levels - 1) for xt, yt in _LP_STRASSEN]
+    D = np.zeros((2 * M1, 2 * N1))
+    for q, terms in enumerate(_LP_STRASSEN_D):
+        acc = np.zeros((M1, N1))
+        for sg, p in terms:
+            acc = acc + sg * P[p]
+        a, c = q >> 1, q & 1
+        D[a * M1:(a + 1) * M1, c * N1:(c + 1) * N1] = acc
+    return D[:M, :N]
+
+
+def ata_lowp(A32: np.ndarray, fmt: str, cutoff: int, levels: int) -> np.ndarray:
+    """Algorithm 1 in a reduced-precision form (packed lower C in FP64): the
+    base-case blocks are products of the converted input (e4m3 with the
+    power-of-two scale of each whole column of A, as one converted copy of A
+    would hold it); each off-diagonal HASA product runs at most `levels`
+    Strassen levels with binary32 operand sums and converted leaf operands
+    (_lowp_hasa); the sums of the recursion are in FP64.  Strassen variant
+    only.  For small inputs (a reference for tests)."""
+    A32 = np.asarray(A32, dtype=np.float32)
+    m, n = A32.shape
+    cs = pow2_column_scales(A32.astype(np.float64)) if fmt == "fp8" else None
+    C = np.zeros((n, n))
+
+    def leaf(rows, c0, c1, d0, d1):
+        X = A32[rows[0]:rows[1], c0:c1].T
+        Y = A32[rows[0]:rows[1], d0:d1]
+        if fmt == "fp8":
+            return _lowp_leaf(X, Y, fmt, cs[c0:c1], cs[d0:d1])
+        return _lowp_leaf(X, Y, fmt)
+
+    def rec(r0, r1, c0, c1):
+        mm, nn = r1 - r0, c1 - c0
+        if mm <= 0 or nn <= 0:
+            return
+        if mm <= cutoff or nn <= cutoff:
+            C[c0:c1, c0:c1] += leaf((r0, r1), c0, c1, c0, c1)
+            return
+        m1, n1 = (mm + 1) // 2, (nn + 1) // 2
+        rec(r0, r0 + m1, c0, c0 + n1)
+        rec(r0 + m1, r1, c0, c0 + n1)
+        rec(r0, r0 + m1, c0 + n1, c1)
+        rec(r0 + m1, r1, c0 + n1, c1)
+        for (a0, a1) in ((r0, r0 + m1), (r0 + m1, r1)):
+            if a1 > a0:
+                X = A32[a0:a1, c0 + n1:c1].T
+                Y = A32[a0:a1, c0:c0 + n1]
+                C[c0 + n1:c1, c0:c0 + n1] += _lowp_hasa(X, Y, fmt, cutoff, levels)
+
+    rec(0, m, 0, n)
+    return pack(np.tril(C) + np.tril(C, -1).T)
 
 
 def pow2_column_scales(A: np.ndarray, target: float = E4M3_MAX) -> np.ndarray:

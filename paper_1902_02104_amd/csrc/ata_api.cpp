@@ -111,8 +111,13 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // transposed converted copy (rows padded to a multiple of 128 elements) can
 // then be staged in whole dwords (q = 2 for bfloat16, 4 for e4m3).
 bool lp_windows_aligned(const Plan& P, int q) {
-    for (const DevTask& t : P.tasks) {
+    std::set<int32_t> desc;  // tasks that only describe operand sums (never launched)
+    for (const Phase& ph : P.phases)
+        for (const DevOpSum& os : ph.opsums) desc.insert(os.task);
+    for (size_t id = 0; id < P.tasks.size(); ++id) {
+        const DevTask& t = P.tasks[id];
         if (t.kind != TK_SYRK && t.kind != TK_GEMM) continue;
+        if (desc.count((int32_t)id)) continue;
         const int stride = kSegHdr + 2 * (t.nx + t.ny);
         for (int sg = 0; sg < t.nseg; ++sg) {
             const int32_t* g = P.segs.data() + t.seg_off + (int64_t)sg * stride;
@@ -224,6 +229,22 @@ bool want_equilibrate(int flags, const Plan& P, int dtype) {
     if (flags & ATA_OPT_EQUILIBRATE) return true;
     return (flags & ATA_OPT_EQUILIBRATE_AUTO) && P.str_mults > 0;
 }
+// Reduced-precision forms: classical leaves by default; Strassen levels (one
+// or two, one for Winograd) run as product tiles on operand sums converted
+// after summing in FP32 (the operand-sum form).  They scale columns themselves,
+// so explicit equilibration is refused.
+int lp_options(const ata_opts* opts, int variant, int& max_depth, int& flags) {
+    if (flags & ATA_OPT_EQUILIBRATE) return ATA_EUNSUPPORTED;
+    flags &= ~(ATA_OPT_ADAPTIVE | ATA_OPT_EQUILIBRATE_AUTO);
+    if (!opts || max_depth == 0) {
+        max_depth = 0;
+        return 0;
+    }
+    if (max_depth < 0 || max_depth > (variant == ATA_VARIANT_WINOGRAD ? 1 : kMaxExpandDepth)) return ATA_EUNSUPPORTED;
+    flags |= ATA_OPT_PRODUCT_TILES | ATA_OPT_OPERAND_SUMS;
+    return 0;
+}
+
 // Default form for a NULL options struct: FP64 runs its Strassen levels as
 // product tiles (the faster fused form there).
 int default_form_flags(const ata_opts* opts, int dtype) {
@@ -244,7 +265,8 @@ bool dtype_lp(int dtype) { return (dtype & 0xff) == ATA_F32_BF16X3 || (dtype & 0
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate, int64_t opsum_elems) {
+WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate, int64_t opsum_elems,
+                   int64_t lp_rows, int64_t lp_k) {
     WsLayout L;
     size_t off = (size_t)ws_elems * sizeof(double);
     off = (off + 255) & ~(size_t)255;
@@ -270,6 +292,22 @@ WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equil
             off += plane;
             off = (off + 255) & ~(size_t)255;
         }
+    }
+    if (lp && lp_rows > 0) {
+        const bool fp8 = (dtype & 0xff) == ATA_F32_FP8;
+        L.rows_o = lp_rows;
+        L.ldto = round_up(lp_k > 0 ? lp_k : 1, 128);
+        const size_t plane = (size_t)lp_rows * L.ldto * (fp8 ? 1 : 2);
+        L.t0o = off;
+        off = (off + plane + 255) & ~(size_t)255;
+        if (!fp8) {
+            L.t1o = off;
+            off = (off + plane + 255) & ~(size_t)255;
+        }
+        L.scale_o = off;
+        off = (off + (size_t)lp_rows * sizeof(float) + 255) & ~(size_t)255;
+        L.colmax_o = off;
+        off = (off + (size_t)lp_rows * sizeof(uint32_t) + 255) & ~(size_t)255;
     }
     if (opsum_elems > 0 && !lp) {
         L.ops = off;
@@ -331,6 +369,7 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
     if (flags & kPlanReducedPrecision) po.split_target = 768;
     if (flags & kPlanNoSplit) po.split_target = 0;
     if (flags & kPlanAccumulate) po.accumulate = true;
+    if (flags & kPlanReducedPrecision) po.lp = true;
     if (flags & ATA_OPT_ADAPTIVE) {
         // Fractions of the MFMA peak measured on MI355X for this library's
         // tiles (rocprof MFMA busy of whole launches at 10000^2): FP64
@@ -480,6 +519,21 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
         if (lp) {
             const float* scale = (const float*)(ws + L.scale);
             const void* t1 = lp_mode == 0 ? (const void*)(ws + L.t1) : nullptr;
+            if (ph.n_ops) {
+                // Strassen products: operand sums converted into the operand copy
+                ProfScope ps(ATA_KERNEL_OTHER, s);
+                err = launch_opsum_lp(lp_mode, (const float*)A, lda, tb, (const DevOpSum*)(pd->blob + ph.off_ops),
+                                      ph.n_ops, ph.ops_rows, L.rows_o, (uint32_t*)(ws + L.colmax_o),
+                                      (float*)(ws + L.scale_o), ws + L.t0o, lp_mode == 0 ? ws + L.t1o : nullptr,
+                                      (int)L.ldto, s);
+            }
+            if (err == hipSuccess && ph.n_tg) {
+                ProfScope ps(ATA_KERNEL_STRASSEN, s);
+                err = launch_gemm_lp(lp_mode, out64, ws + L.t0o, lp_mode == 0 ? (const void*)(ws + L.t1o) : nullptr,
+                                     (int)L.ldto, (const float*)(ws + L.scale_o), tb,
+                                     (const WorkItem*)(pd->blob + ph.off_tg), ph.n_tg, C_lower, W, s,
+                                     pdr.lp_aligned[lp_mode]);
+            }
             // diagonal tiles overlap the off-diagonal ones on a forked stream
             const bool split = fork_ok && ph.n_gemm > 0 && ph.n_syrk > 0;
             ForkCtx fc;
@@ -625,9 +679,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     flags |= default_form_flags(opts, dtype);
     if (!out) return -6;
     if (dtype_lp(dtype)) {
-        if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
-        if (flags & ATA_OPT_EQUILIBRATE) return ATA_EUNSUPPORTED;
-        max_depth = 0;
+        if (const int e = lp_options(opts, variant, max_depth, flags)) return e;
     }
     const int64_t c = cutoff ? cutoff : default_cutoff(m, n, dtype);
     std::shared_ptr<PlanDev> pd;
@@ -645,7 +697,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     out->phases = (int64_t)P.phases.size();
     out->ata_depth = P.ata_depth;
     out->max_hasa_depth = P.max_hasa_depth;
-    out->workspace_bytes = (int64_t)ws_layout(m, n, dtype, P.ws_elems, want_equilibrate(flags, P, dtype), P.opsum_elems).total;
+    out->workspace_bytes = (int64_t)ws_layout(m, n, dtype, P.ws_elems, want_equilibrate(flags, P, dtype), P.opsum_elems, P.lp_ops_rows, P.lp_ops_k).total;
     out->cutoff = c;
     out->strassen_mults = P.str_mults;
     out->gemm_mults = P.gemm_mults;
@@ -672,10 +724,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     flags |= default_form_flags(opts, dtype);
     const bool lp = dtype_lp(dtype);
     if (lp) {
-        // reduced-precision leaves: classical off-diagonal products only
-        if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
-        if (flags & ATA_OPT_EQUILIBRATE) return ATA_EUNSUPPORTED;
-        max_depth = 0;
+        if (const int e = lp_options(opts, variant, max_depth, flags)) return e;
     }
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
@@ -696,7 +745,7 @@ int ata_ex(const void* A, int64_t m, int64_t n, int64_t lda, void* C_lower, int 
     rc = get_plan(m, n, c, variant, max_depth, plan_flags(flags, dtype), true, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
-    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, want_equilibrate(flags, P, dtype), P.opsum_elems);
+    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, want_equilibrate(flags, P, dtype), P.opsum_elems, P.lp_ops_rows, P.lp_ops_k);
     if (L.ldt > INT32_MAX) return ATA_EUNSUPPORTED;
     char* ws = nullptr;
     bool owned = false;
@@ -768,9 +817,7 @@ int ata_ex_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, void* C_low
     if (resolve_opts(opts, variant, max_depth, flags)) return -9;
     flags |= default_form_flags(opts, dtype);
     if (dtype_lp(dtype)) {
-        if (opts && max_depth != 0) return ATA_EUNSUPPORTED;
-        if (flags & ATA_OPT_EQUILIBRATE) return ATA_EUNSUPPORTED;
-        max_depth = 0;
+        if (const int e = lp_options(opts, variant, max_depth, flags)) return e;
     }
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
@@ -796,7 +843,7 @@ int ata_ex_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, void* C_low
     rc = get_plan(m, n, c, variant, max_depth, plan_flags(flags, dtype) | kPlanNoSplit, false, pd);
     if (rc != ATA_OK) return rc;
     const Plan& P = pd->plan;
-    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, want_equilibrate(flags, P, dtype), P.opsum_elems);
+    const WsLayout L = ws_layout(m, n, dtype, P.ws_elems, want_equilibrate(flags, P, dtype), P.opsum_elems, P.lp_ops_rows, P.lp_ops_k);
     if (L.ldt > INT32_MAX) return ATA_EUNSUPPORTED;
     const size_t tbytes = (pd->host_blob.size() + 255) / 256 * 256;
     const size_t need = tbytes + L.total;

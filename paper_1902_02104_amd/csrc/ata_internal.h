@@ -43,9 +43,13 @@ struct PlanDev {
 // partials][converted copy plane 0][plane 1][operand-sum buffers]
 // [equilibrated copy of A], each 256-byte aligned.  The scale and partial areas serve the FP8 scales or the
 // equilibration scales (never both).
+// Reduced-precision plans with Strassen levels add the converted operand copy
+// of the products ([plane 0][plane 1] with row stride ldto), its per-row
+// scales and the column-maximum scratch of the e4m3 scales.
 struct WsLayout {
     size_t w = 0, scale = 0, part = 0, t0 = 0, t1 = 0, ops = 0, eqa = 0, total = 0;
-    int64_t ldt = 0;
+    size_t t0o = 0, t1o = 0, scale_o = 0, colmax_o = 0;
+    int64_t ldt = 0, ldto = 0, rows_o = 0;
     bool eq = false;
 };
 
@@ -93,7 +97,8 @@ bool dtype_lp(int dtype);
 int elem_bytes_in(int dtype);
 int elem_bytes_out(int dtype);
 int64_t default_cutoff(int64_t m, int64_t n, int dtype);
-WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate, int64_t opsum_elems);
+WsLayout ws_layout(int64_t m, int64_t n, int dtype, int64_t ws_elems, bool equilibrate, int64_t opsum_elems,
+                   int64_t lp_rows = 0, int64_t lp_k = 0);
 // Internal plan flag (beside ATA_OPT_* bits): reduced-precision dtype.
 constexpr int kPlanReducedPrecision = 0x10000;
 // Internal plan flag: no K splitting (its partial sums need workspace).

@@ -68,6 +68,14 @@ hipError_t launch_colscale(const float* A, int64_t lda, int m, int n, float* par
                            hipStream_t s);
 hipError_t launch_prep_lp(int mode, const float* A, int64_t lda, int m, int n, int ldt, const float* scale,
                           void* out0, void* out1, hipStream_t s);
+// Strassen operands of the reduced-precision forms: the operand sums of the
+// records (FP32, term order) converted into rows of the operand copy (mode 0
+// bfloat16 hi/lo planes, mode 1 scaled e4m3 with per-row scales; colmax holds
+// `rows` words of scratch for mode 1).  tiles: 64 x 64 conversion tiles of
+// all records.
+hipError_t launch_opsum_lp(int mode, const float* A, int64_t lda, const DevTables& tb, const DevOpSum* recs, int nrec,
+                           int64_t tiles, int64_t rows, uint32_t* colmax, float* scale, void* out0, void* out1, int ldt,
+                           hipStream_t s);
 // aligned: every segment window of the plan starts and ends on a dword of
 // the copy (see lp_windows_aligned), which lets the tiles stage through
 // direct-to-LDS copies.

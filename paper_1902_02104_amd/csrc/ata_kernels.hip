@@ -1421,12 +1421,9 @@ __global__ void __launch_bounds__(256) k_colmax_part(const float* __restrict__ A
     part[(int64_t)chunk * n + j] = mx;
 }
 
-__global__ void __launch_bounds__(256) k_colscale(const float* __restrict__ part, int nchunks, int n,
-                                                  float* __restrict__ scale) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    float mx = 0.0f;
-    for (int c = 0; c < nchunks; ++c) mx = fmaxf(mx, part[(int64_t)c * n + j]);
+// Power-of-two e4m3 scale of a column whose largest magnitude is mx:
+// 2^floor(log2(448 / mx)), 1 for a zero column.
+__device__ __forceinline__ float e4m3_pow2_scale(float mx) {
     float s = 1.0f;
     if (mx > 0.0f) {
         // largest power of two s with s * mx <= 448: 448 / mx = f 2^e, f in [0.5, 1)
@@ -1435,7 +1432,16 @@ __global__ void __launch_bounds__(256) k_colscale(const float* __restrict__ part
         s = __builtin_ldexpf(1.0f, e - 1);
         if (s * mx > 448.0f) s *= 0.5f;  // guard against the rounding of 448 / mx
     }
-    scale[j] = s;
+    return s;
+}
+
+__global__ void __launch_bounds__(256) k_colscale(const float* __restrict__ part, int nchunks, int n,
+                                                  float* __restrict__ scale) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    float mx = 0.0f;
+    for (int c = 0; c < nchunks; ++c) mx = fmaxf(mx, part[(int64_t)c * n + j]);
+    scale[j] = e4m3_pow2_scale(mx);
 }
 
 // ---------------------------------------------------------------------------
@@ -1524,6 +1530,104 @@ __global__ void __launch_bounds__(256) k_prep_lp(const float* __restrict__ A, in
             ((uint16_t*)o1)[o] = bf16_rne(v - hf);
         } else {
             ((uint8_t*)o0)[o] = e4m3_rne(v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Strassen operands of the reduced-precision forms (operand-sum form): the
+// signed sums of quadrant terms are formed in FP32 from A (term order, as the
+// FP32 form stages them) and converted into rows of the operand copy.  One
+// workgroup per 64 x 64 tile (k rows x operand columns) of a record; the M + N
+// operand columns of a record become rows out_off + column, k contiguous.
+//   MAXPASS: column maxima of |sum| into colmax (float bits: non-negative
+//            floats order as their bit patterns), for the e4m3 scales
+//   MODE 0:  bfloat16 hi = bf16(sum), lo = bf16(sum - hi)
+//   MODE 1:  e4m3(sum s) with the column's power-of-two scale s from colmax,
+//            which is also stored for the de-scaling epilogue
+// k rows past the record's K are written as zeros up to the tile's end.
+// ---------------------------------------------------------------------------
+template <int MODE, bool MAXPASS>
+__global__ void __launch_bounds__(256) k_opsum_lp(const float* __restrict__ A, int64_t lda,
+                                                  const DevTask* __restrict__ tasks,
+                                                  const DevTerm* __restrict__ terms,
+                                                  const int32_t* __restrict__ segs,
+                                                  const DevOpSum* __restrict__ recs, int nrec,
+                                                  uint32_t* __restrict__ colmax, float* __restrict__ scale,
+                                                  void* __restrict__ o0, void* __restrict__ o1, int ldt) {
+    __shared__ float tile[64][65];
+    __shared__ int rsel;
+    const int64_t gt = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = nrec - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (recs[mid].row_off <= gt) lo = mid;
+            else hi = mid - 1;
+        }
+        rsel = lo;
+    }
+    __syncthreads();
+    const DevOpSum rec = recs[rsel];
+    const DevTask t = tasks[rec.task];
+    const int width = rec.M + rec.N;
+    const int tiles_c = (width + 63) / 64;
+    const int64_t loc = gt - rec.row_off;
+    const int k0 = (int)(loc / tiles_c) * 64, c0 = (int)(loc % tiles_c) * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
+    const int c = c0 + tx;
+    const bool left = c < rec.M;
+    const int nt = left ? t.nx : t.ny, u0 = left ? 0 : t.nx;
+    const int cc = left ? c : c - rec.M;  // column inside the operand
+    for (int r = ty; r < 64; r += 4) {
+        const int k = k0 + r;
+        float v = 0.0f;
+        if (k < rec.K && c < width) {
+            // chunk (segment) of operand row k and the row inside its window
+            int kk = k, sgi = 0;
+            for (; sgi + 1 < t.nseg; ++sgi) {
+                const int len = segs[t.seg_off + sgi * stride + 2] - segs[t.seg_off + sgi * stride + 1];
+                if (kk < len) break;
+                kk -= len;
+            }
+            const int32_t* sg = segs + t.seg_off + sgi * stride;
+            const int krow = sg[1] + kk;
+            for (int u = 0; u < nt; ++u) {
+                const DevTerm tm = terms[t.term_off + u0 + u];
+                const int row = sg[kSegHdr + 2 * (u0 + u)] + krow;
+                const bool ok = row < sg[kSegHdr + 2 * (u0 + u) + 1] && tm.col + cc < tm.cvend;
+                const float a = ok ? A[(int64_t)row * lda + tm.col + cc] : 0.0f;
+                const float sa = tm.sign < 0 ? -a : a;  // exact
+                v = u == 0 ? sa : v + sa;
+            }
+        }
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    if (MAXPASS) {
+        if (threadIdx.x < 64 && c0 + (int)threadIdx.x < width) {
+            float mx = 0.0f;
+            for (int r = 0; r < 64; ++r) mx = fmaxf(mx, fabsf(tile[r][threadIdx.x]));
+            if (mx > 0.0f) atomicMax(&colmax[rec.out_off + c0 + threadIdx.x], __float_as_uint(mx));
+        }
+        return;
+    }
+    for (int r = ty; r < 64; r += 4) {
+        const int col = c0 + r, k = k0 + tx;
+        if (col >= width || k >= ldt) continue;
+        const float v = tile[tx][r];
+        const int64_t orow = rec.out_off + col;
+        const int64_t o = orow * ldt + k;
+        if (MODE == 0) {
+            const uint16_t h = bf16_rne(v);
+            const float hf = __uint_as_float((uint32_t)h << 16);
+            ((uint16_t*)o0)[o] = h;
+            ((uint16_t*)o1)[o] = bf16_rne(v - hf);
+        } else {
+            const float sc = e4m3_pow2_scale(__uint_as_float(colmax[orow]));
+            ((uint8_t*)o0)[o] = e4m3_rne(v * sc);  // exact scaling by a power of two
+            if (k == 0) scale[orow] = sc;
         }
     }
 }
@@ -2256,6 +2360,25 @@ hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1
         else ATA_LP_LAUNCH(k_gemm_lp, 1, float);
     }
 #undef ATA_LP_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_opsum_lp(int mode, const float* A, int64_t lda, const DevTables& tb, const DevOpSum* recs, int nrec,
+                           int64_t tiles, int64_t rows, uint32_t* colmax, float* scale, void* out0, void* out1, int ldt,
+                           hipStream_t s) {
+    if (nrec <= 0 || tiles <= 0) return hipSuccess;
+    const dim3 g((unsigned)tiles), b(256);
+    if (mode == 0) {
+        hipLaunchKernelGGL((k_opsum_lp<0, false>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, recs, nrec, colmax,
+                           scale, out0, out1, ldt);
+    } else {
+        const hipError_t e = launch_fill_zero(colmax, rows, 4, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_opsum_lp<1, true>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, recs, nrec, colmax,
+                           scale, out0, out1, ldt);
+        hipLaunchKernelGGL((k_opsum_lp<1, false>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, recs, nrec, colmax,
+                           scale, out0, out1, ldt);
+    }
     return hipGetLastError();
 }
 

@@ -369,12 +369,23 @@ int Builder::hasa_block(const std::vector<Chunk>& chunks, int64_t xc, int64_t M,
                 check32(kfull);
                 check32(Mp + Np);
                 DevOpSum os{dsc, (int32_t)kfull, (int32_t)Mp, (int32_t)Np, P.opsum_elems, ph(gphase).opsum_rows};
-                P.opsum_elems += kfull * (Mp + Np);
-                ph(gphase).opsum_rows += kfull;
+                int64_t c0 = 0;  // first column of the product's operands in their buffer
+                if (o.lp) {
+                    // rows of the converted operand copy; 64 x 64 conversion tiles
+                    os.out_off = P.lp_ops_rows;
+                    c0 = P.lp_ops_rows;
+                    check32(P.lp_ops_rows + Mp + Np);
+                    P.lp_ops_rows += Mp + Np;
+                    P.lp_ops_k = std::max(P.lp_ops_k, kfull);
+                    ph(gphase).opsum_rows += ((kfull + 63) / 64) * ((Mp + Np + 63) / 64);
+                } else {
+                    P.opsum_elems += kfull * (Mp + Np);
+                    ph(gphase).opsum_rows += kfull;
+                }
                 ph(gphase).opsums.push_back(os);
                 DevTask g = t;
                 g.nx = g.ny = 1;
-                g.term_off = push_terms({XTerm{1, 0, Mp, {}, {}}}, {XTerm{1, Mp, Mp + Np, {}, {}}});
+                g.term_off = push_terms({XTerm{1, c0, c0 + Mp, {}, {}}}, {XTerm{1, c0 + Mp, c0 + Mp + Np, {}, {}}});
                 g.seg_off = (int32_t)P.segs.size();
                 g.nseg = 1;
                 for (int32_t v : {(int32_t)kfull, 0, (int32_t)kfull, 0, (int32_t)kfull, 0, (int32_t)kfull})

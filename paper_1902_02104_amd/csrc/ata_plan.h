@@ -68,6 +68,10 @@ struct DevOpSum {
     int64_t out_off;
     int64_t row_off;
 };
+// In reduced-precision plans a record describes the same sums, converted into
+// the operand copy: out_off is the record's first row of the copy (its M + N
+// columns become rows out_off .. out_off + M + N, k contiguous) and row_off is
+// its first 64 x 64 (k x column) conversion tile in the launch.
 
 // Combination of workspace products into an off-diagonal block of C.
 // Each output element sums, over nparts K parts (slot sets part_stride
@@ -137,6 +141,10 @@ struct PlanOptions {
     // Accumulate: every write into C adds to what C holds (C += A^t A), for
     // sums of products over row slabs of A.
     bool accumulate = false;
+    // Reduced-precision leaves: the operand sums of the Strassen products
+    // (operand-sum form) are converted into rows of a separate copy instead
+    // of FP32 buffers (see DevOpSum).
+    bool lp = false;
 };
 
 constexpr int kMaxExpandDepth = 2;
@@ -166,6 +174,8 @@ struct Plan {
     std::vector<Phase> phases;
     int64_t ws_elems = 0;
     int64_t opsum_elems = 0;  // operand-sum buffers, in elements of A's type
+    int64_t lp_ops_rows = 0;  // reduced precision: rows of the operand copy
+    int64_t lp_ops_k = 0;     // ... and its longest K
     // statistics
     int64_t mults = 0;
     int64_t str_mults = 0, gemm_mults = 0, syrk_mults = 0, combine_elems = 0;

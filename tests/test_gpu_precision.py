@@ -138,8 +138,10 @@ def test_reduced_precision_ragged_and_strided(env, orc):
             torch.cuda.synchronize()
             tol = TIGHT_FP8 if dt == P.F32_FP8 else TIGHT
             assert orc.rel_fro(C.cpu().numpy(), ref, n) <= tol, (m, n, c, dt)
+    with pytest.raises(P.AtaError):  # at most two expanded levels (one for Winograd)
+        P.gram(torch.zeros(8, 8, device="cuda"), dtype=P.F32_FP8, max_depth=3)
     with pytest.raises(P.AtaError):
-        P.gram(torch.zeros(8, 8, device="cuda"), dtype=P.F32_FP8, max_depth=1)
+        P.gram(torch.zeros(8, 8, device="cuda"), dtype=P.F32_BF16X3, max_depth=2, variant="winograd")
 
 
 def test_precision_forms_full_size_sampled(env, orc):
@@ -206,3 +208,54 @@ def test_reduced_precision_copy_paths(env, orc):
     for dt in (P.F32_BF16X3, P.F32_FP8):
         assert P.plan_info(200000, 64, 10 ** 6, dtype=dt)["combine_tasks"] >= 1
         assert np.array_equal(_gram(env, Ai, dt | P.OUT_F64, cutoff=10 ** 6), exact), dt
+
+
+# Strassen levels in the reduced-precision forms: relative Frobenius bounds
+# against the FP64 Gram, per form and level count.  The operand sums double
+# the operands' range and the combination adds up to four products, so the
+# conversion error grows with each level; the bounds are twice the error of
+# the oracle's reduced-precision recursion (exact products of the converted
+# operands) on this workload: bfloat16 split 5.0e-6 and 8.4e-6, e4m3 4.2e-2
+# and 7.1e-2 at one and two levels.
+LP_STRASSEN_BOUND = {("bf16x3", 1): 5e-5, ("bf16x3", 2): 5e-5, ("fp8", 1): 8.4e-2, ("fp8", 2): 1.42e-1}
+
+
+def _lp_dtype(P, fmt):
+    return (P.F32_BF16X3 if fmt == "bf16x3" else P.F32_FP8) | P.OUT_F64
+
+
+@pytest.mark.parametrize("fmt", ["bf16x3", "fp8"])
+@pytest.mark.parametrize("depth", [1, 2])
+def test_lowp_strassen_integer_exact(env, orc, fmt, depth):
+    """Integers and their operand sums are exact in both formats (96 rows keep
+    every FP32 partial sum of scaled e4m3 products below 2^24)."""
+    torch, P = env
+    print("case: lp strassen integer", fmt, depth, flush=True)
+    A = synthetic.integer(96, 80, 71, dtype=np.float32)
+    C = _gram(env, A, _lp_dtype(P, fmt), cutoff=16, max_depth=depth)
+    assert np.array_equal(C, orc.classical(A.astype(np.float64)))
+
+
+@pytest.mark.parametrize("fmt", ["bf16x3", "fp8"])
+@pytest.mark.parametrize("depth", [1, 2])
+def test_lowp_strassen_uniform(env, orc, fmt, depth):
+    """Uniform input: within the form's Strassen bound of the FP64 Gram, and
+    close to the oracle's reduced-precision recursion.  bfloat16 split: only
+    the FP32 accumulation (and, at two levels, the order of the FP32 operand
+    sums) differs.  e4m3: besides the MFMA's internal accumulation (TIGHT_FP8
+    for classical leaves), the device merges the row chunks of the recursion
+    into one K range per product and scales each operand row by its maximum
+    over that range, the recursion by its maximum per chunk, so a row whose
+    two maxima fall in different binades rounds differently (measured: 1.2e-5
+    and 2.4e-5 at one and two levels)."""
+    torch, P = env
+    print("case: lp strassen uniform", fmt, depth, flush=True)
+    A = synthetic.uniform(600, 450, 72, dtype=np.float32)
+    ex = orc.classical(A.astype(np.float64))
+    C = _gram(env, A, _lp_dtype(P, fmt), cutoff=64, max_depth=depth)
+    err = orc.rel_fro(C, ex, 450)
+    ref = orc.ata_lowp(A, fmt, 64, depth)
+    dif = orc.rel_fro(C, ref, 450)
+    print("   relF vs FP64 %.3e, vs reduced-precision recursion %.3e" % (err, dif), flush=True)
+    assert err <= LP_STRASSEN_BOUND[(fmt, depth)]
+    assert dif <= (TIGHT if fmt == "bf16x3" else 1e-4)

@@ -113,8 +113,10 @@ def test_workspace_size_reduced_precision(lib):
     f8 = P.workspace_bytes(m, n, 0, dtype=P.F32_FP8, max_depth=0)
     assert bf >= 2 * n * ldt * 2 + n * 4
     assert f8 >= n * ldt + n * 4 and f8 < bf
+    # Strassen levels add the converted operand copy of the products
+    assert P.workspace_bytes(m, n, 0, dtype=P.F32_FP8, max_depth=1) > f8
     with pytest.raises(P.AtaError):
-        P.plan_info(m, n, 0, dtype=P.F32_FP8, max_depth=1)  # classical leaves only
+        P.plan_info(m, n, 0, dtype=P.F32_FP8, max_depth=3)  # at most two expanded levels
 
 
 def test_default_cutoff_is_in_tuned_set(lib):

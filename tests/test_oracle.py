@@ -603,3 +603,41 @@ def test_precision_references_reduce_to_exact(orc):
     e_f8 = orc.rel_fro(orc.gram_fp8(Au), ex, 64)
     assert 0 < e_bf < 2.0 ** -15
     assert 2.0 ** -8 < e_f8 < 2.0 ** -3
+
+
+# ---------------------------------------------------------------------------
+# Reduced-precision forms with Strassen levels (ata_lowp)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fmt", ["bf16x3", "fp8"])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_lowp_exact_on_integers(orc, fmt, levels):
+    """Small integers and their Strassen operand sums (|x| <= 12) are
+    represented exactly by both formats at any power-of-two scale, so the
+    reduced-precision recursion gives the exact product."""
+    A = synthetic.integer(96, 70, 3).astype(np.float32)
+    assert np.array_equal(orc.ata_lowp(A, fmt, 16, levels), orc.classical(A.astype(np.float64)))
+
+
+def test_lowp_without_levels_is_the_classical_reference(orc):
+    """With no Strassen level the recursion only regroups the classical
+    product of the converted input (the pinned gram_bf16x3 / gram_fp8)."""
+    U = synthetic.uniform(120, 90, 5).astype(np.float32)
+    assert orc.rel_fro(orc.ata_lowp(U, "bf16x3", 16, 0), orc.gram_bf16x3(U), 90) < 1e-15
+    assert orc.rel_fro(orc.ata_lowp(U, "fp8", 16, 0), orc.gram_fp8(U), 90) < 1e-15
+
+
+def test_lowp_mutants_are_caught(orc, monkeypatch):
+    """A wrong sign in a product or a combination breaks the integer pin."""
+    import oracle as mod
+    A = synthetic.integer(96, 70, 3).astype(np.float32)
+    ex = orc.classical(A.astype(np.float64))
+    bad = [list(p) for p in mod._LP_STRASSEN]
+    bad[3] = ([(1, 1, 1)], [(1, 1, 0), (1, 0, 0)])  # M4 with Y21 + Y11
+    monkeypatch.setattr(mod, "_LP_STRASSEN", [tuple(p) for p in bad])
+    assert not np.array_equal(orc.ata_lowp(A, "bf16x3", 16, 1), ex)
+    monkeypatch.undo()
+    badd = [list(t) for t in mod._LP_STRASSEN_D]
+    badd[3] = [(1, 0), (1, 1), (1, 2), (1, 5)]  # D22 with +M2
+    monkeypatch.setattr(mod, "_LP_STRASSEN_D", badd)
+    assert not np.array_equal(orc.ata_lowp(A, "fp8", 16, 1), ex)
