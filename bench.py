@@ -23,11 +23,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
-FUSED_FORMS = ("intile", "tiles")  # operand sums formed inside the staged operand loads
 HBM_PEAK_GBS = 8000.0
 
 
-def _profiled_traffic(kernel: str, n: int, cutoff: int, depth: int, form: str):
+def _profiled_traffic(kernel: str, n: int, key: str):
     """HBM bytes per launch of `kernel` from its committed counter summary
     (two rocprofv3 --pmc passes scaled by a plain copy), or None when the
     summary was taken on other kernel sources or another configuration."""
@@ -42,9 +41,90 @@ def _profiled_traffic(kernel: str, n: int, cutoff: int, depth: int, form: str):
         return None
     if kv.get("kernels_source_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    if (kv.get("n"), kv.get("cutoff"), kv.get("max_depth"), kv.get("form")) != (str(n), str(cutoff), str(depth), form):
+    if kv.get("n") != str(n) or kv.get("config") != key:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def _sweep_configs(args):
+    """Configurations of the method the headline is tuned over (see main)."""
+    cutoffs = (128, 256, 512) if args.cutoff == 0 else (args.cutoff,)
+    levels = (1, 2) if args.max_depth is None else ((args.max_depth,) if args.max_depth > 0 else ())
+    forms = ("tiles", "intile", "opsums") if args.form == "tune" else (args.form,)
+    out = []
+
+    def add(c, d, f, v):
+        key = "c%d_d0" % c if d == 0 else "c%d_d%d_%s%s" % (c, d, f, "_winograd" if v == "winograd" else "")
+        out.append({"key": key, "cutoff": c, "levels": d, "form": f if d else "classical", "variant": v})
+
+    for c in cutoffs:
+        if args.max_depth in (None, 0):
+            add(c, 0, "tiles", "strassen")
+        for d in levels:
+            for f in forms:
+                add(c, d, f, "strassen")
+        if args.variant_sweep and 1 in levels:
+            for f in ("tiles", "intile"):
+                if f in forms:
+                    add(c, 1, f, "winograd")
+    if args.cutoff == 0 and args.max_depth is None and args.form == "tune":
+        out.append({"key": "default", "cutoff": 0, "levels": -1, "form": "default", "variant": "strassen"})
+    return out
+
+
+def _run_cfg(P, A, C, stream, cfg):
+    if cfg["form"] == "default":
+        P.gram(A, out=C, stream=stream)  # the library's defaults (adaptive depth)
+    else:
+        P.gram(A, cutoff=cfg["cutoff"], max_depth=cfg["levels"], variant=cfg["variant"], out=C, stream=stream,
+               intile=cfg["form"] == "intile", operand_sums=cfg["form"] == "opsums")
+
+
+def _plan_stats(P, m, n, cfg):
+    if cfg["form"] == "default":
+        return P.plan_info(m, n)
+    return P.plan_info(m, n, cfg["cutoff"], max_depth=cfg["levels"], variant=cfg["variant"],
+                       intile=cfg["form"] == "intile", operand_sums=cfg["form"] == "opsums")
+
+
+def _profiled(P, fn, time_steps, steps):
+    """Time `steps` calls with the library's per-launch HIP events on."""
+    P.profile_enable(True)
+    P.profile_collect()
+    ms = time_steps(fn, steps)
+    prof = P.profile_collect()
+    P.profile_enable(False)
+    return ms, prof
+
+
+def _roofline(kt, st, cfg, steps, n):
+    """Roofline record of the dominant kernel kind of a configuration:
+    algorithmic flops per launch (2 per multiplication the launch performs,
+    from the plan) over its average event-timed launch duration."""
+    dom = max(kt, key=lambda k: kt[k][0])
+    dom_ms, dom_launches = kt[dom]
+    avg_ms = dom_ms / dom_launches
+    # the mixed FP64 launch runs the product tiles and the classical tiles of
+    # a phase together: its algorithmic work is all of their multiplications
+    mult_keys = {"strassen": ("strassen_mults",), "gemm": ("gemm_mults",), "syrk": ("syrk_mults",),
+                 "tiles": ("strassen_mults", "gemm_mults", "syrk_mults")}.get(dom)
+    launches_per_step = dom_launches / steps
+    if mult_keys:
+        alg_flops = 2.0 * sum(st[k] for k in mult_keys) / launches_per_step
+        roof = {"bound": "mfma", "achieved": alg_flops / (avg_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "algorithmic_flops_per_launch": alg_flops}
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] else None
+    form, levels = cfg["form"], st["max_hasa_depth"]
+    two_term = form in ("tiles", "default") and levels == 1 and st["strassen_mults"] > 0
+    roof["kernel"] = {"tiles": "k_tile2_f64" if two_term else "k_tile_f64",
+                      "strassen": "k_str_f64" if form == "intile" else "k_gemm_terms_f64",
+                      "gemm": "k_tile_f64", "syrk": "k_tile_f64", "combine": "k_combine_f64"}.get(dom, dom)
+    roof["traffic"] = _profiled_traffic(roof["kernel"], n, cfg["key"])
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches_per_step"] = launches_per_step
+    return roof
 
 
 def _log(msg):
@@ -135,6 +215,47 @@ def _full_check(A_np, C_host, cpu_rows):
             "max_scaled_err": oracle.scaled_err(C_host, ref, n)}
 
 
+def _square_leg(P, torch, dev, stream, n: int, args):
+    """The square workload at another order: the same tuning (classical
+    off-diagonal products and one Strassen level, product tiles and in-tile,
+    and the library default), the classical SYRK on the same GPU, and the
+    fastest output against the oracle entry by entry."""
+    import oracle
+    import synthetic
+    A_np = synthetic.uniform(n, n, synthetic.SEED_SQUARE)
+    A = torch.from_numpy(A_np).to(dev)
+    C = torch.empty(P.tri(n), dtype=torch.float64, device=dev)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize(dev)
+        return e0.elapsed_time(e1) / k
+
+    cfgs = [c for c in _sweep_configs(args) if c["levels"] in (0, 1, -1) and c["variant"] == "strassen"
+            and c["form"] != "opsums"]
+    sweep = {c["key"]: timed(lambda: _run_cfg(P, A, C, stream, c), 5) for c in cfgs}
+    best = min(sweep, key=sweep.get)
+    cfg = {c["key"]: c for c in cfgs}[best]
+    ms = timed(lambda: _run_cfg(P, A, C, stream, cfg), max(5, args.steps))
+    got = C.cpu().numpy()
+    ref = oracle.classical_mt(A_np, threads=_host_info()["threads"])
+    cms = timed(lambda: P.gram(A, cutoff=n, max_depth=0, out=C, stream=stream), 5)
+    flops = float(n) ** 3
+    out = {"workload": "square FP64 A %dx%d, i.i.d. uniform[-1,1] (seed %d)" % (n, n, synthetic.SEED_SQUARE),
+           "tuned": best, "ms": ms, "tflops_mn2": flops / (ms * 1e-3) / 1e12, "tuning_sweep_ms": sweep,
+           "classical_ms": cms, "classical_tflops_mn2": flops / (cms * 1e-3) / 1e12,
+           "rel_fro": oracle.rel_fro(got, ref, n), "max_scaled_err": oracle.scaled_err(got, ref, n)}
+    _log("square %d: %s %.2f ms (classical %.2f ms), relF %.2e" % (n, best, ms, cms, out["rel_fro"]))
+    return out
+
+
 def _precision_forms(P, torch, dev, stream, n: int, steps: int):
     """The 8192 x 8192 precision workload: FP32, bfloat16-split and e4m3
     leaves on the FP32-rounded uniform input, each timed and checked against
@@ -181,11 +302,35 @@ def _precision_forms(P, torch, dev, stream, n: int, steps: int):
     return out
 
 
-def _serving(P, torch, n_req: int, budget: int, max_active: int, streams: int):
+def _freivalds_device(torch, C, A, n, gen):
+    """|| C x - A^t (A x) || / (||A||_F^2 ||x||) for packed C and A on the
+    device, in FP64 (torch's own products; A converted in row blocks)."""
+    dev = C.device
+    x = torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
+    full = torch.zeros(n, n, dtype=torch.float64, device=dev)
+    il = torch.tril_indices(n, n, device=dev)
+    full[il[0], il[1]] = C.double()
+    cx = full @ x + full.t() @ x - torch.diagonal(full) * x
+    del full, il
+    atax = torch.zeros(n, dtype=torch.float64, device=dev)
+    fro2 = 0.0
+    for r0 in range(0, A.shape[0], 8192):
+        blk = A[r0:r0 + 8192].double()
+        atax += blk.t() @ (blk @ x)
+        fro2 += float((blk * blk).sum())
+    den = fro2 * float(x.norm())
+    return float((cx - atax).norm()) / den if den > 0 else float((cx - atax).norm())
+
+
+def _serving(P, torch, n_req: int, budget: int, max_active: int, streams: int, oracle_seconds: float):
     """Gram-request stream: Poisson arrivals, m log-uniform in [1024, 65536],
     n log-uniform in [64, 4096], FP32 N(0,1) entries drawn on the device.
     Closed loop first (all requests at t=0) to find the saturation rate X,
-    then open loop at 0.5 X and 0.8 X.  Latency = completion - submission."""
+    then open loop at 0.5 X and 0.8 X.  Latency = completion - submission.
+    A separate, untimed verification run of the same stream keeps every A:
+    each result is checked by Freivalds' test on the device, and the oracle
+    checks every 100th request with m n^2 <= 1e10 and then the others with
+    m n^2 <= 1e10 (smallest first) within a time budget."""
     import queue
     import threading
 
@@ -195,31 +340,22 @@ def _serving(P, torch, n_req: int, budget: int, max_active: int, streams: int):
 
     t_unit, ms, ns = synthetic.request_stream(n_req, seed=synthetic.SEED_STREAM, rate_per_s=1.0)
     flops = ms.astype(np.float64) * ns.astype(np.float64) ** 2
+    threads = _host_info()["threads"]
 
-    def run(rate, checks=0):
+    def run(rate):
         with Server(budget, max_active=max_active, streams=streams) as s:
             q = queue.Queue()
             infos = [None] * n_req
-            check_out = []
 
             def releaser():
                 for i in range(n_req):
-                    tk, keep = q.get()
-                    if keep:
-                        C, A = s.take(tk, want_a=True)
-                        check_out.append((C, A))
-                        infos[i] = {"t_submit": 0.0, "t_done": 0.0, "checked": True}
-                    else:
-                        infos[i] = s.wait(tk, timeout=600)
-                        s.release(tk)
+                    tk = q.get()
+                    infos[i] = s.wait(tk, timeout=600)
+                    s.release(tk)
 
             th = threading.Thread(target=releaser)
             th.start()
             t0 = time.perf_counter()
-            check_ids = set()
-            if checks:
-                small = [i for i in range(n_req) if flops[i] <= 2e9]
-                check_ids = set(small[:: max(1, len(small) // checks)][:checks])
             for i in range(n_req):
                 if rate:
                     target = t0 + t_unit[i] / rate
@@ -228,28 +364,54 @@ def _serving(P, torch, n_req: int, budget: int, max_active: int, streams: int):
                         if dt <= 0:
                             break
                         time.sleep(min(dt, 0.0005) if dt > 0.0002 else 0)
-                keep = i in check_ids
-                tk = s.submit(int(ms[i]), int(ns[i]), dtype=P.F32, seed=synthetic.SEED_REQUEST_BASE + i,
-                              keep_a=keep)
-                q.put((tk, keep))
+                q.put(s.submit(int(ms[i]), int(ns[i]), dtype=P.F32, seed=synthetic.SEED_REQUEST_BASE + i))
             th.join()
             st = s.stats()
-        recs = [r for r in infos if not r.get("checked")]
-        lat = np.array([r["t_done"] - r["t_submit"] for r in recs]) * 1e3
-        t_first = min(r["t_submit"] for r in recs)
-        t_last = max(r["t_done"] for r in recs)
-        done_flops = float(sum(r["flops"] for r in recs))
-        errs = [oracle.rel_fro(C.astype(np.float64), oracle.classical(A.astype(np.float64)), A.shape[1])
-                for C, A in check_out]
-        return {"requests": len(recs), "makespan_s": t_last - t_first,
-                "throughput_req_s": len(recs) / (t_last - t_first),
+        lat = np.array([r["t_done"] - r["t_submit"] for r in infos]) * 1e3
+        t_first = min(r["t_submit"] for r in infos)
+        t_last = max(r["t_done"] for r in infos)
+        done_flops = float(sum(r["flops"] for r in infos))
+        return {"requests": n_req, "makespan_s": t_last - t_first,
+                "throughput_req_s": n_req / (t_last - t_first),
                 "tflops_mn2": done_flops / (t_last - t_first) / 1e12,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "batched_requests": st["batched_requests"],
-                "grouped_launches": st["batches"], "pool_peak_gb": st["pool_peak"] / 1e9,
-                "oracle_checks": len(errs), "max_rel_fro": max(errs) if errs else None}
+                "grouped_launches": st["batches"], "chunked_requests": int(sum(1 for r in infos if r["slabs"] > 1)),
+                "pool_peak_gb": st["pool_peak"] / 1e9}
 
-    closed = run(None, checks=8)
+    def verify():
+        small = [i for i in range(n_req) if flops[i] <= 1e10]
+        order = small[::100] + sorted(set(small) - set(small[::100]), key=lambda i: flops[i])
+        rank = {i: k for k, i in enumerate(order)}
+        gen = torch.Generator(device="cuda").manual_seed(7)
+        worst_f, worst_o, n_oracle, oracle_s = 0.0, 0.0, 0, 0.0
+        with Server(budget, max_active=max_active, streams=streams) as s:
+            # a window of requests in flight: results (and their kept A) are
+            # taken in submission order, so the pool never fills with finished
+            # requests that wait behind one it cannot admit
+            window = 2 * max_active
+            sub = lambda i: s.submit(int(ms[i]), int(ns[i]), dtype=P.F32, seed=synthetic.SEED_REQUEST_BASE + i,
+                                     keep_a=True)
+            tickets = [sub(i) for i in range(min(window, n_req))]
+            for i in range(n_req):
+                tk = tickets[i]
+                if i + window < n_req:
+                    tickets.append(sub(i + window))
+                C, A = s.take(tk, want_a=True, device=True)
+                worst_f = max(worst_f, _freivalds_device(torch, C, A, int(ns[i]), gen))
+                if i in rank and (rank[i] < len(small[::100]) or oracle_s < oracle_seconds):
+                    t = time.perf_counter()
+                    An = A.cpu().numpy().astype(np.float64)
+                    ref = oracle.classical_mt(An, threads=threads) if flops[i] > 1e8 else oracle.classical(An)
+                    worst_o = max(worst_o, oracle.rel_fro(C.cpu().numpy().astype(np.float64), ref, int(ns[i])))
+                    oracle_s += time.perf_counter() - t
+                    n_oracle += 1
+                del C, A
+        return {"requests": n_req, "freivalds_checked": n_req, "max_freivalds_residual": worst_f,
+                "oracle_checked": n_oracle, "oracle_candidates_mn2_le_1e10": len(small),
+                "oracle_seconds": oracle_s, "max_rel_fro_vs_oracle": worst_o}
+
+    closed = run(None)
     x = closed["throughput_req_s"]
     _log("serving closed loop: %.1f req/s" % x)
     out = {"workload": "%d requests, m log-uniform [1024, 65536], n log-uniform [64, 4096], FP32 N(0,1) "
@@ -261,6 +423,10 @@ def _serving(P, torch, n_req: int, budget: int, max_active: int, streams: int):
         r["rate_req_s"] = frac * x
         out["open_%.1fX" % frac] = r
         _log("serving open loop %.1fX: p50 %.2f ms p99 %.2f ms" % (frac, r["p50_ms"], r["p99_ms"]))
+    out["verification"] = verify()
+    _log("serving verification: Freivalds max %.2e over %d, oracle max relF %.2e over %d"
+         % (out["verification"]["max_freivalds_residual"], n_req, out["verification"]["max_rel_fro_vs_oracle"],
+            out["verification"]["oracle_checked"]))
     return out
 
 
@@ -409,19 +575,23 @@ def main():
     ap.add_argument("--n", type=int, default=10000)
     ap.add_argument("--cutoff", type=int, default=0, help="0: tune over {128,256,512}")
     ap.add_argument("--max-depth", type=int, default=None, help="default: tune over {1, 2}")
-    ap.add_argument("--variant", default="strassen")
+    ap.add_argument("--no-variant-sweep", dest="variant_sweep", action="store_false",
+                    help="do not time the Winograd variant in the sweep")
     ap.add_argument("--form", default="tune", choices=("tune", "intile", "tiles", "opsums"),
                     help="last Strassen level: in-tile, product tiles (fused sums), product tiles on operand sums "
                          "formed in a memory pass, or tuned (all three timed; the headline takes the fastest "
                          "fused form)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-5000", action="store_true", help="skip the 5000 x 5000 leg")
     ap.add_argument("--no-check", action="store_true", help="skip the full-output oracle check")
     ap.add_argument("--no-classical", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--precision-n", type=int, default=8192)
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=5000)
+    ap.add_argument("--serving-requests", type=int, default=10000)
+    ap.add_argument("--serving-oracle-seconds", type=float, default=30.0,
+                    help="time budget of the serving leg's oracle checks beyond every 100th small request")
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--no-tall", action="store_true")
     ap.add_argument("--no-normal", action="store_true", help="skip the Cholesky / least-squares leg")
@@ -448,9 +618,8 @@ def main():
     A = torch.from_numpy(A_np).to(dev)
     C = torch.empty(P.tri(n), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
-    def run(cutoff, d, form="intile", variant=args.variant):
-        P.gram(A, cutoff=cutoff, max_depth=d, variant=variant, out=C, stream=stream, intile=form == "intile",
-               operand_sums=form == "opsums")
+    def run(cfg):
+        _run_cfg(P, A, C, stream, cfg)
 
     def time_steps(fn, steps):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -463,71 +632,63 @@ def main():
         torch.cuda.synchronize(dev)
         return e0.elapsed_time(e1) / steps
 
-    # tuning of the leaf cutoff over the set the workload names, of the
-    # number of Strassen levels per off-diagonal product, and of the form of
-    # the last level.  The headline takes the forms that fuse the operand sums
-    # into the staged operand loads (inside the tile; product tiles); product
-    # tiles on operand sums formed in a separate memory pass are timed beside
-    # them for reference.
+    # Tuning over the configurations of the method: the leaf cutoff over the
+    # set the workload names, the Strassen levels per off-diagonal product
+    # (0: classical off-diagonal products), the form of the Strassen levels
+    # (product tiles or in-tile, both fusing the operand sums into the staged
+    # loads; product tiles on operand sums formed in a memory pass are timed
+    # for reference only), the Winograd variant, and the library's default
+    # call (adaptive depth).  The headline takes the fastest; the fastest
+    # configuration with at least one Strassen level is reported beside it.
+    cfgs = _sweep_configs(args)
     sweep = {}
-    cutoffs = (128, 256, 512) if args.cutoff == 0 else (args.cutoff,)
-    depths = (1, 2) if args.max_depth is None else (args.max_depth,)
-    forms = ("intile", "tiles", "opsums") if args.form == "tune" else (args.form,)
-    for c in cutoffs:
-        for d in depths:
-            for f in forms:
-                key = "c%d_d%d_%s" % (c, d, f)
-                run(c, d, f)
-                sweep[key] = time_steps(lambda: run(c, d, f), 3)
-                _log("sweep %s: %.2f ms" % (key, sweep[key]))
-    fused = {k: v for k, v in sweep.items() if k.split("_")[2] in FUSED_FORMS} or sweep
-    best = min(fused, key=fused.get)
-    cutoff, depth = (int(x[1:]) for x in best.split("_")[:2])
-    form = best.split("_")[2]
-    intile = form == "intile"
+    for cfg in cfgs:
+        run(cfg)
+        sweep[cfg["key"]] = time_steps(lambda: run(cfg), 3)
+        _log("sweep %s: %.2f ms" % (cfg["key"], sweep[cfg["key"]]))
+    by_key = {c["key"]: c for c in cfgs}
+    fused = {k: v for k, v in sweep.items() if by_key[k]["form"] != "opsums"} or sweep
+    best = by_key[min(fused, key=fused.get)]
+    strassen_keys = {k: v for k, v in fused.items() if by_key[k]["levels"] >= 1}
+    best_str = by_key[min(strassen_keys, key=strassen_keys.get)] if strassen_keys else None
 
     for _ in range(args.warmup):
-        run(cutoff, depth, form)
-    ms = time_steps(lambda: run(cutoff, depth, form), args.steps)
-    _log("timed %d steps: %.3f ms/step" % (args.steps, ms))
+        run(best)
+    ms = time_steps(lambda: run(best), args.steps)
+    _log("timed %d steps (%s): %.3f ms/step" % (args.steps, best["key"], ms))
     C_host = C.cpu().numpy()  # the timed output, checked entry by entry below
     # Per-kernel split: the same steps again with HIP events around every
     # launch, on the stream each kernel is launched on (kept out of the
     # headline's timed region above).
-    P.profile_enable(True)
-    P.profile_collect()
-    ms_prof = time_steps(lambda: run(cutoff, depth, form), args.steps)
-    prof = P.profile_collect()
-    P.profile_enable(False)
+    ms_prof, prof = _profiled(P, lambda: run(best), time_steps, args.steps)
     _log("profiled pass: %.3f ms/step" % ms_prof)
-
-    st = P.plan_info(m, n, cutoff, max_depth=depth, variant=args.variant, intile=intile,
-                     operand_sums=form == "opsums")
+    st = _plan_stats(P, m, n, best)
     flops_mn2 = float(m) * n * n
     value = flops_mn2 / (ms * 1e-3) / 1e12
-
-    # dominant kernel: the in-tile Strassen tiles (one launch per product)
     kt = {k: v for k, v in prof.items() if v[1] > 0}
-    dom = max(kt, key=lambda k: kt[k][0])
-    dom_ms, dom_launches = kt[dom]
-    avg_ms = dom_ms / dom_launches
-    # the mixed FP64 launch runs the product tiles and the classical tiles of
-    # the phase together: its algorithmic work is all of their multiplications
-    mult_keys = {"strassen": ("strassen_mults",), "gemm": ("gemm_mults",), "syrk": ("syrk_mults",),
-                 "tiles": ("strassen_mults", "gemm_mults", "syrk_mults")}.get(dom)
-    launches_per_step = dom_launches / args.steps
-    if mult_keys:
-        alg_flops = 2.0 * sum(st[k] for k in mult_keys) / launches_per_step
-        roof = {"bound": "mfma", "achieved": alg_flops / (avg_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "algorithmic_flops_per_launch": alg_flops}
-    else:
-        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] else None
-    roof["kernel"] = {"strassen": {"intile": "k_str_f64", "tiles": "k_gemm_terms_f64", "opsums": "k_tile_f64"}[form],
-                      "tiles": "k_tile2_f64" if (form == "tiles" and depth >= 1) else "k_tile_f64",
-                      "gemm": "k_tile_f64", "syrk": "k_tile_f64", "combine": "k_combine_f64"}.get(dom, dom)
-    roof["traffic"] = _profiled_traffic(roof["kernel"], n, cutoff, depth, form)
-    roof["avg_launch_ms"] = avg_ms
+    roof = _roofline(kt, st, best, args.steps, n)
+
+    strassen = None
+    if best_str is not None:
+        if best_str is best:
+            s_ms, s_kt = ms, kt
+        else:
+            for _ in range(args.warmup):
+                run(best_str)
+            s_ms = time_steps(lambda: run(best_str), args.steps)
+            _, s_prof = _profiled(P, lambda: run(best_str), time_steps, args.steps)
+            s_kt = {k: v for k, v in s_prof.items() if v[1] > 0}
+        s_st = _plan_stats(P, m, n, best_str)
+        strassen = {"config": {k: best_str[k] for k in ("key", "cutoff", "levels", "form", "variant")},
+                    "ms": s_ms, "tflops_mn2": flops_mn2 / (s_ms * 1e-3) / 1e12,
+                    "mults_over_classical": s_st["mults"] / s_st["classical_mults"],
+                    "kernels_ms_per_step": {k: v[0] / args.steps for k, v in s_kt.items()},
+                    "roofline": _roofline(s_kt, s_st, best_str, args.steps, n)}
+        _log("fastest with Strassen levels (%s): %.3f ms" % (best_str["key"], s_ms))
+
+    sq5000 = None
+    if not args.no_5000 and n != 5000:
+        sq5000 = _square_leg(P, torch, dev, stream, 5000, args)
 
     if args.copy_bytes > 0:
         src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
@@ -551,7 +712,8 @@ def main():
 
     serving = None
     if not args.no_serving:
-        serving = _serving(P, torch, args.serving_requests, int(args.serving_budget_gb * 1e9), 32, 4)
+        serving = _serving(P, torch, args.serving_requests, int(args.serving_budget_gb * 1e9), 32, 4,
+                           args.serving_oracle_seconds)
 
     tall = None
     if not args.no_tall:
@@ -587,12 +749,12 @@ def main():
         "config": {
             "workload": "square FP64 A %dx%d, i.i.d. uniform[-1,1] (seed %d), packed lower C = A^tA"
                         % (m, n, synthetic.SEED_SQUARE),
-            "m": m, "n": n, "cutoff": cutoff, "tuning_sweep_ms": sweep, "headline_forms": list(FUSED_FORMS), "variant": args.variant,
-            "max_strassen_depth": depth, "form": form, "last_level": {"intile": "in-tile", "tiles": "product tiles",
-                                                        "opsums": "product tiles on operand sums"}[form],
-            "phases": st["phases"], "ata_depth": st["ata_depth"],
-            "mults_over_classical": st["mults"] / st["classical_mults"],
+            "m": m, "n": n, "tuned": best["key"], "cutoff": st["cutoff"], "strassen_levels": st["max_hasa_depth"],
+            "form": best["form"], "variant": best["variant"], "phases": st["phases"], "ata_depth": st["ata_depth"],
+            "mults_over_classical": st["mults"] / st["classical_mults"], "tuning_sweep_ms": sweep,
         },
+        "strassen_best": strassen,
+        "square_5000": sq5000,
         "value_mn_n1": float(m) * n * (n + 1) / (ms * 1e-3) / 1e12,
         "roofline": roof,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},

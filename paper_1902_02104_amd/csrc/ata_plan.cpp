@@ -106,6 +106,8 @@ private:
         return d;
     }
     void add_segments_merged(DevTask& t, const std::vector<Chunk>& chs);
+    bool subtree_strassen(const std::vector<int64_t>& hs, int64_t w);
+    std::map<std::vector<int64_t>, bool> strassen_memo;
     int32_t push_terms(const std::vector<XTerm>& x, const std::vector<XTerm>& y);
 };
 
@@ -148,11 +150,48 @@ int32_t Builder::push_terms(const std::vector<XTerm>& x, const std::vector<XTerm
     return off;
 }
 
+// Whether the subtree of a node of width w over row chunks of these heights
+// takes a Strassen level anywhere (memoised on the width and the distinct
+// heights).
+bool Builder::subtree_strassen(const std::vector<int64_t>& hs, int64_t w) {
+    std::vector<int64_t> key(hs);
+    std::sort(key.begin(), key.end());
+    key.erase(std::unique(key.begin(), key.end()), key.end());
+    key.push_back(w);
+    auto it = strassen_memo.find(key);
+    if (it != strassen_memo.end()) return it->second;
+    bool any = false;
+    std::vector<int64_t> sub;
+    for (size_t i = 0; i + 1 < key.size(); ++i) {
+        const int64_t h = key[i];
+        if (h <= o.cutoff || w <= o.cutoff) continue;
+        sub.push_back(ceil2(h));
+        if (h / 2 > 0) sub.push_back(h / 2);
+    }
+    if (!sub.empty()) {
+        const int64_t n1 = ceil2(w), n2 = w / 2;
+        for (int64_t h : sub) any = any || hasa_depth(n2, h, n1) > 0;
+        any = any || subtree_strassen(sub, n1) || subtree_strassen(sub, n2);
+    }
+    strassen_memo[key] = any;
+    return any;
+}
+
 int Builder::ata_node(const std::vector<Chunk>& chunks, int64_t c0, int64_t w, int phase,
                       int level) {
     std::vector<Chunk> leaf, rec;
+    // A subtree without any Strassen level is a plain partition of the
+    // classical product of its columns over its rows: it runs as one
+    // diagonal block of the whole width (the same multiplications, in
+    // larger tiles).
+    bool flat = false;
+    {
+        std::vector<int64_t> hs;
+        for (const Chunk& ch : chunks) hs.push_back(ch.h);
+        flat = !subtree_strassen(hs, w);
+    }
     for (const Chunk& ch : chunks) {
-        if (ch.h <= o.cutoff || w <= o.cutoff)
+        if (flat || ch.h <= o.cutoff || w <= o.cutoff)
             leaf.push_back(ch);
         else
             rec.push_back(ch);
