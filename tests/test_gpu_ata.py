@@ -116,11 +116,18 @@ def test_fuzz_shapes_uniform(env, orc):
 
 
 def test_non_uniform_tree(env, orc):
+    """Row chunks whose sub-trees differ run in ordered phases (one Strassen
+    level asked for; the adaptive default flattens this shape to classical
+    tiles in one phase)."""
     torch, P = env
     _say("case: 513x600 cutoff 256 (two phases)")
-    assert P.plan_info(513, 600, 256)["phases"] == 2
     A = synthetic.integer(513, 600, 5)
-    assert np.array_equal(_run(env, A, cutoff=256), orc.classical(A))
+    ref = orc.classical(A)
+    for intile in (True, False):
+        assert P.plan_info(513, 600, 256, max_depth=1, intile=intile)["phases"] == 2
+        assert np.array_equal(_run(env, A, cutoff=256, max_depth=1, intile=intile), ref)
+    assert P.plan_info(513, 600, 256)["phases"] == 1
+    assert np.array_equal(_run(env, A, cutoff=256), ref)
 
 
 def test_edge_cases(env, orc):
@@ -417,3 +424,4 @@ def test_operand_sums_uniform_fp32(env, orc):
     C32 = P.gram(torch.from_numpy(A32).cuda(), dtype=P.F32 | P.OUT_F64, cutoff=64, max_depth=1, operand_sums=True)
     torch.cuda.synchronize()
     assert orc.rel_fro(C32.cpu().numpy(), orc.classical(A32.astype(np.float64)), 700) <= 2e-5
+
