@@ -76,12 +76,15 @@ typedef struct ata_opts {
     int32_t reserved;
 } ata_opts;
 
-/* ata_opts.flags: Strassen product tiles.  By default the last Strassen
- * level of each off-diagonal product runs inside the workgroup tile (seven
- * products in registers, combined in the epilogue).  With this flag every
- * level up to two (one for Winograd) is expanded into signed operand terms
- * instead: each of the 7^d products is a classical tile whose staging sums
- * the terms, written to the workspace and combined by a separate pass. */
+/* ata_opts.flags: Strassen product tiles.  Without it (when an options
+ * struct is given) the last Strassen level of each off-diagonal product runs
+ * inside the workgroup tile (seven products in registers, combined in the
+ * epilogue).  With this flag every level up to two (one for Winograd) is
+ * expanded into signed operand terms instead: each of the 7^d products is a
+ * classical tile whose staging sums the terms, written to the workspace and
+ * combined by a separate pass.  FP64 products with at most two terms per
+ * operand (one level) run in the same launch as the phase's classical tiles.
+ * A NULL options struct selects this form for ATA_F64. */
 #define ATA_OPT_PRODUCT_TILES 0x1
 /* ata_opts.flags: with product tiles, form each product's operand sums in a
  * memory pass (the explicit sums of the paper's HASA listing) into the
@@ -187,10 +190,16 @@ int ata_workspace_bytes(int64_t m, int64_t n, int dtype, int cutoff, const ata_o
                         size_t *bytes);
 
 /*
- * Reduced-precision forms (ATA_F32_BF16X3, ATA_F32_FP8): the leaves are
- * classical products (ata_opts.max_depth must be 0 or the struct NULL); the
- * ATA recursion itself is unchanged.  FP32 MFMA accumulators are added into
- * FP64 every 512 rows; Strassen combinations and the workspace are FP64.
+ * Reduced-precision forms (ATA_F32_BF16X3, ATA_F32_FP8): the ATA recursion is
+ * unchanged and the leaves run on a transposed converted copy of A.  With a
+ * NULL options struct (or max_depth 0) the off-diagonal products are
+ * classical.  max_depth 1 or 2 (1 for Winograd) runs HASA levels as product
+ * tiles on operand sums: each product's signed sums of quadrant terms are
+ * formed in FP32 from A and then converted (bfloat16 hi/lo split, or e4m3
+ * with a power-of-two scale per operand column from the sums' own maxima);
+ * deeper levels and ATA_OPT_EQUILIBRATE return ATA_EUNSUPPORTED.  BF16x3
+ * adds its FP32 MFMA accumulators into FP64 every 512 rows; e4m3 accumulates
+ * in FP32 over the whole K.  Strassen combinations and the workspace are FP64.
  * ATA_F32 leaves support Strassen levels like ATA_F64.
  */
 

@@ -26,6 +26,23 @@ Functions
                             precision forms, written from the format
                             definitions (IEEE-754 binary32 -> bfloat16 with
                             round-to-nearest-even; OCP 8-bit e4m3)
+  gram_bf16x3(A32), gram_fp8(A32)
+                            classical products of the converted operands
+                            (hi^t hi + hi^t lo + lo^t hi; de-scaled e4m3),
+                            in FP64
+  ata_lowp(A32, fmt, cutoff, levels)
+                            Algorithm 1 with HASA levels whose operand sums
+                            are formed in FP32 and converted before each
+                            product (the reduced-precision Strassen form)
+  unpack, pack              packed lower <-> full symmetric matrix
+  rel_fro, scaled_err, freivalds_residual
+                            checkers: relative Frobenius error of packed
+                            results (off-diagonal entries counted twice),
+                            largest |dC_ij| / sqrt(C_ii C_jj), and the
+                            Freivalds residual |C x - A^t (A x)| / (|A|_F^2 |x|)
+
+Every function is pinned by tests that do not reuse it (hand values, closed
+forms, brute force, library routines, planted mistakes).
 """
 from __future__ import annotations
 

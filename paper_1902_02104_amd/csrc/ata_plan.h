@@ -111,7 +111,7 @@ struct BatchEntry {
 struct PlanOptions {
     int64_t cutoff = 32;
     int variant = 0;    // 0 Strassen, 1 Winograd
-    int max_depth = 2;  // < 0: unlimited
+    int max_depth = 1;  // < 0: unlimited (every caller sets it)
     // K splitting: a launch with fewer workgroup tiles than split_target
     // splits long K ranges (at least split_min_k each part) over several
     // workgroups whose partial results a combination sums in part order.
