@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <list>
 #include <map>
@@ -110,7 +111,9 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // classical tasks starts and ends on a multiple of `q` elements: the
 // transposed converted copy (rows padded to a multiple of 128 elements) can
 // then be staged in whole dwords (q = 2 for bfloat16, 4 for e4m3).
-bool lp_windows_aligned(const Plan& P, int q) {
+// tail_ok: a window that ends at row m counts as aligned (the converted copy
+// holds zeros from row m to its padded row length, a multiple of 128).
+bool lp_windows_aligned(const Plan& P, int q, bool tail_ok = false) {
     std::set<int32_t> desc;  // tasks that only describe operand sums (never launched)
     for (const Phase& ph : P.phases)
         for (const DevOpSum& os : ph.opsums) desc.insert(os.task);
@@ -122,10 +125,60 @@ bool lp_windows_aligned(const Plan& P, int q) {
         for (int sg = 0; sg < t.nseg; ++sg) {
             const int32_t* g = P.segs.data() + t.seg_off + (int64_t)sg * stride;
             const int64_t row = g[kSegHdr];
-            if ((row + g[1]) % q != 0 || (row + g[2]) % q != 0) return false;
+            if ((row + g[1]) % q != 0 || ((row + g[2]) % q != 0 && !(tail_ok && row + g[2] == P.m))) return false;
         }
     }
     return true;
+}
+
+// The classical tasks of a reduced-precision phase on 256 x 256 workgroup
+// tiles (k_lp8_big), longest K first, then by tile position.
+std::vector<WorkItem> big_tile_items(const Plan& P, const Phase& ph) {
+    std::vector<int32_t> ids;
+    for (const auto* v : {&ph.gemm_items, &ph.syrk_items})
+        for (const WorkItem& w : *v) ids.push_back(w.task);
+    std::sort(ids.begin(), ids.end());
+    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+    std::vector<std::pair<int64_t, WorkItem>> out;
+    for (int32_t id : ids) {
+        const DevTask& t = P.tasks[id];
+        int64_t k = 0;
+        const int stride = kSegHdr + 2 * (t.nx + t.ny);
+        for (int sg = 0; sg < t.nseg; ++sg) {
+            const int32_t* g = P.segs.data() + t.seg_off + (int64_t)sg * stride;
+            k += g[2] - g[1];
+        }
+        const int tm = (t.dM + kBigTile - 1) / kBigTile, tn = (t.dN + kBigTile - 1) / kBigTile;
+        for (int a = 0; a < tm; ++a)
+            for (int b = 0; b < tn; ++b)
+                if (t.kind != TK_SYRK || b <= a) out.push_back({k, WorkItem{id, a, b, 0}});
+    }
+    // blocks of 4 x 8 tile positions: the 32 workgroups one XCD holds at a
+    // time read 4 row panels and 8 column panels between them
+    std::stable_sort(out.begin(), out.end(), [](const std::pair<int64_t, WorkItem>& x, const std::pair<int64_t, WorkItem>& y) {
+        if (x.first != y.first) return x.first > y.first;
+        if (x.second.task != y.second.task) return x.second.task < y.second.task;
+        if (x.second.ti / 4 != y.second.ti / 4) return x.second.ti / 4 < y.second.ti / 4;
+        if (x.second.tj / 8 != y.second.tj / 8) return x.second.tj / 8 < y.second.tj / 8;
+        if (x.second.ti != y.second.ti) return x.second.ti < y.second.ti;
+        return x.second.tj < y.second.tj;
+    });
+    // workgroup 8 j + x runs on XCD x: runs of 32 consecutive items go to the
+    // positions of one XCD (a short last round uses shorter runs)
+    std::vector<WorkItem> items(out.size());
+    size_t base = 0;
+    while (base < out.size()) {
+        const size_t rem = out.size() - base;
+        const size_t run = rem >= 256 ? 32 : rem / 8;
+        if (run == 0) {
+            for (size_t k = base; k < out.size(); ++k) items[k] = out[k].second;
+            break;
+        }
+        for (size_t c = 0; c < 8; ++c)
+            for (size_t j = 0; j < run; ++j) items[base + j * 8 + c] = out[base + c * run + j].second;
+        base += 8 * run;
+    }
+    return items;
 }
 
 // Lay out a plan's tables in one host image (offsets recorded in pd).
@@ -139,6 +192,7 @@ void serialize(PlanDev& pd) {
     pd.off_segs = off;
     off = align256(off + P.segs.size() * sizeof(int32_t));
     pd.phases.resize(P.phases.size());
+    std::vector<std::vector<WorkItem>> big(P.phases.size());
     for (size_t i = 0; i < P.phases.size(); ++i) {
         const Phase& ph = P.phases[i];
         PhaseDev& d = pd.phases[i];
@@ -167,6 +221,10 @@ void serialize(PlanDev& pd) {
         d.n_mix = (int)ph.mix_items.size();
         d.off_mix = off;
         off = align256(off + ph.mix_items.size() * sizeof(WorkItem));
+        if (P.opt.lp) big[i] = big_tile_items(P, ph);
+        d.n_big = (int)big[i].size();
+        d.off_big = off;
+        off = align256(off + big[i].size() * sizeof(WorkItem));
     }
     std::vector<char>& host = pd.host_blob;
     host.assign(off ? off : 256, 0);
@@ -183,8 +241,10 @@ void serialize(PlanDev& pd) {
         std::memcpy(host.data() + d.off_cb, ph.combines.data(), ph.combines.size() * sizeof(DevCombine));
         std::memcpy(host.data() + d.off_ops, ph.opsums.data(), ph.opsums.size() * sizeof(DevOpSum));
         std::memcpy(host.data() + d.off_mix, ph.mix_items.data(), ph.mix_items.size() * sizeof(WorkItem));
+        std::memcpy(host.data() + d.off_big, big[i].data(), big[i].size() * sizeof(WorkItem));
     }
     for (int mode = 0; mode < 2; ++mode) pd.lp_aligned[mode] = lp_windows_aligned(P, mode == 0 ? 2 : 4);
+    pd.lp_aligned16 = P.opt.lp && lp_windows_aligned(P, 16, true);
 }
 
 // Copy a serialized plan into one device allocation.
@@ -533,6 +593,19 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
                                      (int)L.ldto, (const float*)(ws + L.scale_o), tb,
                                      (const WorkItem*)(pd->blob + ph.off_tg), ph.n_tg, C_lower, W, s,
                                      pdr.lp_aligned[lp_mode]);
+            }
+            if (err == hipSuccess && lp_mode == 1 && out64 && pdr.lp_aligned16 && ph.n_big >= kBigMinTiles &&
+                (int64_t)64 * L.ldt < ((int64_t)1 << 31)) {
+                // e4m3 classical tiles of 256 x 256 in one launch
+                ProfScope ps(ATA_KERNEL_GEMM, s);
+                err = launch_lp8_big(ws + L.t0, (int)L.ldt, scale, tb, (const WorkItem*)(pd->blob + ph.off_big),
+                                     ph.n_big, (double*)C_lower, W, s);
+                if (err == hipSuccess && ph.n_cb) {  // sums of split K parts
+                    ProfScope ps2(ATA_KERNEL_COMBINE, s);
+                    err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W,
+                                         C_lower, s);
+                }
+                continue;
             }
             // diagonal tiles overlap the off-diagonal ones on a forked stream
             const bool split = fork_ok && ph.n_gemm > 0 && ph.n_syrk > 0;

@@ -16,8 +16,9 @@ namespace detail {
 // Device copy of one plan's tables.
 struct PhaseDev {
     int n_str = 0, n_tg = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, n_ops = 0, n_mix = 0, str_tmax = 0, tg_tmax = 0;
+    int n_big = 0;  // reduced-precision plans: 256 x 256 tiles of the phase's classical tasks
     int64_t cb_elems = 0, ops_rows = 0;
-    size_t off_str = 0, off_tg = 0, off_gemm = 0, off_syrk = 0, off_cb = 0, off_ops = 0, off_mix = 0;
+    size_t off_str = 0, off_tg = 0, off_gemm = 0, off_syrk = 0, off_cb = 0, off_ops = 0, off_mix = 0, off_big = 0;
 };
 
 struct PlanDev {
@@ -28,6 +29,7 @@ struct PlanDev {
     size_t off_tasks = 0, off_terms = 0, off_segs = 0;
     std::vector<PhaseDev> phases;
     bool lp_aligned[2] = {false, false};  // reduced-precision modes: windows dword-aligned in the copy
+    bool lp_aligned16 = false;            // windows on 16 elements of the copy (e4m3 256 x 256 tiles)
     ~PlanDev() {
         if (blob) {
             int cur = 0;

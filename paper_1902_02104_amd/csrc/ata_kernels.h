@@ -29,6 +29,12 @@ hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const
 hipError_t launch_tile(int nt, const double* A, int64_t lda, const DevTables& tb, const WorkItem* items, int nitems,
                        double* C, double* W, hipStream_t s, const double* Aops = nullptr);
 
+// e4m3 classical tiles of 256 x 256 (items index kBigTile tiles) on the
+// transposed copy T0 (row stride ldt bytes, windows on 16 elements, 64 ldt
+// below 2^31), FP64 output.
+hipError_t launch_lp8_big(const void* T0, int ldt, const float* scale, const DevTables& tb, const WorkItem* items,
+                          int nitems, double* C, double* W, hipStream_t s);
+
 // Operand sums of the product tasks in `recs` (one workgroup per buffer row;
 // rows = total rows of the records) into `out`, in the input type.
 hipError_t launch_opsum(bool f32, const void* A, int64_t lda, const DevTables& tb, const DevOpSum* recs, int nrec,

@@ -1410,17 +1410,35 @@ __global__ void k_convert(int mode, const float* __restrict__ x, int64_t count, 
 
 // Column maxima of |A| in 256-row chunks, then power-of-two scales
 // s_j = 2^floor(log2(448 / max_j)) (1 for a zero column).
+// Column maxima of |A| over row chunks of 256: four columns per thread
+// (16-byte loads when the row stride and base allow them).
 __global__ void __launch_bounds__(256) k_colmax_part(const float* __restrict__ A, int64_t lda, int m, int n,
                                                      float* __restrict__ part) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int j = (blockIdx.x * 256 + threadIdx.x) * 4;
     const int chunk = blockIdx.y;
     if (j >= n) return;
     const int r0 = chunk * 256, r1 = min(m, r0 + 256);
-    float mx = 0.0f;
-    for (int r = r0; r < r1; ++r) mx = fmaxf(mx, fabsf(A[(int64_t)r * lda + j]));
-    part[(int64_t)chunk * n + j] = mx;
+    float mx[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const bool vec = j + 4 <= n && (lda & 3) == 0 && (((uintptr_t)A) & 15u) == 0;
+    if (vec) {
+#pragma unroll 8
+        for (int r = r0; r < r1; ++r) {
+            const float4 v = *(const float4*)(A + (int64_t)r * lda + j);
+            mx[0] = fmaxf(mx[0], fabsf(v.x));
+            mx[1] = fmaxf(mx[1], fabsf(v.y));
+            mx[2] = fmaxf(mx[2], fabsf(v.z));
+            mx[3] = fmaxf(mx[3], fabsf(v.w));
+        }
+    } else {
+        for (int r = r0; r < r1; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (j + q < n) mx[q] = fmaxf(mx[q], fabsf(A[(int64_t)r * lda + j + q]));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (j + q < n) part[(int64_t)chunk * n + j + q] = mx[q];
 }
-
 // Power-of-two e4m3 scale of a column whose largest magnitude is mx:
 // 2^floor(log2(448 / mx)), 1 for a zero column.
 __device__ __forceinline__ float e4m3_pow2_scale(float mx) {
@@ -1505,31 +1523,74 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_prep_lp(const float* __restrict__ A, int64_t lda, int m, int n, int ldt,
                                                  const float* __restrict__ scale, void* __restrict__ o0,
                                                  void* __restrict__ o1) {
-    __shared__ float tile[64][65];
-    const int k0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+    // KB k values (rows of A) x 64 columns per workgroup; each lane of the
+    // writing pass packs PK consecutive k of one output row into one store.
+    constexpr int PK = 2;
+    constexpr int KB = 64 * PK;
+    __shared__ float tile[KB][65];
+    const int k0 = blockIdx.x * KB, c0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-    for (int r = ty; r < 64; r += 4) {
-        const int k = k0 + r, c = c0 + tx;
-        float v = 0.0f;
-        if (k < m && c < n) {
-            v = A[(int64_t)k * lda + c];
-            if (MODE == 1) v *= scale[c];  // exact: power-of-two scale
+    // reading pass: four consecutive columns per lane (16 rows per round),
+    // every load of the lane in flight before the tile is written
+    {
+        const int cq = (threadIdx.x & 15) * 4, rr = threadIdx.x >> 4;
+        const int c = c0 + cq;
+        const bool vec = c + 4 <= n && (lda & 3) == 0 && (((uintptr_t)A) & 15u) == 0;
+        float4 v[KB / 16];
+#pragma unroll
+        for (int u = 0; u < KB / 16; ++u) {
+            const int k = k0 + rr + 16 * u;
+            v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (k < m) {
+                const float* src = A + (int64_t)k * lda + c;
+                if (vec) {
+                    v[u] = *(const float4*)src;
+                } else {
+                    if (c < n) v[u].x = src[0];
+                    if (c + 1 < n) v[u].y = src[1];
+                    if (c + 2 < n) v[u].z = src[2];
+                    if (c + 3 < n) v[u].w = src[3];
+                }
+            }
         }
-        tile[r][tx] = v;
+        float4 sc = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+        if (MODE == 1) {  // exact: power-of-two scales
+            if (c < n) sc.x = scale[c];
+            if (c + 1 < n) sc.y = scale[c + 1];
+            if (c + 2 < n) sc.z = scale[c + 2];
+            if (c + 3 < n) sc.w = scale[c + 3];
+        }
+#pragma unroll
+        for (int u = 0; u < KB / 16; ++u) {
+            const int r = rr + 16 * u;
+            tile[r][cq] = v[u].x * sc.x;
+            tile[r][cq + 1] = v[u].y * sc.y;
+            tile[r][cq + 2] = v[u].z * sc.z;
+            tile[r][cq + 3] = v[u].w * sc.w;
+        }
     }
     __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        const int c = c0 + r, k = k0 + tx;
-        if (c >= n || k >= ldt) continue;
-        const float v = tile[tx][r];
-        const int64_t o = (int64_t)c * ldt + k;
+    const int kk = k0 + tx * PK;
+    if (kk >= ldt) return;
+    for (int i = 0; i < 16; ++i) {
+        const int cl = ty + 4 * i, c = c0 + cl;
+        if (c >= n) break;
+        const int64_t o = (int64_t)c * ldt + kk;
         if (MODE == 0) {
-            const uint16_t h = bf16_rne(v);
-            const float hf = __uint_as_float((uint32_t)h << 16);
-            ((uint16_t*)o0)[o] = h;
-            ((uint16_t*)o1)[o] = bf16_rne(v - hf);
+            uint32_t hw = 0, lw = 0;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const float v = tile[tx * 2 + q][cl];
+                const uint16_t h = bf16_rne(v);
+                const float hf = __uint_as_float((uint32_t)h << 16);
+                hw |= (uint32_t)h << (16 * q);
+                lw |= (uint32_t)bf16_rne(v - hf) << (16 * q);
+            }
+            *(uint32_t*)((uint16_t*)o0 + o) = hw;
+            *(uint32_t*)((uint16_t*)o1 + o) = lw;
         } else {
-            ((uint8_t*)o0)[o] = e4m3_rne(v);
+            const uint32_t wd = (uint32_t)e4m3_rne(tile[tx * 2][cl]) | ((uint32_t)e4m3_rne(tile[tx * 2 + 1][cl]) << 8);
+            *(uint16_t*)((uint8_t*)o0 + o) = (uint16_t)wd;
         }
     }
 }
@@ -2091,6 +2152,169 @@ __global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8
 }
 
 // ---------------------------------------------------------------------------
+// e4m3 tiles of 256 x 256 (k_lp8_big): the tasks of k_gemm_lpd<1> on
+// workgroup tiles four times larger, for launches with enough of them.  One
+// stage of a 128 x 128 e4m3 tile is 512 MFMA cycles per wave, too short to
+// cover the latency of the next stage's copies from L2 and the MALL; here a
+// stage is 2048 MFMA cycles per SIMD (two waves of 32 MFMAs each) and every
+// byte staged feeds twice the multiply-adds.  512 threads: eight waves of
+// 128 x 64 (rows wm = wave / 4, columns wn = wave % 4), 128 k per stage,
+// double-buffered LDS of 2 x 64 KB, one workgroup per CU.
+//
+// Copies: one 16-byte buffer load per lane that writes LDS moves eight
+// 128-byte tile rows; wave w copies rows [64 (w % 4), 64 (w % 4) + 64) of
+// operand w / 4.  Physical chunk p of row r holds logical chunk
+// p ^ ((r / 2) mod 8) (the swizzle of k_gemm_lpd), so lane L of a copy
+// fetches logical chunk (L % 8) ^ ((r / 2) mod 8) of row r = 8 i + L / 8.
+// Needs every segment window of the plan on 16 elements of the copy
+// (checked on the host); chunks past the window end or the operand's last
+// row get an out-of-range offset and write zeros.
+// ---------------------------------------------------------------------------
+constexpr int BT = kBigTile;  // workgroup tile
+
+__global__ void __launch_bounds__(512, 1) k_lp8_big(const uint8_t* __restrict__ T0, int ldt,
+                                                    const float* __restrict__ scale,
+                                                    const DevTask* __restrict__ tasks,
+                                                    const DevTerm* __restrict__ terms,
+                                                    const int32_t* __restrict__ segs,
+                                                    const WorkItem* __restrict__ items, double* __restrict__ C,
+                                                    double* __restrict__ W) {
+    constexpr int KT = 128;          // k per stage (bytes of a tile row)
+    constexpr int PLANE = BT * KT;   // 32 KB
+    constexpr int NCP = 8;           // copies per wave and stage (8 rows each)
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][PLANE];  // [buffer][operand]
+
+    const WorkItem w = items[blockIdx.x];
+    const DevTask t = tasks[w.task];
+    const DevTerm tx = terms[t.term_off];
+    const DevTerm ty = terms[t.term_off + 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 2, wn = wave & 3;
+    const int i0 = w.ti * BT, j0 = w.tj * BT;
+    const int stride = kSegHdr + 2 * (t.nx + t.ny);
+    const bool syrk = t.kind == TK_SYRK;
+    // waves of a diagonal tile whose 128 x 64 part lies above the diagonal
+    // only copy (the other wave on their SIMD gets the MFMA unit)
+    const bool idle = syrk && w.ti == w.tj && wn * 64 >= wm * 128 + 128;
+
+    // copy role
+    const int cop = wave >> 2, quarter = wave & 3;
+    const DevTerm& tc = cop == 0 ? tx : ty;
+    const int row0 = tc.col + (cop == 0 ? i0 : j0) + quarter * 64;  // first copy row of this wave
+    const int nrv = tc.cvend - row0;                                // rows of the 64 that exist
+    const int rl = lane >> 3, pc = lane & 7;                        // row in a copy, physical chunk
+    uint32_t vrow[NCP];  // byte offset of this lane's chunk from row0's window start, per copy
+    int kcl[NCP];        // first k of the lane's logical chunk
+#pragma unroll
+    for (int i = 0; i < NCP; ++i) {
+        const int r = 8 * i + rl;  // row within the wave's 64 (and within the 256: quarter * 64 + r)
+        const int kc = pc ^ (((quarter * 64 + r) >> 1) & 7);
+        kcl[i] = kc * 16;
+        vrow[i] = (uint32_t)(r * ldt + kc * 16);
+    }
+
+    f4_t acc[8][4];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    int ntiles = 0;
+    for (int sgi = 0; sgi < t.nseg; ++sgi)
+        ntiles += (segs[t.seg_off + sgi * stride + 2] - segs[t.seg_off + sgi * stride + 1] + KT - 1) / KT;
+    int seg = 0;
+    int k0 = t.nseg > 0 ? segs[t.seg_off + 1] : 0;
+    int kend = t.nseg > 0 ? segs[t.seg_off + 2] : 0;
+    int krow = t.nseg > 0 ? segs[t.seg_off + kSegHdr] : 0;
+
+    auto copy_stage = [&](int buf, bool live) {
+        const int krem = live ? kend - k0 : 0;
+        const bool full = krem >= KT && nrv >= 64;
+        const uint8_t* base = T0 + ((int64_t)row0 * ldt + krow + k0);
+        const rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), (short)0, 0x7fffffff,
+                                                            0x00020000);
+        uint8_t* dst = &lds[buf][cop][quarter * 64 * KT];
+#pragma unroll
+        for (int i = 0; i < NCP; ++i) {
+            const bool ok = full || (8 * i + rl < nrv && kcl[i] < krem);
+            lds_copy16(rs, dst + i * 8 * KT, ok ? vrow[i] : kOOB);
+        }
+    };
+    auto advance = [&]() {
+        k0 += KT;
+        if (k0 >= kend) {
+            ++seg;
+            if (seg < t.nseg) {
+                k0 = segs[t.seg_off + seg * stride + 1];
+                kend = segs[t.seg_off + seg * stride + 2];
+                krow = segs[t.seg_off + seg * stride + kSegHdr];
+            }
+        }
+    };
+    auto chunk = [](int r, int kc) { return r * KT + ((kc ^ ((r >> 1) & 7)) << 4); };
+
+    if (ntiles > 0) copy_stage(0, true);
+    for (int it = 0; it < ntiles; ++it) {
+        const int buf = it & 1;
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of stage it have landed
+        __syncthreads();                // every copy of stage it landed; stage it-1 fully read
+        const bool next = it + 1 < ntiles;
+        if (next) advance();
+        copy_stage(buf ^ 1, next);
+        if (!idle) {
+            const int rsel = lane & 15, kc = 2 * (lane >> 4);  // 32 bytes: logical chunks kc, kc + 1
+            i8_t bq[4];
+#pragma unroll
+            for (int cf = 0; cf < 4; ++cf) {
+                const int rr = wn * 64 + cf * 16 + rsel;
+                const u4_t lo = *(const u4_t*)(&lds[buf][1][chunk(rr, kc)]);
+                const u4_t hi = *(const u4_t*)(&lds[buf][1][chunk(rr, kc + 1)]);
+                bq[cf] = i8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+            }
+            __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+            for (int rb = 0; rb < 8; ++rb) {
+                const int rr = wm * 128 + rb * 16 + rsel;
+                const u4_t lo = *(const u4_t*)(&lds[buf][0][chunk(rr, kc)]);
+                const u4_t hi = *(const u4_t*)(&lds[buf][0][chunk(rr, kc + 1)]);
+                const i8_t aq = i8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+#pragma unroll
+                for (int cf = 0; cf < 4; ++cf)
+                    acc[rb][cf] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aq, bq[cf], acc[rb][cf], 0, 0, 0, 0,
+                                                                                  0, 0);
+            }
+            __builtin_amdgcn_s_setprio(0);
+        }
+    }
+
+    // no copy may land after the workgroup's LDS is released
+    __builtin_amdgcn_s_waitcnt(0);
+
+    if (idle) return;
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int gi = i0 + wm * 128 + rb * 16 + 4 * (lane >> 4) + e;
+            if (gi >= t.dM) continue;
+            const int64_t rowbase = packed_index((int64_t)t.r0 + gi, t.q0);
+            const double si = 1.0 / (double)scale[tx.col + gi];
+#pragma unroll
+            for (int cf = 0; cf < 4; ++cf) {
+                const int gj = j0 + wn * 64 + cf * 16 + (lane & 15);
+                if (gj >= t.dN || (syrk && gj > gi)) continue;
+                const double v = (double)acc[rb][cf][e] * si / (double)scale[ty.col + gj];  // exact power-of-two de-scale
+                if (t.dst == 0)
+                    store_out(C + rowbase + gj, t.beta, v);
+                else
+                    W[t.ws_off + (int64_t)gi * t.N + gj] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
@@ -2288,7 +2512,7 @@ hipError_t launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t 
 hipError_t launch_colscale(const float* A, int64_t lda, int m, int n, float* part, float* scale, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int nch = m > 0 ? (m + 255) / 256 : 0;
-    if (nch > 0) hipLaunchKernelGGL(k_colmax_part, dim3((n + 255) / 256, nch), dim3(256), 0, s, A, lda, m, n, part);
+    if (nch > 0) hipLaunchKernelGGL(k_colmax_part, dim3((n + 1023) / 1024, nch), dim3(256), 0, s, A, lda, m, n, part);
     hipLaunchKernelGGL(k_colscale, dim3((n + 255) / 256), dim3(256), 0, s, part, nch, n, scale);
     return hipGetLastError();
 }
@@ -2327,7 +2551,7 @@ hipError_t launch_descale(bool f32, bool out_f64, void* C, int n, const void* sc
 hipError_t launch_prep_lp(int mode, const float* A, int64_t lda, int m, int n, int ldt, const float* scale,
                           void* out0, void* out1, hipStream_t s) {
     if (n <= 0 || ldt <= 0) return hipSuccess;
-    const dim3 g((ldt + 63) / 64, (n + 63) / 64);
+    const dim3 g((ldt + 127) / 128, (n + 63) / 64);
     if (mode == 0)
         hipLaunchKernelGGL(k_prep_lp<0>, g, dim3(256), 0, s, A, lda, m, n, ldt, scale, out0, out1);
     else
@@ -2360,6 +2584,14 @@ hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1
         else ATA_LP_LAUNCH(k_gemm_lp, 1, float);
     }
 #undef ATA_LP_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_lp8_big(const void* T0, int ldt, const float* scale, const DevTables& tb, const WorkItem* items,
+                          int nitems, double* C, double* W, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lp8_big, dim3(nitems), dim3(512), 0, s, (const uint8_t*)T0, ldt, scale, tb.tasks, tb.terms,
+                       tb.segs, items, C, W);
     return hipGetLastError();
 }
 

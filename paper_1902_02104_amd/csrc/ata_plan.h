@@ -191,6 +191,10 @@ struct Plan {
 
 // Tile sizes the kernels use (output tile per workgroup).
 constexpr int kGemmTile = 128;  // TK_GEMM / TK_SYRK
+// e4m3 classical tiles of 256 x 256 (k_lp8_big), for launches of at least
+// kBigMinTiles of them (one per CU).
+constexpr int kBigTile = 256;
+constexpr int kBigMinTiles = 256;
 constexpr int kStrTile = 64;    // TK_STR quadrant tile (4 quadrants per workgroup)
 // Largest row stride in bytes: kernels address a staged slab of rows with
 // 32-bit offsets.

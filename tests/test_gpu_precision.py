@@ -259,3 +259,28 @@ def test_lowp_strassen_uniform(env, orc, fmt, depth):
     print("   relF vs FP64 %.3e, vs reduced-precision recursion %.3e" % (err, dif), flush=True)
     assert err <= LP_STRASSEN_BOUND[(fmt, depth)]
     assert dif <= (TIGHT if fmt == "bf16x3" else 1e-4)
+
+
+@pytest.mark.parametrize("m,n", [(6144, 6144), (6001, 5999)])
+def test_fp8_large_tiles(env, orc, m, n):
+    """e4m3 launches with at least one 256 x 256 tile per CU run on the large
+    tiles (one launch of kind "gemm"; the 128 x 128 tiles of a single SYRK
+    run as kind "syrk").  Every entry against the oracle's e4m3 reference;
+    integer inputs with K = 64 stay exact (every partial sum below 2^24)."""
+    torch, P = env
+    print("case: fp8 large tiles", m, n, flush=True)
+    A = synthetic.uniform(m, n, 41, dtype=np.float32)
+    At = torch.from_numpy(A).cuda()
+    P.profile_enable(True)
+    P.profile_collect()
+    C = P.gram(At, dtype=P.F32_FP8 | P.OUT_F64, cutoff=256, max_depth=0)
+    prof = P.profile_collect()
+    P.profile_enable(False)
+    assert prof["gemm"][1] == 1 and prof["syrk"][1] == 0, prof
+    rel = orc.rel_fro(C.cpu().numpy(), orc.gram_fp8(A), n)
+    print("  relF vs e4m3 reference %.3e" % rel, flush=True)
+    assert rel <= TIGHT_FP8
+    Ai = synthetic.integer(64, n, 42).astype(np.float32)
+    Ci = P.gram(torch.from_numpy(Ai).cuda(), dtype=P.F32_FP8 | P.OUT_F64, cutoff=256, max_depth=0)
+    torch.cuda.synchronize()
+    assert np.array_equal(Ci.cpu().numpy(), orc.classical(Ai.astype(np.float64)))
