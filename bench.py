@@ -26,10 +26,11 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
 
 
-def _profiled_traffic(kernel: str, n: int, key: str):
+def _profiled_traffic(kernel: str, n: int, key: str, work_items: int):
     """HBM bytes per launch of `kernel` from its committed counter summary
     (two rocprofv3 --pmc passes scaled by a plain copy), or None when the
-    summary was taken on other kernel sources or another configuration."""
+    summary was taken on other kernel sources or on another launch (another
+    configuration whose plan has a different tile list)."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "%s_%d_traffic.md" % (kernel, n))
@@ -41,7 +42,7 @@ def _profiled_traffic(kernel: str, n: int, key: str):
         return None
     if kv.get("kernels_source_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    if kv.get("n") != str(n) or kv.get("config") != key:
+    if kv.get("n") != str(n) or (kv.get("config") != key and kv.get("work_items") != str(work_items)):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -121,7 +122,7 @@ def _roofline(kt, st, cfg, steps, n):
     roof["kernel"] = {"tiles": "k_tile2_f64" if two_term else "k_tile_f64",
                       "strassen": "k_str_f64" if form == "intile" else "k_gemm_terms_f64",
                       "gemm": "k_tile_f64", "syrk": "k_tile_f64", "combine": "k_combine_f64"}.get(dom, dom)
-    roof["traffic"] = _profiled_traffic(roof["kernel"], n, cfg["key"])
+    roof["traffic"] = _profiled_traffic(roof["kernel"], n, cfg["key"], st["work_items"])
     roof["avg_launch_ms"] = avg_ms
     roof["launches_per_step"] = launches_per_step
     return roof
@@ -256,7 +257,7 @@ def _square_leg(P, torch, dev, stream, n: int, args):
     return out
 
 
-def _precision_forms(P, torch, dev, stream, n: int, steps: int):
+def _precision_forms(P, torch, dev, stream, n: int, steps: int, depths=(0, 1, 2)):
     """The 8192 x 8192 precision workload: FP32, bfloat16-split and e4m3
     leaves on the FP32-rounded uniform input, each timed and checked against
     the FP64 oracle (plain definition) of the same FP32 input."""
@@ -273,9 +274,8 @@ def _precision_forms(P, torch, dev, stream, n: int, steps: int):
                        % (n, n, synthetic.SEED_PRECISION),
            "oracle": "FP64 plain definition on the FP32 input, %.1f s on the host" % ref_s}
     # (name, dtype, depths, MFMA products per classical product, MFMA peak TFLOP/s)
-    for name, dt, depths, mult, peak in (("fp32", P.F32, (0, 1, 2), 1, 157.3),
-                                         ("bf16x3", P.F32_BF16X3, (0, 1, 2), 3, 2500.0),
-                                         ("fp8_e4m3", P.F32_FP8, (0, 1, 2), 1, 5000.0)):
+    for name, dt, mult, peak in (("fp32", P.F32, 1, 157.3), ("bf16x3", P.F32_BF16X3, 3, 2500.0),
+                                 ("fp8_e4m3", P.F32_FP8, 1, 5000.0)):
         best = None
         for d in depths:
             fn = lambda: P.gram(At, dtype=dt | P.OUT_F64, cutoff=256, max_depth=d, out=C, stream=stream)
@@ -588,6 +588,7 @@ def main():
     ap.add_argument("--no-classical", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--precision-n", type=int, default=8192)
+    ap.add_argument("--precision-depths", default="0,1,2", help="Strassen levels timed for each precision form")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--serving-oracle-seconds", type=float, default=30.0,
@@ -708,7 +709,8 @@ def main():
 
     forms = None
     if not args.no_precision:
-        forms = _precision_forms(P, torch, dev, stream, args.precision_n, 5)
+        forms = _precision_forms(P, torch, dev, stream, args.precision_n, 5,
+                                 tuple(int(d) for d in args.precision_depths.split(",")))
 
     serving = None
     if not args.no_serving:
