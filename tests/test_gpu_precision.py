@@ -261,7 +261,7 @@ def test_lowp_strassen_uniform(env, orc, fmt, depth):
     assert dif <= (TIGHT if fmt == "bf16x3" else 1e-4)
 
 
-@pytest.mark.parametrize("m,n", [(6144, 6144), (6001, 5999)])
+@pytest.mark.parametrize("m,n", [(6144, 6144), (6001, 5999), (9001, 5903)])
 def test_fp8_large_tiles(env, orc, m, n):
     """e4m3 launches with at least one 256 x 256 tile per CU run on the large
     tiles (one launch of kind "gemm"; the 128 x 128 tiles of a single SYRK
