@@ -119,7 +119,7 @@ def _roofline(kt, st, cfg, steps, n):
     roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] else None
     form, levels = cfg["form"], st["max_hasa_depth"]
     two_term = form in ("tiles", "default") and levels == 1 and st["strassen_mults"] > 0
-    roof["kernel"] = {"tiles": "k_tile2_f64" if two_term else "k_tile_f64",
+    roof["kernel"] = {"tiles": "k_tile_q_f64" if two_term else "k_tile_f64",
                       "strassen": "k_str_f64" if form == "intile" else "k_gemm_terms_f64",
                       "gemm": "k_tile_f64", "syrk": "k_tile_f64", "combine": "k_combine_f64"}.get(dom, dom)
     roof["traffic"] = _profiled_traffic(roof["kernel"], n, cfg["key"], st["work_items"])

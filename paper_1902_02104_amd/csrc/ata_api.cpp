@@ -646,10 +646,11 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
                                    ws + L.ops, s);
             }
             if (err == hipSuccess) {
+                // two-term launches run persistent workgroups on work queues
                 ProfScope ps(ATA_KERNEL_TILES, s);
                 err = launch_tile(ph.tg_tmax <= 1 ? 1 : 2, (const double*)A, lda, tb,
                                   (const WorkItem*)(pd->blob + ph.off_mix), ph.n_mix, (double*)C_lower, W, s,
-                                  (const double*)(ws + L.ops));
+                                  (const double*)(ws + L.ops), P.queue_off >= 0 ? (int*)(W + P.queue_off) : nullptr);
             }
             if (err == hipSuccess && ph.n_cb) {
                 ProfScope ps(ATA_KERNEL_COMBINE, s);
@@ -681,7 +682,8 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             const WorkItem* it = (const WorkItem*)(pd->blob + ph.off_tg);
             if (!f32 && ph.tg_tmax <= 2)  // FP64: one-term (operand-sum buffers) or two-term tiles
                 err = launch_tile(ph.tg_tmax <= 1 ? 1 : 2, (const double*)A, lda, tb, it, ph.n_tg, (double*)C_lower, W,
-                                  s, (const double*)(ws + L.ops));
+                                  s, (const double*)(ws + L.ops),
+                                  P.queue_off >= 0 ? (int*)(W + P.queue_off) : nullptr);
             else if (ph.tg_tmax <= 1)  // products on operand-sum buffers
                 err = launch_gemm(f32, out64, A, lda, tb, it, ph.n_tg, C_lower, W, s, ws + L.ops);
             else

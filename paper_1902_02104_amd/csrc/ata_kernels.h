@@ -25,9 +25,13 @@ hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const
 
 // FP64 tiles on 16-byte direct-to-LDS copies: nt = 1 for classical tiles
 // (TK_SYRK / TK_GEMM, and products on operand-sum buffers through Aops),
-// nt = 2 for Strassen product tiles with at most two terms per operand.
+// nt = 2 for Strassen product tiles with at most two terms per operand (and
+// the classical tiles launched with them).  queue (nt = 2): kTileQueues ints
+// of device memory, cleared by the launch, which then runs persistent
+// workgroups taking the items from per-XCD work queues; null: one workgroup
+// per item.
 hipError_t launch_tile(int nt, const double* A, int64_t lda, const DevTables& tb, const WorkItem* items, int nitems,
-                       double* C, double* W, hipStream_t s, const double* Aops = nullptr);
+                       double* C, double* W, hipStream_t s, const double* Aops = nullptr, int* queue = nullptr);
 
 // e4m3 classical tiles of 256 x 256 (items index kBigTile tiles) on the
 // transposed copy T0 (row stride ldt bytes, windows on 16 elements, 64 ldt

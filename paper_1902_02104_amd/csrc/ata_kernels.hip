@@ -22,6 +22,8 @@
 // operands, which it does by construction.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <cstdint>
 #include <type_traits>
 
@@ -610,12 +612,10 @@ __device__ __forceinline__ void lds_copy16(rsrc_t r, void* lds, uint32_t voff) {
 }
 
 template <typename OUT, int NT>
-__global__ void __launch_bounds__(256, 2) k_tile(const double* __restrict__ A_, int64_t lda_,
-                                                const DevTask* __restrict__ tasks_,
-                                                const DevTerm* __restrict__ terms_,
-                                                const int32_t* __restrict__ segs_,
-                                                const WorkItem* __restrict__ items, OUT* __restrict__ C,
-                                                double* __restrict__ W, const double* __restrict__ Aops) {
+__device__ __forceinline__ void tile_body(const WorkItem w, const double* __restrict__ A_, int64_t lda_,
+                                          const DevTask* __restrict__ tasks_, const DevTerm* __restrict__ terms_,
+                                          const int32_t* __restrict__ segs_, OUT* __restrict__ C,
+                                          double* __restrict__ W, const double* __restrict__ Aops) {
     constexpr int GK = 16;               // k rows per stage
     static_assert(GK <= kStageRows, "one slab per stage");
     constexpr int NP = GK / 4;           // MFMA steps per stage
@@ -626,7 +626,6 @@ __global__ void __launch_bounds__(256, 2) k_tile(const double* __restrict__ A_, 
     typedef const __attribute__((address_space(1))) DevTask* TaskP;
     typedef const __attribute__((address_space(1))) DevTerm* TermP;
     typedef const __attribute__((address_space(1))) int32_t* SegP;
-    const WorkItem w = items[blockIdx.x];
     const double* __restrict__ A = A_;
     int64_t lda = lda_;
     const TaskP tasks = (TaskP)tasks_;
@@ -834,6 +833,54 @@ __global__ void __launch_bounds__(256, 2) k_tile(const double* __restrict__ A_, 
                     W[t.ws_off + (int64_t)gi * t.N + gj] = v;
             }
         }
+    }
+}
+
+template <typename OUT, int NT>
+__global__ void __launch_bounds__(256, 2) k_tile(const double* __restrict__ A_, int64_t lda_,
+                                                const DevTask* __restrict__ tasks_,
+                                                const DevTerm* __restrict__ terms_,
+                                                const int32_t* __restrict__ segs_,
+                                                const WorkItem* __restrict__ items, OUT* __restrict__ C,
+                                                double* __restrict__ W, const double* __restrict__ Aops) {
+    tile_body<OUT, NT>(items[blockIdx.x], A_, lda_, tasks_, terms_, segs_, C, W, Aops);
+}
+
+// Persistent two-term launch: each workgroup takes items from the work queues
+// until every queue is empty (at most eight probes per item, so every
+// workgroup leaves the loop).  Queue x holds the items at positions x, x + 8,
+// ...: the positions that a one-item-per-workgroup launch runs on XCD x, in
+// the launch's longest-first order.  The queues start at zero.
+template <typename OUT>
+__global__ void __launch_bounds__(256, 2) k_tile_q(const double* __restrict__ A_, int64_t lda_,
+                                                  const DevTask* __restrict__ tasks_,
+                                                  const DevTerm* __restrict__ terms_,
+                                                  const int32_t* __restrict__ segs_,
+                                                  const WorkItem* __restrict__ items, OUT* __restrict__ C,
+                                                  double* __restrict__ W, const double* __restrict__ Aops,
+                                                  int* __restrict__ queue, int nitems) {
+    __shared__ int s_item[2];
+    const int home = blockIdx.x & 7;
+#pragma clang loop unroll(disable)
+    for (int round = 0;; ++round) {
+        if (threadIdx.x == 0) {
+            int got = nitems;
+            for (int a = 0; a < 8; ++a) {
+                const int x = (home + a) & 7;
+                const int cnt = (nitems - x + 7) >> 3;
+                if (cnt <= 0) continue;
+                const int j = __hip_atomic_fetch_add(queue + x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (j < cnt) {
+                    got = 8 * j + x;
+                    break;
+                }
+            }
+            s_item[round & 1] = got;
+        }
+        __syncthreads();  // also: every wave is done with the previous item's LDS
+        const int idx = __builtin_amdgcn_readfirstlane(s_item[round & 1]);
+        if (idx >= nitems) break;
+        tile_body<OUT, 2>(items[idx], A_, lda_, tasks_, terms_, segs_, C, W, Aops);
     }
 }
 
@@ -2335,15 +2382,39 @@ hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const
 }
 
 hipError_t launch_tile(int nt, const double* A, int64_t lda, const DevTables& tb, const WorkItem* items, int nitems,
-                       double* C, double* W, hipStream_t s, const double* Aops) {
+                       double* C, double* W, hipStream_t s, const double* Aops, int* queue) {
     if (nitems <= 0) return hipSuccess;
-    const dim3 g(nitems), b(256);
-    if (nt <= 1)
-        hipLaunchKernelGGL((k_tile<double, 1>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W, Aops);
-    else if (nt == 2)
-        hipLaunchKernelGGL((k_tile<double, 2>), g, b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C, W, Aops);
+    if (nt < 1 || nt > 2) return hipErrorInvalidValue;
+    const dim3 b(256);
+    if (nt == 2 && queue) {
+        // persistent: as many workgroups as stay resident, queues cleared first
+        static std::atomic<int> resident[64];
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+        int r = resident[dev].load();
+        if (r == 0) {
+            int per_cu = 0, cus = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_q<double>, 256, 0);
+            if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e != hipSuccess) return e;
+            r = per_cu * cus > 0 ? per_cu * cus : 1;
+            resident[dev].store(r);
+        }
+        hipLaunchKernelGGL(k_fill_zero<int>, dim3(1), dim3(64), 0, s, queue, (int64_t)kTileQueues);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tile_q<double>, dim3(nitems < r ? nitems : r), b, 0, s, A, lda, tb.tasks, tb.terms,
+                           tb.segs, items, C, W, Aops, queue, nitems);
+        return hipGetLastError();
+    }
+    if (nt == 1)
+        hipLaunchKernelGGL((k_tile<double, 1>), dim3(nitems), b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C,
+                           W, Aops);
     else
-        return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_tile<double, 2>), dim3(nitems), b, 0, s, A, lda, tb.tasks, tb.terms, tb.segs, items, C,
+                           W, Aops);
     return hipGetLastError();
 }
 

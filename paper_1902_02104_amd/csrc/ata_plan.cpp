@@ -780,6 +780,12 @@ Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
         }
         P.work_items += (int64_t)(ph.str_items.size() + ph.tg_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
     }
+    for (const Phase& ph : P.phases)
+        if (ph.tg_tmax == 2 && (!ph.mix_items.empty() || !ph.tg_items.empty())) {
+            P.queue_off = P.ws_elems;
+            P.ws_elems += (kTileQueues + 1) / 2;  // int32 queues in FP64 elements
+            break;
+        }
     return P;
 }
 

@@ -173,6 +173,10 @@ struct Plan {
     std::vector<int32_t> segs;
     std::vector<Phase> phases;
     int64_t ws_elems = 0;
+    // Work queues of the persistent two-term tile launches (kTileQueues int32
+    // at this FP64 element offset of the workspace, shared by the phases in
+    // turn); -1 when no phase launches two-term tiles with classical ones.
+    int64_t queue_off = -1;
     int64_t opsum_elems = 0;  // operand-sum buffers, in elements of A's type
     int64_t lp_ops_rows = 0;  // reduced precision: rows of the operand copy
     int64_t lp_ops_k = 0;     // ... and its longest K
@@ -191,6 +195,7 @@ struct Plan {
 
 // Tile sizes the kernels use (output tile per workgroup).
 constexpr int kGemmTile = 128;  // TK_GEMM / TK_SYRK
+constexpr int kTileQueues = 8;  // work queues of a persistent FP64 tile launch (one per XCD)
 // e4m3 classical tiles of 256 x 256 (k_lp8_big), for launches of at least
 // kBigMinTiles of them (one per CU).
 constexpr int kBigTile = 256;
