@@ -131,56 +131,6 @@ bool lp_windows_aligned(const Plan& P, int q, bool tail_ok = false) {
     return true;
 }
 
-// The classical tasks of a reduced-precision phase on 256 x 256 workgroup
-// tiles (k_lp8_big), longest K first, then by tile position.
-std::vector<WorkItem> big_tile_items(const Plan& P, const Phase& ph) {
-    std::vector<int32_t> ids;
-    for (const auto* v : {&ph.gemm_items, &ph.syrk_items})
-        for (const WorkItem& w : *v) ids.push_back(w.task);
-    std::sort(ids.begin(), ids.end());
-    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
-    std::vector<std::pair<int64_t, WorkItem>> out;
-    for (int32_t id : ids) {
-        const DevTask& t = P.tasks[id];
-        int64_t k = 0;
-        const int stride = kSegHdr + 2 * (t.nx + t.ny);
-        for (int sg = 0; sg < t.nseg; ++sg) {
-            const int32_t* g = P.segs.data() + t.seg_off + (int64_t)sg * stride;
-            k += g[2] - g[1];
-        }
-        const int tm = (t.dM + kBigTile - 1) / kBigTile, tn = (t.dN + kBigTile - 1) / kBigTile;
-        for (int a = 0; a < tm; ++a)
-            for (int b = 0; b < tn; ++b)
-                if (t.kind != TK_SYRK || b <= a) out.push_back({k, WorkItem{id, a, b, 0}});
-    }
-    // blocks of 4 x 8 tile positions: the 32 workgroups one XCD holds at a
-    // time read 4 row panels and 8 column panels between them
-    std::stable_sort(out.begin(), out.end(), [](const std::pair<int64_t, WorkItem>& x, const std::pair<int64_t, WorkItem>& y) {
-        if (x.first != y.first) return x.first > y.first;
-        if (x.second.task != y.second.task) return x.second.task < y.second.task;
-        if (x.second.ti / 4 != y.second.ti / 4) return x.second.ti / 4 < y.second.ti / 4;
-        if (x.second.tj / 8 != y.second.tj / 8) return x.second.tj / 8 < y.second.tj / 8;
-        if (x.second.ti != y.second.ti) return x.second.ti < y.second.ti;
-        return x.second.tj < y.second.tj;
-    });
-    // workgroup 8 j + x runs on XCD x: runs of 32 consecutive items go to the
-    // positions of one XCD (a short last round uses shorter runs)
-    std::vector<WorkItem> items(out.size());
-    size_t base = 0;
-    while (base < out.size()) {
-        const size_t rem = out.size() - base;
-        const size_t run = rem >= 256 ? 32 : rem / 8;
-        if (run == 0) {
-            for (size_t k = base; k < out.size(); ++k) items[k] = out[k].second;
-            break;
-        }
-        for (size_t c = 0; c < 8; ++c)
-            for (size_t j = 0; j < run; ++j) items[base + j * 8 + c] = out[base + c * run + j].second;
-        base += 8 * run;
-    }
-    return items;
-}
-
 // Lay out a plan's tables in one host image (offsets recorded in pd).
 void serialize(PlanDev& pd) {
     const Plan& P = pd.plan;
@@ -192,7 +142,6 @@ void serialize(PlanDev& pd) {
     pd.off_segs = off;
     off = align256(off + P.segs.size() * sizeof(int32_t));
     pd.phases.resize(P.phases.size());
-    std::vector<std::vector<WorkItem>> big(P.phases.size());
     for (size_t i = 0; i < P.phases.size(); ++i) {
         const Phase& ph = P.phases[i];
         PhaseDev& d = pd.phases[i];
@@ -221,10 +170,13 @@ void serialize(PlanDev& pd) {
         d.n_mix = (int)ph.mix_items.size();
         d.off_mix = off;
         off = align256(off + ph.mix_items.size() * sizeof(WorkItem));
-        if (P.opt.lp) big[i] = big_tile_items(P, ph);
-        d.n_big = (int)big[i].size();
+        d.n_big = (int)ph.big_items.size();
         d.off_big = off;
-        off = align256(off + big[i].size() * sizeof(WorkItem));
+        off = align256(off + ph.big_items.size() * sizeof(WorkItem));
+        d.n_big_tail = (int)ph.big_tail.size();
+        d.big_tail_parts = ph.big_tail_parts;
+        d.off_big_tail = off;
+        off = align256(off + ph.big_tail.size() * sizeof(WorkItem));
     }
     std::vector<char>& host = pd.host_blob;
     host.assign(off ? off : 256, 0);
@@ -241,7 +193,8 @@ void serialize(PlanDev& pd) {
         std::memcpy(host.data() + d.off_cb, ph.combines.data(), ph.combines.size() * sizeof(DevCombine));
         std::memcpy(host.data() + d.off_ops, ph.opsums.data(), ph.opsums.size() * sizeof(DevOpSum));
         std::memcpy(host.data() + d.off_mix, ph.mix_items.data(), ph.mix_items.size() * sizeof(WorkItem));
-        std::memcpy(host.data() + d.off_big, big[i].data(), big[i].size() * sizeof(WorkItem));
+        std::memcpy(host.data() + d.off_big, ph.big_items.data(), ph.big_items.size() * sizeof(WorkItem));
+        std::memcpy(host.data() + d.off_big_tail, ph.big_tail.data(), ph.big_tail.size() * sizeof(WorkItem));
     }
     for (int mode = 0; mode < 2; ++mode) pd.lp_aligned[mode] = lp_windows_aligned(P, mode == 0 ? 2 : 4);
     pd.lp_aligned16 = P.opt.lp && lp_windows_aligned(P, 16, true);
@@ -599,7 +552,19 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
                 // e4m3 classical tiles of 256 x 256 in one launch
                 ProfScope ps(ATA_KERNEL_GEMM, s);
                 err = launch_lp8_big(ws + L.t0, (int)L.ldt, scale, tb, (const WorkItem*)(pd->blob + ph.off_big),
-                                     ph.n_big, (double*)C_lower, W, s);
+                                     ph.n_big, (double*)C_lower, W, s, 1, nullptr);
+                if (err == hipSuccess && ph.n_big_tail) {
+                    // the last, partial round of tiles with its K range split
+                    // over every CU; FP32 partials summed in part order
+                    float* part = (float*)(W + P.lp_tail_off);
+                    err = launch_lp8_big(ws + L.t0, (int)L.ldt, scale, tb,
+                                         (const WorkItem*)(pd->blob + ph.off_big_tail), ph.n_big_tail,
+                                         (double*)C_lower, W, s, ph.big_tail_parts, part);
+                    if (err == hipSuccess)
+                        err = launch_lp8_tail_sum(scale, tb, (const WorkItem*)(pd->blob + ph.off_big_tail),
+                                                  ph.n_big_tail / ph.big_tail_parts, ph.big_tail_parts, part,
+                                                  (double*)C_lower, W, s);
+                }
                 if (err == hipSuccess && ph.n_cb) {  // sums of split K parts
                     ProfScope ps2(ATA_KERNEL_COMBINE, s);
                     err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W,

@@ -17,8 +17,10 @@ namespace detail {
 struct PhaseDev {
     int n_str = 0, n_tg = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, n_ops = 0, n_mix = 0, str_tmax = 0, tg_tmax = 0;
     int n_big = 0;  // reduced-precision plans: 256 x 256 tiles of the phase's classical tasks
+    int n_big_tail = 0, big_tail_parts = 0;  // ... and the K-split tiles of their last round
     int64_t cb_elems = 0, ops_rows = 0;
-    size_t off_str = 0, off_tg = 0, off_gemm = 0, off_syrk = 0, off_cb = 0, off_ops = 0, off_mix = 0, off_big = 0;
+    size_t off_str = 0, off_tg = 0, off_gemm = 0, off_syrk = 0, off_cb = 0, off_ops = 0, off_mix = 0, off_big = 0,
+           off_big_tail = 0;
 };
 
 struct PlanDev {

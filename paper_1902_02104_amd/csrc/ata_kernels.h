@@ -36,8 +36,14 @@ hipError_t launch_tile(int nt, const double* A, int64_t lda, const DevTables& tb
 // e4m3 classical tiles of 256 x 256 (items index kBigTile tiles) on the
 // transposed copy T0 (row stride ldt bytes, windows on 16 elements, 64 ldt
 // below 2^31), FP64 output.
+// nparts > 1: the items are K-split tiles (slot = tile * nparts + part) whose
+// raw FP32 results go to part (kBigTile^2 floats per slot); then
+// launch_lp8_tail_sum sums them (ntiles tiles, the first item of each tile's
+// run describing it) into C.
 hipError_t launch_lp8_big(const void* T0, int ldt, const float* scale, const DevTables& tb, const WorkItem* items,
-                          int nitems, double* C, double* W, hipStream_t s);
+                          int nitems, double* C, double* W, hipStream_t s, int nparts = 1, float* part = nullptr);
+hipError_t launch_lp8_tail_sum(const float* scale, const DevTables& tb, const WorkItem* tail, int ntiles, int nparts,
+                               const float* part, double* C, double* W, hipStream_t s);
 
 // Operand sums of the product tasks in `recs` (one workgroup per buffer row;
 // rows = total rows of the records) into `out`, in the input type.

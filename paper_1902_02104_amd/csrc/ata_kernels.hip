@@ -2225,7 +2225,7 @@ __global__ void __launch_bounds__(512, 1) k_lp8_big(const uint8_t* __restrict__ 
                                                     const DevTerm* __restrict__ terms,
                                                     const int32_t* __restrict__ segs,
                                                     const WorkItem* __restrict__ items, double* __restrict__ C,
-                                                    double* __restrict__ W) {
+                                                    double* __restrict__ W, int nparts, float* __restrict__ part) {
     constexpr int KT = 128;          // k per stage (bytes of a tile row)
     constexpr int PLANE = BT * KT;   // 32 KB
     constexpr int NCP = 8;           // copies per wave and stage (8 rows each)
@@ -2301,6 +2301,14 @@ __global__ void __launch_bounds__(512, 1) k_lp8_big(const uint8_t* __restrict__ 
     };
     auto chunk = [](int r, int kc) { return r * KT + ((kc ^ ((r >> 1) & 7)) << 4); };
 
+    // K-split item (nparts > 1): slot = tile * nparts + part; the part runs
+    // stages [part * ntiles / nparts, (part + 1) * ntiles / nparts)
+    const int tq = nparts > 1 ? w.slot / nparts : 0, tp = nparts > 1 ? w.slot % nparts : 0;
+    if (nparts > 1) {
+        const int s0 = (int)((int64_t)ntiles * tp / nparts), s1 = (int)((int64_t)ntiles * (tp + 1) / nparts);
+        for (int u = 0; u < s0; ++u) advance();
+        ntiles = s1 - s0;
+    }
     if (ntiles > 0) copy_stage(0, true);
     for (int it = 0; it < ntiles; ++it) {
         const int buf = it & 1;
@@ -2339,6 +2347,17 @@ __global__ void __launch_bounds__(512, 1) k_lp8_big(const uint8_t* __restrict__ 
     __builtin_amdgcn_s_waitcnt(0);
 
     if (idle) return;
+    if (nparts > 1) {  // raw FP32 partial tile
+        float* pt = part + (int64_t)(tq * nparts + tp) * BT * BT;
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int cf = 0; cf < 4; ++cf)
+                    pt[(wm * 128 + rb * 16 + 4 * (lane >> 4) + e) * BT + wn * 64 + cf * 16 + (lane & 15)] = acc[rb][cf][e];
+        return;
+    }
 #pragma unroll
     for (int rb = 0; rb < 8; ++rb) {
 #pragma unroll
@@ -2359,6 +2378,31 @@ __global__ void __launch_bounds__(512, 1) k_lp8_big(const uint8_t* __restrict__ 
             }
         }
     }
+}
+
+// Sum of the K parts of the split last-round tiles (FP64, in part order),
+// de-scaled and stored as k_lp8_big stores: block (li, q) covers row li of
+// tail tile q, one thread per column.
+__global__ void __launch_bounds__(256) k_lp8_tail_sum(const float* __restrict__ scale,
+                                                     const DevTask* __restrict__ tasks,
+                                                     const DevTerm* __restrict__ terms,
+                                                     const WorkItem* __restrict__ tail, int nparts,
+                                                     const float* __restrict__ part, double* __restrict__ C,
+                                                     double* __restrict__ W) {
+    const int q = blockIdx.y, li = blockIdx.x, lj = threadIdx.x;
+    const WorkItem w = tail[q * nparts];
+    const DevTask t = tasks[w.task];
+    const int gi = w.ti * BT + li, gj = w.tj * BT + lj;
+    if (gi >= t.dM || gj >= t.dN || (t.kind == TK_SYRK && gj > gi)) return;
+    const DevTerm tx = terms[t.term_off];
+    const DevTerm ty = terms[t.term_off + 1];
+    double v = 0.0;
+    for (int p = 0; p < nparts; ++p) v += (double)part[((int64_t)(q * nparts + p) * BT + li) * BT + lj];
+    v = v * (1.0 / (double)scale[tx.col + gi]) / (double)scale[ty.col + gj];  // exact power-of-two de-scale
+    if (t.dst == 0)
+        store_out(C + packed_index((int64_t)t.r0 + gi, t.q0) + gj, t.beta, v);
+    else
+        W[t.ws_off + (int64_t)gi * t.N + gj] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -2659,10 +2703,18 @@ hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1
 }
 
 hipError_t launch_lp8_big(const void* T0, int ldt, const float* scale, const DevTables& tb, const WorkItem* items,
-                          int nitems, double* C, double* W, hipStream_t s) {
+                          int nitems, double* C, double* W, hipStream_t s, int nparts, float* part) {
     if (nitems <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_lp8_big, dim3(nitems), dim3(512), 0, s, (const uint8_t*)T0, ldt, scale, tb.tasks, tb.terms,
-                       tb.segs, items, C, W);
+                       tb.segs, items, C, W, nparts, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_lp8_tail_sum(const float* scale, const DevTables& tb, const WorkItem* tail, int ntiles, int nparts,
+                               const float* part, double* C, double* W, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lp8_tail_sum, dim3(kBigTile, ntiles), dim3(kBigTile), 0, s, scale, tb.tasks, tb.terms, tail,
+                       nparts, part, C, W);
     return hipGetLastError();
 }
 

@@ -683,6 +683,91 @@ void split_k(Plan& P) {
     }
 }
 
+// The classical tasks of a reduced-precision phase on 256 x 256 workgroup
+// tiles (k_lp8_big), longest K first, then by tile position.
+std::vector<WorkItem> big_tile_items(const Plan& P, const Phase& ph) {
+    std::vector<int32_t> ids;
+    for (const auto* v : {&ph.gemm_items, &ph.syrk_items})
+        for (const WorkItem& w : *v) ids.push_back(w.task);
+    std::sort(ids.begin(), ids.end());
+    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+    std::vector<std::pair<int64_t, WorkItem>> out;
+    for (int32_t id : ids) {
+        const DevTask& t = P.tasks[id];
+        int64_t k = 0;
+        const int stride = kSegHdr + 2 * (t.nx + t.ny);
+        for (int sg = 0; sg < t.nseg; ++sg) {
+            const int32_t* g = P.segs.data() + t.seg_off + (int64_t)sg * stride;
+            k += g[2] - g[1];
+        }
+        const int tm = (t.dM + kBigTile - 1) / kBigTile, tn = (t.dN + kBigTile - 1) / kBigTile;
+        for (int a = 0; a < tm; ++a)
+            for (int b = 0; b < tn; ++b)
+                if (t.kind != TK_SYRK || b <= a) out.push_back({k, WorkItem{id, a, b, 0}});
+    }
+    // blocks of 4 x 8 tile positions: the 32 workgroups one XCD holds at a
+    // time read 4 row panels and 8 column panels between them
+    std::stable_sort(out.begin(), out.end(), [](const std::pair<int64_t, WorkItem>& x, const std::pair<int64_t, WorkItem>& y) {
+        if (x.first != y.first) return x.first > y.first;
+        if (x.second.task != y.second.task) return x.second.task < y.second.task;
+        if (x.second.ti / 4 != y.second.ti / 4) return x.second.ti / 4 < y.second.ti / 4;
+        if (x.second.tj / 8 != y.second.tj / 8) return x.second.tj / 8 < y.second.tj / 8;
+        if (x.second.ti != y.second.ti) return x.second.ti < y.second.ti;
+        return x.second.tj < y.second.tj;
+    });
+    // workgroup 8 j + x runs on XCD x: runs of 32 consecutive items go to the
+    // positions of one XCD (a short last round uses shorter runs)
+    std::vector<WorkItem> items(out.size());
+    size_t base = 0;
+    while (base < out.size()) {
+        const size_t rem = out.size() - base;
+        const size_t run = rem >= 256 ? 32 : rem / 8;
+        if (run == 0) {
+            for (size_t k = base; k < out.size(); ++k) items[k] = out[k].second;
+            break;
+        }
+        for (size_t c = 0; c < 8; ++c)
+            for (size_t j = 0; j < run; ++j) items[base + j * 8 + c] = out[base + c * run + j].second;
+        base += 8 * run;
+    }
+    return items;
+}
+
+// Reduced-precision plans: the 256 x 256 e4m3 tiles of every phase.  When
+// their count leaves a last round of at most half the resident workgroups,
+// those last tiles (the last positions of the launch) become a launch of
+// their own with the K range of each split into parts, so that the round
+// spreads over every CU; the parts' FP32 results go to the workspace and are
+// summed in part order.
+void lp_big_tiles(Plan& P) {
+    int64_t most = 0;
+    for (Phase& ph : P.phases) {
+        ph.big_items = big_tile_items(P, ph);
+        const int64_t nb = (int64_t)ph.big_items.size(), r = nb % kBigMinTiles;
+        if (nb <= kBigMinTiles || r == 0 || r > kBigMinTiles / 2) continue;
+        int parts = (int)(kBigMinTiles / r);
+        for (int64_t q = nb - r; q < nb; ++q) {
+            const DevTask& t = P.tasks[ph.big_items[q].task];
+            const int64_t stages = (task_k(P, t) + 127) / 128;
+            parts = (int)std::min<int64_t>(parts, stages / 4);
+        }
+        if (parts < 2) continue;
+        for (int64_t q = nb - r; q < nb; ++q)
+            for (int p = 0; p < parts; ++p) {
+                WorkItem w = ph.big_items[q];
+                w.slot = (int32_t)((q - (nb - r)) * parts + p);
+                ph.big_tail.push_back(w);
+            }
+        ph.big_items.resize(nb - r);
+        ph.big_tail_parts = parts;
+        most = std::max<int64_t>(most, r * parts);
+    }
+    if (most > 0) {
+        P.lp_tail_off = P.ws_elems;
+        P.ws_elems += most * kBigTile * kBigTile / 2;  // FP32 partial tiles in FP64 elements
+    }
+}
+
 }  // namespace
 
 Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
@@ -780,6 +865,7 @@ Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
         }
         P.work_items += (int64_t)(ph.str_items.size() + ph.tg_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
     }
+    if (opt.lp) lp_big_tiles(P);
     for (const Phase& ph : P.phases)
         if (ph.tg_tmax == 2 && (!ph.mix_items.empty() || !ph.tg_items.empty())) {
             P.queue_off = P.ws_elems;

@@ -159,6 +159,11 @@ struct Phase {
     std::vector<WorkItem> mix_items;
     std::vector<DevCombine> combines;
     std::vector<DevOpSum> opsums;  // run before the product tiles
+    // Reduced-precision plans: the classical tasks on 256 x 256 e4m3 tiles,
+    // and the tiles of a short last round split into big_tail_parts K parts
+    // (slot = tile * parts + part).
+    std::vector<WorkItem> big_items, big_tail;
+    int big_tail_parts = 0;
     int64_t combine_elems = 0;
     int64_t opsum_rows = 0;
     int str_tmax = 0;  // most operand terms of any TK_STR task in this phase
@@ -177,6 +182,9 @@ struct Plan {
     // at this FP64 element offset of the workspace, shared by the phases in
     // turn); -1 when no phase launches two-term tiles with classical ones.
     int64_t queue_off = -1;
+    // FP32 partial tiles of the split last round of e4m3 tiles (element offset
+    // in the FP64 workspace; -1 when no phase splits one)
+    int64_t lp_tail_off = -1;
     int64_t opsum_elems = 0;  // operand-sum buffers, in elements of A's type
     int64_t lp_ops_rows = 0;  // reduced precision: rows of the operand copy
     int64_t lp_ops_k = 0;     // ... and its longest K
