@@ -173,6 +173,10 @@ void serialize(PlanDev& pd) {
         d.n_big = (int)ph.big_items.size();
         d.off_big = off;
         off = align256(off + ph.big_items.size() * sizeof(WorkItem));
+        d.n_tail = (int)ph.tail_items.size();
+        d.tail_parts = ph.tail_parts;
+        d.off_tail = off;
+        off = align256(off + ph.tail_items.size() * sizeof(WorkItem));
         d.n_big_tail = (int)ph.big_tail.size();
         d.big_tail_parts = ph.big_tail_parts;
         d.off_big_tail = off;
@@ -195,6 +199,7 @@ void serialize(PlanDev& pd) {
         std::memcpy(host.data() + d.off_mix, ph.mix_items.data(), ph.mix_items.size() * sizeof(WorkItem));
         std::memcpy(host.data() + d.off_big, ph.big_items.data(), ph.big_items.size() * sizeof(WorkItem));
         std::memcpy(host.data() + d.off_big_tail, ph.big_tail.data(), ph.big_tail.size() * sizeof(WorkItem));
+        std::memcpy(host.data() + d.off_tail, ph.tail_items.data(), ph.tail_items.size() * sizeof(WorkItem));
     }
     for (int mode = 0; mode < 2; ++mode) pd.lp_aligned[mode] = lp_windows_aligned(P, mode == 0 ? 2 : 4);
     pd.lp_aligned16 = P.opt.lp && lp_windows_aligned(P, 16, true);
@@ -235,6 +240,7 @@ int plan_flags(int flags, int dtype) {
             (dtype_lp(dtype) ? kPlanReducedPrecision : 0);
     if ((flags & ATA_OPT_ADAPTIVE) && (dtype & 0xff) != ATA_F64) f |= kPlanF32;
     if ((flags & ATA_OPT_ADAPTIVE) && !dtype_lp(dtype)) f |= flags & ATA_OPT_EQUILIBRATE_AUTO;
+    if ((dtype & 0xff) == ATA_F64) f |= kPlanF64;
     return f;
 }
 bool want_equilibrate(int flags, const Plan& P, int dtype) {
@@ -383,6 +389,7 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
     if (flags & kPlanNoSplit) po.split_target = 0;
     if (flags & kPlanAccumulate) po.accumulate = true;
     if (flags & kPlanReducedPrecision) po.lp = true;
+    if (flags & kPlanF64) po.split_tail = true;
     if (flags & ATA_OPT_ADAPTIVE) {
         // Fractions of the MFMA peak measured on MI355X for this library's
         // tiles (rocprof MFMA busy of whole launches at 10000^2): FP64
@@ -616,6 +623,10 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
                 err = launch_tile(ph.tg_tmax <= 1 ? 1 : 2, (const double*)A, lda, tb,
                                   (const WorkItem*)(pd->blob + ph.off_mix), ph.n_mix, (double*)C_lower, W, s,
                                   (const double*)(ws + L.ops), P.queue_off >= 0 ? (int*)(W + P.queue_off) : nullptr);
+                if (err == hipSuccess && ph.n_tail)  // the K-split last round
+                    err = launch_tile_split((const double*)A, lda, tb, (const WorkItem*)(pd->blob + ph.off_tail),
+                                            ph.n_tail, ph.tail_parts, W + P.tile_tail_off, (double*)C_lower, W, s,
+                                            (const double*)(ws + L.ops));
             }
             if (err == hipSuccess && ph.n_cb) {
                 ProfScope ps(ATA_KERNEL_COMBINE, s);

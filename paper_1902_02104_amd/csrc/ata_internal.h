@@ -18,9 +18,10 @@ struct PhaseDev {
     int n_str = 0, n_tg = 0, n_gemm = 0, n_syrk = 0, n_cb = 0, n_ops = 0, n_mix = 0, str_tmax = 0, tg_tmax = 0;
     int n_big = 0;  // reduced-precision plans: 256 x 256 tiles of the phase's classical tasks
     int n_big_tail = 0, big_tail_parts = 0;  // ... and the K-split tiles of their last round
+    int n_tail = 0, tail_parts = 0;          // FP64: K-split tiles of the last round of the mix launch
     int64_t cb_elems = 0, ops_rows = 0;
     size_t off_str = 0, off_tg = 0, off_gemm = 0, off_syrk = 0, off_cb = 0, off_ops = 0, off_mix = 0, off_big = 0,
-           off_big_tail = 0;
+           off_big_tail = 0, off_tail = 0;
 };
 
 struct PlanDev {
@@ -111,6 +112,9 @@ constexpr int kPlanNoSplit = 0x20000;
 constexpr int kPlanF32 = 0x40000;
 // Internal plan flag: accumulate into C (row slabs of one product).
 constexpr int kPlanAccumulate = 0x80000;
+// Internal plan flag: FP64 input (one-term tile launches split a short last
+// round, see Plan::tile_tail_off).
+constexpr int kPlanF64 = 0x100000;
 // Equilibration in effect for a call with these option flags and this plan.
 bool want_equilibrate(int flags, const Plan& P, int dtype);
 int plan_flags(int flags, int dtype);

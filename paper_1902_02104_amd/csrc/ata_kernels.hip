@@ -611,11 +611,14 @@ __device__ __forceinline__ void lds_copy16(rsrc_t r, void* lds, uint32_t voff) {
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, 0, 0, 0);
 }
 
-template <typename OUT, int NT>
+// SPLIT: the item is part (slot mod nparts) of a K-split tile: it runs that
+// share of the tile's stages and writes its raw result to tile slot of part.
+template <typename OUT, int NT, bool SPLIT = false>
 __device__ __forceinline__ void tile_body(const WorkItem w, const double* __restrict__ A_, int64_t lda_,
                                           const DevTask* __restrict__ tasks_, const DevTerm* __restrict__ terms_,
                                           const int32_t* __restrict__ segs_, OUT* __restrict__ C,
-                                          double* __restrict__ W, const double* __restrict__ Aops) {
+                                          double* __restrict__ W, const double* __restrict__ Aops,
+                                          int nparts = 1, double* __restrict__ part = nullptr) {
     constexpr int GK = 16;               // k rows per stage
     static_assert(GK <= kStageRows, "one slab per stage");
     constexpr int NP = GK / 4;           // MFMA steps per stage
@@ -759,6 +762,12 @@ __device__ __forceinline__ void tile_body(const WorkItem w, const double* __rest
         }
     };
 
+    if constexpr (SPLIT) {
+        const int tp = w.slot % nparts;
+        const int s0 = (int)((int64_t)ntiles * tp / nparts), s1 = (int)((int64_t)ntiles * (tp + 1) / nparts);
+        for (int u = 0; u < s0; ++u) advance();
+        ntiles = s1 - s0;
+    }
     if (ntiles > 0) {
         slab(true);
         copying = true;
@@ -814,6 +823,18 @@ __device__ __forceinline__ void tile_body(const WorkItem w, const double* __rest
 
     // epilogue: slot (2q + ha, row g) -> tile row 8q + 2g + ha of the wave,
     // slot (2u + hb, column j) -> tile column 32u + 2j + hb
+    if constexpr (SPLIT) {
+        double* pt = part + (int64_t)w.slot * GT * GT;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int ha = 0; ha < 2; ++ha)
+#pragma unroll
+                for (int cf = 0; cf < 4; ++cf)
+                    pt[(wm * 64 + 8 * q + 2 * g + ha) * GT + wn * 64 + 32 * (cf >> 1) + 2 * (lane & 15) + (cf & 1)] =
+                        osgn * acc[2 * q + ha][cf];
+        return;
+    }
     const bool syrk = t.kind == TK_SYRK;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -882,6 +903,39 @@ __global__ void __launch_bounds__(256, 2) k_tile_q(const double* __restrict__ A_
         if (idx >= nitems) break;
         tile_body<OUT, 2>(items[idx], A_, lda_, tasks_, terms_, segs_, C, W, Aops);
     }
+}
+
+// K-split last round of a one-term launch: item i is part (slot mod nparts)
+// of tile slot / nparts; the parts' raw results go to `part`.
+template <typename OUT>
+__global__ void __launch_bounds__(256, 2) k_tile_part(const double* __restrict__ A_, int64_t lda_,
+                                                     const DevTask* __restrict__ tasks_,
+                                                     const DevTerm* __restrict__ terms_,
+                                                     const int32_t* __restrict__ segs_,
+                                                     const WorkItem* __restrict__ items, OUT* __restrict__ C,
+                                                     double* __restrict__ W, const double* __restrict__ Aops,
+                                                     int nparts, double* __restrict__ part) {
+    tile_body<OUT, 1, true>(items[blockIdx.x], A_, lda_, tasks_, terms_, segs_, C, W, Aops, nparts, part);
+}
+
+// Sum of the parts of the K-split tiles in part order, stored as k_tile
+// stores a tile: block (li, q) covers row li of split tile q.
+template <typename OUT>
+__global__ void __launch_bounds__(GT) k_tile_part_sum(const DevTask* __restrict__ tasks,
+                                                     const WorkItem* __restrict__ tail, int nparts,
+                                                     const double* __restrict__ part, OUT* __restrict__ C,
+                                                     double* __restrict__ W) {
+    const int q = blockIdx.y, li = blockIdx.x, lj = threadIdx.x;
+    const WorkItem w = tail[q * nparts];
+    const DevTask t = tasks[w.task];
+    const int gi = w.ti * GT + li, gj = w.tj * GT + lj;
+    if (gi >= t.dM || gj >= t.dN || (t.kind == TK_SYRK && gj > gi)) return;
+    double v = 0.0;
+    for (int p = 0; p < nparts; ++p) v += part[((int64_t)(q * nparts + p) * GT + li) * GT + lj];
+    if (t.dst == 0)
+        store_out(C + packed_index((int64_t)t.r0 + gi, t.q0) + gj, t.beta, v);
+    else
+        W[t.ws_off + (int64_t)gi * t.N + gj] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -2597,6 +2651,18 @@ hipError_t launch_combine(bool out_f64, const DevCombine* cbs, int ncb, int64_t 
         hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, (double*)C);
     else
         hipLaunchKernelGGL(k_combine<float>, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, (float*)C);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_split(const double* A, int64_t lda, const DevTables& tb, const WorkItem* tail, int ntail,
+                             int nparts, double* part, double* C, double* W, hipStream_t s, const double* Aops) {
+    if (ntail <= 0 || nparts < 1) return hipSuccess;
+    hipLaunchKernelGGL((k_tile_part<double>), dim3(ntail), dim3(256), 0, s, A, lda, tb.tasks, tb.terms, tb.segs, tail,
+                       C, W, Aops, nparts, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tile_part_sum<double>), dim3(GT, ntail / nparts), dim3(GT), 0, s, tb.tasks, tail, nparts,
+                       (const double*)part, C, W);
     return hipGetLastError();
 }
 

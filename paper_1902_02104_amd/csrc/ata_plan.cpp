@@ -768,6 +768,37 @@ void lp_big_tiles(Plan& P) {
     }
 }
 
+// FP64 one-term tile launches (classical tiles alone, run one workgroup per
+// item): a last round of at most half the resident workgroups leaves most
+// CUs idle at the end; those last items (the last positions of the launch)
+// become a launch of their own with each tile's K range split into parts,
+// written to the workspace and summed in part order.
+void split_tail_rounds(Plan& P) {
+    int64_t most = 0;
+    for (Phase& ph : P.phases) {
+        if (ph.mix_items.empty() || ph.tg_tmax > 1) continue;
+        const int64_t n = (int64_t)ph.mix_items.size(), r = n % kTileSlots;
+        if (n <= kTileSlots || r == 0 || r > kTileSlots / 2) continue;
+        int parts = (int)(kTileSlots / r);
+        for (int64_t q = n - r; q < n; ++q)  // at least 8 stages of 16 rows per part
+            parts = (int)std::min<int64_t>(parts, task_k(P, P.tasks[ph.mix_items[q].task]) / 128);
+        if (parts < 2) continue;
+        for (int64_t q = n - r; q < n; ++q)
+            for (int p = 0; p < parts; ++p) {
+                WorkItem w = ph.mix_items[q];
+                w.slot = (int32_t)((q - (n - r)) * parts + p);
+                ph.tail_items.push_back(w);
+            }
+        ph.mix_items.resize(n - r);
+        ph.tail_parts = parts;
+        most = std::max<int64_t>(most, r * parts);
+    }
+    if (most > 0) {
+        P.tile_tail_off = P.ws_elems;
+        P.ws_elems += most * kGemmTile * kGemmTile;
+    }
+}
+
 }  // namespace
 
 Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
@@ -866,6 +897,7 @@ Plan build_plan(int64_t m, int64_t n, const PlanOptions& opt) {
         P.work_items += (int64_t)(ph.str_items.size() + ph.tg_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
     }
     if (opt.lp) lp_big_tiles(P);
+    if (opt.split_tail && opt.split_target > 0) split_tail_rounds(P);
     for (const Phase& ph : P.phases)
         if (ph.tg_tmax == 2 && (!ph.mix_items.empty() || !ph.tg_items.empty())) {
             P.queue_off = P.ws_elems;

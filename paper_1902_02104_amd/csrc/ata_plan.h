@@ -141,6 +141,9 @@ struct PlanOptions {
     // Accumulate: every write into C adds to what C holds (C += A^t A), for
     // sums of products over row slabs of A.
     bool accumulate = false;
+    // FP64 one-term tile launches whose last round holds at most half the
+    // resident workgroups run that round K-split over every CU.
+    bool split_tail = false;
     // Reduced-precision leaves: the operand sums of the Strassen products
     // (operand-sum form) are converted into rows of a separate copy instead
     // of FP32 buffers (see DevOpSum).
@@ -164,6 +167,11 @@ struct Phase {
     // (slot = tile * parts + part).
     std::vector<WorkItem> big_items, big_tail;
     int big_tail_parts = 0;
+    // FP64 one-term tile launches: the tiles of a short last round (taken off
+    // the end of mix_items) split into tail_parts K parts (slot = tile *
+    // parts + part).
+    std::vector<WorkItem> tail_items;
+    int tail_parts = 0;
     int64_t combine_elems = 0;
     int64_t opsum_rows = 0;
     int str_tmax = 0;  // most operand terms of any TK_STR task in this phase
@@ -185,6 +193,9 @@ struct Plan {
     // FP32 partial tiles of the split last round of e4m3 tiles (element offset
     // in the FP64 workspace; -1 when no phase splits one)
     int64_t lp_tail_off = -1;
+    // FP64 partial tiles of the K-split last round of one-term tile launches
+    // (element offset in the workspace; -1 when no phase splits one)
+    int64_t tile_tail_off = -1;
     int64_t opsum_elems = 0;  // operand-sum buffers, in elements of A's type
     int64_t lp_ops_rows = 0;  // reduced precision: rows of the operand copy
     int64_t lp_ops_k = 0;     // ... and its longest K
@@ -204,6 +215,7 @@ struct Plan {
 // Tile sizes the kernels use (output tile per workgroup).
 constexpr int kGemmTile = 128;  // TK_GEMM / TK_SYRK
 constexpr int kTileQueues = 8;  // work queues of a persistent FP64 tile launch (one per XCD)
+constexpr int kTileSlots = 512;  // resident FP64 tile workgroups (two per CU on 256 CUs)
 // e4m3 classical tiles of 256 x 256 (k_lp8_big), for launches of at least
 // kBigMinTiles of them (one per CU).
 constexpr int kBigTile = 256;
