@@ -137,8 +137,10 @@ typedef struct ata_opts {
  *            HASA stops at min(M, K, N) <= cutoff.  0 = tuned default for
  *            the shape.  cutoff >= min(m, n) gives one classical product.
  *   stream   hipStream_t (as void*), 0 for the null stream
- * Uses ATA_DEFAULT_MAX_DEPTH and allocates its Strassen workspace stream-
- * ordered on `stream`.
+ * Uses the default options (NULL ata_opts) and allocates its workspace
+ * stream-ordered on `stream`: Strassen products, K-split partial tiles (of
+ * launches with few tiles, and of the short last round of a launch of
+ * classical tiles), operand copies of the reduced-precision forms.
  */
 int ata(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int dtype,
         int cutoff, void *stream);
@@ -171,7 +173,8 @@ int ata_ex(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int 
  *   array of ATA_NOALLOC_SCRATCH_BYTES per GPU, which the library holds until
  *   the process ends.  The tables are copied there (hipMemcpyAsync from host
  *   memory) on every call; the product runs with K splitting off (its
- *   partial sums would need workspace) and without the helper stream, so
+ *   partial sums would need workspace; so is the split of a short last round
+ *   of tiles) and without the helper stream, so
  *   floating-point results may differ from ata_ex in rounding order only
  *   (integer-valued inputs give identical results).
  *   scratch_used  if not NULL: bytes of the array the call needs (set also
@@ -185,7 +188,8 @@ int ata_ex(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int 
 int ata_ex_noalloc(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int dtype, int cutoff,
                    void *stream, const ata_opts *opts, size_t *scratch_used);
 
-/* Bytes of device workspace ata_ex needs for this problem (0 if none). */
+/* Bytes of device workspace ata_ex needs for this problem (0 if none; FP64
+ * classical products with a short last round of tiles need some). */
 int ata_workspace_bytes(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts *opts,
                         size_t *bytes);
 
