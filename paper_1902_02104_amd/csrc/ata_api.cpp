@@ -389,7 +389,8 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
     if (flags & kPlanNoSplit) po.split_target = 0;
     if (flags & kPlanAccumulate) po.accumulate = true;
     if (flags & kPlanReducedPrecision) po.lp = true;
-    if (flags & kPlanF64) po.split_tail = true;
+    if (flags & kPlanF64) po.split_tail = 1;
+    else if (!(flags & kPlanReducedPrecision)) po.split_tail = 2;
     if (flags & ATA_OPT_ADAPTIVE) {
         // Fractions of the MFMA peak measured on MI355X for this library's
         // tiles (rocprof MFMA busy of whole launches at 10000^2): FP64
@@ -666,17 +667,25 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
                 err = launch_gemm_terms(f32, out64, ph.tg_tmax, A, lda, tb, it, ph.n_tg, C_lower, W, s);
         }
         hipStream_t s_small = split ? fc.s2 : s;
+        // FP32 phases launching one classical list: its K-split last round
+        const bool tail32 = f32 && ph.n_tail > 0;
         if (err == hipSuccess && ph.n_gemm) {
             ProfScope ps(ATA_KERNEL_GEMM, s_small);
             const WorkItem* it = (const WorkItem*)(pd->blob + ph.off_gemm);
             err = f32 ? launch_gemm(f32, out64, A, lda, tb, it, ph.n_gemm, C_lower, W, s_small)
                       : launch_tile(1, (const double*)A, lda, tb, it, ph.n_gemm, (double*)C_lower, W, s_small);
+            if (err == hipSuccess && tail32 && ph.n_syrk == 0)
+                err = launch_gemm_split(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_tail), ph.n_tail,
+                                        ph.tail_parts, W + P.tile_tail_off, C_lower, W, s_small);
         }
         if (err == hipSuccess && ph.n_syrk) {
             ProfScope ps(ATA_KERNEL_SYRK, s_small);
             const WorkItem* it = (const WorkItem*)(pd->blob + ph.off_syrk);
             err = f32 ? launch_gemm(f32, out64, A, lda, tb, it, ph.n_syrk, C_lower, W, s_small)
                       : launch_tile(1, (const double*)A, lda, tb, it, ph.n_syrk, (double*)C_lower, W, s_small);
+            if (err == hipSuccess && tail32 && ph.n_gemm == 0)
+                err = launch_gemm_split(f32, out64, A, lda, tb, (const WorkItem*)(pd->blob + ph.off_tail), ph.n_tail,
+                                        ph.tail_parts, W + P.tile_tail_off, C_lower, W, s_small);
         }
         if (split) join_fork(fc, s, err, dev);
         if (err == hipSuccess && ph.n_cb) {

@@ -45,6 +45,12 @@ hipError_t launch_lp8_big(const void* T0, int ldt, const float* scale, const Dev
 hipError_t launch_lp8_tail_sum(const float* scale, const DevTables& tb, const WorkItem* tail, int ntiles, int nparts,
                                const float* part, double* C, double* W, hipStream_t s);
 
+// The same for a launch of k_gemmd tiles (FP32, or FP64 batched/operand-sum
+// launches); C of the launch's output type.
+hipError_t launch_gemm_split(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
+                             const WorkItem* tail, int ntail, int nparts, double* part, void* C, double* W,
+                             hipStream_t s, const void* Aops = nullptr);
+
 // The K-split last round of a one-term FP64 tile launch: ntail items (slot =
 // tile * nparts + part) write raw results to `part` (128 x 128 doubles per
 // slot), then one launch sums each tile's parts in part order into C or W.

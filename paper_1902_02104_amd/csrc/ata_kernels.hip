@@ -354,13 +354,17 @@ struct DmaCfg<float> {
     static constexpr int GK = 16;
 };
 
-template <typename T, typename OUT, bool BATCH>
+// SPLIT: every item is part (slot mod nparts) of a K-split tile: it runs
+// that share of the tile's stages and writes its raw FP64 result to tile
+// slot of `part` (summed by k_tile_part_sum).
+template <typename T, typename OUT, bool BATCH, bool SPLIT = false>
 __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int64_t lda_,
                                                  const DevTask* __restrict__ tasks_,
                                                  const int32_t* __restrict__ segs_,
                                                  const WorkItem* __restrict__ items, OUT* __restrict__ C_,
                                                  double* __restrict__ W, const DevTerm* __restrict__ terms_,
-                                                 const T* __restrict__ Aops, const BatchEntry* __restrict__ batch) {
+                                                 const T* __restrict__ Aops, const BatchEntry* __restrict__ batch,
+                                                 int nparts, double* __restrict__ part) {
     typedef Eng<T> E;
     constexpr bool F32 = std::is_same<T, float>::value;
     constexpr int GK = DmaCfg<T>::GK;
@@ -500,6 +504,12 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
         }
     };
 
+    if constexpr (SPLIT) {
+        const int tp = w.slot % nparts;
+        const int s0 = (int)((int64_t)ntiles * tp / nparts), s1 = (int)((int64_t)ntiles * (tp + 1) / nparts);
+        for (int u = 0; u < s0; ++u) advance();
+        ntiles = s1 - s0;
+    }
     if (ntiles > 0) {
         slab(true);
         copying = true;
@@ -548,6 +558,18 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
     }
 
     // epilogue: rows of D go to C rows r0 + gi, columns to C columns q0 + gj
+    if constexpr (SPLIT) {
+        double* pt = part + (int64_t)w.slot * GT * GT;
+#pragma unroll
+        for (int rb = 0; rb < BR; ++rb)
+#pragma unroll
+            for (int e = 0; e < E::NA; ++e)
+#pragma unroll
+                for (int cf = 0; cf < BC; ++cf)
+                    pt[(wm * 64 + rb * E::RM + E::orow(lane, e)) * GT + wn * 64 + cf * E::RN + (lane & 15)] =
+                        F32 ? acc64[F32 ? rb : 0][F32 ? cf : 0][F32 ? e : 0] : E::elem(acc[rb][cf], e);
+        return;
+    }
     const bool syrk = t.kind == TK_SYRK;
 #pragma unroll
     for (int rb = 0; rb < BR; ++rb) {
@@ -2469,13 +2491,13 @@ hipError_t launch_gemm(bool f32, bool out_f64, const void* A, int64_t lda, const
     const BatchEntry* nb = nullptr;
     if (!f32)
         hipLaunchKernelGGL((k_gemmd<double, double, false>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.segs,
-                           items, (double*)C, W, tb.terms, (const double*)Aops, nb);
+                           items, (double*)C, W, tb.terms, (const double*)Aops, nb, 1, (double*)nullptr);
     else if (out_f64)
         hipLaunchKernelGGL((k_gemmd<float, double, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.segs,
-                           items, (double*)C, W, tb.terms, (const float*)Aops, nb);
+                           items, (double*)C, W, tb.terms, (const float*)Aops, nb, 1, (double*)nullptr);
     else
         hipLaunchKernelGGL((k_gemmd<float, float, false>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.segs,
-                           items, (float*)C, W, tb.terms, (const float*)Aops, nb);
+                           items, (float*)C, W, tb.terms, (const float*)Aops, nb, 1, (double*)nullptr);
     return hipGetLastError();
 }
 
@@ -2550,13 +2572,13 @@ hipError_t launch_gemm_batch(bool f32, bool out_f64, const BatchEntry* batch, co
     const dim3 g(nitems), b(256);
     if (!f32)
         hipLaunchKernelGGL((k_gemmd<double, double, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, items, nullptr,
-                           nullptr, nullptr, nullptr, batch);
+                           nullptr, nullptr, nullptr, batch, 1, (double*)nullptr);
     else if (out_f64)
         hipLaunchKernelGGL((k_gemmd<float, double, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, items, nullptr,
-                           nullptr, nullptr, nullptr, batch);
+                           nullptr, nullptr, nullptr, batch, 1, (double*)nullptr);
     else
         hipLaunchKernelGGL((k_gemmd<float, float, true>), g, b, 0, s, nullptr, 0, nullptr, nullptr, items, nullptr,
-                           nullptr, nullptr, nullptr, batch);
+                           nullptr, nullptr, nullptr, batch, 1, (double*)nullptr);
     return hipGetLastError();
 }
 
@@ -2651,6 +2673,31 @@ hipError_t launch_combine(bool out_f64, const DevCombine* cbs, int ncb, int64_t 
         hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, (double*)C);
     else
         hipLaunchKernelGGL(k_combine<float>, dim3((unsigned)blocks), dim3(256), 0, s, cbs, ncb, total, W, (float*)C);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_split(bool f32, bool out_f64, const void* A, int64_t lda, const DevTables& tb,
+                             const WorkItem* tail, int ntail, int nparts, double* part, void* C, double* W,
+                             hipStream_t s, const void* Aops) {
+    if (ntail <= 0 || nparts < 1) return hipSuccess;
+    const dim3 g(ntail), b(256), gs(GT, ntail / nparts), bs(GT);
+    const BatchEntry* nb = nullptr;
+    if (!f32) {
+        hipLaunchKernelGGL((k_gemmd<double, double, false, true>), g, b, 0, s, (const double*)A, lda, tb.tasks, tb.segs,
+                           tail, (double*)C, W, tb.terms, (const double*)Aops, nb, nparts, part);
+        hipLaunchKernelGGL(k_tile_part_sum<double>, gs, bs, 0, s, tb.tasks, tail, nparts, (const double*)part,
+                           (double*)C, W);
+    } else if (out_f64) {
+        hipLaunchKernelGGL((k_gemmd<float, double, false, true>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.segs,
+                           tail, (double*)C, W, tb.terms, (const float*)Aops, nb, nparts, part);
+        hipLaunchKernelGGL(k_tile_part_sum<double>, gs, bs, 0, s, tb.tasks, tail, nparts, (const double*)part,
+                           (double*)C, W);
+    } else {
+        hipLaunchKernelGGL((k_gemmd<float, float, false, true>), g, b, 0, s, (const float*)A, lda, tb.tasks, tb.segs,
+                           tail, (float*)C, W, tb.terms, (const float*)Aops, nb, nparts, part);
+        hipLaunchKernelGGL(k_tile_part_sum<float>, gs, bs, 0, s, tb.tasks, tail, nparts, (const double*)part,
+                           (float*)C, W);
+    }
     return hipGetLastError();
 }
 

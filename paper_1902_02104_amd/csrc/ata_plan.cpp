@@ -776,20 +776,27 @@ void lp_big_tiles(Plan& P) {
 void split_tail_rounds(Plan& P) {
     int64_t most = 0;
     for (Phase& ph : P.phases) {
-        if (ph.mix_items.empty() || ph.tg_tmax > 1) continue;
-        const int64_t n = (int64_t)ph.mix_items.size(), r = n % kTileSlots;
+        std::vector<WorkItem>* list = nullptr;
+        if (P.opt.split_tail == 1 && !ph.mix_items.empty() && ph.tg_tmax <= 1) list = &ph.mix_items;
+        if (P.opt.split_tail == 2 && ph.str_items.empty() && ph.tg_items.empty()) {
+            if (ph.gemm_items.empty()) list = &ph.syrk_items;
+            else if (ph.syrk_items.empty()) list = &ph.gemm_items;
+        }
+        if (!list) continue;
+        std::vector<WorkItem>& items = *list;
+        const int64_t n = (int64_t)items.size(), r = n % kTileSlots;
         if (n <= kTileSlots || r == 0 || r > kTileSlots / 2) continue;
         int parts = (int)(kTileSlots / r);
         for (int64_t q = n - r; q < n; ++q)  // at least 8 stages of 16 rows per part
-            parts = (int)std::min<int64_t>(parts, task_k(P, P.tasks[ph.mix_items[q].task]) / 128);
+            parts = (int)std::min<int64_t>(parts, task_k(P, P.tasks[items[q].task]) / 128);
         if (parts < 2) continue;
         for (int64_t q = n - r; q < n; ++q)
             for (int p = 0; p < parts; ++p) {
-                WorkItem w = ph.mix_items[q];
+                WorkItem w = items[q];
                 w.slot = (int32_t)((q - (n - r)) * parts + p);
                 ph.tail_items.push_back(w);
             }
-        ph.mix_items.resize(n - r);
+        items.resize(n - r);
         ph.tail_parts = parts;
         most = std::max<int64_t>(most, r * parts);
     }

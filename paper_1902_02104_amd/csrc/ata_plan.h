@@ -141,9 +141,11 @@ struct PlanOptions {
     // Accumulate: every write into C adds to what C holds (C += A^t A), for
     // sums of products over row slabs of A.
     bool accumulate = false;
-    // FP64 one-term tile launches whose last round holds at most half the
-    // resident workgroups run that round K-split over every CU.
-    bool split_tail = false;
+    // One-term tile launches whose last round holds at most half the
+    // resident workgroups run that round K-split over every CU: 1 for the
+    // FP64 tile launch of mix_items, 2 for an FP32 phase launching only
+    // gemm_items or only syrk_items (0: never).
+    int split_tail = 0;
     // Reduced-precision leaves: the operand sums of the Strassen products
     // (operand-sum form) are converted into rows of a separate copy instead
     // of FP32 buffers (see DevOpSum).
@@ -167,9 +169,9 @@ struct Phase {
     // (slot = tile * parts + part).
     std::vector<WorkItem> big_items, big_tail;
     int big_tail_parts = 0;
-    // FP64 one-term tile launches: the tiles of a short last round (taken off
-    // the end of mix_items) split into tail_parts K parts (slot = tile *
-    // parts + part).
+    // One-term tile launches: the tiles of a short last round (taken off the
+    // end of mix_items, or of the phase's one classical list for FP32) split
+    // into tail_parts K parts (slot = tile * parts + part).
     std::vector<WorkItem> tail_items;
     int tail_parts = 0;
     int64_t combine_elems = 0;
