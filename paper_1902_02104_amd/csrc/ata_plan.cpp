@@ -566,6 +566,10 @@ void split_k(Plan& P) {
         Phase& ph = P.phases[pi];
         const int64_t items = (int64_t)(ph.str_items.size() + ph.tg_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
         if (items == 0 || items >= o.split_target) continue;
+        // launches of two rounds of tiles or more leave only a short last
+        // round to balance, which the tail split does without partials of
+        // every tile
+        if (o.split_tail != 0 && items >= 2 * kTileSlots) continue;
         const int64_t want = std::min<int64_t>(64, o.split_target / items);
         if (want < 2) continue;
         // decide a part count per task (workspace blocks: per combine block)

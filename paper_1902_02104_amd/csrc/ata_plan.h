@@ -142,7 +142,8 @@ struct PlanOptions {
     // sums of products over row slabs of A.
     bool accumulate = false;
     // One-term tile launches whose last round holds at most half the
-    // resident workgroups run that round K-split over every CU: 1 for the
+    // resident workgroups run that round K-split over every CU (K splitting
+    // of whole launches then stops at two rounds of tiles): 1 for the
     // FP64 tile launch of mix_items, 2 for an FP32 phase launching only
     // gemm_items or only syrk_items (0: never).
     int split_tail = 0;
