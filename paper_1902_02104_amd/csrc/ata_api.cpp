@@ -241,6 +241,7 @@ int plan_flags(int flags, int dtype) {
     if ((flags & ATA_OPT_ADAPTIVE) && (dtype & 0xff) != ATA_F64) f |= kPlanF32;
     if ((flags & ATA_OPT_ADAPTIVE) && !dtype_lp(dtype)) f |= flags & ATA_OPT_EQUILIBRATE_AUTO;
     if ((dtype & 0xff) == ATA_F64) f |= kPlanF64;
+    if ((dtype & 0xff) == ATA_F32_BF16X3) f |= kPlanBf16Pair;
     return f;
 }
 bool want_equilibrate(int flags, const Plan& P, int dtype) {
@@ -391,6 +392,7 @@ int get_plan(int64_t m, int64_t n, int64_t cutoff, int variant, int max_depth, i
     if (flags & kPlanReducedPrecision) po.lp = true;
     if (flags & kPlanF64) po.split_tail = 1;
     else if (!(flags & kPlanReducedPrecision)) po.split_tail = 2;
+    else if (flags & kPlanBf16Pair) po.split_tail = 3;
     if (flags & ATA_OPT_ADAPTIVE) {
         // Fractions of the MFMA peak measured on MI355X for this library's
         // tiles (rocprof MFMA busy of whole launches at 10000^2): FP64
@@ -603,6 +605,14 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
                                      pdr.lp_aligned[lp_mode]);
             }
             if (split) join_fork(fc, s, err, dev);
+            if (err == hipSuccess && ph.n_tail) {
+                // the last, partial round of tiles with its K range split
+                // over every CU; FP64 partials summed in part order
+                ProfScope ps(ph.n_gemm ? ATA_KERNEL_GEMM : ATA_KERNEL_SYRK, s);
+                err = launch_gemm_lp_split(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
+                                           (const WorkItem*)(pd->blob + ph.off_tail), ph.n_tail, ph.tail_parts,
+                                           W + P.tile_tail_off, C_lower, W, s, pdr.lp_aligned[lp_mode]);
+            }
             if (err == hipSuccess && ph.n_cb) {  // sums of split K parts
                 ProfScope ps(ATA_KERNEL_COMBINE, s);
                 err = launch_combine(out64, (const DevCombine*)(pd->blob + ph.off_cb), ph.n_cb, ph.cb_elems, W,

@@ -115,6 +115,8 @@ constexpr int kPlanAccumulate = 0x80000;
 // Internal plan flag: FP64 input (one-term tile launches split a short last
 // round, see Plan::tile_tail_off).
 constexpr int kPlanF64 = 0x100000;
+// Internal plan flag: bfloat16-pair tiles (one resident workgroup per CU).
+constexpr int kPlanBf16Pair = 0x200000;
 // Equilibration in effect for a call with these option flags and this plan.
 bool want_equilibrate(int flags, const Plan& P, int dtype);
 int plan_flags(int flags, int dtype);

@@ -51,6 +51,11 @@ hipError_t launch_gemm_split(bool f32, bool out_f64, const void* A, int64_t lda,
                              const WorkItem* tail, int ntail, int nparts, double* part, void* C, double* W,
                              hipStream_t s, const void* Aops = nullptr);
 
+// The same for the reduced-precision classical tiles (partials de-scaled).
+hipError_t launch_gemm_lp_split(int mode, bool out_f64, const void* T0, const void* T1, int ldt, const float* scale,
+                                const DevTables& tb, const WorkItem* tail, int ntail, int nparts, double* part,
+                                void* C, double* W, hipStream_t s, bool aligned);
+
 // The K-split last round of a one-term FP64 tile launch: ntail items (slot =
 // tile * nparts + part) write raw results to `part` (128 x 128 doubles per
 // slot), then one launch sums each tile's parts in part order into C or W.

@@ -1851,14 +1851,14 @@ struct LpCfg<1> {
 
 static_assert(KFLUSH % LpCfg<0>::KT == 0 && KFLUSH % LpCfg<1>::KT == 0, "flush on stage boundaries");
 
-template <int MODE, typename OUT>
+template <int MODE, typename OUT, bool SPLIT = false>
 __global__ void __launch_bounds__(256, MODE == 1 ? 2 : 1) k_gemm_lp(const uint8_t* __restrict__ T0, const uint8_t* __restrict__ T1,
                                                     int ldt, const float* __restrict__ scale,
                                                     const DevTask* __restrict__ tasks,
                                                     const DevTerm* __restrict__ terms,
                                                     const int32_t* __restrict__ segs,
                                                     const WorkItem* __restrict__ items, OUT* __restrict__ C,
-                                                    double* __restrict__ W) {
+                                                    double* __restrict__ W, int nparts, double* __restrict__ part) {
     typedef LpCfg<MODE> L;
     constexpr int KT = L::KT, EB = L::EB, PL = L::PLANES, ROWB = L::ROWB;
     constexpr int ROWBYTES = KT * EB;           // bytes of one tile row per stage
@@ -1960,6 +1960,12 @@ __global__ void __launch_bounds__(256, MODE == 1 ? 2 : 1) k_gemm_lp(const uint8_
         }
     };
 
+    if constexpr (SPLIT) {  // part (slot mod nparts) of a K-split tile: its share of the stages
+        const int tp = w.slot % nparts;
+        const int s0 = (int)((int64_t)ntiles * tp / nparts), s1 = (int)((int64_t)ntiles * (tp + 1) / nparts);
+        for (int u = 0; u < s0; ++u) advance();
+        ntiles = s1 - s0;
+    }
     if (ntiles > 0) load();
     for (int it = 0; it < ntiles; ++it) {
         __syncthreads();  // previous stage fully read
@@ -2027,6 +2033,24 @@ __global__ void __launch_bounds__(256, MODE == 1 ? 2 : 1) k_gemm_lp(const uint8_
         }
     }
 
+    if constexpr (SPLIT) {  // de-scaled FP64 partial tile (exact power-of-two scales)
+        double* pt = part + (int64_t)w.slot * GT * GT;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int li = wm * 64 + rb * 16 + 4 * (lane >> 4) + e, gi = i0 + li;
+                const double si = MODE == 1 && gi < t.dM ? 1.0 / (double)scale[tx.col + gi] : 1.0;
+#pragma unroll
+                for (int cf = 0; cf < 4; ++cf) {
+                    const int lj = wn * 64 + cf * 16 + (lane & 15), gj = j0 + lj;
+                    double v = FL ? acc64[FL ? rb : 0][FL ? cf : 0][FL ? e : 0] : (double)acc[rb][cf][e];
+                    if (MODE == 1) v = gi < t.dM && gj < t.dN ? v * si / (double)scale[ty.col + gj] : 0.0;
+                    pt[li * GT + lj] = v;
+                }
+            }
+        return;
+    }
     const bool syrk = t.kind == TK_SYRK;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
@@ -2077,7 +2101,7 @@ struct LpdCfg<1> {  // e4m3
     static constexpr int KT = 128, EB = 1, PL = 1, OCC = 2;
 };
 
-template <int MODE, typename OUT>
+template <int MODE, typename OUT, bool SPLIT = false>
 __global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8_t* __restrict__ T0,
                                                                     const uint8_t* __restrict__ T1, int ldt,
                                                                     const float* __restrict__ scale,
@@ -2085,7 +2109,8 @@ __global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8
                                                                     const DevTerm* __restrict__ terms,
                                                                     const int32_t* __restrict__ segs,
                                                                     const WorkItem* __restrict__ items,
-                                                                    OUT* __restrict__ C, double* __restrict__ W) {
+                                                                    OUT* __restrict__ C, double* __restrict__ W,
+                                                                    int nparts, double* __restrict__ part) {
     typedef LpdCfg<MODE> L;
     constexpr int KT = L::KT, EB = L::EB, PL = L::PL;
     constexpr int RB = KT * EB;  // bytes of one tile row per stage
@@ -2180,6 +2205,12 @@ __global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8
     // byte address of logical 16-byte chunk kc of tile row r inside a plane
     auto chunk = [](int r, int kc) { return r * RB + ((kc ^ ((r >> 1) & 7)) << 4); };
 
+    if constexpr (SPLIT) {  // part (slot mod nparts) of a K-split tile: its share of the stages
+        const int tp = w.slot % nparts;
+        const int s0 = (int)((int64_t)ntiles * tp / nparts), s1 = (int)((int64_t)ntiles * (tp + 1) / nparts);
+        for (int u = 0; u < s0; ++u) advance();
+        ntiles = s1 - s0;
+    }
     if (ntiles > 0) copy_stage(0, true);
     for (int it = 0; it < ntiles; ++it) {
         const int buf = it & 1;
@@ -2250,6 +2281,24 @@ __global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8
     // no copy may land after the workgroup's LDS is released
     __builtin_amdgcn_s_waitcnt(0);
 
+    if constexpr (SPLIT) {  // de-scaled FP64 partial tile (exact power-of-two scales)
+        double* pt = part + (int64_t)w.slot * GT * GT;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int li = wm * 64 + rb * 16 + 4 * (lane >> 4) + e, gi = i0 + li;
+                const double si = MODE == 1 && gi < t.dM ? 1.0 / (double)scale[tx.col + gi] : 1.0;
+#pragma unroll
+                for (int cf = 0; cf < 4; ++cf) {
+                    const int lj = wn * 64 + cf * 16 + (lane & 15), gj = j0 + lj;
+                    double v = FL ? acc64[FL ? rb : 0][FL ? cf : 0][FL ? e : 0] : (double)acc[rb][cf][e];
+                    if (MODE == 1) v = gi < t.dM && gj < t.dN ? v * si / (double)scale[ty.col + gj] : 0.0;
+                    pt[li * GT + lj] = v;
+                }
+            }
+        return;
+    }
     const bool syrk = t.kind == TK_SYRK;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
@@ -2799,7 +2848,8 @@ hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1
     const int eb = mode == 0 ? 2 : 1;
     const bool dma = aligned && (int64_t)64 * ldt * eb < ((int64_t)1 << 31);
 #define ATA_LP_LAUNCH(K, M, O)                                                                                       \
-    hipLaunchKernelGGL((K<M, O>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs, items, (O*)C, W)
+    hipLaunchKernelGGL((K<M, O>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs, items, (O*)C, W, 1,    \
+                       (double*)nullptr)
     if (mode == 0) {
         if (dma && out_f64) ATA_LP_LAUNCH(k_gemm_lpd, 0, double);
         else if (dma) ATA_LP_LAUNCH(k_gemm_lpd, 0, float);
@@ -2828,6 +2878,41 @@ hipError_t launch_lp8_tail_sum(const float* scale, const DevTables& tb, const Wo
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_lp8_tail_sum, dim3(kBigTile, ntiles), dim3(kBigTile), 0, s, scale, tb.tasks, tb.terms, tail,
                        nparts, part, C, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_lp_split(int mode, bool out_f64, const void* T0, const void* T1, int ldt, const float* scale,
+                                const DevTables& tb, const WorkItem* tail, int ntail, int nparts, double* part,
+                                void* C, double* W, hipStream_t s, bool aligned) {
+    if (ntail <= 0 || nparts < 1) return hipSuccess;
+    const dim3 g(ntail), b(256), gs(GT, ntail / nparts), bs(GT);
+    const uint8_t* t0 = (const uint8_t*)T0;
+    const uint8_t* t1 = (const uint8_t*)(T1 ? T1 : T0);
+    const int eb = mode == 0 ? 2 : 1;
+    const bool dma = aligned && (int64_t)64 * ldt * eb < ((int64_t)1 << 31);
+#define ATA_LP_SPLIT(K, M, O)                                                                                        \
+    hipLaunchKernelGGL((K<M, O, true>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs, tail, (O*)C, W, \
+                       nparts, part)
+    if (mode == 0) {
+        if (dma && out_f64) ATA_LP_SPLIT(k_gemm_lpd, 0, double);
+        else if (dma) ATA_LP_SPLIT(k_gemm_lpd, 0, float);
+        else if (out_f64) ATA_LP_SPLIT(k_gemm_lp, 0, double);
+        else ATA_LP_SPLIT(k_gemm_lp, 0, float);
+    } else {
+        if (dma && out_f64) ATA_LP_SPLIT(k_gemm_lpd, 1, double);
+        else if (dma) ATA_LP_SPLIT(k_gemm_lpd, 1, float);
+        else if (out_f64) ATA_LP_SPLIT(k_gemm_lp, 1, double);
+        else ATA_LP_SPLIT(k_gemm_lp, 1, float);
+    }
+#undef ATA_LP_SPLIT
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (out_f64)
+        hipLaunchKernelGGL(k_tile_part_sum<double>, gs, bs, 0, s, tb.tasks, tail, nparts, (const double*)part,
+                           (double*)C, W);
+    else
+        hipLaunchKernelGGL(k_tile_part_sum<float>, gs, bs, 0, s, tb.tasks, tail, nparts, (const double*)part,
+                           (float*)C, W);
     return hipGetLastError();
 }
 

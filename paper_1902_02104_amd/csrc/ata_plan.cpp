@@ -772,7 +772,7 @@ void lp_big_tiles(Plan& P) {
     }
 }
 
-// FP64 one-term tile launches (classical tiles alone, run one workgroup per
+// One-term tile launches (classical tiles alone, run one workgroup per
 // item): a last round of at most half the resident workgroups leaves most
 // CUs idle at the end; those last items (the last positions of the launch)
 // become a launch of their own with each tile's K range split into parts,
@@ -782,15 +782,16 @@ void split_tail_rounds(Plan& P) {
     for (Phase& ph : P.phases) {
         std::vector<WorkItem>* list = nullptr;
         if (P.opt.split_tail == 1 && !ph.mix_items.empty() && ph.tg_tmax <= 1) list = &ph.mix_items;
-        if (P.opt.split_tail == 2 && ph.str_items.empty() && ph.tg_items.empty()) {
+        if (P.opt.split_tail >= 2 && ph.str_items.empty() && ph.tg_items.empty()) {
             if (ph.gemm_items.empty()) list = &ph.syrk_items;
             else if (ph.syrk_items.empty()) list = &ph.gemm_items;
         }
         if (!list) continue;
         std::vector<WorkItem>& items = *list;
-        const int64_t n = (int64_t)items.size(), r = n % kTileSlots;
-        if (n <= kTileSlots || r == 0 || r > kTileSlots / 2) continue;
-        int parts = (int)(kTileSlots / r);
+        const int64_t slots = P.opt.split_tail == 3 ? kTileSlots / 2 : kTileSlots;
+        const int64_t n = (int64_t)items.size(), r = n % slots;
+        if (n <= slots || r == 0 || r > slots / 2) continue;
+        int parts = (int)(slots / r);
         for (int64_t q = n - r; q < n; ++q)  // at least 8 stages of 16 rows per part
             parts = (int)std::min<int64_t>(parts, task_k(P, P.tasks[items[q].task]) / 128);
         if (parts < 2) continue;

@@ -145,7 +145,8 @@ struct PlanOptions {
     // resident workgroups run that round K-split over every CU (K splitting
     // of whole launches then stops at two rounds of tiles): 1 for the
     // FP64 tile launch of mix_items, 2 for an FP32 phase launching only
-    // gemm_items or only syrk_items (0: never).
+    // gemm_items or only syrk_items, 3 for the same bfloat16-pair phase (one
+    // resident workgroup per CU) (0: never).
     int split_tail = 0;
     // Reduced-precision leaves: the operand sums of the Strassen products
     // (operand-sum form) are converted into rows of a separate copy instead

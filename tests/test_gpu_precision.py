@@ -284,3 +284,32 @@ def test_fp8_large_tiles(env, orc, m, n):
     Ci = P.gram(torch.from_numpy(Ai).cuda(), dtype=P.F32_FP8 | P.OUT_F64, cutoff=256, max_depth=0)
     torch.cuda.synchronize()
     assert np.array_equal(Ci.cpu().numpy(), orc.classical(Ai.astype(np.float64)))
+
+
+@pytest.mark.parametrize("m", [1000, 1001])
+def test_bf16x3_split_last_round(env, orc, m):
+    """A single SYRK of 300 tiles of 128 x 128 at one resident bfloat16-pair
+    workgroup per CU: 256 tiles run whole, the last 44 run as a second launch
+    with each K range split into parts (partials summed in part order).  Even
+    m stages through direct-to-LDS copies, odd m through registers.  Every
+    entry against the oracle's bfloat16-pair reference, and exact on small
+    integers, with both output types."""
+    torch, P = env
+    n = 3000
+    print("case: bf16x3 split last round", m, n, flush=True)
+    A = synthetic.uniform(m, n, 43 + m, dtype=np.float32)
+    At = torch.from_numpy(A).cuda()
+    P.profile_enable(True)
+    P.profile_collect()
+    C = P.gram(At, dtype=P.F32_BF16X3 | P.OUT_F64, cutoff=256, max_depth=0)
+    prof = P.profile_collect()
+    P.profile_enable(False)
+    assert prof["syrk"][1] == 2 and prof["gemm"][1] == 0, prof
+    ref = orc.gram_bf16x3(A)
+    assert orc.rel_fro(C.cpu().numpy(), ref, n) <= TIGHT
+    C32 = P.gram(At, dtype=P.F32_BF16X3, cutoff=256, max_depth=0)
+    torch.cuda.synchronize()
+    assert orc.rel_fro(C32.double().cpu().numpy(), ref, n) <= TIGHT
+    Ai = synthetic.integer(m, n, 44 + m).astype(np.float32)
+    assert np.array_equal(_gram(env, Ai, P.F32_BF16X3 | P.OUT_F64, cutoff=256, max_depth=0),
+                          orc.classical(Ai.astype(np.float64)))
