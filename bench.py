@@ -281,14 +281,17 @@ def _precision_forms(P, torch, dev, stream, n: int, steps: int, depths=(0, 1, 2)
             fn = lambda: P.gram(At, dtype=dt | P.OUT_F64, cutoff=256, max_depth=d, out=C, stream=stream)
             fn()
             torch.cuda.synchronize(dev)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(steps):
-                fn()
-            e1.record(stream)
-            torch.cuda.synchronize(dev)
-            ms = e0.elapsed_time(e1) / steps
+            ms = None
+            for _ in range(2):  # the faster of two timed passes (the first may still see clocks ramp)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(steps):
+                    fn()
+                e1.record(stream)
+                torch.cuda.synchronize(dev)
+                t = e0.elapsed_time(e1) / steps
+                ms = t if ms is None else min(ms, t)
             err = oracle.rel_fro(C.cpu().numpy(), ref, n)
             rec = {"ms": ms, "tflops_mn2": flops / (ms * 1e-3) / 1e12, "rel_fro_vs_fp64": err, "depth": d,
                    "cutoff": 256}

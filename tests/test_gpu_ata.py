@@ -314,6 +314,34 @@ def test_split_k_tall_scaled_fp64(env, orc):
     assert orc.scaled_err(C, ref, 256) <= FP64_TOL
 
 
+@pytest.mark.parametrize("m", [1000, 1003])
+def test_split_last_round(env, orc, m):
+    """A single SYRK of 528 tiles of 128 x 128 at 512 resident workgroups:
+    512 tiles run whole and the last 16 run as a second launch with each K
+    range split into seven parts, summed in part order.  FP64 and FP32 (both
+    output types): every entry against the oracle, and exact on integers."""
+    torch, P = env
+    n = 4000
+    _say("case: split last round", m, n)
+    for dt in (P.F64, P.F32, P.F32 | P.OUT_F64):
+        # the partial tiles of the split round: 16 tiles x 7 parts x 128 x 128 doubles
+        assert P.workspace_bytes(m, n, 256, dtype=dt, max_depth=0) >= 16 * 7 * 128 * 128 * 8, dt
+    A = synthetic.uniform(m, n, 51 + m)
+    ref = orc.classical(A)
+    C = _run(env, A, cutoff=256, max_depth=0)
+    assert orc.rel_fro(C, ref, n) <= 1e-15
+    assert orc.scaled_err(C, ref, n) <= 1e-14
+    A32 = A.astype(np.float32)
+    ref32 = orc.classical(A32.astype(np.float64))
+    for dt in (P.F32, P.F32 | P.OUT_F64):
+        C = _run(env, A32, cutoff=256, max_depth=0, dtype=dt)
+        assert orc.rel_fro(C.astype(np.float64), ref32, n) <= 2e-6, dt
+    Ai = synthetic.integer(m, n, 52 + m)
+    refi = orc.classical(Ai)
+    assert np.array_equal(_run(env, Ai, cutoff=256, max_depth=0), refi)
+    assert np.array_equal(_run(env, Ai.astype(np.float32), cutoff=256, max_depth=0, dtype=P.F32 | P.OUT_F64), refi)
+
+
 @pytest.fixture(scope="module")
 def tall_full(env):
     torch, P = env

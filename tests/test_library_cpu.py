@@ -119,6 +119,24 @@ def test_workspace_size_reduced_precision(lib):
         P.plan_info(m, n, 0, dtype=P.F32_FP8, max_depth=3)  # at most two expanded levels
 
 
+def test_split_last_round_workspace(lib):
+    """A single classical launch whose last round fills at most half the
+    resident workgroups (512 for FP64 and FP32 tiles, 256 for bfloat16
+    pairs) splits the K range of those last r tiles into
+    min(slots / r, K / 128) parts; the workspace holds their FP64 partial
+    tiles.  One round, or parts below two, splits nothing."""
+    tile = 128 * 128 * 8
+    for dt in (P.F64, P.F32, P.F32 | P.OUT_F64):
+        assert P.workspace_bytes(1000, 4000, 256, dtype=dt, max_depth=0) == 16 * 7 * tile  # 528 tiles
+        assert P.workspace_bytes(1000, 4200, 256, dtype=dt, max_depth=0) == 49 * 7 * tile  # 561 tiles
+        assert P.workspace_bytes(1000, 3000, 256, dtype=dt, max_depth=0) == 0  # 300 tiles: one round
+        assert P.workspace_bytes(100, 4000, 256, dtype=dt, max_depth=0) == 0  # 100 rows: one part
+    conv = lambda n: 2 * n * 1024 * 2 + n * 4  # bfloat16 hi and lo copies, rows padded to 1024
+    bf = P.workspace_bytes(1000, 3000, 256, dtype=P.F32_BF16X3, max_depth=0)
+    assert 44 * 5 * tile <= bf - conv(3000) < 44 * 5 * tile + 65536  # 300 tiles: 256 + 44 in 5 parts
+    assert P.workspace_bytes(1000, 2000, 256, dtype=P.F32_BF16X3, max_depth=0) - conv(2000) < 65536  # 136 tiles
+
+
 def test_default_cutoff_is_in_tuned_set(lib):
     for m, n in [(256, 192), (5000, 5000), (10000, 10000), (262144, 2048)]:
         assert P.default_cutoff(m, n) in (128, 256, 512)
