@@ -284,8 +284,11 @@ bool ata_server::admit(Req* q, int pass_stream) {
     ++st.admitted;
     if (sim()) return true;
     const Plan& P = q->plan->plan;
+    // a grouped launch runs the SYRK tiles of each member whole: plans with a
+    // K-split last round launch on their own
     q->small = q->nslab == 1 && P.phases.size() == 1 && P.phases[0].str_items.empty() &&
-               P.phases[0].tg_items.empty() && P.phases[0].gemm_items.empty() && P.phases[0].combines.empty();
+               P.phases[0].tg_items.empty() && P.phases[0].gemm_items.empty() && P.phases[0].combines.empty() &&
+               P.phases[0].tail_items.empty();
     q->stream = q->small ? pass_stream : (int)((pass + q->id) % streams.size());
     hipStream_t s = streams[q->stream];
     void* A = base + q->a.off;
@@ -580,8 +583,9 @@ int ata_server_submit(ata_server* srv, const ata_request* req, uint64_t* ticket)
         const int64_t rows = q->slab_rows ? q->slab_rows : req->m;
         q->nslab = q->slab_rows ? (int)((req->m + rows - 1) / rows) : 1;
         if (q->slab_rows && !req->cutoff) q->cutoff = default_cutoff(rows, req->n, req->dtype);
-        // the library's default depth rule for requests that leave it open
-        const int pf = req->max_depth == -2 ? plan_flags(ATA_OPT_ADAPTIVE, req->dtype) : 0;
+        // the library's default depth rule for requests that leave it open;
+        // the dtype class always (it selects the plan's split of short last rounds)
+        const int pf = plan_flags(req->max_depth == -2 ? ATA_OPT_ADAPTIVE : 0, req->dtype);
         rc = get_plan(rows, req->n, q->cutoff, q->variant, q->depth, pf, false, hp);
         if (rc != ATA_OK) return rc;
         q->L = ws_layout(rows, req->n, req->dtype, hp->plan.ws_elems, false, hp->plan.opsum_elems);

@@ -119,3 +119,29 @@ def test_chunked_request_exact_and_identical_in_mix(srv_env, orc):
             s.wait(k)
             s.release(k)
         assert s.stats()["pool_in_use"] == 0
+
+
+def test_split_last_round_requests(srv_env, orc):
+    """Requests whose plan is one SYRK of 528 tiles (n = 4000) run their last
+    16 tiles K-split in a launch of their own: also where the request would
+    otherwise join a grouped launch, and in every row slab of a chunked
+    request (which accumulates into C).  Exact on integer input in both
+    precisions, with the default and an explicit depth."""
+    torch, P, Server = srv_env
+    print("case: serving split last round", flush=True)
+    n = 4000
+    A1 = synthetic.integer(1000, n, 801)
+    A2 = synthetic.integer(9000, n, 802)
+    ref1 = orc.classical(A1)
+    ref2 = orc.classical_mt(A2, threads=8)
+    with Server(8 << 30, max_active=16, streams=4) as s:
+        jobs = []
+        for dt in (P.F64, P.F32):
+            want = np.float64 if dt == P.F64 else np.float32
+            for d in (None, 0):
+                jobs.append((s.submit(1000, n, dtype=dt, a=A1.astype(want), max_depth=d), ref1, 1, dt, d))
+                jobs.append((s.submit(9000, n, dtype=dt, a=A2.astype(want), max_depth=d), ref2, 3, dt, d))
+        for t, ref, slabs, dt, d in jobs:
+            assert s.wait(t)["slabs"] == slabs, (dt, d)
+            assert np.array_equal(s.take(t).astype(np.float64), ref), (dt, d, slabs)
+        assert s.stats()["pool_in_use"] == 0
