@@ -553,6 +553,27 @@ void restrict_window(Plan& P, DevTask& t, int64_t a, int64_t b) {
 
 constexpr int64_t kSplitAlign = 16;
 
+// Resident workgroups of a one-term tile launch in the given split_tail mode.
+int64_t tail_slots(int mode) { return mode == 3 ? kTileSlots / 2 : kTileSlots; }
+
+// The one-term classical list of a phase whose short last round the plan
+// splits (PlanOptions::split_tail), or null.  Before the mixed lists are
+// built (mix_built false) an FP64 phase qualifies by what its mixed list
+// will hold.
+std::vector<WorkItem>* tail_list(const PlanOptions& o, Phase& ph, bool mix_built) {
+    if (o.split_tail == 1) {
+        if (ph.tg_tmax > 1) return nullptr;
+        if (mix_built) return ph.mix_items.empty() ? nullptr : &ph.mix_items;
+        const bool any = !(ph.tg_items.empty() && ph.gemm_items.empty() && ph.syrk_items.empty());
+        return ph.str_items.empty() && any ? &ph.mix_items : nullptr;
+    }
+    if (o.split_tail >= 2 && ph.str_items.empty() && ph.tg_items.empty()) {
+        if (ph.gemm_items.empty() && !ph.syrk_items.empty()) return &ph.syrk_items;
+        if (ph.syrk_items.empty() && !ph.gemm_items.empty()) return &ph.gemm_items;
+    }
+    return nullptr;
+}
+
 // Split long K ranges of launches that have too few tiles to fill the GPU.
 // A task writing C becomes nparts tasks writing dense partial blocks to the
 // workspace plus a combination that sums them (in part order) into C; the
@@ -566,10 +587,10 @@ void split_k(Plan& P) {
         Phase& ph = P.phases[pi];
         const int64_t items = (int64_t)(ph.str_items.size() + ph.tg_items.size() + ph.gemm_items.size() + ph.syrk_items.size());
         if (items == 0 || items >= o.split_target) continue;
-        // launches of two rounds of tiles or more leave only a short last
-        // round to balance, which the tail split does without partials of
-        // every tile
-        if (o.split_tail != 0 && items >= 2 * kTileSlots) continue;
+        // launches of more than one round of tiles leave only a last round
+        // to balance, which the split of that round does without partials
+        // of every tile
+        if (items > tail_slots(o.split_tail) && tail_list(o, ph, false)) continue;
         const int64_t want = std::min<int64_t>(64, o.split_target / items);
         if (want < 2) continue;
         // decide a part count per task (workspace blocks: per combine block)
@@ -773,27 +794,39 @@ void lp_big_tiles(Plan& P) {
 }
 
 // One-term tile launches (classical tiles alone, run one workgroup per
-// item): a last round of at most half the resident workgroups leaves most
-// CUs idle at the end; those last items (the last positions of the launch)
-// become a launch of their own with each tile's K range split into parts,
-// written to the workspace and summed in part order.
+// item) of more than one round: the r items of the last round (the last
+// positions of the launch, the shortest in longest-first order) become a
+// launch of their own with each tile's K range split into p parts, written
+// to the workspace and summed in part order.  The round then takes
+// ceil(r p / slots) / p of a tile time instead of one: p = slots / r when r
+// is at most half the slots (one round of parts), else the smallest p of at
+// most 8 within 0.05 tile times of the best, taken when it saves at least a
+// fifth of a tile time.  Every part keeps at least eight 16-row stages.
 void split_tail_rounds(Plan& P) {
     int64_t most = 0;
+    const int64_t slots = tail_slots(P.opt.split_tail);
     for (Phase& ph : P.phases) {
-        std::vector<WorkItem>* list = nullptr;
-        if (P.opt.split_tail == 1 && !ph.mix_items.empty() && ph.tg_tmax <= 1) list = &ph.mix_items;
-        if (P.opt.split_tail >= 2 && ph.str_items.empty() && ph.tg_items.empty()) {
-            if (ph.gemm_items.empty()) list = &ph.syrk_items;
-            else if (ph.syrk_items.empty()) list = &ph.gemm_items;
-        }
+        std::vector<WorkItem>* list = tail_list(P.opt, ph, true);
         if (!list) continue;
         std::vector<WorkItem>& items = *list;
-        const int64_t slots = P.opt.split_tail == 3 ? kTileSlots / 2 : kTileSlots;
         const int64_t n = (int64_t)items.size(), r = n % slots;
-        if (n <= slots || r == 0 || r > slots / 2) continue;
-        int parts = (int)(slots / r);
-        for (int64_t q = n - r; q < n; ++q)  // at least 8 stages of 16 rows per part
-            parts = (int)std::min<int64_t>(parts, task_k(P, P.tasks[items[q].task]) / 128);
+        if (n <= slots || r == 0) continue;
+        int64_t pk = 64;
+        for (int64_t q = n - r; q < n; ++q) pk = std::min<int64_t>(pk, task_k(P, P.tasks[items[q].task]) / 128);
+        auto cost = [&](int64_t p) { return (double)((r * p + slots - 1) / slots) / (double)p; };
+        int parts = 1;
+        if (2 * r <= slots) {
+            parts = (int)std::min<int64_t>(slots / r, pk);
+        } else {
+            double best = 1.0;
+            for (int64_t p = 2; p <= std::min<int64_t>(8, pk); ++p) best = std::min(best, cost(p));
+            for (int64_t p = 2; p <= std::min<int64_t>(8, pk); ++p)
+                if (cost(p) <= best + 0.05) {
+                    parts = (int)p;
+                    break;
+                }
+            if (parts > 1 && cost(parts) > 0.8) parts = 1;
+        }
         if (parts < 2) continue;
         for (int64_t q = n - r; q < n; ++q)
             for (int p = 0; p < parts; ++p) {

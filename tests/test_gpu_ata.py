@@ -314,18 +314,19 @@ def test_split_k_tall_scaled_fp64(env, orc):
     assert orc.scaled_err(C, ref, 256) <= FP64_TOL
 
 
-@pytest.mark.parametrize("m", [1000, 1003])
-def test_split_last_round(env, orc, m):
-    """A single SYRK of 528 tiles of 128 x 128 at 512 resident workgroups:
-    512 tiles run whole and the last 16 run as a second launch with each K
-    range split into seven parts, summed in part order.  FP64 and FP32 (both
-    output types): every entry against the oracle, and exact on integers."""
+@pytest.mark.parametrize("m,n,tail,parts", [(1000, 4000, 16, 7), (1003, 4000, 16, 7), (1000, 5000, 308, 3)])
+def test_split_last_round(env, orc, m, n, tail, parts):
+    """A single SYRK at 512 resident workgroups: 528 tiles of 128 x 128 run
+    512 whole and the last 16 as a second launch with each K range split into
+    seven parts (one round of parts); 820 tiles run 512 whole and the last 308
+    in three parts each (two rounds of parts).  Parts are summed in part
+    order.  FP64 and FP32 (both output types): every entry against the
+    oracle, and exact on integers."""
     torch, P = env
-    n = 4000
     _say("case: split last round", m, n)
     for dt in (P.F64, P.F32, P.F32 | P.OUT_F64):
-        # the partial tiles of the split round: 16 tiles x 7 parts x 128 x 128 doubles
-        assert P.workspace_bytes(m, n, 256, dtype=dt, max_depth=0) >= 16 * 7 * 128 * 128 * 8, dt
+        # the partial tiles of the split round: tail tiles x parts x 128 x 128 doubles
+        assert P.workspace_bytes(m, n, 256, dtype=dt, max_depth=0) == tail * parts * 128 * 128 * 8, dt
     A = synthetic.uniform(m, n, 51 + m)
     ref = orc.classical(A)
     C = _run(env, A, cutoff=256, max_depth=0)

@@ -120,17 +120,23 @@ def test_workspace_size_reduced_precision(lib):
 
 
 def test_split_last_round_workspace(lib):
-    """A single classical launch whose last round fills at most half the
-    resident workgroups (512 for FP64 and FP32 tiles, 256 for bfloat16
-    pairs) splits the K range of those last r tiles into
-    min(slots / r, K / 128) parts; the workspace holds their FP64 partial
-    tiles.  One round, or parts below two, splits nothing."""
+    """A single classical launch of more than one round (512 resident
+    workgroups for FP64 and FP32 tiles, 256 for bfloat16 pairs) splits the K
+    range of its last r tiles: into min(slots / r, K / 128) parts when r is
+    at most half the slots, else into the smallest part count of at most 8
+    that comes within 0.05 tile times of the best and saves a fifth of a tile
+    time.  The workspace holds their FP64 partial tiles.  One round, or parts
+    below two, splits nothing."""
     tile = 128 * 128 * 8
     for dt in (P.F64, P.F32, P.F32 | P.OUT_F64):
         assert P.workspace_bytes(1000, 4000, 256, dtype=dt, max_depth=0) == 16 * 7 * tile  # 528 tiles
         assert P.workspace_bytes(1000, 4200, 256, dtype=dt, max_depth=0) == 49 * 7 * tile  # 561 tiles
         assert P.workspace_bytes(1000, 3000, 256, dtype=dt, max_depth=0) == 0  # 300 tiles: one round
         assert P.workspace_bytes(100, 4000, 256, dtype=dt, max_depth=0) == 0  # 100 rows: one part
+        # 820 tiles: the last 308 in 3 parts (two rounds of parts, 2/3 of a tile time instead of one)
+        assert P.workspace_bytes(5000, 5000, 512, dtype=dt, max_depth=0) == 308 * 3 * tile
+        # 990 tiles: 478 left, no part count up to 8 saves a fifth of a tile time; nor is K split as a whole
+        assert P.workspace_bytes(5632, 5632, 512, dtype=dt, max_depth=0) == 0
     conv = lambda n: 2 * n * 1024 * 2 + n * 4  # bfloat16 hi and lo copies, rows padded to 1024
     bf = P.workspace_bytes(1000, 3000, 256, dtype=P.F32_BF16X3, max_depth=0)
     assert 44 * 5 * tile <= bf - conv(3000) < 44 * 5 * tile + 65536  # 300 tiles: 256 + 44 in 5 parts
