@@ -246,8 +246,9 @@ def _square_leg(P, torch, dev, stream, n: int, args):
     cfg = {c["key"]: c for c in cfgs}[best]
     ms = timed(lambda: _run_cfg(P, A, C, stream, cfg), max(5, args.steps))
     got = C.cpu().numpy()
+    # timed before the host oracle runs: an idle GPU starts the next calls at lower clocks
+    cms = timed(lambda: P.gram(A, cutoff=n, max_depth=0, out=C, stream=stream), max(5, args.steps))
     ref = oracle.classical_mt(A_np, threads=_host_info()["threads"])
-    cms = timed(lambda: P.gram(A, cutoff=n, max_depth=0, out=C, stream=stream), 5)
     flops = float(n) ** 3
     out = {"workload": "square FP64 A %dx%d, i.i.d. uniform[-1,1] (seed %d)" % (n, n, synthetic.SEED_SQUARE),
            "tuned": best, "ms": ms, "tflops_mn2": flops / (ms * 1e-3) / 1e12, "tuning_sweep_ms": sweep,
