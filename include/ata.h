@@ -236,6 +236,11 @@ typedef struct ata_plan_stats {
     int64_t gemm_mults;      /* ... by classical off-diagonal tiles */
     int64_t syrk_mults;      /* ... by diagonal base-case tiles */
     int64_t combine_elems;   /* output elements formed by workspace combinations */
+    int64_t lp_staging;      /* reduced-precision dtypes: how the 128 x 128 tiles stage their
+                                operands, as the plan's K windows allow: 2 direct-to-LDS copies
+                                of 16 bytes, 1 of dwords, 0 through registers (copy rows of
+                                2^31 / 64 bytes or more always stage through registers);
+                                -1 for other dtypes */
 } ata_plan_stats;
 
 int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts *opts,

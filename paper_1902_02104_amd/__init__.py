@@ -58,7 +58,7 @@ class PlanStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "mults", "classical_mults", "syrk_tasks", "gemm_tasks", "strassen_tasks", "combine_tasks",
         "work_items", "phases", "ata_depth", "max_hasa_depth", "workspace_bytes", "cutoff",
-        "strassen_mults", "gemm_mults", "syrk_mults", "combine_elems")]
+        "strassen_mults", "gemm_mults", "syrk_mults", "combine_elems", "lp_staging")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

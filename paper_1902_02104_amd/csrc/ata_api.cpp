@@ -131,6 +131,10 @@ bool lp_windows_aligned(const Plan& P, int q, bool tail_ok = false) {
     return true;
 }
 
+// Staging of the reduced-precision tiles the plan's windows allow: 2 for
+// 16-byte direct-to-LDS copies, 1 for dword copies, 0 through registers.
+int lp_align(const PlanDev& pd, int mode) { return pd.lp_dma16[mode] ? 2 : pd.lp_aligned[mode] ? 1 : 0; }
+
 // Lay out a plan's tables in one host image (offsets recorded in pd).
 void serialize(PlanDev& pd) {
     const Plan& P = pd.plan;
@@ -203,6 +207,7 @@ void serialize(PlanDev& pd) {
     }
     for (int mode = 0; mode < 2; ++mode) pd.lp_aligned[mode] = lp_windows_aligned(P, mode == 0 ? 2 : 4);
     pd.lp_aligned16 = P.opt.lp && lp_windows_aligned(P, 16, true);
+    for (int mode = 0; mode < 2; ++mode) pd.lp_dma16[mode] = P.opt.lp && lp_windows_aligned(P, mode == 0 ? 8 : 16, true);
 }
 
 // Copy a serialized plan into one device allocation.
@@ -555,7 +560,7 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
                 err = launch_gemm_lp(lp_mode, out64, ws + L.t0o, lp_mode == 0 ? (const void*)(ws + L.t1o) : nullptr,
                                      (int)L.ldto, (const float*)(ws + L.scale_o), tb,
                                      (const WorkItem*)(pd->blob + ph.off_tg), ph.n_tg, C_lower, W, s,
-                                     pdr.lp_aligned[lp_mode]);
+                                     lp_align(pdr, lp_mode));
             }
             if (err == hipSuccess && lp_mode == 1 && out64 && pdr.lp_aligned16 && ph.n_big >= kBigMinTiles &&
                 (int64_t)64 * L.ldt < ((int64_t)1 << 31)) {
@@ -595,14 +600,14 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
                 ProfScope ps(ATA_KERNEL_GEMM, s);
                 err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
                                      (const WorkItem*)(pd->blob + ph.off_gemm), ph.n_gemm, C_lower, W, s,
-                                     pdr.lp_aligned[lp_mode]);
+                                     lp_align(pdr, lp_mode));
             }
             hipStream_t s_small = split ? fc.s2 : s;
             if (err == hipSuccess && ph.n_syrk) {
                 ProfScope ps(ATA_KERNEL_SYRK, s_small);
                 err = launch_gemm_lp(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
                                      (const WorkItem*)(pd->blob + ph.off_syrk), ph.n_syrk, C_lower, W, s_small,
-                                     pdr.lp_aligned[lp_mode]);
+                                     lp_align(pdr, lp_mode));
             }
             if (split) join_fork(fc, s, err, dev);
             if (err == hipSuccess && ph.n_tail) {
@@ -611,7 +616,7 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
                 ProfScope ps(ph.n_gemm ? ATA_KERNEL_GEMM : ATA_KERNEL_SYRK, s);
                 err = launch_gemm_lp_split(lp_mode, out64, ws + L.t0, t1, (int)L.ldt, scale, tb,
                                            (const WorkItem*)(pd->blob + ph.off_tail), ph.n_tail, ph.tail_parts,
-                                           W + P.tile_tail_off, C_lower, W, s, pdr.lp_aligned[lp_mode]);
+                                           W + P.tile_tail_off, C_lower, W, s, lp_align(pdr, lp_mode));
             }
             if (err == hipSuccess && ph.n_cb) {  // sums of split K parts
                 ProfScope ps(ATA_KERNEL_COMBINE, s);
@@ -773,6 +778,7 @@ int ata_plan_info(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts* o
     out->gemm_mults = P.gemm_mults;
     out->syrk_mults = P.syrk_mults;
     out->combine_elems = P.combine_elems;
+    out->lp_staging = dtype_lp(dtype) ? lp_align(*pd, (dtype & 0xff) == ATA_F32_FP8 ? 1 : 0) : -1;
     return ATA_OK;
 }
 

@@ -33,6 +33,7 @@ struct PlanDev {
     std::vector<PhaseDev> phases;
     bool lp_aligned[2] = {false, false};  // reduced-precision modes: windows dword-aligned in the copy
     bool lp_aligned16 = false;            // windows on 16 elements of the copy (e4m3 256 x 256 tiles)
+    bool lp_dma16[2] = {false, false};    // reduced-precision modes: windows on 16 bytes of the copy
     ~PlanDev() {
         if (blob) {
             int cur = 0;

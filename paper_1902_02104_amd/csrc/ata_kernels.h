@@ -54,7 +54,7 @@ hipError_t launch_gemm_split(bool f32, bool out_f64, const void* A, int64_t lda,
 // The same for the reduced-precision classical tiles (partials de-scaled).
 hipError_t launch_gemm_lp_split(int mode, bool out_f64, const void* T0, const void* T1, int ldt, const float* scale,
                                 const DevTables& tb, const WorkItem* tail, int ntail, int nparts, double* part,
-                                void* C, double* W, hipStream_t s, bool aligned);
+                                void* C, double* W, hipStream_t s, int align);
 
 // The K-split last round of a one-term FP64 tile launch: ntail items (slot =
 // tile * nparts + part) write raw results to `part` (128 x 128 doubles per
@@ -110,12 +110,13 @@ hipError_t launch_prep_lp(int mode, const float* A, int64_t lda, int m, int n, i
 hipError_t launch_opsum_lp(int mode, const float* A, int64_t lda, const DevTables& tb, const DevOpSum* recs, int nrec,
                            int64_t tiles, int64_t rows, uint32_t* colmax, float* scale, void* out0, void* out1, int ldt,
                            hipStream_t s);
-// aligned: every segment window of the plan starts and ends on a dword of
-// the copy (see lp_windows_aligned), which lets the tiles stage through
-// direct-to-LDS copies.
+// align: 2 when every segment window of the plan starts and ends on 16
+// bytes of the copy (or ends at its last row, past which the copy holds
+// zeros), 1 when on dwords, else 0 (see lp_windows_aligned): the tiles stage
+// through 16-byte or dword direct-to-LDS copies, or through registers.
 hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1, int ldt,
                           const float* scale, const DevTables& tb, const WorkItem* items, int nitems,
-                          void* C, double* W, hipStream_t s, bool aligned);
+                          void* C, double* W, hipStream_t s, int align);
 
 // Column equilibration (power-of-two column scales into `scale`, the scaled
 // copy of A into `out` with row stride n; `part` holds ceil(m/256) x n

@@ -2101,7 +2101,7 @@ struct LpdCfg<1> {  // e4m3
     static constexpr int KT = 128, EB = 1, PL = 1, OCC = 2;
 };
 
-template <int MODE, typename OUT, bool SPLIT = false>
+template <int MODE, typename OUT, bool SPLIT = false, bool B16 = false>
 __global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8_t* __restrict__ T0,
                                                                     const uint8_t* __restrict__ T1, int ldt,
                                                                     const float* __restrict__ scale,
@@ -2134,16 +2134,28 @@ __global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8
     // rows 2i (lanes 0-31) and 2i + 1 (lanes 32-63) of that range; lane
     // dword d of a row holds logical chunk (d / 4) ^ (i mod 8).  Per i mod 8:
     // the lane's byte offset inside the row block and its first k element.
+    // B16: sixteen bytes per lane instead, copy i moving rows 8i to 8i + 7
+    // (lane L: row 8i + L / 8, physical chunk L % 8, so logical chunk
+    // (L % 8) ^ ((8i + L / 8) / 2 mod 8)); vb and ke then hold, per copy,
+    // the lane's byte offset from the block's window start and first k.
     const int cop = wave >> 1, half = wave & 1;
     const int hb = lane >> 5, d = lane & 31;
+    const int rl = lane >> 3;
     uint32_t vb[8];
     int ke[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const int lc = (d >> 2) ^ q;
-        const int byte = lc * 16 + (d & 3) * 4;
-        vb[q] = (uint32_t)(hb * rowb) + (uint32_t)byte;
-        ke[q] = byte / EB;
+        if constexpr (B16) {
+            const int r = 8 * q + rl;
+            const int kc = (lane & 7) ^ ((r >> 1) & 7);
+            vb[q] = (uint32_t)(r * rowb) + (uint32_t)(kc * 16);
+            ke[q] = kc * 16 / EB;
+        } else {
+            const int lc = (d >> 2) ^ q;
+            const int byte = lc * 16 + (d & 3) * 4;
+            vb[q] = (uint32_t)(hb * rowb) + (uint32_t)byte;
+            ke[q] = byte / EB;
+        }
     }
     const DevTerm& tc = cop == 0 ? tx : ty;
     const int row0 = tc.col + (cop == 0 ? i0 : j0) + half * 64;  // first row of the copy this wave reads
@@ -2183,11 +2195,20 @@ __global__ void __launch_bounds__(256, LpdCfg<MODE>::OCC) k_gemm_lpd(const uint8
             const rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), (short)0, 0x7fffffff,
                                                                 0x00020000);
             uint8_t* dst = &lds[buf][p][cop][half * 64 * RB];
+            if constexpr (B16) {
 #pragma unroll
-            for (int i = 0; i < NCP; ++i) {
-                const uint32_t off = full || (i < ilim && ke[i & 7] < krem) ? vb[i & 7] : kOOB;
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(dst + 2 * i * RB),
-                                                         4, off, (int)(2 * i * rowb), 0, 0);
+                for (int i = 0; i < 8; ++i) {
+                    const bool ok = full || (8 * i + rl < nrv && ke[i] < krem);
+                    lds_copy16(rs, dst + i * 8 * RB, ok ? vb[i] : kOOB);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < NCP; ++i) {
+                    const uint32_t off = full || (i < ilim && ke[i & 7] < krem) ? vb[i & 7] : kOOB;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rs, (__attribute__((address_space(3))) void*)(dst + 2 * i * RB), 4, off, (int)(2 * i * rowb), 0,
+                        0);
+                }
             }
         }
     };
@@ -2836,32 +2857,46 @@ hipError_t launch_prep_lp(int mode, const float* A, int64_t lda, int m, int n, i
     return hipGetLastError();
 }
 
+// Launch of the reduced-precision tiles of mode / output type / split form
+// by staging path: 2 direct-to-LDS 16-byte copies, 1 dword copies,
+// 0 through registers.
+template <int M, typename O, bool S>
+static void lp_tiles(int path, dim3 g, hipStream_t s, const uint8_t* t0, const uint8_t* t1, int ldt,
+                     const float* scale, const DevTables& tb, const WorkItem* items, void* C, double* W, int nparts,
+                     double* part) {
+    const dim3 b(256);
+    if (path == 2)
+        hipLaunchKernelGGL((k_gemm_lpd<M, O, S, true>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
+                           items, (O*)C, W, nparts, part);
+    else if (path == 1)
+        hipLaunchKernelGGL((k_gemm_lpd<M, O, S, false>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs,
+                           items, (O*)C, W, nparts, part);
+    else
+        hipLaunchKernelGGL((k_gemm_lp<M, O, S>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs, items,
+                           (O*)C, W, nparts, part);
+}
+
+// Staging path for windows aligned on `align` (0: none, 1: dwords, 2: 16
+// bytes) of a copy with rows of ldt elements: direct-to-LDS copies need the
+// byte offsets of one 64-row copy block below 2^31.
+static int lp_path(int mode, int ldt, int align) {
+    const int eb = mode == 0 ? 2 : 1;
+    if ((int64_t)64 * ldt * eb >= ((int64_t)1 << 31)) return 0;
+    return align;
+}
+
 hipError_t launch_gemm_lp(int mode, bool out_f64, const void* T0, const void* T1, int ldt, const float* scale,
                           const DevTables& tb, const WorkItem* items, int nitems, void* C, double* W,
-                          hipStream_t s, bool aligned) {
+                          hipStream_t s, int align) {
     if (nitems <= 0) return hipSuccess;
-    const dim3 g(nitems), b(256);
+    const dim3 g(nitems);
     const uint8_t* t0 = (const uint8_t*)T0;
     const uint8_t* t1 = (const uint8_t*)(T1 ? T1 : T0);
-    // direct-to-LDS copies: dword-aligned windows, row offsets of one copy
-    // block below 2^31
-    const int eb = mode == 0 ? 2 : 1;
-    const bool dma = aligned && (int64_t)64 * ldt * eb < ((int64_t)1 << 31);
-#define ATA_LP_LAUNCH(K, M, O)                                                                                       \
-    hipLaunchKernelGGL((K<M, O>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs, items, (O*)C, W, 1,    \
-                       (double*)nullptr)
-    if (mode == 0) {
-        if (dma && out_f64) ATA_LP_LAUNCH(k_gemm_lpd, 0, double);
-        else if (dma) ATA_LP_LAUNCH(k_gemm_lpd, 0, float);
-        else if (out_f64) ATA_LP_LAUNCH(k_gemm_lp, 0, double);
-        else ATA_LP_LAUNCH(k_gemm_lp, 0, float);
-    } else {
-        if (dma && out_f64) ATA_LP_LAUNCH(k_gemm_lpd, 1, double);
-        else if (dma) ATA_LP_LAUNCH(k_gemm_lpd, 1, float);
-        else if (out_f64) ATA_LP_LAUNCH(k_gemm_lp, 1, double);
-        else ATA_LP_LAUNCH(k_gemm_lp, 1, float);
-    }
-#undef ATA_LP_LAUNCH
+    const int path = lp_path(mode, ldt, align);
+    if (mode == 0 && out_f64) lp_tiles<0, double, false>(path, g, s, t0, t1, ldt, scale, tb, items, C, W, 1, nullptr);
+    else if (mode == 0) lp_tiles<0, float, false>(path, g, s, t0, t1, ldt, scale, tb, items, C, W, 1, nullptr);
+    else if (out_f64) lp_tiles<1, double, false>(path, g, s, t0, t1, ldt, scale, tb, items, C, W, 1, nullptr);
+    else lp_tiles<1, float, false>(path, g, s, t0, t1, ldt, scale, tb, items, C, W, 1, nullptr);
     return hipGetLastError();
 }
 
@@ -2883,28 +2918,16 @@ hipError_t launch_lp8_tail_sum(const float* scale, const DevTables& tb, const Wo
 
 hipError_t launch_gemm_lp_split(int mode, bool out_f64, const void* T0, const void* T1, int ldt, const float* scale,
                                 const DevTables& tb, const WorkItem* tail, int ntail, int nparts, double* part,
-                                void* C, double* W, hipStream_t s, bool aligned) {
+                                void* C, double* W, hipStream_t s, int align) {
     if (ntail <= 0 || nparts < 1) return hipSuccess;
-    const dim3 g(ntail), b(256), gs(GT, ntail / nparts), bs(GT);
+    const dim3 g(ntail), gs(GT, ntail / nparts), bs(GT);
     const uint8_t* t0 = (const uint8_t*)T0;
     const uint8_t* t1 = (const uint8_t*)(T1 ? T1 : T0);
-    const int eb = mode == 0 ? 2 : 1;
-    const bool dma = aligned && (int64_t)64 * ldt * eb < ((int64_t)1 << 31);
-#define ATA_LP_SPLIT(K, M, O)                                                                                        \
-    hipLaunchKernelGGL((K<M, O, true>), g, b, 0, s, t0, t1, ldt, scale, tb.tasks, tb.terms, tb.segs, tail, (O*)C, W, \
-                       nparts, part)
-    if (mode == 0) {
-        if (dma && out_f64) ATA_LP_SPLIT(k_gemm_lpd, 0, double);
-        else if (dma) ATA_LP_SPLIT(k_gemm_lpd, 0, float);
-        else if (out_f64) ATA_LP_SPLIT(k_gemm_lp, 0, double);
-        else ATA_LP_SPLIT(k_gemm_lp, 0, float);
-    } else {
-        if (dma && out_f64) ATA_LP_SPLIT(k_gemm_lpd, 1, double);
-        else if (dma) ATA_LP_SPLIT(k_gemm_lpd, 1, float);
-        else if (out_f64) ATA_LP_SPLIT(k_gemm_lp, 1, double);
-        else ATA_LP_SPLIT(k_gemm_lp, 1, float);
-    }
-#undef ATA_LP_SPLIT
+    const int path = lp_path(mode, ldt, align);
+    if (mode == 0 && out_f64) lp_tiles<0, double, true>(path, g, s, t0, t1, ldt, scale, tb, tail, C, W, nparts, part);
+    else if (mode == 0) lp_tiles<0, float, true>(path, g, s, t0, t1, ldt, scale, tb, tail, C, W, nparts, part);
+    else if (out_f64) lp_tiles<1, double, true>(path, g, s, t0, t1, ldt, scale, tb, tail, C, W, nparts, part);
+    else lp_tiles<1, float, true>(path, g, s, t0, t1, ldt, scale, tb, tail, C, W, nparts, part);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (out_f64)

@@ -187,26 +187,34 @@ def test_reduced_precision_split_k(env, orc):
         assert orc.rel_fro(C, ref, 200) <= tol
 
 
+# (rows, Strassen levels) -> staging of the 128 x 128 tiles (bfloat16 pairs, e4m3):
+# 2 direct-to-LDS copies of 16 bytes, 1 of dwords, 0 through registers
+COPY_PATH_CASES = [((2048, 1), (2, 2)), ((2047, 1), (2, 2)), ((2047, 0), (2, 2)), ((2044, 1), (1, 0)),
+                   ((2040, 1), (1, 1)), ((2041, 1), (0, 0))]
+
+
 def test_reduced_precision_copy_paths(env, orc):
-    """Plans whose segment windows all start and end on a dword of the
-    converted copy stage it through direct-to-LDS copies; other plans stage
-    through registers.  Both are exact on small-integer inputs.  Row counts:
-    2048 (every window aligned for both forms), 2047 (odd windows: register
-    staging), 4102 (aligned for bfloat16 pairs, not for e4m3 quadruples);
-    with a 200000-row matrix split-K parts (boundaries on multiples of 16
-    rows) keep the windows aligned."""
+    """Plans whose segment windows all start and end on 16 bytes of the
+    converted copy (or end at its last row, past which the copy holds zeros)
+    stage through 16-byte direct-to-LDS copies, on dwords through dword
+    copies, otherwise through registers.  Every path is exact on
+    small-integer inputs.  The row counts pick each path: the split rows of
+    one Strassen level (ceil(m/2)) decide.  A 200000-row matrix runs split-K
+    parts (boundaries on multiples of 16 rows) with 16-byte copies."""
     torch, P = env
     print("case: lp copy paths", flush=True)
-    for m in (2048, 2047, 4102):
+    for (m, d), want in COPY_PATH_CASES:
         Ai = synthetic.integer(m, 130, m).astype(np.float32)
         exact = orc.classical(Ai.astype(np.float64))
-        for dt in (P.F32_BF16X3, P.F32_FP8):
-            for c in (64, 10 ** 6):
-                assert np.array_equal(_gram(env, Ai, dt | P.OUT_F64, cutoff=c), exact), (m, dt, c)
+        c = 64 if d else 10 ** 6
+        for dt, w in zip((P.F32_BF16X3, P.F32_FP8), want):
+            assert P.plan_info(m, 130, c, dtype=dt, max_depth=d)["lp_staging"] == w, (m, d, dt)
+            assert np.array_equal(_gram(env, Ai, dt | P.OUT_F64, cutoff=c, max_depth=d), exact), (m, d, dt)
     Ai = synthetic.integer(200000, 64, 5).astype(np.float32)
     exact = orc.classical(Ai.astype(np.float64))
     for dt in (P.F32_BF16X3, P.F32_FP8):
-        assert P.plan_info(200000, 64, 10 ** 6, dtype=dt)["combine_tasks"] >= 1
+        st = P.plan_info(200000, 64, 10 ** 6, dtype=dt)
+        assert st["combine_tasks"] >= 1 and st["lp_staging"] == 2
         assert np.array_equal(_gram(env, Ai, dt | P.OUT_F64, cutoff=10 ** 6), exact), dt
 
 

@@ -143,6 +143,21 @@ def test_split_last_round_workspace(lib):
     assert P.workspace_bytes(1000, 2000, 256, dtype=P.F32_BF16X3, max_depth=0) - conv(2000) < 65536  # 136 tiles
 
 
+def test_lp_staging_paths(lib):
+    """Staging of the reduced-precision tiles from the plan's K windows: 16
+    bytes of the copy per window start and end (8 bfloat16 pairs, 16 e4m3),
+    where a window ending at the last row counts as aligned (zeros follow in
+    the copy); else dwords (2 and 4 elements); else registers.  One Strassen
+    level splits the rows at ceil(m/2); other dtypes report -1."""
+    cases = {(2048, 1): (2, 2), (2047, 1): (2, 2), (2047, 0): (2, 2), (2044, 1): (1, 0), (2040, 1): (1, 1),
+             (2041, 1): (0, 0), (4104, 1): (1, 1)}
+    for (m, d), want in cases.items():
+        got = tuple(P.plan_info(m, 130, 64, dtype=dt, max_depth=d)["lp_staging"] for dt in (P.F32_BF16X3, P.F32_FP8))
+        assert got == want, (m, d, got)
+    assert P.plan_info(2048, 130, 64, dtype=P.F64)["lp_staging"] == -1
+    assert P.plan_info(2048, 130, 64, dtype=P.F32)["lp_staging"] == -1
+
+
 def test_default_cutoff_is_in_tuned_set(lib):
     for m, n in [(256, 192), (5000, 5000), (10000, 10000), (262144, 2048)]:
         assert P.default_cutoff(m, n) in (128, 256, 512)
