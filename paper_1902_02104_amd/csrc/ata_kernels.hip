@@ -343,6 +343,13 @@ __device__ __forceinline__ S load_rec(const __attribute__((address_space(1))) S*
     return v;
 }
 
+// One 16-byte buffer load per lane into LDS at lds + 16 * lane.  (A plain
+// device function: the host pass does not know the 16-byte form, which
+// would otherwise fail the host-side instantiation of the kernel templates.)
+__device__ __forceinline__ void lds_copy16(rsrc_t r, void* lds, uint32_t voff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, 0, 0, 0);
+}
+
 template <typename T>
 struct DmaCfg;
 template <>
@@ -412,12 +419,23 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
     // Copy role: operand cs (0: left X, 1: right Y), k rows of parity cpar.
     // Byte offset of this lane's dword per row residue (mod 4, the two of
     // this parity) and per 256-byte copy of the row.
+    // FP32 (D16): 16-byte copies instead, each moving two adjacent 512-byte
+    // rows (lanes 0-31 the first, 32-63 the second); the wave copies row
+    // pairs 2j + cpar, whose rows r have r mod 4 = 2 cpar + (lane / 32), so
+    // one offset per lane serves every copy.
+    constexpr bool D16 = F32;
     const int cs = wave >> 1, cpar = wave & 1;
     const int swx = F32 ? 4 : 2, swy = 4;  // swizzle unit: 1 << swx (left) / 1 << swy (right) elements
     uint32_t doff[2][CPR];
+    uint32_t doff16 = 0;
     {
         const DevTerm tm = load_rec(terms + t.term_off + (cs == 0 ? 0 : t.nx));
         const int colbase = tm.col + (cs == 0 ? i0 : j0);
+        if (D16) {
+            const int r4 = 2 * cpar + (lane >> 5);
+            const int c = (4 * (lane & 31)) ^ (r4 << (cs == 0 ? swx : swy));  // first column of the chunk
+            doff16 = (uint32_t)(colbase + c) * (uint32_t)sizeof(T);
+        }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int r4 = cpar + 2 * q;
@@ -482,6 +500,12 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
     auto copy_part = [&](int buf, int j) {
         if (cnt <= 0 || !copying) return;
         T* pl = lds[buf][cs];
+        if constexpr (D16) {
+            static_assert(GT * sizeof(T) == 512 && GK == kStageRows, "two rows per copy, one slab per stage");
+            const int r = 2 * (2 * j + cpar) + (lane >> 5);  // this lane's row
+            lds_copy16(rs[0], pl + 2 * (2 * j + cpar) * GT, (uint32_t)(r * row_bytes) + doff16);
+            return;
+        }
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii) {
             const int r = 2 * (2 * j + ii) + cpar;
@@ -626,12 +650,6 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
 // ---------------------------------------------------------------------------
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
-// One 16-byte buffer load per lane into LDS at lds + 16 * lane.  (A plain
-// device function: the host pass does not know the 16-byte form, which
-// would otherwise fail the host-side instantiation of the kernel templates.)
-__device__ __forceinline__ void lds_copy16(rsrc_t r, void* lds, uint32_t voff) {
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, 0, 0, 0);
-}
 
 // SPLIT: the item is part (slot mod nparts) of a K-split tile: it runs that
 // share of the tile's stages and writes its raw result to tile slot of part.
