@@ -636,13 +636,16 @@ hipError_t enqueue_product(const PlanDev& pdr, const char* dblob, const WsLayout
             if (err == hipSuccess) {
                 // two-term launches run persistent workgroups on work queues
                 ProfScope ps(ATA_KERNEL_TILES, s);
-                err = launch_tile(ph.tg_tmax <= 1 ? 1 : 2, (const double*)A, lda, tb,
-                                  (const WorkItem*)(pd->blob + ph.off_mix), ph.n_mix, (double*)C_lower, W, s,
-                                  (const double*)(ws + L.ops), P.queue_off >= 0 ? (int*)(W + P.queue_off) : nullptr);
-                if (err == hipSuccess && ph.n_tail)  // the K-split last round
-                    err = launch_tile_split((const double*)A, lda, tb, (const WorkItem*)(pd->blob + ph.off_tail),
-                                            ph.n_tail, ph.tail_parts, W + P.tile_tail_off, (double*)C_lower, W, s,
-                                            (const double*)(ws + L.ops));
+                if (ph.n_tail)  // with the K-split last round in the same grid
+                    err = launch_tile_cat((const double*)A, lda, tb, (const WorkItem*)(pd->blob + ph.off_mix),
+                                          ph.n_mix, (const WorkItem*)(pd->blob + ph.off_tail), ph.n_tail,
+                                          ph.tail_parts, W + P.tile_tail_off, (double*)C_lower, W, s,
+                                          (const double*)(ws + L.ops));
+                else
+                    err = launch_tile(ph.tg_tmax <= 1 ? 1 : 2, (const double*)A, lda, tb,
+                                      (const WorkItem*)(pd->blob + ph.off_mix), ph.n_mix, (double*)C_lower, W, s,
+                                      (const double*)(ws + L.ops),
+                                      P.queue_off >= 0 ? (int*)(W + P.queue_off) : nullptr);
             }
             if (err == hipSuccess && ph.n_cb) {
                 ProfScope ps(ATA_KERNEL_COMBINE, s);

@@ -56,6 +56,12 @@ hipError_t launch_gemm_lp_split(int mode, bool out_f64, const void* T0, const vo
                                 const DevTables& tb, const WorkItem* tail, int ntail, int nparts, double* part,
                                 void* C, double* W, hipStream_t s, int align);
 
+// A one-term FP64 tile launch with its K-split last round in the same grid
+// (the parts run as the whole tiles finish), then the sum of the parts.
+hipError_t launch_tile_cat(const double* A, int64_t lda, const DevTables& tb, const WorkItem* items, int nmain,
+                           const WorkItem* tail, int ntail, int nparts, double* part, double* C, double* W,
+                           hipStream_t s, const double* Aops);
+
 // The K-split last round of a one-term FP64 tile launch: ntail items (slot =
 // tile * nparts + part) write raw results to `part` (128 x 128 doubles per
 // slot), then one launch sums each tile's parts in part order into C or W.

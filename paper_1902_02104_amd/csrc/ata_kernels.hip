@@ -651,14 +651,15 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
 
-// SPLIT: the item is part (slot mod nparts) of a K-split tile: it runs that
-// share of the tile's stages and writes its raw result to tile slot of part.
+// SPLIT (or split, decided at run time): the item is part (slot mod
+// nparts) of a K-split tile: it runs that share of the tile's stages and
+// writes its raw result to tile slot of part.
 template <typename OUT, int NT, bool SPLIT = false>
 __device__ __forceinline__ void tile_body(const WorkItem w, const double* __restrict__ A_, int64_t lda_,
                                           const DevTask* __restrict__ tasks_, const DevTerm* __restrict__ terms_,
                                           const int32_t* __restrict__ segs_, OUT* __restrict__ C,
                                           double* __restrict__ W, const double* __restrict__ Aops,
-                                          int nparts = 1, double* __restrict__ part = nullptr) {
+                                          int nparts = 1, double* __restrict__ part = nullptr, bool split = false) {
     constexpr int GK = 16;               // k rows per stage
     static_assert(GK <= kStageRows, "one slab per stage");
     constexpr int NP = GK / 4;           // MFMA steps per stage
@@ -802,7 +803,7 @@ __device__ __forceinline__ void tile_body(const WorkItem w, const double* __rest
         }
     };
 
-    if constexpr (SPLIT) {
+    if (SPLIT || split) {
         const int tp = w.slot % nparts;
         const int s0 = (int)((int64_t)ntiles * tp / nparts), s1 = (int)((int64_t)ntiles * (tp + 1) / nparts);
         for (int u = 0; u < s0; ++u) advance();
@@ -863,7 +864,7 @@ __device__ __forceinline__ void tile_body(const WorkItem w, const double* __rest
 
     // epilogue: slot (2q + ha, row g) -> tile row 8q + 2g + ha of the wave,
     // slot (2u + hb, column j) -> tile column 32u + 2j + hb
-    if constexpr (SPLIT) {
+    if (SPLIT || split) {
         double* pt = part + (int64_t)w.slot * GT * GT;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
@@ -956,6 +957,24 @@ __global__ void __launch_bounds__(256, 2) k_tile_part(const double* __restrict__
                                                      double* __restrict__ W, const double* __restrict__ Aops,
                                                      int nparts, double* __restrict__ part) {
     tile_body<OUT, 1, true>(items[blockIdx.x], A_, lda_, tasks_, terms_, segs_, C, W, Aops, nparts, part);
+}
+
+// A one-term launch and its K-split last round in one grid: blocks
+// [0, nmain) run the whole tiles of items, the rest the parts of tail, so
+// parts start on CUs as the last whole tiles finish.
+template <typename OUT>
+__global__ void __launch_bounds__(256, 2) k_tile_cat(const double* __restrict__ A_, int64_t lda_,
+                                                    const DevTask* __restrict__ tasks_,
+                                                    const DevTerm* __restrict__ terms_,
+                                                    const int32_t* __restrict__ segs_,
+                                                    const WorkItem* __restrict__ items, int nmain,
+                                                    const WorkItem* __restrict__ tail, OUT* __restrict__ C,
+                                                    double* __restrict__ W, const double* __restrict__ Aops,
+                                                    int nparts, double* __restrict__ part) {
+    const int b = blockIdx.x;
+    const bool split = b >= nmain;
+    tile_body<OUT, 1>(split ? tail[b - nmain] : items[b], A_, lda_, tasks_, terms_, segs_, C, W, Aops, nparts, part,
+                      split);
 }
 
 // Sum of the parts of the K-split tiles in part order, stored as k_tile
@@ -2786,6 +2805,19 @@ hipError_t launch_gemm_split(bool f32, bool out_f64, const void* A, int64_t lda,
         hipLaunchKernelGGL(k_tile_part_sum<float>, gs, bs, 0, s, tb.tasks, tail, nparts, (const double*)part,
                            (float*)C, W);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_cat(const double* A, int64_t lda, const DevTables& tb, const WorkItem* items, int nmain,
+                           const WorkItem* tail, int ntail, int nparts, double* part, double* C, double* W,
+                           hipStream_t s, const double* Aops) {
+    if (ntail <= 0 || nparts < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_tile_cat<double>), dim3(nmain + ntail), dim3(256), 0, s, A, lda, tb.tasks, tb.terms, tb.segs,
+                       items, nmain, tail, C, W, Aops, nparts, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tile_part_sum<double>), dim3(GT, ntail / nparts), dim3(GT), 0, s, tb.tasks, tail, nparts,
+                       (const double*)part, C, W);
     return hipGetLastError();
 }
 
