@@ -62,13 +62,6 @@ hipError_t launch_tile_cat(const double* A, int64_t lda, const DevTables& tb, co
                            const WorkItem* tail, int ntail, int nparts, double* part, double* C, double* W,
                            hipStream_t s, const double* Aops);
 
-// The K-split last round of a one-term FP64 tile launch: ntail items (slot =
-// tile * nparts + part) write raw results to `part` (128 x 128 doubles per
-// slot), then one launch sums each tile's parts in part order into C or W.
-hipError_t launch_tile_split(const double* A, int64_t lda, const DevTables& tb, const WorkItem* tail, int ntail,
-                             int nparts, double* part, double* C, double* W, hipStream_t s,
-                             const double* Aops = nullptr);
-
 // Operand sums of the product tasks in `recs` (one workgroup per buffer row;
 // rows = total rows of the records) into `out`, in the input type.
 hipError_t launch_opsum(bool f32, const void* A, int64_t lda, const DevTables& tb, const DevOpSum* recs, int nrec,

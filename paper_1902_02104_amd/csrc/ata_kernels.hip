@@ -651,10 +651,9 @@ __global__ void __launch_bounds__(256, 2) k_gemmd(const T* __restrict__ A_, int6
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
 
-// SPLIT (or split, decided at run time): the item is part (slot mod
-// nparts) of a K-split tile: it runs that share of the tile's stages and
-// writes its raw result to tile slot of part.
-template <typename OUT, int NT, bool SPLIT = false>
+// split: the item is part (slot mod nparts) of a K-split tile: it runs that
+// share of the tile's stages and writes its raw result to tile slot of part.
+template <typename OUT, int NT>
 __device__ __forceinline__ void tile_body(const WorkItem w, const double* __restrict__ A_, int64_t lda_,
                                           const DevTask* __restrict__ tasks_, const DevTerm* __restrict__ terms_,
                                           const int32_t* __restrict__ segs_, OUT* __restrict__ C,
@@ -803,7 +802,7 @@ __device__ __forceinline__ void tile_body(const WorkItem w, const double* __rest
         }
     };
 
-    if (SPLIT || split) {
+    if (split) {
         const int tp = w.slot % nparts;
         const int s0 = (int)((int64_t)ntiles * tp / nparts), s1 = (int)((int64_t)ntiles * (tp + 1) / nparts);
         for (int u = 0; u < s0; ++u) advance();
@@ -864,7 +863,7 @@ __device__ __forceinline__ void tile_body(const WorkItem w, const double* __rest
 
     // epilogue: slot (2q + ha, row g) -> tile row 8q + 2g + ha of the wave,
     // slot (2u + hb, column j) -> tile column 32u + 2j + hb
-    if (SPLIT || split) {
+    if (split) {
         double* pt = part + (int64_t)w.slot * GT * GT;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
@@ -944,19 +943,6 @@ __global__ void __launch_bounds__(256, 2) k_tile_q(const double* __restrict__ A_
         if (idx >= nitems) break;
         tile_body<OUT, 2>(items[idx], A_, lda_, tasks_, terms_, segs_, C, W, Aops);
     }
-}
-
-// K-split last round of a one-term launch: item i is part (slot mod nparts)
-// of tile slot / nparts; the parts' raw results go to `part`.
-template <typename OUT>
-__global__ void __launch_bounds__(256, 2) k_tile_part(const double* __restrict__ A_, int64_t lda_,
-                                                     const DevTask* __restrict__ tasks_,
-                                                     const DevTerm* __restrict__ terms_,
-                                                     const int32_t* __restrict__ segs_,
-                                                     const WorkItem* __restrict__ items, OUT* __restrict__ C,
-                                                     double* __restrict__ W, const double* __restrict__ Aops,
-                                                     int nparts, double* __restrict__ part) {
-    tile_body<OUT, 1, true>(items[blockIdx.x], A_, lda_, tasks_, terms_, segs_, C, W, Aops, nparts, part);
 }
 
 // A one-term launch and its K-split last round in one grid: blocks
@@ -2814,18 +2800,6 @@ hipError_t launch_tile_cat(const double* A, int64_t lda, const DevTables& tb, co
     if (ntail <= 0 || nparts < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_tile_cat<double>), dim3(nmain + ntail), dim3(256), 0, s, A, lda, tb.tasks, tb.terms, tb.segs,
                        items, nmain, tail, C, W, Aops, nparts, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_tile_part_sum<double>), dim3(GT, ntail / nparts), dim3(GT), 0, s, tb.tasks, tail, nparts,
-                       (const double*)part, C, W);
-    return hipGetLastError();
-}
-
-hipError_t launch_tile_split(const double* A, int64_t lda, const DevTables& tb, const WorkItem* tail, int ntail,
-                             int nparts, double* part, double* C, double* W, hipStream_t s, const double* Aops) {
-    if (ntail <= 0 || nparts < 1) return hipSuccess;
-    hipLaunchKernelGGL((k_tile_part<double>), dim3(ntail), dim3(256), 0, s, A, lda, tb.tasks, tb.terms, tb.segs, tail,
-                       C, W, Aops, nparts, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_tile_part_sum<double>), dim3(GT, ntail / nparts), dim3(GT), 0, s, tb.tasks, tail, nparts,
