@@ -713,7 +713,8 @@ def main():
 
     forms = None
     if not args.no_precision:
-        forms = _precision_forms(P, torch, dev, stream, args.precision_n, 5,
+        # 20 calls per timed pass: the sub-millisecond forms need that many for steady clocks
+        forms = _precision_forms(P, torch, dev, stream, args.precision_n, 20,
                                  tuple(int(d) for d in args.precision_depths.split(",")))
 
     serving = None
