@@ -591,8 +591,23 @@ void split_k(Plan& P) {
         // to balance, which the split of that round does without partials
         // of every tile
         if (items > tail_slots(o.split_tail) && tail_list(o, ph, false)) continue;
-        const int64_t want = std::min<int64_t>(64, o.split_target / items);
+        int64_t want = std::min<int64_t>(64, o.split_target / items);
         if (want < 2) continue;
+        if (o.split_tail == 1 || o.split_tail == 2) {
+            // every part writes a partial tile and the sum reads it back: take
+            // the fewest parts whose rounds of the resident workgroups come
+            // within half a percent of the best tile time up to `want` parts
+            auto rounds = [&](int64_t p) {
+                return (double)((items * p + kTileSlots - 1) / kTileSlots) / (double)p;
+            };
+            double best = rounds(want);
+            for (int64_t p = 2; p < want; ++p) best = std::min(best, rounds(p));
+            for (int64_t p = 2; p <= want; ++p)
+                if (rounds(p) <= best * 1.005) {
+                    want = p;
+                    break;
+                }
+        }
         // decide a part count per task (workspace blocks: per combine block)
         std::map<int32_t, int> parts;  // task id -> parts
         auto decide = [&](int32_t id) {
