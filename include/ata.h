@@ -188,8 +188,9 @@ int ata_ex(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int 
 int ata_ex_noalloc(const void *A, int64_t m, int64_t n, int64_t lda, void *C_lower, int dtype, int cutoff,
                    void *stream, const ata_opts *opts, size_t *scratch_used);
 
-/* Bytes of device workspace ata_ex needs for this problem (0 if none; FP64
- * classical products with a short last round of tiles need some). */
+/* Bytes of device workspace ata_ex needs for this problem (0 if none;
+ * classical launches of more than one round of tiles (FP64, FP32, bfloat16
+ * pairs) need some for the K parts of their last round). */
 int ata_workspace_bytes(int64_t m, int64_t n, int dtype, int cutoff, const ata_opts *opts,
                         size_t *bytes);
 
