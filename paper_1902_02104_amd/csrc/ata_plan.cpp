@@ -593,8 +593,9 @@ void split_k(Plan& P) {
         if (items > tail_slots(o.split_tail) && tail_list(o, ph, false)) continue;
         int64_t want = std::min<int64_t>(64, o.split_target / items);
         if (want < 2) continue;
-        if (o.split_tail == 1 || o.split_tail == 2) {
-            // every part writes a partial tile and the sum reads it back: take
+        if ((o.split_tail == 1 || o.split_tail == 2) && ph.str_items.empty() && ph.tg_items.empty()) {
+            // classical tiles alone (items of equal cost per unit of K): every
+            // part writes a partial tile and the sum reads it back, so take
             // the fewest parts whose rounds of the resident workgroups come
             // within half a percent of the best tile time up to `want` parts
             auto rounds = [&](int64_t p) {
