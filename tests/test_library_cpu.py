@@ -143,6 +143,19 @@ def test_split_last_round_workspace(lib):
     assert P.workspace_bytes(1000, 2000, 256, dtype=P.F32_BF16X3, max_depth=0) - conv(2000) < 65536  # 136 tiles
 
 
+def test_split_k_part_counts(lib):
+    """K splitting of launches with few tiles.  Classical tiles alone (FP64,
+    FP32): the fewest parts whose rounds of the 512 resident workgroups come
+    within half a percent of the best count, here 136 tiles x 15 parts = 2040
+    (3.98 rounds; 45 parts would give 11.95).  Phases with Strassen product
+    tiles keep the largest count allowed (6144 items targeted: 45 parts)."""
+    for dt in (P.F64, P.F32):
+        st = P.plan_info(262144, 2048, 256, dtype=dt, max_depth=0)
+        assert st["work_items"] == 136 * 15 and st["combine_tasks"] == 1, st
+    st = P.plan_info(262144, 2048, 256, dtype=P.F64, max_depth=1)
+    assert st["work_items"] == 6120, st
+
+
 def test_lp_staging_paths(lib):
     """Staging of the reduced-precision tiles from the plan's K windows: 16
     bytes of the copy per window start and end (8 bfloat16 pairs, 16 e4m3),
