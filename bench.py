@@ -606,7 +606,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(row sharding with one reduce of packed partials is the designed extension)",
               file=sys.stderr)
         sys.exit(2)
